@@ -1,0 +1,155 @@
+/*
+ * eik.h -- C ABI of the MI355X (gfx950) Randers-Finsler eikonal library.
+ *
+ * Method: "Differentiable Randers-Finsler Eikonal Solvers" (arXiv 2603.00035).
+ *   forward   Sec. 3.2 and Alg. forward: fast-sweeping solve of
+ *             (grad T - b)^T G^-1 (grad T - b) = 1 (Eq. randers_eikonal) with the
+ *             two-point (Eq. two_point) and one-point (Eq. one_point) local
+ *             updates on the eight triangular stencils;
+ *   backward  Sec. 3.3 and Alg. backward: implicit differentiation of the
+ *             converged fixed point (Eqs. implicit, param_grad, adjoint) by one
+ *             reverse pass over the causal order of the nodes;
+ *   project   App. learning details, "Feasibility Projections".
+ *
+ * Layout (all arrays device memory, caller-allocated, row-major, x fastest):
+ *   node (i, j), 0 <= i < nx, 0 <= j < ny, flat index j*nx + i, position (i h, j h);
+ *   M      [3][ny][nx]  metric planes m11, m12, m22 (G = [[m11, m12], [m12, m22]]);
+ *   omega  [2][ny][nx]  drift planes bx, by;
+ *   T      [ny][nx]     arrival times; +inf where no source is reachable;
+ *   parent [ny][nx]     uint8 active update of each node:
+ *                       0..7   two-point stencil k (neighbours k and (k+1) mod 8),
+ *                       8..15  one-point from neighbour k-8,
+ *                       0xFE   source, 0xFF unreached;
+ *                       neighbour k of (i,j) is (i + dx_k, j + dy_k) with
+ *                       (dx,dy)_k = (-1,1) (-1,0) (-1,-1) (0,-1) (1,-1) (1,0) (1,1) (0,1)
+ *                       (counter-clockwise from the upper-left neighbour);
+ *   level  [ny][nx]     int32 dependency level: 0 at sources, 1 + the largest
+ *                       level of the donors elsewhere, -1 where unreached.
+ * Real arrays are float (EIK_F32) or double (EIK_F64) as the dtype argument says.
+ *
+ * Ownership: the caller owns every buffer, including the workspace (size from
+ * eik_workspace_bytes). The library keeps no state between calls and never
+ * allocates device memory. Work is enqueued on the given HIP stream.
+ *
+ * Errors: every call returns an int status and never throws. Negative values
+ * are errors (nothing useful was written); EIK_NOT_CONVERGED is a warning
+ * (outputs are valid, the tolerance was not reached within the budget).
+ * eik_last_error() returns a thread-local message for the last non-OK status.
+ */
+#ifndef EIK_H
+#define EIK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { EIK_F32 = 0, EIK_F64 = 1 } eik_dtype;
+
+enum {
+    EIK_OK = 0,
+    EIK_NOT_CONVERGED = 1,
+    EIK_EINVAL = -1,      /* bad argument (size, pointer, dtype, source index) */
+    EIK_EINFEASIBLE = -2, /* metric not SPD or |omega|_{M^-1} >= 1 (when checked) */
+    EIK_EDEVICE = -3,     /* a HIP runtime call failed */
+    EIK_EWORKSPACE = -4   /* workspace missing or smaller than eik_workspace_bytes */
+};
+
+/* Flags for eik_forward. */
+enum {
+    EIK_CHECK_FEASIBLE = 1, /* verify m11 > 0, det M > 0, |omega|_{M^-1} < 1 first */
+    EIK_TIME_KERNELS = 2    /* time each sweep-kernel launch with HIP events (stats) */
+};
+
+/* One grid. src_idx: device array of n_src distinct flat node indices.
+ * src_t: device array of n_src source times in the run's dtype, or NULL for 0. */
+typedef struct eik_grid {
+    int32_t nx, ny;
+    double h;
+    int32_t n_src;
+    const int32_t *src_idx;
+    const void *src_t;
+} eik_grid;
+
+/* Host-side report of a solve (filled only when a non-NULL pointer is given;
+ * asking for it synchronises the stream). */
+typedef struct eik_stats {
+    int32_t rounds;        /* scheduling rounds of the tiled sweep */
+    int32_t converged;     /* 1 when no node changed by more than tol */
+    int64_t cell_updates;  /* local-update evaluations (one per node per sweep) */
+    int32_t n_levels;      /* largest level + 1 */
+    int32_t status;        /* same as the return value */
+    int32_t sweep_launches;/* launches of the tile-sweep kernel */
+    double sweep_ms;       /* their summed duration (EIK_TIME_KERNELS), else 0 */
+} eik_stats;
+
+/* Scheduling knobs (NULL = library defaults). */
+typedef struct eik_tuning {
+    int32_t max_local_cycles; /* four-sweep cycles a tile may run per round (>= 1) */
+    int32_t rounds_per_check; /* rounds enqueued between convergence checks (>= 1) */
+    int32_t adjoint_single_wg_max_cells; /* grids up to this size run the level loop in one workgroup */
+} eik_tuning;
+
+/* Bytes of workspace eik_forward / eik_backward need for this grid and dtype. */
+size_t eik_workspace_bytes(const eik_grid *grid, int32_t dtype);
+
+/* Forward solve (Sec. 3.2, Alg. forward).
+ *   M, omega  inputs as laid out above;
+ *   T_init    optional [ny][nx] initial field (warm start) or NULL for the
+ *             cold start (+inf away from the sources); the update overwrites
+ *             T rather than taking a minimum with the previous value;
+ *   tol       a node counts as changed when |dT| > tol |T| (or it changes
+ *             between finite and infinite); the solve ends when a full
+ *             four-direction cycle leaves no node changed. tol = 0 asks for
+ *             exact stationarity;
+ *   max_rounds bound on scheduling rounds (EIK_NOT_CONVERGED past it);
+ *   T, parent, level outputs; ws/ws_bytes workspace; stats optional.
+ * Errors: EIK_EINVAL (nx, ny < 1, h <= 0, n_src < 1, NULL pointers, dtype),
+ *         EIK_EWORKSPACE, EIK_EINFEASIBLE (with EIK_CHECK_FEASIBLE),
+ *         EIK_EDEVICE. Out-of-range source indices are ignored on the device
+ *         and reported as EIK_EINVAL when stats is requested. */
+int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T_init,
+                double tol, int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level,
+                void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
+
+/* Adjoint (Sec. 3.3, Alg. backward): given dL/dT and the saved state
+ * (M, omega, T, parent, level) of eik_forward, writes dL/dM [3][ny][nx]
+ * (derivatives with respect to the stored m11, m12, m22), dL/domega
+ * [2][ny][nx] and dL/dt_src [n_src]. Nodes are processed level by level in
+ * decreasing order; each node gathers from the nodes it feeds (no atomics).
+ * Unreached nodes and the parameters of source nodes get zero gradient. */
+int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
+                 const uint8_t *parent, const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega,
+                 void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning, hipStream_t stream);
+
+/* Feasibility projection parameters (App. learning details); the paper leaves
+ * the constants open. Defaults: 1e-3, 1e3, 1e3, 0.95. */
+typedef struct eik_project_params {
+    double eig_min, eig_max, eucl_clip, rho_max;
+} eik_project_params;
+
+/* Per node of n: eigenvalues of M by the trace-discriminant formula, clamped to
+ * [eig_min, eig_max]; when a clamp is active M is rebuilt from the clamped
+ * eigenvalues and the principal angle atan2(2 m12, m11 - m22)/2, otherwise it
+ * passes unchanged. omega is clipped to Euclidean norm eucl_clip, then rescaled
+ * so that |omega|_{M^-1} <= rho_max. Planes as above with n = nx*ny. */
+int eik_project(int64_t n, int32_t dtype, const void *M_in, const void *omega_in, void *M_out, void *omega_out,
+                const eik_project_params *params, hipStream_t stream);
+
+/* Vector-Jacobian product of eik_project: given gradients with respect to its
+ * outputs, writes gradients with respect to its inputs. */
+int eik_project_backward(int64_t n, int32_t dtype, const void *M_in, const void *omega_in, const void *gM_out,
+                         const void *gomega_out, void *gM_in, void *gomega_in, const eik_project_params *params,
+                         hipStream_t stream);
+
+/* Thread-local description of the last non-OK status. */
+const char *eik_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EIK_H */

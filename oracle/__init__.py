@@ -56,6 +56,8 @@ def lib():
         L.ora_two_point.restype = i
         L.ora_one_point.argtypes = [dp, dp, d, i, d]
         L.ora_one_point.restype = d
+        L.ora_candidate.argtypes = [i, i, d, dp, dp, dp, i, i, ip]
+        L.ora_candidate.restype = d
         L.ora_parents_levels.argtypes = [i, i, d, dp, dp, i, ip, dp, up, ip]
         L.ora_vjp.argtypes = [i, i, d, dp, dp, i, ip, dp, up, dp, dp, dp, dp]
         L.ora_jvp.argtypes = [i, i, d, dp, dp, i, ip, dp, up, dp, dp, dp, dp]
@@ -135,6 +137,15 @@ def local_update(prob, T, c, one_point_only=False):
     v = lib().ora_local_update(prob.nx, prob.ny, prob.h, _dp(M), _dp(om), _dp(T), int(c),
                                int(one_point_only), ctypes.byref(code))
     return v, code.value
+
+
+def candidate(prob, T, c, code):
+    """(value, valid) of one given candidate code at node c of the field T."""
+    M, om, T = _d(prob.M), _d(prob.omega), _d(T)
+    ok = ctypes.c_int(0)
+    v = lib().ora_candidate(prob.nx, prob.ny, prob.h, _dp(M), _dp(om), _dp(T), int(c), int(code),
+                            ctypes.byref(ok))
+    return v, bool(ok.value)
 
 
 def two_point(g, b, h, kp, kq, Tp, Tq):

@@ -458,3 +458,28 @@ void ora_jvp(int nx, int ny, double h, const double *M, const double *om, int n_
     }
     free(ord);
 }
+
+/* Value of one given candidate (code 0..7 two-point, 8..15 one-point) at node c
+ * of the field T, for tests that accept any minimiser among near-equal
+ * candidates. Returns +inf when a donor is missing or infinite; *valid tells
+ * whether the candidate passes the validity and causality tests. */
+double ora_candidate(int nx, int ny, double h, const double *M, const double *om, const double *T, int c,
+                     int code, int *valid)
+{
+    ora_field f = {nx, ny, h, M, om};
+    double g[3], b[2], Tn[8];
+    params_at(&f, c, g, b);
+    neighbour_times(&f, T, c % nx, c / nx, Tn);
+    *valid = 0;
+    if (code >= 8 && code < 16) {
+        if (!isfinite(Tn[code - 8])) return INFINITY;
+        *valid = 1;
+        return one_point(g, b, h, code - 8, Tn[code - 8]);
+    }
+    if (code < 0 || code >= 8) return INFINITY;
+    int kq = (code + 1) & 7;
+    if (!isfinite(Tn[code]) || !isfinite(Tn[kq])) return INFINITY;
+    double t;
+    *valid = two_point(g, b, h, code, kq, Tn[code], Tn[kq], &t, NULL, NULL);
+    return t;
+}

@@ -1,0 +1,183 @@
+"""PyTorch-facing API of the gfx950 Randers eikonal library.
+
+``solve`` / ``adjoint`` call ``eik_forward`` / ``eik_backward``; ``EikonalFn``
+wraps them as a ``torch.autograd.Function`` (implicit differentiation of the
+converged fixed point, Sec. 3.3); ``ProjectFn`` wraps ``eik_project`` and its
+VJP (App. learning details). PyTorch provides device memory and the stream;
+the arithmetic runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class Stats:
+    rounds: int
+    converged: bool
+    cell_updates: int
+    n_levels: int
+    status: int
+    sweep_launches: int = 0
+    sweep_ms: float = 0.0
+
+
+def _check_fields(M, omega):
+    if M.dim() != 3 or M.shape[0] != 3:
+        raise ValueError("M must have shape (3, ny, nx)")
+    if omega.shape != (2,) + tuple(M.shape[1:]):
+        raise ValueError("omega must have shape (2, ny, nx)")
+    if M.dtype != omega.dtype:
+        raise TypeError("M and omega must share a dtype")
+    if not (M.is_cuda and omega.is_cuda):
+        raise ValueError("fields must be on the GPU")
+    if not (M.is_contiguous() and omega.is_contiguous()):
+        raise ValueError("fields must be contiguous")
+
+
+def make_grid(nx, ny, h, src_idx, src_t=None) -> L.EikGrid:
+    if src_idx.dtype != torch.int32 or not src_idx.is_cuda or not src_idx.is_contiguous():
+        raise ValueError("src_idx must be a contiguous int32 GPU tensor")
+    return L.EikGrid(int(nx), int(ny), float(h), int(src_idx.numel()), src_idx.data_ptr(),
+                     None if src_t is None else src_t.data_ptr())
+
+
+def workspace(grid: L.EikGrid, dtype_code: int, device) -> torch.Tensor:
+    nbytes = L.lib().eik_workspace_bytes(ctypes.byref(grid), dtype_code)
+    if nbytes == 0:
+        L.check("eik_workspace_bytes", L.EIK_EINVAL)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def tuning(max_local_cycles=0, rounds_per_check=0, adjoint_single_wg_max_cells=-1):
+    return L.EikTuning(max_local_cycles, rounds_per_check, adjoint_single_wg_max_cells)
+
+
+def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=4096, check_feasible=False,
+          tune=None, ws=None, time_kernels=False):
+    """Forward solve. Returns (T, parent, level, Stats)."""
+    _check_fields(M, omega)
+    ny, nx = M.shape[1:]
+    dev = M.device
+    if src_t is not None:
+        src_t = src_t.to(device=dev, dtype=M.dtype).contiguous()
+    grid = make_grid(nx, ny, h, src_idx, src_t)
+    dc = L.dtype_code(M)
+    if ws is None:
+        ws = workspace(grid, dc, dev)
+    T = torch.empty((ny, nx), dtype=M.dtype, device=dev)
+    parent = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
+    level = torch.empty((ny, nx), dtype=torch.int32, device=dev)
+    if T_init is not None:
+        T_init = T_init.to(device=dev, dtype=M.dtype).contiguous()
+    st = L.EikStats()
+    rc = L.lib().eik_forward(ctypes.byref(grid), dc, L.ptr(M), L.ptr(omega), L.ptr(T_init), float(tol),
+                             int(max_rounds),
+                             (L.EIK_CHECK_FEASIBLE if check_feasible else 0) | (L.EIK_TIME_KERNELS if time_kernels else 0),
+                             L.ptr(T),
+                             L.ptr(parent), L.ptr(level), L.ptr(ws), ws.numel(),
+                             None if tune is None else ctypes.byref(tune), ctypes.byref(st), L.stream_handle(dev))
+    L.check("eik_forward", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
+    return T, parent, level, Stats(st.rounds, bool(st.converged), st.cell_updates, st.n_levels, st.status,
+                                   st.sweep_launches, st.sweep_ms)
+
+
+def adjoint(M, omega, T, parent, level, src_idx, h, dLdT, src_t=None, tune=None, ws=None):
+    """Backward pass. Returns (dL/dM, dL/domega, dL/dt_src)."""
+    _check_fields(M, omega)
+    ny, nx = M.shape[1:]
+    dev = M.device
+    grid = make_grid(nx, ny, h, src_idx, src_t)
+    dc = L.dtype_code(M)
+    if ws is None:
+        ws = workspace(grid, dc, dev)
+    dLdT = dLdT.to(dtype=M.dtype).contiguous()
+    dM = torch.empty_like(M)
+    dom = torch.empty_like(omega)
+    ds = torch.empty(src_idx.numel(), dtype=M.dtype, device=dev)
+    rc = L.lib().eik_backward(ctypes.byref(grid), dc, L.ptr(M), L.ptr(omega), L.ptr(T), L.ptr(parent),
+                              L.ptr(level), L.ptr(dLdT), L.ptr(dM), L.ptr(dom), L.ptr(ds), L.ptr(ws), ws.numel(),
+                              None if tune is None else ctypes.byref(tune), L.stream_handle(dev))
+    L.check("eik_backward", rc)
+    return dM, dom, ds
+
+
+class EikonalFn(torch.autograd.Function):
+    """T = eikonal(M, omega, src_t); gradients by implicit differentiation."""
+
+    @staticmethod
+    def forward(ctx, M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink=None, time_kernels=False):
+        M = M.contiguous()
+        omega = omega.contiguous()
+        T, parent, level, stats = solve(M, omega, src_idx, h, src_t=src_t, tol=tol, max_rounds=max_rounds,
+                                        time_kernels=time_kernels)
+        if stats_sink is not None:
+            stats_sink.append(stats)
+        ctx.save_for_backward(M, omega, T, parent, level, src_idx)
+        ctx.h = h
+        ctx.has_src_t = src_t is not None
+        ctx.stats = stats
+        ctx.mark_non_differentiable(parent, level)
+        return T, parent, level
+
+    @staticmethod
+    def backward(ctx, gT, _gp=None, _gl=None):
+        M, omega, T, parent, level, src_idx = ctx.saved_tensors
+        dM, dom, ds = adjoint(M, omega, T, parent, level, src_idx, ctx.h, gT)
+        return dM, dom, (ds if ctx.has_src_t else None), None, None, None, None, None, None
+
+
+def eikonal(M, omega, src_idx, h, src_t=None, tol=1e-5, max_rounds=4096, stats_sink=None, time_kernels=False):
+    """Differentiable solve; returns (T, parent, level). ``stats_sink`` (a list)
+    receives the forward's Stats."""
+    return EikonalFn.apply(M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink, time_kernels)
+
+
+def _proj_params(eig_min, eig_max, eucl_clip, rho_max):
+    return L.EikProjectParams(eig_min, eig_max, eucl_clip, rho_max)
+
+
+def project(M, omega, eig_min=1e-3, eig_max=1e3, eucl_clip=1e3, rho_max=0.95):
+    _check_fields(M, omega)
+    n = M[0].numel()
+    Mo, oo = torch.empty_like(M), torch.empty_like(omega)
+    p = _proj_params(eig_min, eig_max, eucl_clip, rho_max)
+    L.check("eik_project", L.lib().eik_project(n, L.dtype_code(M), L.ptr(M), L.ptr(omega), L.ptr(Mo), L.ptr(oo),
+                                               ctypes.byref(p), L.stream_handle(M.device)))
+    return Mo, oo
+
+
+def project_backward(M, omega, gMo, goo, eig_min=1e-3, eig_max=1e3, eucl_clip=1e3, rho_max=0.95):
+    _check_fields(M, omega)
+    n = M[0].numel()
+    gMo, goo = gMo.to(M.dtype).contiguous(), goo.to(M.dtype).contiguous()
+    gM, go = torch.empty_like(M), torch.empty_like(omega)
+    p = _proj_params(eig_min, eig_max, eucl_clip, rho_max)
+    L.check("eik_project_backward",
+            L.lib().eik_project_backward(n, L.dtype_code(M), L.ptr(M), L.ptr(omega), L.ptr(gMo), L.ptr(goo),
+                                         L.ptr(gM), L.ptr(go), ctypes.byref(p), L.stream_handle(M.device)))
+    return gM, go
+
+
+class ProjectFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, M, omega, eig_min=1e-3, eig_max=1e3, eucl_clip=1e3, rho_max=0.95):
+        M, omega = M.contiguous(), omega.contiguous()
+        ctx.save_for_backward(M, omega)
+        ctx.p = (eig_min, eig_max, eucl_clip, rho_max)
+        return project(M, omega, *ctx.p)
+
+    @staticmethod
+    def backward(ctx, gMo, goo):
+        M, omega = ctx.saved_tensors
+        if gMo is None:
+            gMo = torch.zeros_like(M)
+        if goo is None:
+            goo = torch.zeros_like(omega)
+        gM, go = project_backward(M, omega, gMo, goo, *ctx.p)
+        return gM, go, None, None, None, None

@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports every entry point include/eik.h
+declares; host-side argument checks reject bad calls before any launch.
+No kernel runs here (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "eik.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(eik_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for need in ("eik_forward", "eik_backward", "eik_project", "eik_project_backward", "eik_workspace_bytes",
+                 "eik_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2603_00035_amd import _lib as L
+    lib = L.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTS) <= set(declared_functions())
+
+
+def grid(nx=64, ny=64, h=0.1, n_src=1, src=1):
+    from paper_2603_00035_amd import _lib as L
+    return L.EikGrid(nx, ny, h, n_src, src, None)
+
+
+def test_workspace_size_and_invalid_grids():
+    from paper_2603_00035_amd import _lib as L
+    lib = L.lib()
+    small = lib.eik_workspace_bytes(ctypes.byref(grid()), L.EIK_F32)
+    big = lib.eik_workspace_bytes(ctypes.byref(grid(512, 512)), L.EIK_F32)
+    dbl = lib.eik_workspace_bytes(ctypes.byref(grid(512, 512)), L.EIK_F64)
+    assert 0 < small < big < dbl
+    for bad in (grid(0, 5), grid(5, 5, h=0.0), grid(5, 5, n_src=0), grid(5, 5, src=0)):
+        assert lib.eik_workspace_bytes(ctypes.byref(bad), L.EIK_F32) == 0
+    assert lib.eik_workspace_bytes(ctypes.byref(grid()), 7) == 0
+
+
+@pytest.mark.parametrize("case", ["null_fields", "negative_tol", "rounds", "dtype", "workspace"])
+def test_forward_rejects_bad_arguments_on_host(case):
+    from paper_2603_00035_amd import _lib as L
+    lib = L.lib()
+    g = grid()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the checks run before any launch
+    args = dict(dtype=L.EIK_F32, M=fake, om=fake, tol=1e-5, rounds=10, ws=fake, wsb=1 << 40)
+    if case == "null_fields":
+        args["M"] = None
+    elif case == "negative_tol":
+        args["tol"] = -1.0
+    elif case == "rounds":
+        args["rounds"] = 0
+    elif case == "dtype":
+        args["dtype"] = 3
+    elif case == "workspace":
+        args["wsb"] = 16
+    rc = lib.eik_forward(ctypes.byref(g), args["dtype"], args["M"], args["om"], None, args["tol"], args["rounds"],
+                         0, fake, fake, fake, args["ws"], args["wsb"], None, None, None)
+    assert rc == (-4 if case == "workspace" else -1)
+    assert lib.eik_last_error()
+
+
+def test_project_rejects_bad_parameters():
+    from paper_2603_00035_amd import _lib as L
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    p = L.EikProjectParams(1e-3, 1e3, 1e3, 1.5)  # rho_max must be < 1
+    assert lib.eik_project(10, L.EIK_F32, fake, fake, fake, fake, ctypes.byref(p), None) == -1
+    assert lib.eik_project(0, L.EIK_F32, None, None, None, None, None, None) == 0
