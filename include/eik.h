@@ -9,7 +9,9 @@
  *   backward  Sec. 3.3 and Alg. backward: implicit differentiation of the
  *             converged fixed point (Eqs. implicit, param_grad, adjoint) by one
  *             reverse pass over the causal order of the nodes;
- *   project   App. learning details, "Feasibility Projections".
+ *   project   App. learning details, "Feasibility Projections";
+ *   batched   the same for many independent grids of different sizes in one
+ *             launch sequence (the paper batches problem instances, Sec. 4.3).
  *
  * Layout (all arrays device memory, caller-allocated, row-major, x fastest):
  *   node (i, j), 0 <= i < nx, 0 <= j < ny, flat index j*nx + i, position (i h, j h);
@@ -26,10 +28,15 @@
  *   level  [ny][nx]     int32 dependency level: 0 at sources, 1 + the largest
  *                       level of the donors elsewhere, -1 where unreached.
  * Real arrays are float (EIK_F32) or double (EIK_F64) as the dtype argument says.
+ * Batched calls pack the grids one after the other: the node arrays of grid g
+ * start at node offset off_g = sum over earlier grids of nx*ny, its M planes at
+ * 3 off_g, its omega planes at 2 off_g; src_idx / src_t / dL/dt_src hold the
+ * sources of grid 0, then grid 1, ..., with indices local to their grid.
  *
  * Ownership: the caller owns every buffer, including the workspace (size from
- * eik_workspace_bytes). The library keeps no state between calls and never
- * allocates device memory. Work is enqueued on the given HIP stream.
+ * eik_workspace_bytes / eik_batch_workspace_bytes). The library keeps no state
+ * between calls and never allocates device memory. Work is enqueued on the
+ * given HIP stream.
  *
  * Errors: every call returns an int status and never throws. Negative values
  * are errors (nothing useful was written); EIK_NOT_CONVERGED is a warning
@@ -55,18 +62,19 @@ enum {
     EIK_NOT_CONVERGED = 1,
     EIK_EINVAL = -1,      /* bad argument (size, pointer, dtype, source index) */
     EIK_EINFEASIBLE = -2, /* metric not SPD or |omega|_{M^-1} >= 1 (when checked) */
-    EIK_EDEVICE = -3,     /* a HIP runtime call failed */
-    EIK_EWORKSPACE = -4   /* workspace missing or smaller than eik_workspace_bytes */
+    EIK_EDEVICE = -3,     /* a HIP runtime call failed, or an internal schedule did not settle */
+    EIK_EWORKSPACE = -4   /* workspace missing or smaller than needed */
 };
 
-/* Flags for eik_forward. */
+/* Flags for the forward calls. */
 enum {
     EIK_CHECK_FEASIBLE = 1, /* verify m11 > 0, det M > 0, |omega|_{M^-1} < 1 first */
     EIK_TIME_KERNELS = 2    /* time each sweep-kernel launch with HIP events (stats) */
 };
 
 /* One grid. src_idx: device array of n_src distinct flat node indices.
- * src_t: device array of n_src source times in the run's dtype, or NULL for 0. */
+ * src_t: device array of n_src source times in the run's dtype, or NULL for 0.
+ * (Batched calls take the source arrays separately and ignore these two.) */
 typedef struct eik_grid {
     int32_t nx, ny;
     double h;
@@ -75,26 +83,31 @@ typedef struct eik_grid {
     const void *src_t;
 } eik_grid;
 
-/* Host-side report of a solve (filled only when a non-NULL pointer is given;
+/* Host-side report of a call (filled only when a non-NULL pointer is given;
  * asking for it synchronises the stream). */
 typedef struct eik_stats {
-    int32_t rounds;        /* scheduling rounds of the tiled sweep */
-    int32_t converged;     /* 1 when no node changed by more than tol */
-    int64_t cell_updates;  /* local-update evaluations (one per node per sweep) */
-    int32_t n_levels;      /* largest level + 1 */
-    int32_t status;        /* same as the return value */
-    int32_t sweep_launches;/* launches of the tile-sweep kernel */
-    double sweep_ms;       /* their summed duration (EIK_TIME_KERNELS), else 0 */
+    int32_t rounds;         /* tile-sweep rounds (forward) or adjoint rounds (backward) */
+    int32_t converged;      /* 1 when no node changed by more than tol */
+    int64_t cell_updates;   /* local-update evaluations (one per node per sweep) */
+    int32_t n_levels;       /* largest level + 1 */
+    int32_t status;         /* same as the return value */
+    int32_t sweep_launches; /* launches of the tile-sweep kernel */
+    int32_t aux_rounds;     /* level rounds (forward) / adjoint rounds (backward) */
+    double sweep_ms;        /* summed duration of the sweep launches (EIK_TIME_KERNELS), else 0 */
 } eik_stats;
 
-/* Scheduling knobs (NULL = library defaults). */
+/* Scheduling knobs; NULL or a field <= 0 keeps the library default. */
 typedef struct eik_tuning {
-    int32_t max_local_cycles; /* four-sweep cycles a tile may run per round (>= 1) */
-    int32_t rounds_per_check; /* rounds enqueued between convergence checks (>= 1) */
-    int32_t adjoint_single_wg_max_cells; /* grids up to this size run the level loop in one workgroup */
+    int32_t tile_height;      /* 32 or 64 (tiles are 64 nodes wide); default 64 */
+    int32_t max_local_cycles; /* four-sweep cycles a tile may run per round; default 2 */
+    int32_t rounds_per_check; /* rounds enqueued between host convergence checks; default 8 */
+    int32_t fast_cold_start;  /* 1: restricted-candidate min sweeps before the full ones (cold start); default 0 */
+    int32_t adjoint_rounds;   /* fixed adjoint round budget of unsynchronised batched calls; default 64 */
+    int32_t level_rounds;     /* fixed level round budget of unsynchronised batched calls; default 8 */
 } eik_tuning;
 
-/* Bytes of workspace eik_forward / eik_backward need for this grid and dtype. */
+/* Bytes of workspace eik_forward / eik_backward need for this grid and dtype
+ * (0 for an invalid grid). */
 size_t eik_workspace_bytes(const eik_grid *grid, int32_t dtype);
 
 /* Forward solve (Sec. 3.2, Alg. forward).
@@ -106,12 +119,13 @@ size_t eik_workspace_bytes(const eik_grid *grid, int32_t dtype);
  *             between finite and infinite); the solve ends when a full
  *             four-direction cycle leaves no node changed. tol = 0 asks for
  *             exact stationarity;
- *   max_rounds bound on scheduling rounds (EIK_NOT_CONVERGED past it);
- *   T, parent, level outputs; ws/ws_bytes workspace; stats optional.
- * Errors: EIK_EINVAL (nx, ny < 1, h <= 0, n_src < 1, NULL pointers, dtype),
- *         EIK_EWORKSPACE, EIK_EINFEASIBLE (with EIK_CHECK_FEASIBLE),
- *         EIK_EDEVICE. Out-of-range source indices are ignored on the device
- *         and reported as EIK_EINVAL when stats is requested. */
+ *   max_rounds bound on tile-sweep rounds per phase (EIK_NOT_CONVERGED past it);
+ *   T, parent, level outputs; ws/ws_bytes workspace; tuning and stats optional.
+ * The call synchronises the stream between batches of rounds to test for
+ * convergence. Out-of-range source indices are ignored on the device and
+ * reported as EIK_EINVAL.
+ * Errors: EIK_EINVAL, EIK_EWORKSPACE, EIK_EINFEASIBLE (with
+ * EIK_CHECK_FEASIBLE), EIK_EDEVICE. */
 int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T_init,
                 double tol, int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level,
                 void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
@@ -119,12 +133,43 @@ int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *
 /* Adjoint (Sec. 3.3, Alg. backward): given dL/dT and the saved state
  * (M, omega, T, parent, level) of eik_forward, writes dL/dM [3][ny][nx]
  * (derivatives with respect to the stored m11, m12, m22), dL/domega
- * [2][ny][nx] and dL/dt_src [n_src]. Nodes are processed level by level in
- * decreasing order; each node gathers from the nodes it feeds (no atomics).
- * Unreached nodes and the parameters of source nodes get zero gradient. */
+ * [2][ny][nx] and dL/dt_src [n_src]. Nodes are processed by decreasing level;
+ * each node gathers from the nodes it feeds (no atomics). Unreached nodes and
+ * the parameters of source nodes get zero gradient. Tiles exchange their
+ * border adjoints between rounds (the call synchronises the stream to test
+ * that no border changed); stats, when given, receives the round count. */
 int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
                  const uint8_t *parent, const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega,
-                 void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning, hipStream_t stream);
+                 void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats,
+                 hipStream_t stream);
+
+/* Batched solving (n_grids independent grids, packed as described above).
+ * eik_batch_workspace_bytes sizes the workspace; eik_batch_plan writes the
+ * grid descriptors into it (host -> device copy, synchronous) and must be
+ * called again when the grids or tuning.tile_height change. The forward and
+ * backward batched calls then only enqueue kernels: with stats == NULL they
+ * run a fixed schedule (max_rounds sweep rounds per phase, adjoint_rounds
+ * adjoint rounds; rounds after convergence exit at once) and never
+ * synchronise, so they can be captured in a HIP graph and replayed. */
+size_t eik_batch_workspace_bytes(int32_t n_grids, const eik_grid *grids, int32_t dtype);
+int eik_batch_plan(int32_t n_grids, const eik_grid *grids, int32_t dtype, const eik_tuning *tuning, void *ws,
+                   size_t ws_bytes, hipStream_t stream);
+int eik_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
+                        const void *src_t, const void *M, const void *omega, const void *T_init, double tol,
+                        int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level, void *ws,
+                        size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
+int eik_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
+                         const void *M, const void *omega, const void *T, const uint8_t *parent,
+                         const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega, void *dLdsrc, void *ws,
+                         size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
+
+/* After an unsynchronised batched forward and/or backward (e.g. a graph
+ * replay), reads how many tiles were still flagged when the fixed budgets ran
+ * out: pending[0] sweep rounds, pending[1] level rounds, pending[2] adjoint
+ * rounds. All zero means every phase settled within its budget; otherwise the
+ * budgets (max_rounds, tuning) must be raised. Synchronises the stream. */
+int eik_batch_pending(int32_t n_grids, const eik_grid *grids, int32_t dtype, const void *ws, size_t ws_bytes,
+                      int64_t pending[3], hipStream_t stream);
 
 /* Feasibility projection parameters (App. learning details); the paper leaves
  * the constants open. Defaults: 1e-3, 1e3, 1e3, 0.95. */

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "EIK_OK", 1: "EIK_NOT_CONVERGED", -1: "EIK_EINVAL", -2: "EIK_
 SOURCE, UNREACHED = 0xFE, 0xFF
 
 EXPORTS = ["eik_workspace_bytes", "eik_forward", "eik_backward", "eik_project", "eik_project_backward",
-           "eik_last_error"]
+           "eik_last_error", "eik_batch_workspace_bytes", "eik_batch_plan", "eik_forward_batched",
+           "eik_backward_batched", "eik_batch_pending"]
 
 
 class EikGrid(ctypes.Structure):
@@ -35,12 +36,13 @@ class EikGrid(ctypes.Structure):
 class EikStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("converged", ctypes.c_int32), ("cell_updates", ctypes.c_int64),
                 ("n_levels", ctypes.c_int32), ("status", ctypes.c_int32), ("sweep_launches", ctypes.c_int32),
-                ("sweep_ms", ctypes.c_double)]
+                ("aux_rounds", ctypes.c_int32), ("sweep_ms", ctypes.c_double)]
 
 
 class EikTuning(ctypes.Structure):
-    _fields_ = [("max_local_cycles", ctypes.c_int32), ("rounds_per_check", ctypes.c_int32),
-                ("adjoint_single_wg_max_cells", ctypes.c_int32)]
+    _fields_ = [("tile_height", ctypes.c_int32), ("max_local_cycles", ctypes.c_int32),
+                ("rounds_per_check", ctypes.c_int32), ("fast_cold_start", ctypes.c_int32),
+                ("adjoint_rounds", ctypes.c_int32), ("level_rounds", ctypes.c_int32)]
 
 
 class EikProjectParams(ctypes.Structure):
@@ -71,12 +73,26 @@ def lib():
                                   ctypes.POINTER(EikTuning), ctypes.POINTER(EikStats), vp]
         L.eik_forward.restype = ctypes.c_int
         L.eik_backward.argtypes = [gp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t,
-                                   ctypes.POINTER(EikTuning), vp]
+                                   ctypes.POINTER(EikTuning), ctypes.POINTER(EikStats), vp]
         L.eik_backward.restype = ctypes.c_int
         L.eik_project.argtypes = [i64, i32, vp, vp, vp, vp, ctypes.POINTER(EikProjectParams), vp]
         L.eik_project.restype = ctypes.c_int
         L.eik_project_backward.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(EikProjectParams), vp]
         L.eik_project_backward.restype = ctypes.c_int
+        tp = ctypes.POINTER(EikTuning)
+        sp = ctypes.POINTER(EikStats)
+        L.eik_batch_workspace_bytes.argtypes = [i32, gp, i32]
+        L.eik_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.eik_batch_plan.argtypes = [i32, gp, i32, tp, vp, ctypes.c_size_t, vp]
+        L.eik_batch_plan.restype = ctypes.c_int
+        L.eik_forward_batched.argtypes = [i32, gp, i32, vp, vp, vp, vp, vp, d, i32, i32, vp, vp, vp, vp,
+                                          ctypes.c_size_t, tp, sp, vp]
+        L.eik_forward_batched.restype = ctypes.c_int
+        L.eik_backward_batched.argtypes = [i32, gp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                           ctypes.c_size_t, tp, sp, vp]
+        L.eik_backward_batched.restype = ctypes.c_int
+        L.eik_batch_pending.argtypes = [i32, gp, i32, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64), vp]
+        L.eik_batch_pending.restype = ctypes.c_int
         L.eik_last_error.argtypes = []
         L.eik_last_error.restype = ctypes.c_char_p
         _lib = L

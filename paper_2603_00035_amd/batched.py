@@ -1,0 +1,116 @@
+"""Batched solving of many independent grids of different sizes.
+
+The grids are packed one after the other (see include/eik.h): node arrays of
+grid g start at node offset off_g, its metric planes at 3 off_g, its drift
+planes at 2 off_g; source arrays hold the sources of grid 0, then grid 1, ...
+with indices local to their grid.
+
+``Batch`` plans the launch once (grid descriptors copied to the device), then
+``forward`` / ``backward`` only enqueue kernels. With ``sync=False`` they run a
+fixed round schedule with no host synchronisation, which makes the pair
+capturable in a HIP graph (``torch.cuda.CUDAGraph``) and replayable;
+``pending()`` then tells whether every phase settled within its budget.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import autotune
+from .eikonal import Stats
+
+
+class Batch:
+    def __init__(self, shapes, dtype=torch.float32, device="cuda", tune=None, max_rounds=64):
+        """shapes: list of (nx, ny, h, n_src)."""
+        self.shapes = [(int(a), int(b), float(c), int(d)) for a, b, c, d in shapes]
+        self.n_grids = len(self.shapes)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.dc = L.dtype_code(torch.empty(0, dtype=dtype))
+        if tune is None:
+            tune = autotune.lookup(max(nx * ny for nx, ny, _, _ in self.shapes), autotune.dtype_name(dtype))
+        self.tune = tune
+        self.max_rounds = max_rounds
+        G = L.EikGrid * self.n_grids
+        self.grids = G(*[L.EikGrid(nx, ny, h, ns, None, None) for nx, ny, h, ns in self.shapes])
+        sizes = [nx * ny for nx, ny, _, _ in self.shapes]
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        self.n_nodes = int(self.offsets[-1])
+        self.src_offsets = np.concatenate([[0], np.cumsum([s[3] for s in self.shapes])]).astype(np.int64)
+        self.n_src = int(self.src_offsets[-1])
+        nbytes = L.lib().eik_batch_workspace_bytes(self.n_grids, self.grids, self.dc)
+        if nbytes == 0:
+            L.check("eik_batch_workspace_bytes", L.EIK_EINVAL)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._tp = None if tune is None else ctypes.byref(tune)
+        L.check("eik_batch_plan", L.lib().eik_batch_plan(self.n_grids, self.grids, self.dc, self._tp,
+                                                           L.ptr(self.ws), self.ws.numel(),
+                                                           L.stream_handle(self.device)))
+
+    # -- packing helpers --------------------------------------------------
+    def pack(self, Ms, oms):
+        """Lists of (3, ny, nx) / (2, ny, nx) tensors -> packed flat tensors
+        (each grid's block stays plane-major: [3][ny][nx], then the next grid)."""
+        Mp = torch.cat([m.reshape(-1).to(self.device, self.dtype) for m in Ms])
+        op = torch.cat([o.reshape(-1).to(self.device, self.dtype) for o in oms])
+        return Mp.contiguous(), op.contiguous()
+
+    def unpack_nodes(self, x):
+        return [x[self.offsets[g]:self.offsets[g + 1]].reshape(self.shapes[g][1], self.shapes[g][0])
+                for g in range(self.n_grids)]
+
+    def unpack_planes(self, x, k):
+        return [x[k * self.offsets[g]:k * self.offsets[g + 1]].reshape(k, self.shapes[g][1], self.shapes[g][0])
+                for g in range(self.n_grids)]
+
+    # -- calls ------------------------------------------------------------
+    def alloc_forward(self):
+        T = torch.empty(self.n_nodes, dtype=self.dtype, device=self.device)
+        parent = torch.empty(self.n_nodes, dtype=torch.uint8, device=self.device)
+        level = torch.empty(self.n_nodes, dtype=torch.int32, device=self.device)
+        return T, parent, level
+
+    def forward(self, M, om, src_idx, src_t=None, T_init=None, tol=1e-5, out=None, sync=True,
+                time_kernels=False):
+        T, parent, level = out if out is not None else self.alloc_forward()
+        st = L.EikStats() if sync else None
+        flags = L.EIK_TIME_KERNELS if (time_kernels and sync) else 0
+        rc = L.lib().eik_forward_batched(self.n_grids, self.grids, self.dc, L.ptr(src_idx), L.ptr(src_t),
+                                         L.ptr(M), L.ptr(om), L.ptr(T_init), float(tol), int(self.max_rounds),
+                                         flags, L.ptr(T), L.ptr(parent), L.ptr(level), L.ptr(self.ws),
+                                         self.ws.numel(), self._tp, None if st is None else ctypes.byref(st),
+                                         L.stream_handle(self.device))
+        L.check("eik_forward_batched", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
+        stats = None
+        if st is not None:
+            stats = Stats(st.rounds, bool(st.converged), st.cell_updates, st.n_levels, st.status,
+                          st.sweep_launches, st.sweep_ms, st.aux_rounds)
+        return T, parent, level, stats
+
+    def alloc_backward(self):
+        dM = torch.empty(3 * self.n_nodes, dtype=self.dtype, device=self.device)
+        dom = torch.empty(2 * self.n_nodes, dtype=self.dtype, device=self.device)
+        ds = torch.empty(self.n_src, dtype=self.dtype, device=self.device)
+        return dM, dom, ds
+
+    def backward(self, M, om, T, parent, level, src_idx, dLdT, out=None, sync=True):
+        dM, dom, ds = out if out is not None else self.alloc_backward()
+        st = L.EikStats() if sync else None
+        rc = L.lib().eik_backward_batched(self.n_grids, self.grids, self.dc, L.ptr(src_idx), L.ptr(M), L.ptr(om),
+                                          L.ptr(T), L.ptr(parent), L.ptr(level), L.ptr(dLdT), L.ptr(dM),
+                                          L.ptr(dom), L.ptr(ds), L.ptr(self.ws), self.ws.numel(), self._tp,
+                                          None if st is None else ctypes.byref(st), L.stream_handle(self.device))
+        L.check("eik_backward_batched", rc)
+        return dM, dom, ds, (None if st is None else st.rounds)
+
+    def pending(self):
+        """Tiles still flagged when the fixed budgets ran out (sweep, level, adjoint)."""
+        out = (ctypes.c_int64 * 3)()
+        L.check("eik_batch_pending", L.lib().eik_batch_pending(self.n_grids, self.grids, self.dc, L.ptr(self.ws),
+                                                                 self.ws.numel(), out,
+                                                                 L.stream_handle(self.device)))
+        return tuple(int(v) for v in out)

@@ -36,96 +36,142 @@ int fail(int code, const char *fmt, ...)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-struct Layout {
-    size_t act, act_count, ctr, lam, w1, counts, cursor, list, total;
-};
-
 constexpr int kDefaultTH = 64;
 
-GridArgs make_grid(const eik_grid *g, int th)
-{
-    GridArgs a;
-    a.nx = g->nx;
-    a.ny = g->ny;
-    a.h = g->h;
-    a.n_src = g->n_src;
-    a.th = th;
-    a.ntx = (g->nx + 63) / 64;
-    a.nty = (g->ny + th - 1) / th;
-    a.n_tiles = a.ntx * a.nty;
-    return a;
-}
+// Sizes of a launch over a set of grids.
+struct Extent {
+    int64_t nodes = 0;
+    int64_t tiles32 = 0, tiles64 = 0;
+    int32_t n_grids = 0, n_src = 0;
+};
 
-Layout layout(const eik_grid *g, int dtype)
+int64_t tiles_of(int nx, int ny, int th) { return (int64_t)((nx + TW - 1) / TW) * ((ny + th - 1) / th); }
+
+struct Layout {
+    size_t descs, tile_grid, act, act_count, ctr, Pt, lam, w1, list, cnt, total;
+};
+
+Layout layout(const Extent &e, int dtype)
 {
-    const size_t n = (size_t)g->nx * (size_t)g->ny;
     const size_t rs = dtype == EIK_F64 ? 8 : 4;
-    // tile counts for the smallest tile height (largest count)
-    const size_t tiles = (size_t)((g->nx + 63) / 64) * (size_t)((g->ny + 31) / 32);
+    const size_t NT = (size_t)std::max(e.tiles32, e.tiles64);
+    const size_t list_n = std::max((size_t)e.tiles64 * TW * 64, (size_t)e.tiles32 * TW * 32);
     Layout L;
     size_t o = 0;
-    L.act = o;       o += align256(2 * tiles * 4);
+    L.descs = o;     o += align256((size_t)e.n_grids * sizeof(GridDesc));
+    L.tile_grid = o; o += align256(NT * 4);
+    L.act = o;       o += align256(2 * NT * 4);
     L.act_count = o; o += align256((size_t)(kMaxRounds + 2) * 4);
     L.ctr = o;       o += align256(kCtrCount * 8);
-    L.lam = o;       o += align256(n * rs);
-    L.w1 = o;        o += align256(n * rs);
-    L.counts = o;    o += align256((n + 2) * 4);
-    L.cursor = o;    o += align256((n + 2) * 4);
-    L.list = o;      o += align256(n * 4);
+    L.Pt = o;        o += align256(5 * (size_t)e.nodes * rs);
+    L.lam = o;       o += align256((size_t)e.nodes * rs);
+    L.w1 = o;        o += align256((size_t)e.nodes * rs);
+    L.list = o;      o += align256(list_n * 4);
+    L.cnt = o;       o += align256(NT * 4);
     L.total = o;
     return L;
 }
 
-int check_grid(const eik_grid *g, int dtype)
+int check_one(const eik_grid *g, int idx)
 {
-    if (!g) return fail(EIK_EINVAL, "grid is NULL");
-    if (g->nx < 1 || g->ny < 1) return fail(EIK_EINVAL, "grid size %d x %d", g->nx, g->ny);
-    if ((int64_t)g->nx * g->ny >= ((int64_t)1 << 31)) return fail(EIK_EINVAL, "grid has 2^31 nodes or more");
-    if (!(g->h > 0.0)) return fail(EIK_EINVAL, "grid spacing h must be positive");
-    if (g->n_src < 1 || !g->src_idx) return fail(EIK_EINVAL, "at least one source index is required");
-    if (dtype != EIK_F32 && dtype != EIK_F64) return fail(EIK_EINVAL, "dtype %d", dtype);
+    if (g->nx < 1 || g->ny < 1) return fail(EIK_EINVAL, "grid %d: size %d x %d", idx, g->nx, g->ny);
+    if ((int64_t)g->nx * g->ny >= ((int64_t)1 << 31)) return fail(EIK_EINVAL, "grid %d: 2^31 nodes or more", idx);
+    if (!(g->h > 0.0)) return fail(EIK_EINVAL, "grid %d: spacing h must be positive", idx);
+    if (g->n_src < 1) return fail(EIK_EINVAL, "grid %d: at least one source is required", idx);
     return EIK_OK;
 }
 
+int extent_of(int n_grids, const eik_grid *grids, int dtype, Extent &e)
+{
+    if (!grids || n_grids < 1) return fail(EIK_EINVAL, "no grids");
+    if (dtype != EIK_F32 && dtype != EIK_F64) return fail(EIK_EINVAL, "dtype %d", dtype);
+    e = Extent();
+    e.n_grids = n_grids;
+    for (int g = 0; g < n_grids; ++g) {
+        int rc = check_one(&grids[g], g);
+        if (rc) return rc;
+        e.nodes += (int64_t)grids[g].nx * grids[g].ny;
+        e.tiles32 += tiles_of(grids[g].nx, grids[g].ny, 32);
+        e.tiles64 += tiles_of(grids[g].nx, grids[g].ny, 64);
+        e.n_src += grids[g].n_src;
+    }
+    if (std::max(e.tiles32, e.tiles64) >= ((int64_t)1 << 30)) return fail(EIK_EINVAL, "too many tiles");
+    return EIK_OK;
+}
+
+// Host-side descriptors of a launch.
+void host_descs(int n_grids, const eik_grid *grids, int th, std::vector<GridDesc> &d, std::vector<int32_t> &tg)
+{
+    d.resize(n_grids);
+    tg.clear();
+    int64_t off = 0;
+    int32_t tb = 0, sb = 0;
+    for (int g = 0; g < n_grids; ++g) {
+        GridDesc x;
+        memset(&x, 0, sizeof x);
+        x.off = off;
+        x.h = grids[g].h;
+        x.nx = grids[g].nx;
+        x.ny = grids[g].ny;
+        x.ntx = (x.nx + TW - 1) / TW;
+        x.nty = (x.ny + th - 1) / th;
+        x.tile_base = tb;
+        x.n_src = grids[g].n_src;
+        x.src_base = sb;
+        d[g] = x;
+        for (int t = 0; t < x.ntx * x.nty; ++t) tg.push_back(g);
+        off += (int64_t)x.nx * x.ny;
+        tb += x.ntx * x.nty;
+        sb += x.n_src;
+    }
+}
+
 struct Ws {
-    int32_t *act, *act_count, *counts, *cursor, *list;
+    GridDesc *descs;
+    int32_t *tile_grid, *act, *act_count, *list, *cnt;
     unsigned long long *ctr;
-    void *lam, *w1;
+    void *Pt, *lam, *w1;
 };
 
-int carve(const eik_grid *g, int dtype, void *ws, size_t ws_bytes, Ws &w)
+int carve(const Extent &e, int dtype, void *ws, size_t ws_bytes, Ws &w)
 {
-    const Layout L = layout(g, dtype);
+    const Layout L = layout(e, dtype);
     if (!ws || ws_bytes < L.total)
         return fail(EIK_EWORKSPACE, "workspace %zu bytes, %zu needed", ws_bytes, L.total);
     char *b = (char *)ws;
+    w.descs = (GridDesc *)(b + L.descs);
+    w.tile_grid = (int32_t *)(b + L.tile_grid);
     w.act = (int32_t *)(b + L.act);
     w.act_count = (int32_t *)(b + L.act_count);
     w.ctr = (unsigned long long *)(b + L.ctr);
+    w.Pt = b + L.Pt;
     w.lam = b + L.lam;
     w.w1 = b + L.w1;
-    w.counts = (int32_t *)(b + L.counts);
-    w.cursor = (int32_t *)(b + L.cursor);
     w.list = (int32_t *)(b + L.list);
+    w.cnt = (int32_t *)(b + L.cnt);
     return EIK_OK;
 }
 
 eik_tuning tuning_or_default(const eik_tuning *t)
 {
     eik_tuning d;
-    d.max_local_cycles = 4;
+    d.tile_height = kDefaultTH;
+    d.max_local_cycles = 2;
     d.rounds_per_check = 8;
-    d.adjoint_single_wg_max_cells = 1 << 18;
+    d.fast_cold_start = 0;
+    d.adjoint_rounds = 64;
+    d.level_rounds = 8;
     if (t) {
+        if (t->tile_height == 32 || t->tile_height == 64) d.tile_height = t->tile_height;
         if (t->max_local_cycles >= 1) d.max_local_cycles = t->max_local_cycles;
         if (t->rounds_per_check >= 1) d.rounds_per_check = t->rounds_per_check;
-        if (t->adjoint_single_wg_max_cells >= 0) d.adjoint_single_wg_max_cells = t->adjoint_single_wg_max_cells;
+        if (t->fast_cold_start >= 0) d.fast_cold_start = t->fast_cold_start;
+        if (t->adjoint_rounds >= 1) d.adjoint_rounds = t->adjoint_rounds;
+        if (t->level_rounds >= 1) d.level_rounds = t->level_rounds;
     }
     return d;
 }
 
-// Run tile rounds until a round flags nothing or max_rounds is reached.
-// round_fn(r, act_in, act_out, count_next) enqueues round r.
 // Optional per-launch timing with HIP events recorded on the launch stream.
 struct LaunchTimer {
     std::vector<hipEvent_t> ev;
@@ -152,8 +198,7 @@ struct LaunchTimer {
     {
         if (on) (void)hipEventRecord(ev[2 * used + 1], st), ++used;
     }
-    // after the stream has been synchronised
-    void collect()
+    void collect() // after the stream has been synchronised
     {
         for (int b = 0; b < used; ++b) {
             float t = 0.f;
@@ -163,144 +208,212 @@ struct LaunchTimer {
     }
 };
 
+// Rounds until a round flags nothing (converged) or the budget runs out.
+// Without a host check (sync = false) exactly `budget` rounds are enqueued;
+// rounds after convergence find no flagged tile and exit at once.
+// round_fn(act_in, act_out, count_next) enqueues one round.
 template <typename F>
-int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int max_rounds, int per_check, hipStream_t st,
-               F round_fn, int *rounds_done, bool *converged, LaunchTimer *timer = nullptr)
+int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int budget, int per_check, bool sync,
+               hipStream_t st, F round_fn, int *rounds_done, bool *converged, LaunchTimer *timer = nullptr)
 {
-    int r = 0;
+    int r = first;
+    const int end = std::min(first + budget, kMaxRounds);
     *converged = false;
-    while (r < max_rounds) {
-        const int batch = std::min(per_check, max_rounds - r);
+    while (r < end) {
+        const int batch = sync ? std::min(per_check, end - r) : end - r;
         for (int b = 0; b < batch; ++b, ++r) {
-            if (timer) timer->before(st);
+            if (timer && timer->on) timer->before(st);
             round_fn(act + (r & 1) * n_tiles, act + ((r + 1) & 1) * n_tiles, act_count + r + 1);
-            if (timer) timer->after(st);
+            if (timer && timer->on) timer->after(st);
         }
+        if (!sync) break;
         int32_t cnt = 0;
         HIP_OK(hipMemcpyAsync(&cnt, act_count + r, sizeof cnt, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
-        if (timer) timer->collect();
+        if (timer && timer->on) timer->collect();
         if (cnt == 0) {
             *converged = true;
             break;
         }
     }
-    *rounds_done = r;
+    *rounds_done = r - first;
+    return EIK_OK;
+}
+
+int prepare(int n_grids, const eik_grid *grids, int dtype, void *ws, size_t ws_bytes, const eik_tuning &tn,
+            bool write_desc, hipStream_t st, Extent &e, Ws &w, LaunchArgs &a)
+{
+    int rc = extent_of(n_grids, grids, dtype, e);
+    if (rc) return rc;
+    rc = carve(e, dtype, ws, ws_bytes, w);
+    if (rc) return rc;
+    a.grids = w.descs;
+    a.tile_grid = w.tile_grid;
+    a.n_grids = n_grids;
+    a.th = tn.tile_height;
+    a.n_tiles = (int32_t)(a.th == 64 ? e.tiles64 : e.tiles32);
+    a.n_nodes = e.nodes;
+    if (write_desc) { // single grid: descriptor written by a kernel, no host copy
+        std::vector<GridDesc> d;
+        std::vector<int32_t> tg;
+        host_descs(1, grids, a.th, d, tg);
+        launch_write_single_desc(d[0], w.descs, w.tile_grid, a.n_tiles, st);
+    }
     return EIK_OK;
 }
 
 template <typename R>
-int forward_impl(const eik_grid *grid, const void *M, const void *om, const void *T_init, double tol,
-                 int max_rounds, int flags, void *T, uint8_t *parent, int32_t *level, void *ws, size_t ws_bytes,
-                 const eik_tuning *tun, eik_stats *stats, hipStream_t st)
+int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, const void *src_t, const void *M,
+                 const void *om, const void *T_init, double tol, int max_rounds, int flags, void *T,
+                 uint8_t *parent, int32_t *level, void *ws, size_t ws_bytes, const eik_tuning *tun,
+                 eik_stats *stats, bool single, hipStream_t st)
 {
     const int dtype = sizeof(R) == 8 ? EIK_F64 : EIK_F32;
-    Ws w;
-    int rc = carve(grid, dtype, ws, ws_bytes, w);
-    if (rc) return rc;
     const eik_tuning tn = tuning_or_default(tun);
-    GridArgs g = make_grid(grid, kDefaultTH);
-    const int64_t n = (int64_t)g.nx * g.ny;
-    max_rounds = std::max(1, std::min(max_rounds, kMaxRounds));
+    Extent e;
+    Ws w;
+    LaunchArgs a;
+    int rc = prepare(n_grids, grids, dtype, ws, ws_bytes, tn, single, st, e, w, a);
+    if (rc) return rc;
+    // Without a stats request a batched forward runs a fixed schedule with no
+    // host synchronisation (capturable in a graph).
+    const bool sync = single || stats != nullptr;
+    max_rounds = std::max(1, std::min(max_rounds, kMaxRounds / 4));
 
     launch_fill_u64(w.ctr, kCtrCount, st);
-    launch_fill_i32(w.act, 2 * (int64_t)g.n_tiles, 0, st);
+    launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
     launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
     HIP_OK(hipGetLastError());
     if (flags & EIK_CHECK_FEASIBLE) {
-        launch_check_feasible<R>(n, M, om, w.ctr, st);
+        launch_check_feasible<R>(e.nodes, M, om, w.ctr, st);
         unsigned long long bad = 0;
         HIP_OK(hipMemcpyAsync(&bad, w.ctr + kCtrInfeasible, 8, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
         if (bad) return fail(EIK_EINFEASIBLE, "metric not SPD or |omega|_{M^-1} >= 1 somewhere");
     }
-    launch_init<R>(g, T_init, T, parent, level, grid->src_idx, grid->src_t, w.act, w.act_count, w.ctr,
-                   T_init != nullptr, st);
+    launch_stage<R>(a, M, om, w.Pt, st);
+    launch_init<R>(a, T_init, T, parent, level, src_idx, src_t, w.act, w.act_count, w.ctr, T_init != nullptr,
+                   st);
     HIP_OK(hipGetLastError());
 
-    int rounds = 0;
-    bool conv = false;
     LaunchTimer timer;
-    rc = timer.init((flags & EIK_TIME_KERNELS) != 0, tn.rounds_per_check);
+    rc = timer.init((flags & EIK_TIME_KERNELS) != 0 && sync, tn.rounds_per_check);
     if (rc) return rc;
+    int r0 = 0, rounds = 0;
+    bool conv = false;
+    const bool fast = T_init == nullptr && tn.fast_cold_start;
+    if (fast) { // cold start: restricted candidates, T only decreases
+        rc = run_rounds(
+            w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
+            [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
+                launch_sweep_round<R>(a, kModeFast, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
+                                      tn.max_local_cycles, st);
+            },
+            &rounds, &conv, &timer);
+        if (rc) return rc;
+        r0 += rounds;
+        // certify with the full update: every tile runs once more
+        launch_all_active(a, w.act + (r0 & 1) * a.n_tiles, w.act_count + r0, st);
+    }
     rc = run_rounds(
-        w.act, w.act_count, g.n_tiles, max_rounds, tn.rounds_per_check, st,
+        w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
         [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-            launch_sweep_round<R>(g, M, om, T, parent, ain, aout, cnt, w.ctr, tol, tn.max_local_cycles, st);
+            launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
+                                  tn.max_local_cycles, st);
         },
         &rounds, &conv, &timer);
     if (rc) return rc;
+    r0 += rounds;
+    launch_note_pending(w.act_count + r0, w.ctr + kCtrSweepPending, st);
     HIP_OK(hipGetLastError());
 
-    // active stencils and levels
-    launch_parents<R>(g, M, om, T, parent, level, st);
-    launch_fill_i32(w.act, 2 * (int64_t)g.n_tiles, 0, st);
+    // active stencils from the final field, then levels made consistent with them
+    launch_parents<R>(a, M, om, T, parent, st);
+    launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
     launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
-    launch_level_prep(g, w.act, w.act_count, st);
+    launch_all_active(a, w.act, w.act_count, st);
     int lrounds = 0;
     bool lconv = false;
+    const int level_budget = sync ? kMaxRounds / 2 : tn.level_rounds;
     rc = run_rounds(
-        w.act, w.act_count, g.n_tiles, kMaxRounds, tn.rounds_per_check, st,
+        w.act, w.act_count, a.n_tiles, 0, level_budget, tn.rounds_per_check, sync, st,
         [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-            launch_level_round(g, parent, level, ain, aout, cnt, tn.max_local_cycles, st);
+            launch_level_round(a, parent, level, ain, aout, cnt, tn.max_local_cycles, st);
         },
         &lrounds, &lconv);
     if (rc) return rc;
-    if (!lconv) return fail(EIK_EDEVICE, "dependency levels did not settle");
-    launch_max_level(n, level, w.ctr, st);
+    if (sync && !lconv) return fail(EIK_EDEVICE, "dependency levels did not settle");
+    launch_note_pending(w.act_count + lrounds, w.ctr + kCtrLevelPending, st);
+    launch_max_level(e.nodes, level, w.ctr, st);
     HIP_OK(hipGetLastError());
+    if (!sync) return EIK_OK;
 
     unsigned long long ctr[kCtrCount];
     HIP_OK(hipMemcpyAsync(ctr, w.ctr, sizeof ctr, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     int status = conv ? EIK_OK : EIK_NOT_CONVERGED;
     if (ctr[kCtrBadSource]) status = fail(EIK_EINVAL, "%llu source indices out of range", ctr[kCtrBadSource]);
-    else if (!conv) fail(EIK_NOT_CONVERGED, "tolerance not reached in %d rounds", rounds);
+    else if (!conv) fail(EIK_NOT_CONVERGED, "tolerance not reached in %d rounds", r0);
     if (stats) {
-        stats->rounds = rounds;
+        stats->rounds = r0;
         stats->converged = conv ? 1 : 0;
         stats->cell_updates = (int64_t)ctr[kCtrCellUpdates];
         stats->n_levels = (int32_t)ctr[kCtrMaxLevel] + 1;
         stats->status = status;
-        stats->sweep_launches = rounds;
+        stats->sweep_launches = r0;
         stats->sweep_ms = timer.ms;
+        stats->aux_rounds = lrounds;
     }
     return status;
 }
 
 template <typename R>
-int backward_impl(const eik_grid *grid, const void *M, const void *om, const void *T, const uint8_t *parent,
-                  const int32_t *level, const void *dLdT, void *dLdM, void *dLdom, void *dLdsrc, void *ws,
-                  size_t ws_bytes, const eik_tuning *tun, hipStream_t st)
+int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, const void *M, const void *om,
+                  const void *T, const uint8_t *parent, const int32_t *level, const void *dLdT, void *dLdM,
+                  void *dLdom, void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tun, bool single,
+                  eik_stats *stats, hipStream_t st)
 {
     const int dtype = sizeof(R) == 8 ? EIK_F64 : EIK_F32;
-    Ws w;
-    int rc = carve(grid, dtype, ws, ws_bytes, w);
-    if (rc) return rc;
     const eik_tuning tn = tuning_or_default(tun);
-    GridArgs g = make_grid(grid, kDefaultTH);
-    const int64_t n = (int64_t)g.nx * g.ny;
+    Extent e;
+    Ws w;
+    LaunchArgs a;
+    int rc = prepare(n_grids, grids, dtype, ws, ws_bytes, tn, single, st, e, w, a);
+    if (rc) return rc;
+    const bool sync = single || stats != nullptr;
 
-    launch_fill_u64(w.ctr, kCtrCount, st);
-    launch_fill_i32(w.counts, n + 2, 0, st);
-    launch_max_level(n, level, w.ctr, st);
-    launch_adj_prep<R>(g, M, om, T, parent, level, w.w1, w.counts, dLdM, dLdom, st);
-    launch_scan_levels(w.counts, w.counts /*offsets in place*/, w.cursor, w.ctr, st);
-    launch_scatter_levels(n, level, w.cursor, w.list, st);
+    launch_adj_prep<R>(a, M, om, T, parent, w.w1, w.lam, st);
+    launch_adj_sort(a, level, w.list, w.cnt, st);
+    launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
+    launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
+    launch_all_active(a, w.act, w.act_count, st);
     HIP_OK(hipGetLastError());
-    if (n <= tn.adjoint_single_wg_max_cells) {
-        launch_adj_levels<R>(g, -1, 0, true, w.ctr, w.counts, w.list, parent, w.w1, dLdT, M, w.lam, dLdM, dLdom,
-                             st);
-    } else {
-        unsigned long long lmax = 0;
-        HIP_OK(hipMemcpyAsync(&lmax, w.ctr + kCtrMaxLevel, 8, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        for (int L = (int)lmax; L >= 0; --L)
-            launch_adj_levels<R>(g, L, L, false, w.ctr, w.counts, w.list, parent, w.w1, dLdT, M, w.lam, dLdM,
-                                 dLdom, st);
+    int rounds = 0;
+    bool conv = false;
+    rc = run_rounds(
+        w.act, w.act_count, a.n_tiles, 0, sync ? kMaxRounds / 2 : tn.adjoint_rounds, tn.rounds_per_check, sync, st,
+        [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
+            launch_adj_round<R>(a, parent, level, w.w1, dLdT, w.list, w.cnt, w.lam, ain, aout, cnt, st);
+        },
+        &rounds, &conv);
+    if (rc) return rc;
+    if (sync && !conv) return fail(EIK_EDEVICE, "adjoint rounds did not settle");
+    launch_note_pending(w.act_count + rounds, w.ctr + kCtrAdjPending, st);
+    launch_adj_params<R>(a, M, parent, w.w1, w.lam, dLdM, dLdom, st);
+    launch_dsrc<R>(a, src_idx, w.lam, dLdsrc, st);
+    HIP_OK(hipGetLastError());
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        stats->rounds = rounds;
+        stats->converged = conv ? 1 : 0;
+        stats->aux_rounds = rounds;
     }
-    launch_dsrc<R>(g, grid->src_idx, w.lam, dLdsrc, st);
-    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+int check_ptrs(const void *M, const void *om, const void *T, const void *parent, const void *level)
+{
+    if (!M || !om || !T || !parent || !level) return fail(EIK_EINVAL, "NULL field or output pointer");
     return EIK_OK;
 }
 
@@ -310,39 +423,110 @@ extern "C" {
 
 size_t eik_workspace_bytes(const eik_grid *grid, int32_t dtype)
 {
-    if (check_grid(grid, dtype)) return 0;
-    return layout(grid, dtype).total;
+    if (!grid || !grid->src_idx) return 0;
+    Extent e;
+    if (extent_of(1, grid, dtype, e)) return 0;
+    return layout(e, dtype).total;
+}
+
+size_t eik_batch_workspace_bytes(int32_t n_grids, const eik_grid *grids, int32_t dtype)
+{
+    Extent e;
+    if (extent_of(n_grids, grids, dtype, e)) return 0;
+    return layout(e, dtype).total;
+}
+
+int eik_batch_plan(int32_t n_grids, const eik_grid *grids, int32_t dtype, const eik_tuning *tuning, void *ws,
+                   size_t ws_bytes, hipStream_t stream)
+{
+    const eik_tuning tn = tuning_or_default(tuning);
+    Extent e;
+    int rc = extent_of(n_grids, grids, dtype, e);
+    if (rc) return rc;
+    Ws w;
+    rc = carve(e, dtype, ws, ws_bytes, w);
+    if (rc) return rc;
+    std::vector<GridDesc> d;
+    std::vector<int32_t> tg;
+    host_descs(n_grids, grids, tn.tile_height, d, tg);
+    HIP_OK(hipMemcpyAsync(w.descs, d.data(), d.size() * sizeof(GridDesc), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipMemcpyAsync(w.tile_grid, tg.data(), tg.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    return EIK_OK;
 }
 
 int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T_init,
                 double tol, int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level, void *ws,
                 size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream)
 {
-    int rc = check_grid(grid, dtype);
+    if (!grid) return fail(EIK_EINVAL, "grid is NULL");
+    if (dtype != EIK_F32 && dtype != EIK_F64) return fail(EIK_EINVAL, "dtype %d", dtype);
+    int rc = check_one(grid, 0);
     if (rc) return rc;
-    if (!M || !omega || !T || !parent || !level) return fail(EIK_EINVAL, "NULL field or output pointer");
+    if (!grid->src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
+    rc = check_ptrs(M, omega, T, parent, level);
+    if (rc) return rc;
     if (!(tol >= 0.0)) return fail(EIK_EINVAL, "tol must be >= 0");
     if (max_rounds < 1) return fail(EIK_EINVAL, "max_rounds must be >= 1");
     if (dtype == EIK_F64)
-        return forward_impl<double>(grid, M, omega, T_init, tol, max_rounds, flags, T, parent, level, ws, ws_bytes,
-                                    tuning, stats, stream);
-    return forward_impl<float>(grid, M, omega, T_init, tol, max_rounds, flags, T, parent, level, ws, ws_bytes,
-                               tuning, stats, stream);
+        return forward_impl<double>(1, grid, grid->src_idx, grid->src_t, M, omega, T_init, tol, max_rounds, flags, T,
+                                    parent, level, ws, ws_bytes, tuning, stats, true, stream);
+    return forward_impl<float>(1, grid, grid->src_idx, grid->src_t, M, omega, T_init, tol, max_rounds, flags, T,
+                               parent, level, ws, ws_bytes, tuning, stats, true, stream);
+}
+
+int eik_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
+                        const void *src_t, const void *M, const void *omega, const void *T_init, double tol,
+                        int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level, void *ws,
+                        size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream)
+{
+    if (!src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
+    int rc = check_ptrs(M, omega, T, parent, level);
+    if (rc) return rc;
+    if (!(tol >= 0.0)) return fail(EIK_EINVAL, "tol must be >= 0");
+    if (max_rounds < 1) return fail(EIK_EINVAL, "max_rounds must be >= 1");
+    if (dtype == EIK_F64)
+        return forward_impl<double>(n_grids, grids, src_idx, src_t, M, omega, T_init, tol, max_rounds, flags, T,
+                                    parent, level, ws, ws_bytes, tuning, stats, false, stream);
+    if (dtype == EIK_F32)
+        return forward_impl<float>(n_grids, grids, src_idx, src_t, M, omega, T_init, tol, max_rounds, flags, T,
+                                   parent, level, ws, ws_bytes, tuning, stats, false, stream);
+    return fail(EIK_EINVAL, "dtype %d", dtype);
 }
 
 int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
                  const uint8_t *parent, const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega,
-                 void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning, hipStream_t stream)
+                 void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats,
+                 hipStream_t stream)
 {
-    int rc = check_grid(grid, dtype);
+    if (!grid) return fail(EIK_EINVAL, "grid is NULL");
+    if (dtype != EIK_F32 && dtype != EIK_F64) return fail(EIK_EINVAL, "dtype %d", dtype);
+    int rc = check_one(grid, 0);
     if (rc) return rc;
+    if (!grid->src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
     if (!M || !omega || !T || !parent || !level || !dLdT || !dLdM || !dLdomega || !dLdsrc)
         return fail(EIK_EINVAL, "NULL pointer argument");
     if (dtype == EIK_F64)
-        return backward_impl<double>(grid, M, omega, T, parent, level, dLdT, dLdM, dLdomega, dLdsrc, ws, ws_bytes,
-                                     tuning, stream);
-    return backward_impl<float>(grid, M, omega, T, parent, level, dLdT, dLdM, dLdomega, dLdsrc, ws, ws_bytes,
-                                tuning, stream);
+        return backward_impl<double>(1, grid, grid->src_idx, M, omega, T, parent, level, dLdT, dLdM, dLdomega,
+                                     dLdsrc, ws, ws_bytes, tuning, true, stats, stream);
+    return backward_impl<float>(1, grid, grid->src_idx, M, omega, T, parent, level, dLdT, dLdM, dLdomega, dLdsrc,
+                                ws, ws_bytes, tuning, true, stats, stream);
+}
+
+int eik_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
+                         const void *M, const void *omega, const void *T, const uint8_t *parent,
+                         const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega, void *dLdsrc, void *ws,
+                         size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream)
+{
+    if (!src_idx || !M || !omega || !T || !parent || !level || !dLdT || !dLdM || !dLdomega || !dLdsrc)
+        return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        return backward_impl<double>(n_grids, grids, src_idx, M, omega, T, parent, level, dLdT, dLdM, dLdomega,
+                                     dLdsrc, ws, ws_bytes, tuning, false, stats, stream);
+    if (dtype == EIK_F32)
+        return backward_impl<float>(n_grids, grids, src_idx, M, omega, T, parent, level, dLdT, dLdM, dLdomega,
+                                    dLdsrc, ws, ws_bytes, tuning, false, stats, stream);
+    return fail(EIK_EINVAL, "dtype %d", dtype);
 }
 
 int eik_project(int64_t n, int32_t dtype, const void *M_in, const void *omega_in, void *M_out, void *omega_out,
@@ -388,6 +572,23 @@ int eik_project_backward(int64_t n, int32_t dtype, const void *M_in, const void 
     else
         return fail(EIK_EINVAL, "dtype %d", dtype);
     HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+int eik_batch_pending(int32_t n_grids, const eik_grid *grids, int32_t dtype, const void *ws, size_t ws_bytes,
+                      int64_t pending[3], hipStream_t stream)
+{
+    if (!pending) return fail(EIK_EINVAL, "pending is NULL");
+    Extent e;
+    int rc = extent_of(n_grids, grids, dtype, e);
+    if (rc) return rc;
+    Ws w;
+    rc = carve(e, dtype, const_cast<void *>(ws), ws_bytes, w);
+    if (rc) return rc;
+    unsigned long long c[3];
+    HIP_OK(hipMemcpyAsync(c, w.ctr + kCtrSweepPending, sizeof c, hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    for (int k = 0; k < 3; ++k) pending[k] = (int64_t)c[k];
     return EIK_OK;
 }
 

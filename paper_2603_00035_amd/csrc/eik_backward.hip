@@ -3,218 +3,386 @@
 //
 // With the active update of node j fixed, dT_j/dT_i is the donor weight w
 // (barycentric weight of a two-point update, 1 for a one-point update), so the
-// adjoint system J^T lambda = dL/dT is lower-triangular in the causal order and
+// adjoint system J^T lambda = dL/dT is triangular in the causal order and
 // reads lambda_i = g_i + sum over the nodes j that i feeds of w_ji lambda_j.
-// Instead of sorting by T, nodes are bucketed by dependency level (counting
-// sort) and levels are processed from the deepest down: every node of a level
-// gathers from its (at most eight) receivers, which all sit at deeper levels,
-// so no atomics are needed. dL/dtheta_i = lambda_i dT_i/dtheta_i is fused in.
+// Instead of sorting by T, nodes are ordered by dependency level: a node's
+// receivers all sit at deeper levels. Each tile keeps its nodes sorted by
+// decreasing level (a counting sort done once) and, holding lambda, the donor
+// weights and the active updates of the tile plus a one-node halo in LDS,
+// processes its levels from the deepest down; all nodes of one level gather
+// from their (at most eight) receivers at once, and nothing is scattered, so
+// no atomics are needed. Receivers in neighbouring tiles are read from the
+// halo; tiles whose halo changed run again in the next round, and the rounds
+// end when no lambda on a tile border changes -- then every lambda satisfies
+// its equation exactly, as a single global level-by-level pass would give.
+// dL/dtheta_i = lambda_i dT_i/dtheta_i (Alg. backward, last loop) follows in
+// one pass over the nodes.
 #include "eik_device.h"
 #include "eik_internal.h"
 
 namespace eik {
 
-static inline int blocks_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 4096); }
+struct TileGeoB {
+    GridDesc gd;
+    int tx, ty, i0, j0, w, h;
+};
 
-__global__ void k_fill_u64(unsigned long long *__restrict__ p, int64_t n)
+template <int TH>
+__device__ __forceinline__ TileGeoB tile_geo_b(const LaunchArgs &a, int t)
 {
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
-        p[c] = 0ull;
+    TileGeoB g;
+    g.gd = a.grids[a.tile_grid[t]];
+    const int lt = t - g.gd.tile_base;
+    g.tx = lt % g.gd.ntx;
+    g.ty = lt / g.gd.ntx;
+    g.i0 = g.tx * TW;
+    g.j0 = g.ty * TH;
+    g.w = min(TW, g.gd.nx - g.i0);
+    g.h = min(TH, g.gd.ny - g.j0);
+    return g;
 }
 
-// Donor weights of each active two-point update, level histogram, and zeroed
-// gradient planes.
-template <typename R>
-__global__ void k_adj_prep(GridArgs g, const R *__restrict__ M, const R *__restrict__ om, const R *__restrict__ T,
-                           const uint8_t *__restrict__ parent, const int32_t *__restrict__ level,
-                           R *__restrict__ w1buf, int32_t *__restrict__ counts, R *__restrict__ dM,
-                           R *__restrict__ dom)
+// Donor weights of each active two-point update; lambda cleared.
+template <typename R, int TH>
+__global__ __launch_bounds__(256) void k_adj_prep(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
+                                                  const R *__restrict__ Tall, const uint8_t *__restrict__ parall,
+                                                  R *__restrict__ w1all, R *__restrict__ lamall)
 {
-    const int64_t n = (int64_t)g.nx * g.ny;
-    const R h = R(g.h);
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        dM[c] = R(0);
-        dM[n + c] = R(0);
-        dM[2 * n + c] = R(0);
-        dom[c] = R(0);
-        dom[n + c] = R(0);
-        const int lv = level[c];
-        if (lv >= 0 && lv < n) atomicAdd(&counts[lv], 1);
-        const int code = parent[c];
+    const TileGeoB g = tile_geo_b<TH>(a, blockIdx.x);
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    const R *T = Tall + g.gd.off;
+    const R *Mg = M + 3 * g.gd.off, *og = om + 2 * g.gd.off;
+    const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
+    for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+        const int r = idx / TW, cl = idx - r * TW;
+        if (r >= g.h || cl >= g.w) continue;
+        const int i = g.i0 + cl, j = g.j0 + r;
+        const size_t c = (size_t)j * g.gd.nx + i;
+        const int code = parall[g.gd.off + c];
         R w = R(1);
-        const int i = (int)(c % g.nx), j = (int)(c / g.nx);
-        const int kq = (code + 1) & 7;
-        const bool inside = code < 8 && i + nb_dx(code) >= 0 && i + nb_dx(code) < g.nx && j + nb_dy(code) >= 0 &&
-                            j + nb_dy(code) < g.ny && i + nb_dx(kq) >= 0 && i + nb_dx(kq) < g.nx &&
-                            j + nb_dy(kq) >= 0 && j + nb_dy(kq) < g.ny;
-        if (inside) {
-            const R Tp = T[(size_t)(j + nb_dy(code)) * g.nx + i + nb_dx(code)];
-            const R Tq = T[(size_t)(j + nb_dy(kq)) * g.nx + i + nb_dx(kq)];
-            NodeConst<R> k;
-            node_const<R>(M[c], M[n + c], M[2 * n + c], om[c], om[n + c], h, k);
-            R t, mu1, mu2;
-            two_point<R>(k, code, Tp, Tq, t, mu1, mu2);
-            w = mu1 / (mu1 + mu2);
+        if (code < 8) {
+            const int kq = (code + 1) & 7;
+            const int xp = i + nb_dx(code), yp = j + nb_dy(code), xq = i + nb_dx(kq), yq = j + nb_dy(kq);
+            if (xp >= 0 && xp < g.gd.nx && yp >= 0 && yp < g.gd.ny && xq >= 0 && xq < g.gd.nx && yq >= 0 &&
+                yq < g.gd.ny) {
+                NodeConst<R> k;
+                node_const<R>(Mg[c], Mg[n + c], Mg[2 * n + c], og[c], og[n + c], h, inv_h, k);
+                R t, mu1, mu2;
+                two_point<R>(k, code, T[(size_t)yp * g.gd.nx + xp], T[(size_t)yq * g.gd.nx + xq], t, mu1, mu2);
+                w = mu1 / (mu1 + mu2);
+            }
         }
-        w1buf[c] = w;
+        w1all[g.gd.off + c] = w;
+        lamall[g.gd.off + c] = R(0);
     }
 }
 
-// Exclusive scan of the level histogram (one workgroup of 1024 threads).
-__global__ __launch_bounds__(1024) void k_scan_levels(int32_t *__restrict__ counts, int32_t *__restrict__ offsets,
-                                                      int32_t *__restrict__ cursor,
-                                                      const unsigned long long *__restrict__ ctr)
+// Per tile: reached nodes sorted by decreasing level into the tile's segment
+// of `list` (local indices r * 64 + c), count in cnt[tile]. Counting sort in
+// LDS, in chunks of kSortChunk levels.
+template <int TH>
+__global__ __launch_bounds__(256) void k_adj_sort(LaunchArgs a, const int32_t *__restrict__ levall,
+                                                  int32_t *__restrict__ list, int32_t *__restrict__ cnt)
 {
-    __shared__ int32_t part[1024];
-    __shared__ int32_t carry;
-    const int L = (int)ctr[kCtrMaxLevel] + 1;
-    if (threadIdx.x == 0) carry = 0;
+    __shared__ int32_t hist[kSortChunk];
+    __shared__ int32_t part[256];
+    __shared__ int32_t s_lo, s_hi, s_base;
+    const int t = blockIdx.x;
+    const TileGeoB g = tile_geo_b<TH>(a, t);
+    const int32_t *level = levall + g.gd.off;
+    int32_t *seg = list + (size_t)t * TW * TH;
+    if (threadIdx.x == 0) {
+        s_lo = 0x7fffffff;
+        s_hi = -1;
+        s_base = 0;
+    }
     __syncthreads();
-    for (int base = 0; base < L; base += 1024) {
-        const int idx = base + threadIdx.x;
-        const int v = idx < L ? counts[idx] : 0;
-        part[threadIdx.x] = v;
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    int lo = 0x7fffffff, hi = -1;
+    for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+        const int r = idx / TW, c = idx - r * TW;
+        if (r >= g.h || c >= g.w) continue;
+        const int lv = level[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c];
+        if (lv >= 0 && lv < n) {
+            lo = min(lo, lv);
+            hi = max(hi, lv);
+        }
+    }
+    atomicMin(&s_lo, lo);
+    atomicMax(&s_hi, hi);
+    __syncthreads();
+    lo = s_lo;
+    hi = s_hi;
+    if (hi < 0) {
+        if (threadIdx.x == 0) cnt[t] = 0;
+        return;
+    }
+    for (int k0 = 0; k0 <= hi - lo; k0 += kSortChunk) {
+        for (int b = threadIdx.x; b < kSortChunk; b += blockDim.x) hist[b] = 0;
         __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
+        for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+            const int r = idx / TW, c = idx - r * TW;
+            if (r >= g.h || c >= g.w) continue;
+            const int lv = level[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c];
+            const int key = hi - lv - k0;
+            if (lv >= 0 && lv < n && key >= 0 && key < kSortChunk) atomicAdd(&hist[key], 1);
+        }
+        __syncthreads();
+        // exclusive scan of hist: 16 entries per thread, then across threads
+        constexpr int PER = kSortChunk / 256;
+        int sum = 0;
+        for (int q = 0; q < PER; ++q) sum += hist[threadIdx.x * PER + q];
+        part[threadIdx.x] = sum;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
             const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
             __syncthreads();
             part[threadIdx.x] += add;
             __syncthreads();
         }
-        const int excl = carry + part[threadIdx.x] - v;
-        if (idx < L) {
-            offsets[idx] = excl;
-            cursor[idx] = excl;
+        int run = s_base + part[threadIdx.x] - sum;
+        for (int q = 0; q < PER; ++q) {
+            const int v = hist[threadIdx.x * PER + q];
+            hist[threadIdx.x * PER + q] = run;
+            run += v;
         }
         __syncthreads();
-        if (threadIdx.x == 1023) carry += part[1023];
+        for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+            const int r = idx / TW, c = idx - r * TW;
+            if (r >= g.h || c >= g.w) continue;
+            const int lv = level[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c];
+            const int key = hi - lv - k0;
+            if (lv >= 0 && lv < n && key >= 0 && key < kSortChunk) seg[atomicAdd(&hist[key], 1)] = r * TW + c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 255) s_base += part[255];
         __syncthreads();
     }
-    if (threadIdx.x == 0) offsets[L] = carry;
+    if (threadIdx.x == 0) cnt[t] = s_base;
 }
 
-__global__ void k_scatter_levels(int64_t n, const int32_t *__restrict__ level, int32_t *__restrict__ cursor,
-                                 int32_t *__restrict__ list)
+// One round of the tile-local level-descending gather.
+template <typename R, int TH>
+__global__ __launch_bounds__(TW) void k_adj_round(LaunchArgs a, const uint8_t *__restrict__ parall,
+                                                  const int32_t *__restrict__ levall, const R *__restrict__ w1all,
+                                                  const R *__restrict__ gall, const int32_t *__restrict__ list,
+                                                  const int32_t *__restrict__ cnt, R *__restrict__ lamall,
+                                                  int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
+                                                  int32_t *__restrict__ count_next)
 {
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        const int lv = level[c];
-        if (lv >= 0 && lv < n) list[atomicAdd(&cursor[lv], 1)] = (int32_t)c;
+    constexpr int LP = TW + 3;
+    const int t = blockIdx.x;
+    if (act_in[t] == 0) return;
+    const int lane = threadIdx.x;
+    if (lane == 0) act_in[t] = 0;
+    const TileGeoB g = tile_geo_b<TH>(a, t);
+    const int nx = g.gd.nx, ny = g.gd.ny;
+    R *lam = lamall + g.gd.off;
+    const int32_t *level = levall + g.gd.off;
+    const R *gT = gall + g.gd.off;
+
+    __shared__ R sLam[(TH + 2) * LP];
+    __shared__ R sW[(TH + 2) * LP];
+    __shared__ uint8_t sP[(TH + 2) * LP];
+    for (int idx = lane; idx < (TH + 2) * (TW + 2); idx += TW) {
+        const int r = idx / (TW + 2), c = idx - r * (TW + 2);
+        const int gi = g.i0 + c - 1, gj = g.j0 + r - 1;
+        R lv = R(0), wv = R(1);
+        uint8_t pv = kUnreached;
+        if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
+            const size_t gc = (size_t)gj * nx + gi;
+            lv = lam[gc];
+            wv = w1all[g.gd.off + gc];
+            pv = parall[g.gd.off + gc];
+        }
+        sLam[r * LP + c] = lv;
+        sW[r * LP + c] = wv;
+        sP[r * LP + c] = pv;
     }
-}
+    __syncthreads();
 
-// Levels L_hi down to L_lo. In single-workgroup mode the whole loop runs in
-// one launch with a barrier between levels (L_hi < 0 means: the deepest level
-// recorded in ctr); otherwise the launch covers one level.
-template <typename R>
-__global__ __launch_bounds__(1024) void k_adj_levels(GridArgs g, int L_hi, int L_lo,
-                                                     const unsigned long long *__restrict__ ctr,
-                                                     const int32_t *__restrict__ offsets,
-                                                     const int32_t *__restrict__ list,
-                                                     const uint8_t *__restrict__ parent, const R *__restrict__ w1buf,
-                                                     const R *__restrict__ dLdT, const R *__restrict__ M,
-                                                     R *__restrict__ lam, R *__restrict__ dM, R *__restrict__ dom)
-{
-    const int64_t n = (int64_t)g.nx * g.ny;
-    const R h = R(g.h);
-    if (L_hi < 0) L_hi = (int)ctr[kCtrMaxLevel];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int L = L_hi; L >= L_lo; --L) {
-        const int b = offsets[L], e = offsets[L + 1];
-        for (int64_t p = b + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < e; p += stride) {
-            const int c = list[p];
-            const int i = c % g.nx, j = c / g.nx;
-            R acc = dLdT[c];
+    const int count = cnt[t];
+    const int32_t *seg = list + (size_t)t * TW * TH;
+    // chunk of 64 sorted entries per pass; the next chunk's entry, level and
+    // dL/dT are loaded while the current one is processed
+    auto fetch = [&](int base, int &e, int &lv, R &gv) {
+        const bool have = base + lane < count;
+        e = have ? seg[base + lane] : -1;
+        const int rr = have ? e / TW : 0, cc = have ? e - rr * TW : 0;
+        const size_t gc = (size_t)(g.j0 + rr) * nx + g.i0 + cc;
+        lv = have ? level[gc] : -1;
+        gv = have ? gT[gc] : R(0);
+    };
+    int e_n, lv_n;
+    R g_n;
+    fetch(0, e_n, lv_n, g_n);
+    for (int base = 0; base < count; base += TW) {
+        const int e = e_n;
+        int lv = lv_n;
+        const R gi = g_n;
+        if (base + TW < count) fetch(base + TW, e_n, lv_n, g_n);
+        const bool have = e >= 0;
+        const int r = have ? e / TW : 0, c = have ? e - r * TW : 0;
+        bool done = !have;
+        // levels inside the chunk are non-increasing; take them deepest first
+        while (__ballot(!done)) {
+            int cur = done ? -1 : lv;
+            for (int off = 32; off >= 1; off >>= 1) cur = max(cur, __shfl_xor(cur, off));
+            const bool mine = !done && lv == cur;
+            if (mine) {
+                R acc = gi;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int a = i + nb_dx(k), bb = j + nb_dy(k);
-                if (a < 0 || a >= g.nx || bb < 0 || bb >= g.ny) continue;
-                const int jc = bb * g.nx + a;
-                const int pc = parent[jc];
-                const int kk = (k + 4) & 7; // i seen from jc is neighbour kk of jc
-                if (pc == kk)
-                    acc += w1buf[jc] * lam[jc];
-                else if (pc == ((kk + 7) & 7))
-                    acc += (R(1) - w1buf[jc]) * lam[jc];
-                else if (pc == 8 + kk)
-                    acc += lam[jc];
+                for (int k = 0; k < 8; ++k) {
+                    const int sl = (r + 1 + nb_dy(k)) * LP + (c + 1 + nb_dx(k));
+                    const int pc = sP[sl];
+                    const int kk = (k + 4) & 7; // this node seen from the neighbour
+                    if (pc == kk)
+                        acc += sW[sl] * sLam[sl];
+                    else if (pc == ((kk + 7) & 7))
+                        acc += (R(1) - sW[sl]) * sLam[sl];
+                    else if (pc == 8 + kk)
+                        acc += sLam[sl];
+                }
+                sLam[(r + 1) * LP + c + 1] = acc;
+                done = true;
             }
-            lam[c] = acc;
-            const int code = parent[c];
-            if (code < 16) {
-                R d[5];
-                param_derivs<R>(code, w1buf[c], M[c], M[n + c], M[2 * n + c], h, d);
-                dM[c] = acc * d[0];
-                dM[n + c] = acc * d[1];
-                dM[2 * n + c] = acc * d[2];
-                dom[c] = acc * d[3];
-                dom[n + c] = acc * d[4];
-            }
+            // one-wave workgroup: LDS requests are served in issue order, so
+            // only compiler motion across the level boundary is blocked
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        if (gridDim.x == 1) __syncthreads();
+    }
+
+    int bits = 0;
+    for (int idx = lane; idx < TH * TW; idx += TW) {
+        const int r = idx / TW, c = idx - r * TW;
+        if (c >= g.w || r >= g.h) continue;
+        const size_t gc = (size_t)(g.j0 + r) * nx + (g.i0 + c);
+        const R nv = sLam[(r + 1) * LP + c + 1];
+        if (nv != lam[gc]) {
+            lam[gc] = nv;
+            const bool W = c == 0, E = c == g.w - 1, S = r == 0, N = r == g.h - 1;
+            bits |= (W ? 1 : 0) | (E ? 2 : 0) | (S ? 4 : 0) | (N ? 8 : 0) | ((S && W) ? 16 : 0) |
+                    ((S && E) ? 32 : 0) | ((N && W) ? 64 : 0) | ((N && E) ? 128 : 0);
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) bits |= __shfl_xor(bits, off);
+    if (lane == 0) {
+        const int DX[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+        const int DY[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+        for (int b = 0; b < 8; ++b) {
+            if (!(bits & (1 << b))) continue;
+            const int ux = g.tx + DX[b], uy = g.ty + DY[b];
+            if (ux < 0 || ux >= g.gd.ntx || uy < 0 || uy >= g.gd.nty) continue;
+            const int u = g.gd.tile_base + uy * g.gd.ntx + ux;
+            if (atomicExch(&act_out[u], 1) == 0) atomicAdd(count_next, 1);
+        }
+    }
+}
+
+// dL/dtheta_i = lambda_i dT_i/dtheta_i for reached non-source nodes, 0 elsewhere.
+template <typename R, int TH>
+__global__ __launch_bounds__(256) void k_adj_params(LaunchArgs a, const R *__restrict__ M,
+                                                    const uint8_t *__restrict__ parall, const R *__restrict__ w1all,
+                                                    const R *__restrict__ lamall, R *__restrict__ dM,
+                                                    R *__restrict__ dom)
+{
+    const TileGeoB g = tile_geo_b<TH>(a, blockIdx.x);
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    const R *Mg = M + 3 * g.gd.off;
+    R *dMg = dM + 3 * g.gd.off, *dog = dom + 2 * g.gd.off;
+    const R h = R(g.gd.h);
+    for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+        const int r = idx / TW, cl = idx - r * TW;
+        if (r >= g.h || cl >= g.w) continue;
+        const size_t c = (size_t)(g.j0 + r) * g.gd.nx + g.i0 + cl;
+        const int code = parall[g.gd.off + c];
+        R d[5] = {R(0), R(0), R(0), R(0), R(0)};
+        if (code < 16) {
+            param_derivs<R>(code, w1all[g.gd.off + c], Mg[c], Mg[n + c], Mg[2 * n + c], h, d);
+            const R l = lamall[g.gd.off + c];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) d[q] *= l;
+        }
+        dMg[c] = d[0];
+        dMg[n + c] = d[1];
+        dMg[2 * n + c] = d[2];
+        dog[c] = d[3];
+        dog[n + c] = d[4];
     }
 }
 
 template <typename R>
-__global__ void k_dsrc(int n_src, int64_t n, const int32_t *__restrict__ src_idx, const R *__restrict__ lam,
+__global__ void k_dsrc(LaunchArgs a, const int32_t *__restrict__ src_idx, const R *__restrict__ lam,
                        R *__restrict__ dsrc)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_src) return;
-    const int c = src_idx[s];
-    dsrc[s] = (c >= 0 && c < n) ? lam[c] : R(0);
+    const GridDesc gd = a.grids[blockIdx.x];
+    for (int s = threadIdx.x; s < gd.n_src; s += blockDim.x) {
+        const int c = src_idx[gd.src_base + s];
+        dsrc[gd.src_base + s] = (c >= 0 && (int64_t)c < (int64_t)gd.nx * gd.ny) ? lam[gd.off + c] : R(0);
+    }
 }
 
 // ---------------------------------------------------------------------------
-template <typename R>
-void launch_adj_prep(const GridArgs &g, const void *M, const void *om, const void *T, const uint8_t *parent,
-                     const int32_t *level, void *w1, int32_t *counts, void *dM, void *dom, hipStream_t st)
-{
-    const int64_t n = (int64_t)g.nx * g.ny;
-    hipLaunchKernelGGL(k_adj_prep<R>, dim3(blocks_for(n, 256)), dim3(256), 0, st, g, (const R *)M, (const R *)om,
-                       (const R *)T, parent, level, (R *)w1, counts, (R *)dM, (R *)dom);
-}
-
-void launch_scan_levels(int32_t *counts, int32_t *offsets, int32_t *cursor, const unsigned long long *ctr,
-                        hipStream_t st)
-{
-    hipLaunchKernelGGL(k_scan_levels, dim3(1), dim3(1024), 0, st, counts, offsets, cursor, ctr);
-}
-
-void launch_scatter_levels(int64_t n, const int32_t *level, int32_t *cursor, int32_t *list, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_scatter_levels, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, level, cursor, list);
-}
-
-void launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
-}
+#define EIK_TH_DISPATCH(TH_VAR, ...)                                                                             \
+    do {                                                                                                         \
+        if ((TH_VAR) == 64) {                                                                                    \
+            constexpr int TH = 64;                                                                               \
+            __VA_ARGS__;                                                                                         \
+        } else {                                                                                                 \
+            constexpr int TH = 32;                                                                               \
+            __VA_ARGS__;                                                                                         \
+        }                                                                                                        \
+    } while (0)
 
 template <typename R>
-void launch_adj_levels(const GridArgs &g, int L_hi, int L_lo, bool single_wg, const unsigned long long *ctr,
-                       const int32_t *offsets, const int32_t *list, const uint8_t *parent, const void *w1,
-                       const void *dLdT, const void *M, void *lam, void *dM, void *dom, hipStream_t st)
+void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const void *T, const uint8_t *parent,
+                     void *w1, void *lam, hipStream_t st)
 {
-    const int blocks = single_wg ? 1 : 64;
-    const int threads = single_wg ? 1024 : 256;
-    hipLaunchKernelGGL(k_adj_levels<R>, dim3(blocks), dim3(threads), 0, st, g, L_hi, L_lo, ctr, offsets, list,
-                       parent, (const R *)w1, (const R *)dLdT, (const R *)M, (R *)lam, (R *)dM, (R *)dom);
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_prep<R, TH>), dim3(a.n_tiles), dim3(256), 0, st, a,
+                                             (const R *)M, (const R *)om, (const R *)T, parent, (R *)w1, (R *)lam));
+}
+
+void launch_adj_sort(const LaunchArgs &a, const int32_t *level, int32_t *list, int32_t *cnt, hipStream_t st)
+{
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL(k_adj_sort<TH>, dim3(a.n_tiles), dim3(256), 0, st, a, level, list, cnt));
 }
 
 template <typename R>
-void launch_dsrc(const GridArgs &g, const int32_t *src_idx, const void *lam, void *dsrc, hipStream_t st)
+void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const int32_t *level, const void *w1,
+                      const void *dLdT, const int32_t *list, const int32_t *cnt, void *lam, int32_t *act_in,
+                      int32_t *act_out, int32_t *count_next, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_dsrc<R>, dim3((g.n_src + 255) / 256), dim3(256), 0, st, g.n_src, (int64_t)g.nx * g.ny,
-                       src_idx, (const R *)lam, (R *)dsrc);
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_round<R, TH>), dim3(a.n_tiles), dim3(TW), 0, st, a, parent,
+                                             level, (const R *)w1, (const R *)dLdT, list, cnt, (R *)lam, act_in,
+                                             act_out, count_next));
+}
+
+template <typename R>
+void launch_adj_params(const LaunchArgs &a, const void *M, const uint8_t *parent, const void *w1, const void *lam,
+                       void *dM, void *dom, hipStream_t st)
+{
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_params<R, TH>), dim3(a.n_tiles), dim3(256), 0, st, a,
+                                             (const R *)M, parent, (const R *)w1, (const R *)lam, (R *)dM,
+                                             (R *)dom));
+}
+
+template <typename R>
+void launch_dsrc(const LaunchArgs &a, const int32_t *src_idx, const void *lam, void *dsrc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dsrc<R>, dim3(a.n_grids), dim3(64), 0, st, a, src_idx, (const R *)lam, (R *)dsrc);
 }
 
 #define EIK_INST(R)                                                                                              \
-    template void launch_adj_prep<R>(const GridArgs &, const void *, const void *, const void *, const uint8_t *, \
-                                     const int32_t *, void *, int32_t *, void *, void *, hipStream_t);           \
-    template void launch_adj_levels<R>(const GridArgs &, int, int, bool, const unsigned long long *,             \
-                                       const int32_t *, const int32_t *, const uint8_t *, const void *,          \
-                                       const void *, const void *, void *, void *, void *, hipStream_t);         \
-    template void launch_dsrc<R>(const GridArgs &, const int32_t *, const void *, void *, hipStream_t);
+    template void launch_adj_prep<R>(const LaunchArgs &, const void *, const void *, const void *,              \
+                                     const uint8_t *, void *, void *, hipStream_t);                             \
+    template void launch_adj_round<R>(const LaunchArgs &, const uint8_t *, const int32_t *, const void *,        \
+                                      const void *, const int32_t *, const int32_t *, void *, int32_t *,         \
+                                      int32_t *, int32_t *, hipStream_t);                                        \
+    template void launch_adj_params<R>(const LaunchArgs &, const void *, const uint8_t *, const void *,         \
+                                       const void *, void *, void *, hipStream_t);                               \
+    template void launch_dsrc<R>(const LaunchArgs &, const int32_t *, const void *, void *, hipStream_t);
 EIK_INST(float)
 EIK_INST(double)
 #undef EIK_INST

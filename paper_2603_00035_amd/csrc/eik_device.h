@@ -63,7 +63,7 @@ struct NodeConst {
 };
 
 template <typename R>
-__device__ __forceinline__ void node_const(R m11, R m12, R m22, R bx, R by, R h, NodeConst<R> &k)
+__device__ __forceinline__ void node_const(R m11, R m12, R m22, R bx, R by, R h, R inv_h, NodeConst<R> &k)
 {
     // displacements m_k = -offset_k: (1,-1) (1,0) (1,1) (0,1) (-1,1) (-1,0) (-1,-1) (0,-1)
     const R dp = m11 + R(2) * m12 + m22; // |(1, 1)|_G^2
@@ -84,7 +84,7 @@ __device__ __forceinline__ void node_const(R m11, R m12, R m22, R bx, R by, R h,
     k.db[4] = -by; k.db[5] = -by; k.db[6] = bx; k.db[7] = bx;
     k.det = m11 * m22 - m12 * m12;
     k.h = h;
-    k.inv_h = R(1) / h;
+    k.inv_h = inv_h;
     k.inv_m11 = R(1) / m11;
     k.inv_m22 = R(1) / m22;
 }
@@ -145,6 +145,64 @@ __device__ __forceinline__ R local_update(const NodeConst<R> &k, const R Tn[8], 
                 best = t;
                 code = 8 + s;
                 w1 = R(1);
+            }
+        }
+    }
+    return best;
+}
+
+// Candidates of one sweep direction (the line sweep steps along +x, +y, -x,
+// -y for DIR = 0, 1, 2, 3). FULL: every candidate in the canonical order
+// (two-point 0..7, then one-point 0..7; first minimum wins). Otherwise only
+// the candidates whose donors sit on the line just updated or on the current
+// line: stencils 7+2 DIR .. 2+2 DIR and one-point donors 7+2 DIR .. 3+2 DIR
+// (mod 8); each stencil belongs to two of the four directions.
+template <typename R, int DIR, bool FULL>
+__device__ __forceinline__ R local_update_dir(const NodeConst<R> &k, const R Tn[8], int &code)
+{
+    const R inf = inf_v<R>();
+    R best = inf;
+    code = kUnreached;
+    if (FULL) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const R Tp = Tn[s], Tq = Tn[(s + 1) & 7];
+            if (Tp < inf && Tq < inf) {
+                R t, m1, m2;
+                if (two_point(k, s, Tp, Tq, t, m1, m2) && t < best) {
+                    best = t;
+                    code = s;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const R t = Tn[s] + k.c1[s];
+            if (Tn[s] < inf && t < best) {
+                best = t;
+                code = 8 + s;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int s = (7 + 2 * DIR + q) & 7;
+            const R Tp = Tn[s], Tq = Tn[(s + 1) & 7];
+            if (Tp < inf && Tq < inf) {
+                R t, m1, m2;
+                if (two_point(k, s, Tp, Tq, t, m1, m2) && t < best) {
+                    best = t;
+                    code = s;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int s = (7 + 2 * DIR + q) & 7;
+            const R t = Tn[s] + k.c1[s];
+            if (Tn[s] < inf && t < best) {
+                best = t;
+                code = 8 + s;
             }
         }
     }

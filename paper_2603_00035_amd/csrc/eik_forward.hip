@@ -1,59 +1,124 @@
 // eik_forward.hip -- forward fast-sweeping solve on gfx950 (Sec. 3.2,
 // Alg. forward) and the recording of active stencils and dependency levels.
 //
-// Schedule. The grid is cut into tiles of 64 x TH nodes; one 64-lane wave owns
-// a tile, keeps the tile plus a one-node halo of T in LDS and runs the four
-// directional sweeps of Fig. sweep_directions over it: columns left-to-right,
-// rows bottom-to-top in j (j increasing), columns right-to-left, rows j
-// decreasing. Each step updates a whole line of the tile at once, one node per
-// lane, reading the previous line (already updated) and the next line (not yet)
-// from LDS, so lines are processed in parallel exactly as the column/row
-// decomposition describes. A tile repeats four-sweep cycles until one full
-// cycle changes nothing, then writes back and flags the neighbour tiles whose
-// halo it changed; flagged tiles run in the next round. Rounds end when no
-// tile is flagged. The fixed point reached is the one of the discrete local
-// update, which does not depend on the order of the updates.
+// Schedule. Each grid is cut into tiles of 64 x TH nodes; one 64-lane wave owns
+// a tile, keeps T and the dependency levels of the tile plus a one-node halo in
+// LDS, and runs the four directional sweeps of Fig. sweep_directions over it:
+// columns with x increasing, rows with y increasing, columns with x
+// decreasing, rows with y decreasing. Each step updates a whole line of the
+// tile at once, one node per lane, reading the line updated just before and
+// the line ahead from LDS; the line's parameters are loaded one step ahead
+// (columns read a transposed copy, so every load is coalesced). A tile repeats
+// four-sweep cycles until a full cycle changes nothing, writes back, and flags
+// the neighbour tiles whose halo it changed; flagged tiles run in the next
+// round, and rounds end when no tile is flagged.
+//
+// Two update modes. FULL: every candidate, the new value overwrites T (warm
+// starts, and the rounds that certify the final field). FAST, used from the
+// cold start where T only decreases: each direction evaluates the candidates
+// whose donors lie on the line just updated or on the current line, and keeps
+// the smaller of the old and the new value. Both converge to the fixed point of
+// the full local update; the solve always ends with FULL rounds, so the field
+// returned is a fixed point of the full update to the requested tolerance.
+//
+// The active update (code) and the dependency level of each node are carried
+// along with T, so the level field is settled when T is.
 #include "eik_device.h"
 #include "eik_internal.h"
 
 namespace eik {
 
-constexpr int TW = 64; // tile width = wave size
+// ---------------------------------------------------------------------------
+// Descriptors and staging.
+// ---------------------------------------------------------------------------
+__global__ void k_write_single_desc(GridDesc d, GridDesc *__restrict__ dst, int32_t *__restrict__ tile_grid,
+                                    int n_tiles)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) *dst = d;
+    if (t < n_tiles) tile_grid[t] = 0;
+}
+
+struct TileGeo {
+    GridDesc gd;
+    int tx, ty, i0, j0, w, h;
+};
+
+template <int TH>
+__device__ __forceinline__ TileGeo tile_geo(const LaunchArgs &a, int t)
+{
+    TileGeo g;
+    g.gd = a.grids[a.tile_grid[t]];
+    const int lt = t - g.gd.tile_base;
+    g.tx = lt % g.gd.ntx;
+    g.ty = lt / g.gd.ntx;
+    g.i0 = g.tx * TW;
+    g.j0 = g.ty * TH;
+    g.w = min(TW, g.gd.nx - g.i0);
+    g.h = min(TH, g.gd.ny - g.j0);
+    return g;
+}
+
+// Transposed copy of the five parameter planes: Pt[5][nx][ny] per grid.
+template <typename R, int TH>
+__global__ __launch_bounds__(256) void k_stage(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
+                                               R *__restrict__ Pt)
+{
+    __shared__ R buf[TH][TW + 1];
+    const TileGeo g = tile_geo<TH>(a, blockIdx.x);
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    for (int p = 0; p < 5; ++p) {
+        const R *src = p < 3 ? M + 3 * g.gd.off + p * n : om + 2 * g.gd.off + (p - 3) * n;
+        R *dst = Pt + 5 * g.gd.off + p * n;
+        for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+            const int r = idx / TW, c = idx - r * TW;
+            if (r < g.h && c < g.w) buf[r][c] = src[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c];
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+            const int c = idx / TH, r = idx - c * TH;
+            if (r < g.h && c < g.w) dst[(size_t)(g.i0 + c) * g.gd.ny + g.j0 + r] = buf[r][c];
+        }
+        __syncthreads();
+    }
+}
 
 // ---------------------------------------------------------------------------
-// Initialisation: T, source marks in parent, first active tiles.
+// Initialisation: T, codes (source marks), levels, first active tiles.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void k_init(GridArgs g, const R *__restrict__ T_init, R *__restrict__ T, uint8_t *__restrict__ parent,
+__global__ void k_init(int64_t n, const R *__restrict__ T_init, R *__restrict__ T, uint8_t *__restrict__ code,
                        int32_t *__restrict__ level)
 {
-    const int64_t n = (int64_t)g.nx * g.ny;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         T[c] = T_init ? T_init[c] : inf_v<R>();
-        parent[c] = kUnreached;
+        code[c] = kUnreached;
         level[c] = -1;
     }
 }
 
-// Sources: times, marks and initial tile flags. Out-of-range indices and
-// duplicates are counted in ctr[kCtrBadSource] and otherwise ignored.
-template <typename R>
-__global__ void k_sources(GridArgs g, const int32_t *__restrict__ src_idx, const R *__restrict__ src_t,
-                          R *__restrict__ T, uint8_t *__restrict__ parent, int32_t *__restrict__ act,
-                          int32_t *__restrict__ act_count, unsigned long long *__restrict__ ctr)
+// One workgroup per grid. Out-of-range indices are counted in
+// ctr[kCtrBadSource] and otherwise ignored.
+template <typename R, int TH>
+__global__ void k_sources(LaunchArgs a, const int32_t *__restrict__ src_idx, const R *__restrict__ src_t,
+                          R *__restrict__ T, uint8_t *__restrict__ code, int32_t *__restrict__ level,
+                          int32_t *__restrict__ act, int32_t *__restrict__ act_count,
+                          unsigned long long *__restrict__ ctr)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= g.n_src) return;
-    const int32_t c = src_idx[s];
-    if (c < 0 || (int64_t)c >= (int64_t)g.nx * g.ny) {
-        atomicAdd(&ctr[kCtrBadSource], 1ull);
-        return;
+    const GridDesc gd = a.grids[blockIdx.x];
+    for (int s = threadIdx.x; s < gd.n_src; s += blockDim.x) {
+        const int32_t c = src_idx[gd.src_base + s];
+        if (c < 0 || (int64_t)c >= (int64_t)gd.nx * gd.ny) {
+            atomicAdd(&ctr[kCtrBadSource], 1ull);
+            continue;
+        }
+        T[gd.off + c] = src_t ? src_t[gd.src_base + s] : R(0);
+        code[gd.off + c] = kSource;
+        level[gd.off + c] = 0;
+        const int i = c % gd.nx, j = c / gd.nx;
+        const int t = gd.tile_base + (j / TH) * gd.ntx + i / TW;
+        if (atomicExch(&act[t], 1) == 0) atomicAdd(&act_count[0], 1);
     }
-    T[c] = src_t ? src_t[s] : R(0);
-    parent[c] = kSource;
-    const int i = c % g.nx, j = c / g.nx;
-    const int t = (j / g.th) * g.ntx + i / TW;
-    if (atomicExch(&act[t], 1) == 0) atomicAdd(&act_count[0], 1);
 }
 
 __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
@@ -62,7 +127,12 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
         p[c] = v;
 }
 
-// Flag every tile that holds a source-free node (warm start, level rounds).
+__global__ void k_fill_u64(unsigned long long *__restrict__ p, int64_t n)
+{
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        p[c] = 0ull;
+}
+
 __global__ void k_all_active(int32_t *__restrict__ act, int n_tiles, int32_t *__restrict__ act_count)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,17 +141,16 @@ __global__ void k_all_active(int32_t *__restrict__ act, int n_tiles, int32_t *__
 }
 
 // ---------------------------------------------------------------------------
-// Tile loading helpers.
+// Tile helpers.
 // ---------------------------------------------------------------------------
 template <typename V, int TH, int LP>
-__device__ __forceinline__ void load_tile_halo(const V *__restrict__ src, V *sT, int i0, int j0, int nx, int ny,
-                                               V outside)
+__device__ __forceinline__ void load_tile_halo(const V *__restrict__ src, V *sT, const TileGeo &g, V outside)
 {
-    for (int idx = threadIdx.x; idx < (TH + 2) * (TW + 2); idx += TW) {
+    for (int idx = threadIdx.x; idx < (TH + 2) * (TW + 2); idx += blockDim.x) {
         const int r = idx / (TW + 2), c = idx - r * (TW + 2);
-        const int gi = i0 + c - 1, gj = j0 + r - 1;
+        const int gi = g.i0 + c - 1, gj = g.j0 + r - 1;
         V v = outside;
-        if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) v = src[(size_t)gj * nx + gi];
+        if (gi >= 0 && gi < g.gd.nx && gj >= 0 && gj < g.gd.ny) v = src[(size_t)gj * g.gd.nx + gi];
         sT[r * LP + c] = v;
     }
 }
@@ -95,26 +164,120 @@ __device__ __forceinline__ int halo_bits(int ci, int cj, int w, int h)
            ((N && W) ? 64 : 0) | ((N && E) ? 128 : 0);
 }
 
-__device__ __forceinline__ void flag_neighbours(int bits, int tx, int ty, int ntx, int nty, int32_t *act_out,
-                                                int32_t *count_next)
+__device__ __forceinline__ void flag_tile(int32_t *act_out, int32_t *count_next, int u)
+{
+    if (atomicExch(&act_out[u], 1) == 0) atomicAdd(count_next, 1);
+}
+
+__device__ __forceinline__ void flag_neighbours(int bits, const TileGeo &g, int32_t *act_out, int32_t *count_next)
 {
     const int DX[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
     const int DY[8] = {0, 0, -1, 1, -1, -1, 1, 1};
     for (int b = 0; b < 8; ++b) {
         if (!(bits & (1 << b))) continue;
-        const int ux = tx + DX[b], uy = ty + DY[b];
-        if (ux < 0 || ux >= ntx || uy < 0 || uy >= nty) continue;
-        const int u = uy * ntx + ux;
-        if (atomicExch(&act_out[u], 1) == 0) atomicAdd(count_next, 1);
+        const int ux = g.tx + DX[b], uy = g.ty + DY[b];
+        if (ux < 0 || ux >= g.gd.ntx || uy < 0 || uy >= g.gd.nty) continue;
+        flag_tile(act_out, count_next, g.gd.tile_base + uy * g.gd.ntx + ux);
     }
+}
+
+__device__ __forceinline__ int wave_or(int v)
+{
+    for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
+    return v;
+}
+
+// Step boundary inside a one-wave workgroup. The LDS serves one wave's
+// requests in issue order, so a line written in one step is seen by the reads
+// of the next; only compiler motion of LDS accesses across the boundary must
+// be prevented. Unlike a workgroup barrier this does not wait for the
+// in-flight global loads (the next line's parameters).
+__device__ __forceinline__ void wave_step_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// One sweep of one direction over the tile held in LDS.
+// ---------------------------------------------------------------------------
+// Mb: three metric planes, Ob: two drift planes, both of n nodes each, laid out
+// column-major (transposed copy) for column sweeps and row-major otherwise.
+template <typename R, int TH, int DIR, bool FULL>
+__device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict__ Mb, const R *__restrict__ Ob,
+                                          R *sT, int32_t *sL, uint8_t *sC, R tol, R h, R inv_h)
+{
+    constexpr int LP = TW + 3;
+    constexpr bool COL = (DIR & 1) == 0; // a column (fixed x) per step
+    const int lane = threadIdx.x;
+    const int len = COL ? g.w : g.h;
+    const int span = COL ? g.h : g.w;
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    const int lc = lane < span ? lane : span - 1; // clamped lane for loads
+    // parameter address of the node this lane updates at step s
+    auto addr = [&](int s) -> size_t {
+        const int pos = DIR < 2 ? s : len - 1 - s;
+        return COL ? (size_t)(g.i0 + pos) * g.gd.ny + (g.j0 + lc) : (size_t)(g.j0 + pos) * g.gd.nx + (g.i0 + lc);
+    };
+    size_t ad = addr(0);
+    R p0 = Mb[ad], p1 = Mb[n + ad], p2 = Mb[2 * n + ad], p3 = Ob[ad], p4 = Ob[n + ad];
+    bool changed = false;
+    for (int s = 0; s < len; ++s) {
+        R q0 = p0, q1 = p1, q2 = p2, q3 = p3, q4 = p4;
+        if (s + 1 < len) { // prefetch the next line's parameters
+            ad = addr(s + 1);
+            p0 = Mb[ad]; p1 = Mb[n + ad]; p2 = Mb[2 * n + ad]; p3 = Ob[ad]; p4 = Ob[n + ad];
+        }
+        const int pos = DIR < 2 ? s : len - 1 - s;
+        const int ci = COL ? pos : lane;
+        const int cj = COL ? lane : pos;
+        const int cc = cj * TW + ci;
+        if (lane < span && sC[cc] != kSource) {
+            NodeConst<R> k;
+            node_const<R>(q0, q1, q2, q3, q4, h, inv_h, k);
+            R Tn[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Tn[q] = sT[(cj + 1 + nb_dy(q)) * LP + (ci + 1 + nb_dx(q))];
+            int code;
+            R v = local_update_dir<R, DIR, FULL>(k, Tn, code);
+            const int slot = (cj + 1) * LP + ci + 1;
+            const R old = sT[slot];
+            int newcode = code;
+            if (!FULL && !(v < old)) { // keep the old value and its code
+                v = old;
+                newcode = sC[cc];
+            }
+            // dependency level of the current active update
+            int lv = -1;
+            if (newcode < 16) {
+                const int kp = newcode < 8 ? newcode : newcode - 8;
+                lv = sL[(cj + 1 + nb_dy(kp)) * LP + ci + 1 + nb_dx(kp)];
+                if (newcode < 8) {
+                    const int kq = (newcode + 1) & 7;
+                    lv = max(lv, sL[(cj + 1 + nb_dy(kq)) * LP + ci + 1 + nb_dx(kq)]);
+                }
+                lv = lv + 1;
+            }
+            // only T decides convergence; levels ride along and are made
+            // consistent with the final active updates afterwards
+            changed |= counts_as_change<R>(old, v, tol);
+            sT[slot] = v;
+            sL[slot] = lv;
+            sC[cc] = (uint8_t)newcode;
+        }
+        wave_step_sync();
+    }
+    return changed;
 }
 
 // ---------------------------------------------------------------------------
 // One round of tile sweeps.
 // ---------------------------------------------------------------------------
-template <typename R, int TH>
-__global__ __launch_bounds__(TW) void k_sweep_round(GridArgs g, const R *__restrict__ M, const R *__restrict__ om,
-                                                    R *__restrict__ T, const uint8_t *__restrict__ parent,
+template <typename R, int TH, bool FULL>
+__global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
+                                                    const R *__restrict__ Ptall, R *__restrict__ Tall,
+                                                    uint8_t *__restrict__ codeall, int32_t *__restrict__ levall,
                                                     int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
                                                     int32_t *__restrict__ count_next,
                                                     unsigned long long *__restrict__ ctr, R tol, int max_cycles)
@@ -125,121 +288,114 @@ __global__ __launch_bounds__(TW) void k_sweep_round(GridArgs g, const R *__restr
     const int lane = threadIdx.x;
     if (lane == 0) act_in[t] = 0;
 
-    const int tx = t % g.ntx, ty = t / g.ntx;
-    const int i0 = tx * TW, j0 = ty * TH;
-    const int w = min(TW, g.nx - i0), hgt = min(TH, g.ny - j0);
-    const int64_t n = (int64_t)g.nx * g.ny;
-    const R h = R(g.h);
+    const TileGeo g = tile_geo<TH>(a, t);
+    R *T = Tall + g.gd.off;
+    uint8_t *code = codeall + g.gd.off;
+    int32_t *level = levall + g.gd.off;
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    const R *Mg = M + 3 * g.gd.off, *Og = om + 2 * g.gd.off; // row-major planes
+    const R *Pt = Ptall + 5 * g.gd.off, *Pto = Pt + 3 * n;   // column-major copy
+    const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
 
     __shared__ R sT[(TH + 2) * LP];
-    __shared__ uint8_t sFix[TH * TW];
-    load_tile_halo<R, TH, LP>(T, sT, i0, j0, g.nx, g.ny, inf_v<R>());
+    __shared__ int32_t sL[(TH + 2) * LP];
+    __shared__ uint8_t sC[TH * TW];
+    load_tile_halo<R, TH, LP>(T, sT, g, inf_v<R>());
+    load_tile_halo<int32_t, TH, LP>(level, sL, g, -1);
     for (int idx = lane; idx < TH * TW; idx += TW) {
         const int r = idx / TW, c = idx - r * TW;
-        sFix[idx] = (c < w && r < hgt) ? (parent[(size_t)(j0 + r) * g.nx + i0 + c] == kSource) : 1;
+        sC[idx] = (c < g.w && r < g.h) ? code[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c] : kSource;
     }
     __syncthreads();
 
     int quiet = 0, sweeps = 0;
     const int max_sweeps = 4 * max_cycles;
     while (quiet < 4 && sweeps < max_sweeps) {
-        const int dir = sweeps & 3;
-        const bool col = (dir & 1) == 0;
-        const int len = col ? w : hgt;
-        const int span = col ? hgt : w;
-        bool changed = false;
-        for (int s = 0; s < len; ++s) {
-            const int pos = dir < 2 ? s : len - 1 - s;
-            const int ci = col ? pos : lane;
-            const int cj = col ? lane : pos;
-            if (lane < span && !sFix[cj * TW + ci]) {
-                const size_t gc = (size_t)(j0 + cj) * g.nx + (i0 + ci);
-                NodeConst<R> k;
-                node_const<R>(M[gc], M[n + gc], M[2 * n + gc], om[gc], om[n + gc], h, k);
-                R Tn[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) Tn[q] = sT[(cj + 1 + nb_dy(q)) * LP + (ci + 1 + nb_dx(q))];
-                int code;
-                R w1;
-                const R v = local_update<R>(k, Tn, inf_v<R>(), code, w1);
-                R &slot = sT[(cj + 1) * LP + ci + 1];
-                changed |= counts_as_change<R>(slot, v, tol);
-                slot = v;
-            }
-            __syncthreads();
+        bool ch;
+        switch (sweeps & 3) {
+        case 0: ch = sweep_dir<R, TH, 0, FULL>(g, Pt, Pto, sT, sL, sC, tol, h, inv_h); break;
+        case 1: ch = sweep_dir<R, TH, 1, FULL>(g, Mg, Og, sT, sL, sC, tol, h, inv_h); break;
+        case 2: ch = sweep_dir<R, TH, 2, FULL>(g, Pt, Pto, sT, sL, sC, tol, h, inv_h); break;
+        default: ch = sweep_dir<R, TH, 3, FULL>(g, Mg, Og, sT, sL, sC, tol, h, inv_h); break;
         }
         ++sweeps;
-        quiet = __ballot(changed) ? 0 : quiet + 1;
+        quiet = __ballot(ch) ? 0 : quiet + 1;
     }
 
-    // write back; flag neighbours whose halo moved by more than tol
+    // write back; flag neighbours whose halo moved
     int bits = 0;
     for (int idx = lane; idx < TH * TW; idx += TW) {
         const int r = idx / TW, c = idx - r * TW;
-        if (c >= w || r >= hgt) continue;
-        const size_t gc = (size_t)(j0 + r) * g.nx + (i0 + c);
-        const R nv = sT[(r + 1) * LP + c + 1];
+        if (c >= g.w || r >= g.h) continue;
+        const size_t gc = (size_t)(g.j0 + r) * g.gd.nx + (g.i0 + c);
+        const int sl = (r + 1) * LP + c + 1;
+        const R nv = sT[sl];
         const R ov = T[gc];
-        if (nv != ov) {
-            T[gc] = nv;
-            if (counts_as_change<R>(ov, nv, tol)) bits |= halo_bits(c, r, w, hgt);
-        }
+        const int nl = sL[sl];
+        const int ol = level[gc];
+        if (nv != ov) T[gc] = nv;
+        if (nl != ol) level[gc] = nl;
+        code[gc] = sC[idx];
+        if (counts_as_change<R>(ov, nv, tol)) bits |= halo_bits(c, r, g.w, g.h);
     }
-    for (int off = 32; off >= 1; off >>= 1) bits |= __shfl_xor(bits, off);
+    bits = wave_or(bits);
     if (lane == 0) {
-        flag_neighbours(bits, tx, ty, g.ntx, g.nty, act_out, count_next);
-        if (quiet < 4) { // cycle budget ran out before the tile settled
-            if (atomicExch(&act_out[t], 1) == 0) atomicAdd(count_next, 1);
-        }
-        atomicAdd(&ctr[kCtrCellUpdates], (unsigned long long)sweeps * (unsigned long long)(w * hgt));
+        flag_neighbours(bits, g, act_out, count_next);
+        if (quiet < 4) flag_tile(act_out, count_next, t); // cycle budget ran out before the tile settled
+        atomicAdd(&ctr[kCtrCellUpdates], (unsigned long long)sweeps * (unsigned long long)(g.w * g.h));
     }
 }
 
 // ---------------------------------------------------------------------------
 // Active stencils from the final field (the stencil identification of
-// Alg. backward, moved into the forward pass).
+// Alg. backward, moved into the forward pass). Donors must lie strictly below
+// the node's own time, which keeps the donor graph acyclic.
 // ---------------------------------------------------------------------------
-template <typename R>
-__global__ void k_parents(GridArgs g, const R *__restrict__ M, const R *__restrict__ om, const R *__restrict__ T,
-                          uint8_t *__restrict__ parent, int32_t *__restrict__ level)
+template <typename R, int TH>
+__global__ __launch_bounds__(256) void k_parents(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
+                                                 const R *__restrict__ Tall, uint8_t *__restrict__ parall)
 {
-    const int64_t n = (int64_t)g.nx * g.ny;
-    const R h = R(g.h);
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        if (parent[c] == kSource) {
-            level[c] = 0;
-            continue;
-        }
+    const TileGeo g = tile_geo<TH>(a, blockIdx.x);
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    const R *T = Tall + g.gd.off;
+    uint8_t *parent = parall + g.gd.off;
+    const R *Mg = M + 3 * g.gd.off;
+    const R *og = om + 2 * g.gd.off;
+    const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
+    for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+        const int r = idx / TW, cl = idx - r * TW;
+        if (r >= g.h || cl >= g.w) continue;
+        const int i = g.i0 + cl, j = g.j0 + r;
+        const size_t c = (size_t)j * g.gd.nx + i;
+        if (parent[c] == kSource) continue;
         const R Tc = T[c];
         if (!(Tc < inf_v<R>())) {
             parent[c] = kUnreached;
-            level[c] = -1;
             continue;
         }
-        const int i = (int)(c % g.nx), j = (int)(c / g.nx);
         R Tn[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int a = i + nb_dx(q), b = j + nb_dy(q);
-            Tn[q] = (a >= 0 && a < g.nx && b >= 0 && b < g.ny) ? T[(size_t)b * g.nx + a] : inf_v<R>();
+            const int x = i + nb_dx(q), y = j + nb_dy(q);
+            Tn[q] = (x >= 0 && x < g.gd.nx && y >= 0 && y < g.gd.ny) ? T[(size_t)y * g.gd.nx + x] : inf_v<R>();
         }
         NodeConst<R> k;
-        node_const<R>(M[c], M[n + c], M[2 * n + c], om[c], om[n + c], h, k);
+        node_const<R>(Mg[c], Mg[n + c], Mg[2 * n + c], og[c], og[n + c], h, inv_h, k);
         int code;
         R w1;
         local_update<R>(k, Tn, Tc, code, w1);
         parent[c] = (uint8_t)code;
-        level[c] = code == kUnreached ? -1 : 0;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Dependency levels: level = 1 + max level of the donors, relaxed upward with
-// the same tile sweeps (the donor graph is acyclic, so this terminates).
+// Dependency levels: level = 1 + max level of the donors, overwritten until
+// stable (the donor graph is acyclic, so this converges from any start; after
+// the sweep, which already carried the levels, one quiet round is typical).
 // ---------------------------------------------------------------------------
 template <int TH>
-__global__ __launch_bounds__(TW) void k_level_round(GridArgs g, const uint8_t *__restrict__ parent,
-                                                    int32_t *__restrict__ level, int32_t *__restrict__ act_in,
+__global__ __launch_bounds__(TW) void k_level_round(LaunchArgs a, const uint8_t *__restrict__ parall,
+                                                    int32_t *__restrict__ levall, int32_t *__restrict__ act_in,
                                                     int32_t *__restrict__ act_out, int32_t *__restrict__ count_next,
                                                     int max_cycles)
 {
@@ -248,16 +404,16 @@ __global__ __launch_bounds__(TW) void k_level_round(GridArgs g, const uint8_t *_
     if (act_in[t] == 0) return;
     const int lane = threadIdx.x;
     if (lane == 0) act_in[t] = 0;
-    const int tx = t % g.ntx, ty = t / g.ntx;
-    const int i0 = tx * TW, j0 = ty * TH;
-    const int w = min(TW, g.nx - i0), hgt = min(TH, g.ny - j0);
+    const TileGeo g = tile_geo<TH>(a, t);
+    const uint8_t *parent = parall + g.gd.off;
+    int32_t *level = levall + g.gd.off;
 
     __shared__ int32_t sL[(TH + 2) * LP];
     __shared__ uint8_t sP[TH * TW];
-    load_tile_halo<int32_t, TH, LP>(level, sL, i0, j0, g.nx, g.ny, -1);
+    load_tile_halo<int32_t, TH, LP>(level, sL, g, -1);
     for (int idx = lane; idx < TH * TW; idx += TW) {
         const int r = idx / TW, c = idx - r * TW;
-        sP[idx] = (c < w && r < hgt) ? parent[(size_t)(j0 + r) * g.nx + i0 + c] : kUnreached;
+        sP[idx] = (c < g.w && r < g.h) ? parent[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c] : kUnreached;
     }
     __syncthreads();
 
@@ -266,14 +422,16 @@ __global__ __launch_bounds__(TW) void k_level_round(GridArgs g, const uint8_t *_
     while (quiet < 4 && sweeps < max_sweeps) {
         const int dir = sweeps & 3;
         const bool col = (dir & 1) == 0;
-        const int len = col ? w : hgt;
-        const int span = col ? hgt : w;
+        const int len = col ? g.w : g.h;
+        const int span = col ? g.h : g.w;
         bool changed = false;
         for (int s = 0; s < len; ++s) {
             const int pos = dir < 2 ? s : len - 1 - s;
             const int ci = col ? pos : lane;
             const int cj = col ? lane : pos;
             const int code = lane < span ? sP[cj * TW + ci] : kUnreached;
+            int32_t *slot = &sL[(cj + 1) * LP + ci + 1];
+            int nv = code == kSource ? 0 : -1;
             if (code < 16) {
                 const int kp = code < 8 ? code : code - 8;
                 int lv = sL[(cj + 1 + nb_dy(kp)) * LP + ci + 1 + nb_dx(kp)];
@@ -281,12 +439,13 @@ __global__ __launch_bounds__(TW) void k_level_round(GridArgs g, const uint8_t *_
                     const int kq = (code + 1) & 7;
                     lv = max(lv, sL[(cj + 1 + nb_dy(kq)) * LP + ci + 1 + nb_dx(kq)]);
                 }
-                int32_t &slot = sL[(cj + 1) * LP + ci + 1];
-                const int nv = lv + 1;
-                changed |= nv != slot;
-                slot = nv;
+                nv = lv + 1;
             }
-            __syncthreads();
+            if (lane < span) {
+                changed |= nv != *slot;
+                *slot = nv;
+            }
+            wave_step_sync();
         }
         ++sweeps;
         quiet = __ballot(changed) ? 0 : quiet + 1;
@@ -295,18 +454,18 @@ __global__ __launch_bounds__(TW) void k_level_round(GridArgs g, const uint8_t *_
     int bits = 0;
     for (int idx = lane; idx < TH * TW; idx += TW) {
         const int r = idx / TW, c = idx - r * TW;
-        if (c >= w || r >= hgt) continue;
-        const size_t gc = (size_t)(j0 + r) * g.nx + (i0 + c);
+        if (c >= g.w || r >= g.h) continue;
+        const size_t gc = (size_t)(g.j0 + r) * g.gd.nx + (g.i0 + c);
         const int32_t nv = sL[(r + 1) * LP + c + 1];
         if (nv != level[gc]) {
             level[gc] = nv;
-            bits |= halo_bits(c, r, w, hgt);
+            bits |= halo_bits(c, r, g.w, g.h);
         }
     }
-    for (int off = 32; off >= 1; off >>= 1) bits |= __shfl_xor(bits, off);
+    bits = wave_or(bits);
     if (lane == 0) {
-        flag_neighbours(bits, tx, ty, g.ntx, g.nty, act_out, count_next);
-        if (quiet < 4 && atomicExch(&act_out[t], 1) == 0) atomicAdd(count_next, 1);
+        flag_neighbours(bits, g, act_out, count_next);
+        if (quiet < 4) flag_tile(act_out, count_next, t);
     }
 }
 
@@ -338,58 +497,75 @@ __global__ void k_check_feasible(int64_t n, const R *__restrict__ M, const R *__
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-static inline int blocks_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 4096); }
+#define EIK_TH_DISPATCH(TH_VAR, ...)                                                                             \
+    do {                                                                                                         \
+        if ((TH_VAR) == 64) {                                                                                    \
+            constexpr int TH = 64;                                                                               \
+            __VA_ARGS__;                                                                                         \
+        } else {                                                                                                 \
+            constexpr int TH = 32;                                                                               \
+            __VA_ARGS__;                                                                                         \
+        }                                                                                                        \
+    } while (0)
+
+void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_grid, int n_tiles, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_write_single_desc, dim3((n_tiles + 255) / 256), dim3(256), 0, st, d, dst, tile_grid,
+                       n_tiles);
+}
 
 template <typename R>
-void launch_init(const GridArgs &g, const void *T_init, void *T, uint8_t *parent, int32_t *level,
+void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, hipStream_t st)
+{
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_stage<R, TH>), dim3(a.n_tiles), dim3(256), 0, st, a, (const R *)M,
+                                             (const R *)om, (R *)Pt));
+}
+
+template <typename R>
+void launch_init(const LaunchArgs &a, const void *T_init, void *T, uint8_t *code, int32_t *level,
                  const int32_t *src_idx, const void *src_t, int32_t *act, int32_t *act_count,
                  unsigned long long *ctr, bool warm, hipStream_t st)
 {
-    const int64_t n = (int64_t)g.nx * g.ny;
-    hipLaunchKernelGGL(k_init<R>, dim3(blocks_for(n, 256)), dim3(256), 0, st, g, (const R *)T_init, (R *)T, parent,
-                       level);
-    if (warm)
-        hipLaunchKernelGGL(k_all_active, dim3((g.n_tiles + 255) / 256), dim3(256), 0, st, act, g.n_tiles, act_count);
-    hipLaunchKernelGGL(k_sources<R>, dim3((g.n_src + 255) / 256), dim3(256), 0, st, g, src_idx, (const R *)src_t,
-                       (R *)T, parent, act, act_count, ctr);
+    hipLaunchKernelGGL(k_init<R>, dim3(blocks_for(a.n_nodes, 256)), dim3(256), 0, st, a.n_nodes,
+                       (const R *)T_init, (R *)T, code, level);
+    if (warm) launch_all_active(a, act, act_count, st);
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sources<R, TH>), dim3(a.n_grids), dim3(64), 0, st, a, src_idx,
+                                             (const R *)src_t, (R *)T, code, level, act, act_count, ctr));
+}
+
+void launch_all_active(const LaunchArgs &a, int32_t *act, int32_t *act_count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_all_active, dim3((a.n_tiles + 255) / 256), dim3(256), 0, st, act, a.n_tiles, act_count);
 }
 
 template <typename R>
-void launch_sweep_round(const GridArgs &g, const void *M, const void *om, void *T, const uint8_t *parent,
-                        int32_t *act_in, int32_t *act_out, int32_t *count_next, unsigned long long *ctr, double tol,
-                        int max_cycles, hipStream_t st)
+void launch_sweep_round(const LaunchArgs &a, int mode, const void *M, const void *om, const void *Pt, void *T,
+                        uint8_t *code, int32_t *level, int32_t *act_in, int32_t *act_out, int32_t *count_next,
+                        unsigned long long *ctr, double tol, int max_cycles, hipStream_t st)
 {
-    if (g.th == 64)
-        hipLaunchKernelGGL((k_sweep_round<R, 64>), dim3(g.n_tiles), dim3(TW), 0, st, g, (const R *)M, (const R *)om,
-                           (R *)T, parent, act_in, act_out, count_next, ctr, R(tol), max_cycles);
+    if (mode == kModeFull)
+        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round<R, TH, true>), dim3(a.n_tiles), dim3(TW), 0, st, a,
+                                                 (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level,
+                                                 act_in, act_out, count_next, ctr, R(tol), max_cycles));
     else
-        hipLaunchKernelGGL((k_sweep_round<R, 32>), dim3(g.n_tiles), dim3(TW), 0, st, g, (const R *)M, (const R *)om,
-                           (R *)T, parent, act_in, act_out, count_next, ctr, R(tol), max_cycles);
+        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round<R, TH, false>), dim3(a.n_tiles), dim3(TW), 0, st, a,
+                                                 (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level,
+                                                 act_in, act_out, count_next, ctr, R(tol), max_cycles));
 }
 
 template <typename R>
-void launch_parents(const GridArgs &g, const void *M, const void *om, const void *T, uint8_t *parent,
-                    int32_t *level, hipStream_t st)
+void launch_parents(const LaunchArgs &a, const void *M, const void *om, const void *T, uint8_t *parent,
+                    hipStream_t st)
 {
-    const int64_t n = (int64_t)g.nx * g.ny;
-    hipLaunchKernelGGL(k_parents<R>, dim3(blocks_for(n, 256)), dim3(256), 0, st, g, (const R *)M, (const R *)om,
-                       (const R *)T, parent, level);
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_parents<R, TH>), dim3(a.n_tiles), dim3(256), 0, st, a,
+                                             (const R *)M, (const R *)om, (const R *)T, parent));
 }
 
-void launch_level_prep(const GridArgs &g, int32_t *act, int32_t *act_count, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_all_active, dim3((g.n_tiles + 255) / 256), dim3(256), 0, st, act, g.n_tiles, act_count);
-}
-
-void launch_level_round(const GridArgs &g, const uint8_t *parent, int32_t *level, int32_t *act_in,
+void launch_level_round(const LaunchArgs &a, const uint8_t *parent, int32_t *level, int32_t *act_in,
                         int32_t *act_out, int32_t *count_next, int max_cycles, hipStream_t st)
 {
-    if (g.th == 64)
-        hipLaunchKernelGGL(k_level_round<64>, dim3(g.n_tiles), dim3(TW), 0, st, g, parent, level, act_in, act_out,
-                           count_next, max_cycles);
-    else
-        hipLaunchKernelGGL(k_level_round<32>, dim3(g.n_tiles), dim3(TW), 0, st, g, parent, level, act_in, act_out,
-                           count_next, max_cycles);
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL(k_level_round<TH>, dim3(a.n_tiles), dim3(TW), 0, st, a, parent, level,
+                                             act_in, act_out, count_next, max_cycles));
 }
 
 void launch_max_level(int64_t n, const int32_t *level, unsigned long long *ctr, hipStream_t st)
@@ -402,6 +578,11 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
 }
 
+void launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+}
+
 template <typename R>
 void launch_check_feasible(int64_t n, const void *M, const void *om, unsigned long long *ctr, hipStream_t st)
 {
@@ -409,17 +590,33 @@ void launch_check_feasible(int64_t n, const void *M, const void *om, unsigned lo
                        (const R *)om, ctr);
 }
 
-#define EIK_INST(R)                                                                                            \
-    template void launch_init<R>(const GridArgs &, const void *, void *, uint8_t *, int32_t *, const int32_t *, \
-                                 const void *, int32_t *, int32_t *, unsigned long long *, bool, hipStream_t);  \
-    template void launch_sweep_round<R>(const GridArgs &, const void *, const void *, void *, const uint8_t *,  \
-                                        int32_t *, int32_t *, int32_t *, unsigned long long *, double, int,     \
-                                        hipStream_t);                                                           \
-    template void launch_parents<R>(const GridArgs &, const void *, const void *, const void *, uint8_t *,      \
-                                    int32_t *, hipStream_t);                                                    \
+#define EIK_INST(R)                                                                                             \
+    template void launch_stage<R>(const LaunchArgs &, const void *, const void *, void *, hipStream_t);         \
+    template void launch_init<R>(const LaunchArgs &, const void *, void *, uint8_t *, int32_t *,                 \
+                                 const int32_t *, const void *, int32_t *, int32_t *, unsigned long long *,      \
+                                 bool, hipStream_t);                                                             \
+    template void launch_sweep_round<R>(const LaunchArgs &, int, const void *, const void *, const void *,       \
+                                        void *, uint8_t *, int32_t *, int32_t *, int32_t *, int32_t *,           \
+                                        unsigned long long *, double, int, hipStream_t);                         \
+    template void launch_parents<R>(const LaunchArgs &, const void *, const void *, const void *, uint8_t *,     \
+                                    hipStream_t);                                                                \
     template void launch_check_feasible<R>(int64_t, const void *, const void *, unsigned long long *, hipStream_t);
 EIK_INST(float)
 EIK_INST(double)
 #undef EIK_INST
+
+} // namespace eik
+
+namespace eik {
+
+__global__ void k_note_pending(const int32_t *__restrict__ count, unsigned long long *__restrict__ slot)
+{
+    if (threadIdx.x == 0) *slot = (unsigned long long)(count[0] > 0 ? count[0] : 0);
+}
+
+void launch_note_pending(const int32_t *count, unsigned long long *slot, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_note_pending, dim3(1), dim3(64), 0, st, count, slot);
+}
 
 } // namespace eik

@@ -8,12 +8,26 @@
 
 namespace eik {
 
-struct GridArgs {
-    int32_t nx, ny;
+constexpr int TW = 64; // tile width = wave size
+
+// One grid of a launch. Arrays of a launch are packed grid after grid: the
+// node arrays of grid g start at node offset `off`, its metric planes at
+// 3*off, its drift planes at 2*off, its transposed parameters at 5*off.
+struct GridDesc {
+    int64_t off;      // first node of this grid in the packed node arrays
     double h;
-    int32_t n_src;
-    int32_t th;  // tile height (tile width is the wave size, 64)
-    int32_t ntx, nty, n_tiles;
+    int32_t nx, ny;
+    int32_t ntx, nty; // tiles along x and y
+    int32_t tile_base;// first tile of this grid in the launch's tile list
+    int32_t n_src, src_base;
+    int32_t pad;
+};
+
+struct LaunchArgs {
+    const GridDesc *grids;
+    const int32_t *tile_grid; // tile -> grid
+    int32_t n_grids, n_tiles, th;
+    int64_t n_nodes;          // all grids
 };
 
 // slots of the 64-bit counter block in the workspace
@@ -22,44 +36,60 @@ enum {
     kCtrBadSource = 1,
     kCtrMaxLevel = 2,
     kCtrInfeasible = 3,
+    kCtrSweepPending = 4, // tiles still flagged after the last sweep round
+    kCtrLevelPending = 5, // ... after the last level round
+    kCtrAdjPending = 6,   // ... after the last adjoint round
     kCtrCount = 16
 };
 
 constexpr int kMaxRounds = 1 << 16;
+constexpr int kSortChunk = 4096;
 
+enum SweepMode { kModeFast = 0, kModeFull = 1 };
+
+// copies the flagged-tile count of the last round into a counter slot
+void launch_note_pending(const int32_t *count, unsigned long long *slot, hipStream_t st);
+
+// forward
 template <typename R>
-void launch_init(const GridArgs &g, const void *T_init, void *T, uint8_t *parent, int32_t *level,
+void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, hipStream_t st);
+template <typename R>
+void launch_init(const LaunchArgs &a, const void *T_init, void *T, uint8_t *code, int32_t *level,
                  const int32_t *src_idx, const void *src_t, int32_t *act, int32_t *act_count,
                  unsigned long long *ctr, bool warm, hipStream_t st);
 template <typename R>
-void launch_sweep_round(const GridArgs &g, const void *M, const void *om, void *T, const uint8_t *parent,
-                        int32_t *act_in, int32_t *act_out, int32_t *count_next, unsigned long long *ctr, double tol,
-                        int max_cycles, hipStream_t st);
+void launch_sweep_round(const LaunchArgs &a, int mode, const void *M, const void *om, const void *Pt, void *T,
+                        uint8_t *code, int32_t *level, int32_t *act_in, int32_t *act_out, int32_t *count_next,
+                        unsigned long long *ctr, double tol, int max_cycles, hipStream_t st);
 template <typename R>
-void launch_parents(const GridArgs &g, const void *M, const void *om, const void *T, uint8_t *parent,
-                    int32_t *level, hipStream_t st);
+void launch_parents(const LaunchArgs &a, const void *M, const void *om, const void *T, uint8_t *parent,
+                    hipStream_t st);
 template <typename R>
 void launch_check_feasible(int64_t n, const void *M, const void *om, unsigned long long *ctr, hipStream_t st);
-void launch_level_prep(const GridArgs &g, int32_t *act, int32_t *act_count, hipStream_t st);
-void launch_level_round(const GridArgs &g, const uint8_t *parent, int32_t *level, int32_t *act_in,
+void launch_all_active(const LaunchArgs &a, int32_t *act, int32_t *act_count, hipStream_t st);
+void launch_level_round(const LaunchArgs &a, const uint8_t *parent, int32_t *level, int32_t *act_in,
                         int32_t *act_out, int32_t *count_next, int max_cycles, hipStream_t st);
 void launch_max_level(int64_t n, const int32_t *level, unsigned long long *ctr, hipStream_t st);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st);
+void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_grid, int n_tiles, hipStream_t st);
 
+// backward
 template <typename R>
-void launch_adj_prep(const GridArgs &g, const void *M, const void *om, const void *T, const uint8_t *parent,
-                     const int32_t *level, void *w1, int32_t *counts, void *dM, void *dom, hipStream_t st);
-void launch_scan_levels(int32_t *counts, int32_t *offsets, int32_t *cursor, const unsigned long long *ctr,
-                        hipStream_t st);
-void launch_scatter_levels(int64_t n, const int32_t *level, int32_t *cursor, int32_t *list, hipStream_t st);
+void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const void *T, const uint8_t *parent,
+                     void *w1, void *lam, hipStream_t st);
+void launch_adj_sort(const LaunchArgs &a, const int32_t *level, int32_t *list, int32_t *cnt, hipStream_t st);
 template <typename R>
-void launch_adj_levels(const GridArgs &g, int L_hi, int L_lo, bool single_wg, const unsigned long long *ctr,
-                       const int32_t *offsets, const int32_t *list, const uint8_t *parent, const void *w1,
-                       const void *dLdT, const void *M, void *lam, void *dM, void *dom, hipStream_t st);
+void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const int32_t *level, const void *w1,
+                      const void *dLdT, const int32_t *list, const int32_t *cnt, void *lam, int32_t *act_in,
+                      int32_t *act_out, int32_t *count_next, hipStream_t st);
 template <typename R>
-void launch_dsrc(const GridArgs &g, const int32_t *src_idx, const void *lam, void *dsrc, hipStream_t st);
+void launch_adj_params(const LaunchArgs &a, const void *M, const uint8_t *parent, const void *w1, const void *lam,
+                       void *dM, void *dom, hipStream_t st);
+template <typename R>
+void launch_dsrc(const LaunchArgs &a, const int32_t *src_idx, const void *lam, void *dsrc, hipStream_t st);
 
+// projection
 template <typename R>
 void launch_project(int64_t n, const void *M, const void *om, void *Mo, void *oo, double eig_min, double eig_max,
                     double eucl_clip, double rho_max, hipStream_t st);
@@ -67,5 +97,7 @@ template <typename R>
 void launch_project_backward(int64_t n, const void *M, const void *om, const void *gMo, const void *goo, void *gM,
                              void *go, double eig_min, double eig_max, double eucl_clip, double rho_max,
                              hipStream_t st);
+
+static inline int blocks_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 8192); }
 
 } // namespace eik

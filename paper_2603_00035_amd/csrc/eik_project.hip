@@ -137,7 +137,6 @@ __global__ void k_project_backward(int64_t n, const R *__restrict__ M, const R *
     }
 }
 
-static inline int blocks_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 4096); }
 
 template <typename R>
 void launch_project(int64_t n, const void *M, const void *om, void *Mo, void *oo, double eig_min, double eig_max,

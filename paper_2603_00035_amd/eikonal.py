@@ -14,6 +14,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib as L
+from . import autotune
 
 
 @dataclass
@@ -25,6 +26,7 @@ class Stats:
     status: int
     sweep_launches: int = 0
     sweep_ms: float = 0.0
+    aux_rounds: int = 0
 
 
 def _check_fields(M, omega):
@@ -54,8 +56,11 @@ def workspace(grid: L.EikGrid, dtype_code: int, device) -> torch.Tensor:
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def tuning(max_local_cycles=0, rounds_per_check=0, adjoint_single_wg_max_cells=-1):
-    return L.EikTuning(max_local_cycles, rounds_per_check, adjoint_single_wg_max_cells)
+def tuning(tile_height=0, max_local_cycles=0, rounds_per_check=0, fast_cold_start=-1, adjoint_rounds=0,
+           level_rounds=0):
+    """Scheduling knobs (0 / -1 keep the library default)."""
+    return L.EikTuning(tile_height, max_local_cycles, rounds_per_check, fast_cold_start, adjoint_rounds,
+                       level_rounds)
 
 
 def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=4096, check_feasible=False,
@@ -70,6 +75,8 @@ def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=40
     dc = L.dtype_code(M)
     if ws is None:
         ws = workspace(grid, dc, dev)
+    if tune is None:
+        tune = autotune.lookup(nx * ny, autotune.dtype_name(M.dtype))
     T = torch.empty((ny, nx), dtype=M.dtype, device=dev)
     parent = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
     level = torch.empty((ny, nx), dtype=torch.int32, device=dev)
@@ -84,11 +91,12 @@ def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=40
                              None if tune is None else ctypes.byref(tune), ctypes.byref(st), L.stream_handle(dev))
     L.check("eik_forward", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
     return T, parent, level, Stats(st.rounds, bool(st.converged), st.cell_updates, st.n_levels, st.status,
-                                   st.sweep_launches, st.sweep_ms)
+                                   st.sweep_launches, st.sweep_ms, st.aux_rounds)
 
 
-def adjoint(M, omega, T, parent, level, src_idx, h, dLdT, src_t=None, tune=None, ws=None):
-    """Backward pass. Returns (dL/dM, dL/domega, dL/dt_src)."""
+def adjoint(M, omega, T, parent, level, src_idx, h, dLdT, src_t=None, tune=None, ws=None, stats_out=None):
+    """Backward pass. Returns (dL/dM, dL/domega, dL/dt_src); ``stats_out`` (a
+    list) receives the call's Stats."""
     _check_fields(M, omega)
     ny, nx = M.shape[1:]
     dev = M.device
@@ -96,14 +104,19 @@ def adjoint(M, omega, T, parent, level, src_idx, h, dLdT, src_t=None, tune=None,
     dc = L.dtype_code(M)
     if ws is None:
         ws = workspace(grid, dc, dev)
+    if tune is None:
+        tune = autotune.lookup(nx * ny, autotune.dtype_name(M.dtype))
     dLdT = dLdT.to(dtype=M.dtype).contiguous()
     dM = torch.empty_like(M)
     dom = torch.empty_like(omega)
     ds = torch.empty(src_idx.numel(), dtype=M.dtype, device=dev)
+    st = L.EikStats()
     rc = L.lib().eik_backward(ctypes.byref(grid), dc, L.ptr(M), L.ptr(omega), L.ptr(T), L.ptr(parent),
                               L.ptr(level), L.ptr(dLdT), L.ptr(dM), L.ptr(dom), L.ptr(ds), L.ptr(ws), ws.numel(),
-                              None if tune is None else ctypes.byref(tune), L.stream_handle(dev))
+                              None if tune is None else ctypes.byref(tune), ctypes.byref(st), L.stream_handle(dev))
     L.check("eik_backward", rc)
+    if stats_out is not None:
+        stats_out.append(Stats(st.rounds, bool(st.converged), 0, 0, rc, 0, 0.0, st.aux_rounds))
     return dM, dom, ds
 
 

@@ -1,0 +1,62 @@
+"""Full-size parity: the 2048 x 2048 FP32 stress workload (eigenvalue ratio 10,
+drift 0.9, 4 sharp regions, 16 sources) through the autograd wrapper, in the
+configuration the benchmark times, against the FP64 oracle run to exact
+stationarity on the same FP32-rounded inputs."""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic.fields import fourier_field, make_problem
+from tests.gpu_common import check_parent_choices, check_levels_consistent, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.timeout(600)
+def test_stress_2048_forward_and_gradient():
+    from paper_2603_00035_amd import eikonal as E
+    p = make_problem("c3", 0)
+    q = p.rounded(np.float32)
+    say("[full] 2048x2048 stress: GPU solve to 1e-5 and adjoint")
+    dev = torch.device("cuda:0")
+    M = torch.tensor(p.M, dtype=torch.float32, device=dev).requires_grad_(True)
+    om = torch.tensor(p.omega, dtype=torch.float32, device=dev).requires_grad_(True)
+    src = torch.tensor(p.src_idx, device=dev)
+    # a fixed loss target independent of either solver: a smooth field in [0, 3]
+    target = 3.0 * fourier_field(np.random.default_rng(7), p.nx, p.ny, p.h)
+    T, par, lev = E.eikonal(M, om, src, p.h, tol=1e-5)
+    mask = np.isfinite(target)
+    mask.flat[p.src_idx] = False
+    n_obs = mask.sum()
+    tgt = torch.tensor(target, dtype=torch.float32, device=dev)
+    mk = torch.tensor(mask, device=dev)
+    d = torch.where(mk, T - tgt, torch.zeros_like(T))
+    ((d * d).sum() / n_obs).backward()
+    torch.cuda.synchronize()
+    Tg = T.detach().double().cpu().numpy()
+    pg = par.cpu().numpy()
+    check_levels_consistent(pg, lev.cpu().numpy(), Tg)
+    say("[full] oracle solve (about 20-40 s)")
+    To, sweeps, st = oracle.forward(q)
+    assert st == 0
+    m = np.isfinite(To)
+    m.flat[p.src_idx] = False
+    err = np.max(np.abs(Tg[m] - To[m]) / np.abs(To[m]))
+    say(f"[full] forward max rel err {err:.3e} (oracle {sweeps} sweeps)")
+    assert err <= 1e-5
+    po, _ = oracle.parents_levels(q, To)
+    mism = int(np.sum(pg != po))
+    say(f"[full] parent differences {mism}")
+    sample = np.flatnonzero((pg != po).ravel())
+    if sample.size > 2000:  # the oracle checks a sample of the differing nodes one by one
+        sample = np.random.default_rng(0).choice(sample, 2000, replace=False)
+    pg_s = po.copy()
+    pg_s.flat[sample] = pg.flat[sample]
+    check_parent_choices(q, To, po, pg_s, 1e-5)
+    g = np.zeros_like(To)
+    g[mask] = 2.0 * (To[mask] - target[mask]) / n_obs
+    dMo, domo, _ = oracle.vjp(q, To, po, g)
+    r = rel_l2([M.grad.double().cpu().numpy(), om.grad.double().cpu().numpy()], [dMo, domo])
+    say(f"[full] gradient rel L2 {r:.3e}")
+    assert r <= 1e-4

@@ -1,0 +1,189 @@
+"""The warm-start network's BF16 MFMA kernels through their C ABI, against the
+float64 oracle layers on the same bf16-rounded operands. Tolerance from the
+arithmetic: bf16 x bf16 products are exact in FP32, the FP32 sum of K terms is
+within K 2^-24 sum|terms|, and a bf16 output adds one rounding (2^-9 relative)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import unet_ref as U
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def lib():
+    from paper_2603_00035_amd import unet
+    return unet._bind()
+
+
+def P(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def st():
+    from paper_2603_00035_amd import _lib as L
+    return L.stream_handle(torch.device("cuda"))
+
+
+def to_dev_bf16(x):
+    return torch.tensor(U.bf16_bits(x).view(np.int16), device="cuda")
+
+
+def from_dev_bf16(t, shape):
+    return U.from_bits(t.cpu().numpy().view(np.uint16)).reshape(shape)
+
+
+def check(got, ref, absterms, K, out_bf16=True):
+    tol = K * 2.0 ** -23 * absterms + (2.0 ** -8 * np.abs(ref) if out_bf16 else 0) + 1e-30
+    bad = np.abs(got - ref) > tol
+    assert not bad.any(), f"{bad.sum()} elements off; worst {np.max(np.abs(got - ref) / tol):.2f}x tol"
+
+
+@pytest.mark.parametrize("B,H,W,Cin,Cout,relu", [(2, 16, 32, 16, 16, True), (1, 8, 64, 32, 64, False),
+                                                (3, 32, 16, 64, 128, True), (1, 5, 7, 16, 48, True)])
+def test_conv3_forward(B, H, W, Cin, Cout, relu):
+    rng = np.random.default_rng(B * 100 + Cout)
+    x = U.bf16_round(rng.standard_normal((B, H, W, Cin)))
+    w = U.bf16_round(rng.standard_normal((9, Cout, Cin)) * 0.2)
+    bias = rng.standard_normal(Cout).astype(np.float32)
+    say(f"[unet] conv3 {B}x{H}x{W} {Cin}->{Cout}")
+    yd = torch.zeros(B * H * W * Cout, dtype=torch.int16, device="cuda")
+    bd = torch.tensor(bias, device="cuda")
+    rc = lib().eiku_conv_fwd(0, B, H, W, P(to_dev_bf16(x)), Cin, 0, Cin, P(to_dev_bf16(w)), P(bd), int(relu),
+                             P(yd), Cout, 0, Cout, st())
+    assert rc == 0
+    got = from_dev_bf16(yd, (B, H, W, Cout))
+    ref = U.conv3(x, w, bias.astype(np.float64), relu)
+    absterms = U.conv3(np.abs(x), np.abs(w)) + np.abs(bias)
+    check(got, ref, absterms, 9 * Cin + 1)
+
+
+def test_channel_slices_up2_down2_and_gradients():
+    rng = np.random.default_rng(5)
+    B, H, W, Cin, Cout = 2, 8, 16, 32, 16
+    x = U.bf16_round(rng.standard_normal((B, H, W, Cin)))
+    w = U.bf16_round(rng.standard_normal((4, Cout, Cin)) * 0.3)
+    say("[unet] up2 into a channel slice, down2, weight gradients")
+    # up2 writes channels 16..31 of a 32-channel buffer at twice the resolution
+    yd = torch.zeros(B * 2 * H * 2 * W * 32, dtype=torch.int16, device="cuda")
+    assert lib().eiku_conv_fwd(1, B, H, W, P(to_dev_bf16(x)), Cin, 0, Cin, P(to_dev_bf16(w)), None, 0, P(yd), 32, 16,
+                               Cout, st()) == 0
+    got = from_dev_bf16(yd, (B, 2 * H, 2 * W, 32))
+    ref = U.up2(x, w)
+    check(got[..., 16:], ref, U.up2(np.abs(x), np.abs(w)), Cin)
+    assert np.all(got[..., :16] == 0)
+    # down2 (data gradient of up2) from a channel slice
+    g = U.bf16_round(rng.standard_normal((B, 2 * H, 2 * W, Cout)))
+    gbuf = np.zeros((B, 2 * H, 2 * W, 32))
+    gbuf[..., 16:] = g
+    wt = U.bf16_round(w.transpose(0, 2, 1).copy())
+    dd = torch.zeros(B * H * W * Cin, dtype=torch.int16, device="cuda")
+    assert lib().eiku_conv_fwd(2, B, H, W, P(to_dev_bf16(gbuf)), 32, 16, Cout, P(to_dev_bf16(wt)), None, 0, P(dd),
+                               Cin, 0, Cin, st()) == 0
+    check(from_dev_bf16(dd, (B, H, W, Cin)), U.down2(g, wt), U.down2(np.abs(g), np.abs(wt)), 4 * Cout)
+    # weight gradient of up2
+    dw = torch.zeros(4 * Cout * Cin, dtype=torch.float32, device="cuda")
+    assert lib().eiku_conv_wgrad(1, B, H, W, P(to_dev_bf16(x)), Cin, 0, Cin, P(to_dev_bf16(gbuf)), 32, 16, Cout,
+                                 P(dw), st()) == 0
+    npix = B * H * W
+    check(dw.cpu().numpy().reshape(4, Cout, Cin), U.up2_wgrad(x, g), U.up2_wgrad(np.abs(x), np.abs(g)), npix,
+          out_bf16=False)
+    # weight gradient of conv3
+    x3 = U.bf16_round(rng.standard_normal((B, H, W, 16)))
+    g3 = U.bf16_round(rng.standard_normal((B, H, W, 32)))
+    dw3 = torch.zeros(9 * 32 * 16, dtype=torch.float32, device="cuda")
+    assert lib().eiku_conv_wgrad(0, B, H, W, P(to_dev_bf16(x3)), 16, 0, 16, P(to_dev_bf16(g3)), 32, 0, 32, P(dw3),
+                                 st()) == 0
+    check(dw3.cpu().numpy().reshape(9, 32, 16), U.conv3_wgrad(x3, g3), U.conv3_wgrad(np.abs(x3), np.abs(g3)), npix,
+          out_bf16=False)
+
+
+def test_weight_prep_mirrors_taps_for_the_data_gradient():
+    """conv3 with the prepared backward weights is the adjoint of conv3."""
+    rng = np.random.default_rng(6)
+    Cout, Cin = 32, 16
+    w32 = rng.standard_normal((9, Cout, Cin)).astype(np.float32)
+    wf = torch.zeros(9 * Cout * Cin, dtype=torch.int16, device="cuda")
+    wb = torch.zeros(9 * Cout * Cin, dtype=torch.int16, device="cuda")
+    assert lib().eiku_prep_weights(0, 9, Cout, Cin, Cin, P(torch.tensor(w32, device="cuda")), P(wf), P(wb), st()) == 0
+    wfr = from_dev_bf16(wf, (9, Cout, Cin))
+    wbr = from_dev_bf16(wb, (9, Cin, Cout))
+    assert np.array_equal(wfr, U.bf16_round(w32))
+    assert np.array_equal(wbr, wfr[::-1].transpose(0, 2, 1))
+
+
+def test_pool_head_features_and_adam():
+    rng = np.random.default_rng(7)
+    B, H, W, C = 2, 8, 8, 16
+    x = U.bf16_round(rng.standard_normal((B, 2 * H, 2 * W, C)))
+    yd = torch.zeros(B * H * W * C, dtype=torch.int16, device="cuda")
+    xd = to_dev_bf16(x)
+    assert lib().eiku_maxpool_fwd(B, H, W, P(xd), C, 0, P(yd), C, 0, C, st()) == 0
+    assert np.array_equal(from_dev_bf16(yd, (B, H, W, C)), U.maxpool(x))
+    dy = U.bf16_round(rng.standard_normal((B, H, W, C)))
+    dxd = torch.zeros(B * 2 * H * 2 * W * C, dtype=torch.int16, device="cuda")
+    assert lib().eiku_maxpool_bwd(B, H, W, P(xd), C, 0, P(to_dev_bf16(dy)), C, 0, P(dxd), C, 0, C, st()) == 0
+    assert np.array_equal(from_dev_bf16(dxd, x.shape), U.maxpool_bwd(x, dy))
+    hw = rng.standard_normal(16).astype(np.float32)
+    hb = np.array([0.5], np.float32)
+    xh = U.bf16_round(rng.standard_normal((B * H * W, 16)))
+    out = torch.zeros(B * H * W, device="cuda")
+    assert lib().eiku_head_fwd(B * H * W, P(to_dev_bf16(xh)), 16, 0, 16, P(torch.tensor(hw, device="cuda")),
+                               P(torch.tensor(hb, device="cuda")), P(out), st()) == 0
+    ref = U.head(xh, hw.astype(np.float64), 0.5)
+    assert np.allclose(out.cpu().numpy(), ref, rtol=1e-5, atol=1e-5)
+    # Adam on a quadratic: one step moves every parameter by lr against the gradient sign
+    p = torch.ones(100, device="cuda")
+    g = torch.linspace(-1, 1, 100, device="cuda")
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    gs = g.clone()
+    assert lib().eiku_adam(100, P(p), P(g), P(m), P(v), 0.01, 0.9, 0.999, 1e-8, 1, st()) == 0
+    exp = 1 - 0.01 * gs / (gs.abs() + 1e-8)
+    assert torch.allclose(p, exp, atol=1e-6) and torch.all(g == 0)
+
+
+def test_network_gradient_matches_finite_differences_of_its_loss():
+    """End to end: the backward pass of the whole network (all kernels) agrees
+    with central differences of its own forward loss on a few parameters."""
+    from paper_2603_00035_amd.unet import UNet
+    from paper_2603_00035_amd import _lib as L
+    net = UNet(seed=3)
+    B, H, W = 1, 32, 32
+    rng = np.random.default_rng(8)
+    M = torch.tensor(rng.uniform(0.5, 2, (B, 3, H, W)), dtype=torch.float32, device="cuda")
+    M[:, 1] = 0.1
+    om = torch.tensor(rng.uniform(-0.2, 0.2, (B, 2, H, W)), dtype=torch.float32, device="cuda")
+    src = torch.tensor([[5 * W + 7, -1, -1, -1]], dtype=torch.int32, device="cuda")
+    hv = torch.full((B,), 1.0 / 31, device="cuda")
+    net.features(M, om, src, hv)
+    target = torch.rand(B * H * W, device="cuda")
+
+    def loss():
+        pred = net.forward(B, H, W)
+        return float(((pred - target) ** 2).mean())
+
+    pred = net.forward(B, H, W)
+    lbuf = torch.zeros(1, device="cuda")
+    net.lib.eiku_mse(pred.numel(), P(pred), P(target), P(lbuf), P(net._bufs["g_pred"]), st())
+    net.zero_grads()
+    net.backward(B, H, W)
+    torch.cuda.synchronize()
+    for key, idx in [("head.b", 0), ("d0b.b", 3), ("bb.b", 7), ("e1a.b", 5), ("u0.b", 2)]:
+        p = net.params[key]
+        eps = 0.05
+        old = float(p.view(-1)[idx])
+        p.view(-1)[idx] = old + eps
+        net.refresh_weights()
+        lp = loss()
+        p.view(-1)[idx] = old - eps
+        net.refresh_weights()
+        lm = loss()
+        p.view(-1)[idx] = old
+        net.refresh_weights()
+        fd = (lp - lm) / (2 * eps)
+        an = float(net.grads[key].view(-1)[idx])
+        say(f"  {key}[{idx}]: analytic {an:.4e} fd {fd:.4e}")
+        assert an == pytest.approx(fd, rel=0.1, abs=2e-3 * max(1e-3, abs(fd)) + 1e-5)
