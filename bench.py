@@ -185,6 +185,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="after the steps, copy a 1 GiB buffer once (a plain copy kernel of known size that "
+                         "calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the method here runs one grid (or one batch of grids) per GPU "
@@ -281,6 +284,14 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if args.copy_calib:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = {"read": a.numel() * 4, "write": b.numel() * 4}
+        del a, b
     if not args.no_cpu_baseline:
         cb, T_ora = cpu_baseline(prob, args.tol)
         out["cpu_baseline"] = cb

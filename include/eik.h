@@ -104,7 +104,13 @@ typedef struct eik_tuning {
     int32_t fast_cold_start;  /* 1: restricted-candidate min sweeps before the full ones (cold start); default 0 */
     int32_t adjoint_rounds;   /* fixed adjoint round budget of unsynchronised batched calls; default 64 */
     int32_t level_rounds;     /* fixed level round budget of unsynchronised batched calls; default 8 */
+    int32_t scheduler;        /* EIK_SCHED_ROUNDS: one launch per round of flagged tiles, host checks between
+                                 batches of rounds; EIK_SCHED_QUEUE: one persistent launch whose waves take
+                                 flagged tiles from a device work queue (max_rounds then bounds the tile visits
+                                 to max_rounds x tiles); default EIK_SCHED_ROUNDS */
 } eik_tuning;
+
+enum { EIK_SCHED_ROUNDS = 1, EIK_SCHED_QUEUE = 2 };
 
 /* Bytes of workspace eik_forward / eik_backward need for this grid and dtype
  * (0 for an invalid grid). */

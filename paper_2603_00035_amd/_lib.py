@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libeik.so")
 EIK_F32, EIK_F64 = 0, 1
 EIK_OK, EIK_NOT_CONVERGED = 0, 1
 EIK_EINVAL, EIK_EINFEASIBLE, EIK_EDEVICE, EIK_EWORKSPACE = -1, -2, -3, -4
+EIK_SCHED_ROUNDS, EIK_SCHED_QUEUE = 1, 2
 EIK_CHECK_FEASIBLE = 1
 EIK_TIME_KERNELS = 2
 STATUS_NAMES = {0: "EIK_OK", 1: "EIK_NOT_CONVERGED", -1: "EIK_EINVAL", -2: "EIK_EINFEASIBLE",
@@ -42,7 +43,8 @@ class EikStats(ctypes.Structure):
 class EikTuning(ctypes.Structure):
     _fields_ = [("tile_height", ctypes.c_int32), ("max_local_cycles", ctypes.c_int32),
                 ("rounds_per_check", ctypes.c_int32), ("fast_cold_start", ctypes.c_int32),
-                ("adjoint_rounds", ctypes.c_int32), ("level_rounds", ctypes.c_int32)]
+                ("adjoint_rounds", ctypes.c_int32), ("level_rounds", ctypes.c_int32),
+                ("scheduler", ctypes.c_int32)]
 
 
 class EikProjectParams(ctypes.Structure):

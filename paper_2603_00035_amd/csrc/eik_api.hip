@@ -48,8 +48,19 @@ struct Extent {
 int64_t tiles_of(int nx, int ny, int th) { return (int64_t)((nx + TW - 1) / TW) * ((ny + th - 1) / th); }
 
 struct Layout {
-    size_t descs, tile_grid, act, act_count, ctr, Pt, lam, w1, list, cnt, total;
+    size_t descs, tile_grid, act, act_count, ctr, Pt, lam, w1, list, cnt, qring, qstate, qctl, total;
+    uint32_t qslots;
 };
+
+constexpr int kMaxQueueWaves = 4096;
+
+// Ring slots of the work queue: a power of two above twice (tiles + waves).
+uint32_t queue_slots(size_t n_tiles)
+{
+    uint32_t c = 1024;
+    while (c < 2 * (n_tiles + kMaxQueueWaves)) c <<= 1;
+    return c;
+}
 
 Layout layout(const Extent &e, int dtype)
 {
@@ -68,6 +79,10 @@ Layout layout(const Extent &e, int dtype)
     L.w1 = o;        o += align256((size_t)e.nodes * rs);
     L.list = o;      o += align256(list_n * 4);
     L.cnt = o;       o += align256(NT * 4);
+    L.qslots = queue_slots(NT);
+    L.qring = o;     o += align256((size_t)L.qslots * 4);
+    L.qstate = o;    o += align256(NT * 4);
+    L.qctl = o;      o += align256(kQCtlWords * 4);
     L.total = o;
     return L;
 }
@@ -131,6 +146,7 @@ struct Ws {
     int32_t *tile_grid, *act, *act_count, *list, *cnt;
     unsigned long long *ctr;
     void *Pt, *lam, *w1;
+    WorkQueue q;
 };
 
 int carve(const Extent &e, int dtype, void *ws, size_t ws_bytes, Ws &w)
@@ -149,6 +165,11 @@ int carve(const Extent &e, int dtype, void *ws, size_t ws_bytes, Ws &w)
     w.w1 = b + L.w1;
     w.list = (int32_t *)(b + L.list);
     w.cnt = (int32_t *)(b + L.cnt);
+    w.q.ring = (uint32_t *)(b + L.qring);
+    w.q.state = (uint32_t *)(b + L.qstate);
+    w.q.ctl = (uint32_t *)(b + L.qctl);
+    w.q.mask = L.qslots - 1;
+    w.q.spin_limit = 1u << 21;
     return EIK_OK;
 }
 
@@ -161,6 +182,7 @@ eik_tuning tuning_or_default(const eik_tuning *t)
     d.fast_cold_start = 0;
     d.adjoint_rounds = 64;
     d.level_rounds = 8;
+    d.scheduler = EIK_SCHED_ROUNDS;
     if (t) {
         if (t->tile_height == 32 || t->tile_height == 64) d.tile_height = t->tile_height;
         if (t->max_local_cycles >= 1) d.max_local_cycles = t->max_local_cycles;
@@ -168,6 +190,7 @@ eik_tuning tuning_or_default(const eik_tuning *t)
         if (t->fast_cold_start >= 0) d.fast_cold_start = t->fast_cold_start;
         if (t->adjoint_rounds >= 1) d.adjoint_rounds = t->adjoint_rounds;
         if (t->level_rounds >= 1) d.level_rounds = t->level_rounds;
+        if (t->scheduler == EIK_SCHED_ROUNDS || t->scheduler == EIK_SCHED_QUEUE) d.scheduler = t->scheduler;
     }
     return d;
 }
@@ -315,17 +338,42 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         // certify with the full update: every tile runs once more
         launch_all_active(a, w.act + (r0 & 1) * a.n_tiles, w.act_count + r0, st);
     }
-    rc = run_rounds(
-        w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
-        [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-            launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
-                                  tn.max_local_cycles, st);
-        },
-        &rounds, &conv, &timer);
-    if (rc) return rc;
-    r0 += rounds;
-    launch_note_pending(w.act_count + r0, w.ctr + kCtrSweepPending, st);
-    HIP_OK(hipGetLastError());
+    int launches = r0;
+    if (tn.scheduler == EIK_SCHED_QUEUE) {
+        // one persistent launch over a device queue of flagged tiles
+        const int waves = std::min({sweep_queue_waves(a.th, dtype), kMaxQueueWaves, a.n_tiles});
+        if (waves < 1) return fail(EIK_EDEVICE, "no occupancy for the work-queue sweep kernel");
+        const uint32_t budget = (uint32_t)std::min<int64_t>((int64_t)max_rounds * a.n_tiles, INT32_MAX);
+        launch_queue_setup(a, w.act + (r0 & 1) * a.n_tiles, w.q, budget, st);
+        if (timer.on) timer.before(st);
+        launch_sweep_queue<R>(a, waves, M, om, w.Pt, T, parent, level, w.q, w.ctr, tol, tn.max_local_cycles, st);
+        if (timer.on) timer.after(st);
+        launch_note_queue(w.q, w.ctr + kCtrSweepPending, st);
+        HIP_OK(hipGetLastError());
+        launches += 1;
+        if (sync) {
+            uint32_t ctl[kQCtlWords];
+            HIP_OK(hipMemcpyAsync(ctl, w.q.ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            if (timer.on) timer.collect();
+            if (ctl[kQFail]) return fail(EIK_EDEVICE, "work queue: a wait exceeded its poll limit");
+            conv = ctl[kQPending] == 0 && !ctl[kQStop];
+            r0 += (int)(((int64_t)ctl[kQVisits] + a.n_tiles - 1) / a.n_tiles);
+        }
+    } else {
+        rc = run_rounds(
+            w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
+            [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
+                launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
+                                      tn.max_local_cycles, st);
+            },
+            &rounds, &conv, &timer);
+        if (rc) return rc;
+        r0 += rounds;
+        launches = r0;
+        launch_note_pending(w.act_count + r0, w.ctr + kCtrSweepPending, st);
+        HIP_OK(hipGetLastError());
+    }
 
     // active stencils from the final field, then levels made consistent with them
     launch_parents<R>(a, M, om, T, parent, st);
@@ -360,7 +408,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         stats->cell_updates = (int64_t)ctr[kCtrCellUpdates];
         stats->n_levels = (int32_t)ctr[kCtrMaxLevel] + 1;
         stats->status = status;
-        stats->sweep_launches = r0;
+        stats->sweep_launches = launches;
         stats->sweep_ms = timer.ms;
         stats->aux_rounds = lrounds;
     }
@@ -390,15 +438,36 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
     HIP_OK(hipGetLastError());
     int rounds = 0;
     bool conv = false;
-    rc = run_rounds(
-        w.act, w.act_count, a.n_tiles, 0, sync ? kMaxRounds / 2 : tn.adjoint_rounds, tn.rounds_per_check, sync, st,
-        [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-            launch_adj_round<R>(a, parent, level, w.w1, dLdT, w.list, w.cnt, w.lam, ain, aout, cnt, st);
-        },
-        &rounds, &conv);
-    if (rc) return rc;
-    if (sync && !conv) return fail(EIK_EDEVICE, "adjoint rounds did not settle");
-    launch_note_pending(w.act_count + rounds, w.ctr + kCtrAdjPending, st);
+    if (tn.scheduler == EIK_SCHED_QUEUE) {
+        const int waves = std::min({adj_queue_waves(a.th, dtype), kMaxQueueWaves, a.n_tiles});
+        if (waves < 1) return fail(EIK_EDEVICE, "no occupancy for the work-queue adjoint kernel");
+        const int budget_rounds = sync ? kMaxRounds / 2 : tn.adjoint_rounds;
+        const uint32_t budget = (uint32_t)std::min<int64_t>((int64_t)budget_rounds * a.n_tiles, INT32_MAX);
+        launch_queue_setup(a, w.act, w.q, budget, st);
+        launch_adj_queue<R>(a, waves, parent, level, w.w1, dLdT, w.list, w.cnt, w.lam, w.q, st);
+        launch_note_queue(w.q, w.ctr + kCtrAdjPending, st);
+        HIP_OK(hipGetLastError());
+        if (sync) {
+            uint32_t ctl[kQCtlWords];
+            HIP_OK(hipMemcpyAsync(ctl, w.q.ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            if (ctl[kQFail]) return fail(EIK_EDEVICE, "work queue: a wait exceeded its poll limit");
+            conv = ctl[kQPending] == 0 && !ctl[kQStop];
+            rounds = (int)(((int64_t)ctl[kQVisits] + a.n_tiles - 1) / a.n_tiles);
+            if (!conv) return fail(EIK_EDEVICE, "adjoint visits did not settle");
+        }
+    } else {
+        rc = run_rounds(
+            w.act, w.act_count, a.n_tiles, 0, sync ? kMaxRounds / 2 : tn.adjoint_rounds, tn.rounds_per_check, sync,
+            st,
+            [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
+                launch_adj_round<R>(a, parent, level, w.w1, dLdT, w.list, w.cnt, w.lam, ain, aout, cnt, st);
+            },
+            &rounds, &conv);
+        if (rc) return rc;
+        if (sync && !conv) return fail(EIK_EDEVICE, "adjoint rounds did not settle");
+        launch_note_pending(w.act_count + rounds, w.ctr + kCtrAdjPending, st);
+    }
     launch_adj_params<R>(a, M, parent, w.w1, w.lam, dLdM, dLdom, st);
     launch_dsrc<R>(a, src_idx, w.lam, dLdsrc, st);
     HIP_OK(hipGetLastError());

@@ -19,6 +19,7 @@
 // one pass over the nodes.
 #include "eik_device.h"
 #include "eik_internal.h"
+#include "eik_queue.h"
 
 namespace eik {
 
@@ -161,29 +162,24 @@ __global__ __launch_bounds__(256) void k_adj_sort(LaunchArgs a, const int32_t *_
     if (threadIdx.x == 0) cnt[t] = s_base;
 }
 
-// One round of the tile-local level-descending gather.
+// One visit of a tile: lambda of every reached node of the tile, levels
+// deepest first, from the receivers' lambda (inside the tile, or in the halo
+// as last written back by the neighbours). Returns the halo bits of the
+// neighbours whose halo changed (OR over the wave).
 template <typename R, int TH>
-__global__ __launch_bounds__(TW) void k_adj_round(LaunchArgs a, const uint8_t *__restrict__ parall,
-                                                  const int32_t *__restrict__ levall, const R *__restrict__ w1all,
-                                                  const R *__restrict__ gall, const int32_t *__restrict__ list,
-                                                  const int32_t *__restrict__ cnt, R *__restrict__ lamall,
-                                                  int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
-                                                  int32_t *__restrict__ count_next)
+__device__ __forceinline__ int adj_visit(const LaunchArgs &a, int t, const uint8_t *__restrict__ parall,
+                                         const int32_t *__restrict__ levall, const R *__restrict__ w1all,
+                                         const R *__restrict__ gall, const int32_t *__restrict__ list,
+                                         const int32_t *__restrict__ cnt, R *lamall, R *sLam, R *sW, uint8_t *sP)
 {
     constexpr int LP = TW + 3;
-    const int t = blockIdx.x;
-    if (act_in[t] == 0) return;
     const int lane = threadIdx.x;
-    if (lane == 0) act_in[t] = 0;
     const TileGeoB g = tile_geo_b<TH>(a, t);
     const int nx = g.gd.nx, ny = g.gd.ny;
     R *lam = lamall + g.gd.off;
     const int32_t *level = levall + g.gd.off;
     const R *gT = gall + g.gd.off;
 
-    __shared__ R sLam[(TH + 2) * LP];
-    __shared__ R sW[(TH + 2) * LP];
-    __shared__ uint8_t sP[(TH + 2) * LP];
     for (int idx = lane; idx < (TH + 2) * (TW + 2); idx += TW) {
         const int r = idx / (TW + 2), c = idx - r * (TW + 2);
         const int gi = g.i0 + c - 1, gj = g.j0 + r - 1;
@@ -268,16 +264,76 @@ __global__ __launch_bounds__(TW) void k_adj_round(LaunchArgs a, const uint8_t *_
         }
     }
     for (int off = 32; off >= 1; off >>= 1) bits |= __shfl_xor(bits, off);
-    if (lane == 0) {
-        const int DX[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
-        const int DY[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+    return bits;
+}
+
+// tile index of the neighbour in halo-bit direction b, or -1 outside the grid
+__device__ __forceinline__ int adj_neighbour(const TileGeoB &g, int b)
+{
+    const int DX[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+    const int DY[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+    const int ux = g.tx + DX[b], uy = g.ty + DY[b];
+    if (ux < 0 || ux >= g.gd.ntx || uy < 0 || uy >= g.gd.nty) return -1;
+    return g.gd.tile_base + uy * g.gd.ntx + ux;
+}
+
+// One round of the tile-local level-descending gather.
+template <typename R, int TH>
+__global__ __launch_bounds__(TW) void k_adj_round(LaunchArgs a, const uint8_t *__restrict__ parall,
+                                                  const int32_t *__restrict__ levall, const R *__restrict__ w1all,
+                                                  const R *__restrict__ gall, const int32_t *__restrict__ list,
+                                                  const int32_t *__restrict__ cnt, R *__restrict__ lamall,
+                                                  int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
+                                                  int32_t *__restrict__ count_next)
+{
+    constexpr int LP = TW + 3;
+    const int t = blockIdx.x;
+    if (act_in[t] == 0) return;
+    if (threadIdx.x == 0) act_in[t] = 0;
+    __shared__ R sLam[(TH + 2) * LP];
+    __shared__ R sW[(TH + 2) * LP];
+    __shared__ uint8_t sP[(TH + 2) * LP];
+    const int bits = adj_visit<R, TH>(a, t, parall, levall, w1all, gall, list, cnt, lamall, sLam, sW, sP);
+    if (threadIdx.x == 0) {
+        const TileGeoB g = tile_geo_b<TH>(a, t);
         for (int b = 0; b < 8; ++b) {
             if (!(bits & (1 << b))) continue;
-            const int ux = g.tx + DX[b], uy = g.ty + DY[b];
-            if (ux < 0 || ux >= g.gd.ntx || uy < 0 || uy >= g.gd.nty) continue;
-            const int u = g.gd.tile_base + uy * g.gd.ntx + ux;
-            if (atomicExch(&act_out[u], 1) == 0) atomicAdd(count_next, 1);
+            const int u = adj_neighbour(g, b);
+            if (u >= 0 && atomicExch(&act_out[u], 1) == 0) atomicAdd(count_next, 1);
         }
+    }
+}
+
+// Work-queue form: one launch; waves take flagged tiles from the device
+// queue (same protocol as the forward's queue scheduler), visit them and flag
+// the neighbours whose halo changed.
+template <typename R, int TH>
+__global__ __launch_bounds__(TW) void k_adj_queue(LaunchArgs a, const uint8_t *__restrict__ parall,
+                                                  const int32_t *__restrict__ levall, const R *__restrict__ w1all,
+                                                  const R *__restrict__ gall, const int32_t *__restrict__ list,
+                                                  const int32_t *__restrict__ cnt, R *lamall, WorkQueue q)
+{
+    constexpr int LP = TW + 3;
+    __shared__ R sLam[(TH + 2) * LP];
+    __shared__ R sW[(TH + 2) * LP];
+    __shared__ uint8_t sP[(TH + 2) * LP];
+    for (;;) {
+        int t = threadIdx.x == 0 ? q_take(q) : 0;
+        t = __shfl(t, 0);
+        if (t < 0) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int bits = adj_visit<R, TH>(a, t, parall, levall, w1all, gall, list, cnt, lamall, sLam, sW, sP);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (threadIdx.x == 0) {
+            const TileGeoB g = tile_geo_b<TH>(a, t);
+            for (int b = 0; b < 8; ++b) {
+                if (!(bits & (1 << b))) continue;
+                const int u = adj_neighbour(g, b);
+                if (u >= 0) q_flag(q, u);
+            }
+            q_done(q, t, true);
+        }
+        __syncthreads(); // LDS reuse by the next visit
     }
 }
 
@@ -360,6 +416,32 @@ void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const int32_t 
 }
 
 template <typename R>
+void launch_adj_queue(const LaunchArgs &a, int n_waves, const uint8_t *parent, const int32_t *level, const void *w1,
+                      const void *dLdT, const int32_t *list, const int32_t *cnt, void *lam, const WorkQueue &q,
+                      hipStream_t st)
+{
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_queue<R, TH>), dim3(n_waves), dim3(TW), 0, st, a, parent, level,
+                                             (const R *)w1, (const R *)dLdT, list, cnt, (R *)lam, q));
+}
+
+int adj_queue_waves(int th, int dtype)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    hipError_t e;
+    if (dtype == 1)
+        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_queue<double, 64>, TW, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_queue<double, 32>, TW, 0);
+    else
+        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_queue<float, 64>, TW, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_queue<float, 32>, TW, 0);
+    if (e != hipSuccess) return 0;
+    return std::max(1, per_cu) * cus;
+}
+
+template <typename R>
 void launch_adj_params(const LaunchArgs &a, const void *M, const uint8_t *parent, const void *w1, const void *lam,
                        void *dM, void *dom, hipStream_t st)
 {
@@ -380,6 +462,9 @@ void launch_dsrc(const LaunchArgs &a, const int32_t *src_idx, const void *lam, v
     template void launch_adj_round<R>(const LaunchArgs &, const uint8_t *, const int32_t *, const void *,        \
                                       const void *, const int32_t *, const int32_t *, void *, int32_t *,         \
                                       int32_t *, int32_t *, hipStream_t);                                        \
+    template void launch_adj_queue<R>(const LaunchArgs &, int, const uint8_t *, const int32_t *, const void *,  \
+                                      const void *, const int32_t *, const int32_t *, void *, const WorkQueue &, \
+                                      hipStream_t);                                                              \
     template void launch_adj_params<R>(const LaunchArgs &, const void *, const uint8_t *, const void *,         \
                                        const void *, void *, void *, hipStream_t);                               \
     template void launch_dsrc<R>(const LaunchArgs &, const int32_t *, const void *, void *, hipStream_t);

@@ -164,10 +164,25 @@ __device__ __forceinline__ R local_update_dir(const NodeConst<R> &k, const R Tn[
     R best = inf;
     code = kUnreached;
     if (FULL) {
+        // One-point candidates first. A valid two-point value exceeds both of
+        // its donors, so a stencil whose donors are not both below the best
+        // one-point value can neither beat nor tie it and is skipped; the
+        // value and code returned are those of the canonical order (two-point
+        // wins ties with one-point, lower index wins within a kind).
+        R b1 = inf;
+        int c1 = kUnreached;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const R t = Tn[s] + k.c1[s];
+            if (Tn[s] < inf && t < b1) {
+                b1 = t;
+                c1 = 8 + s;
+            }
+        }
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const R Tp = Tn[s], Tq = Tn[(s + 1) & 7];
-            if (Tp < inf && Tq < inf) {
+            if (Tp < b1 && Tq < b1) {
                 R t, m1, m2;
                 if (two_point(k, s, Tp, Tq, t, m1, m2) && t < best) {
                     best = t;
@@ -175,13 +190,9 @@ __device__ __forceinline__ R local_update_dir(const NodeConst<R> &k, const R Tn[
                 }
             }
         }
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const R t = Tn[s] + k.c1[s];
-            if (Tn[s] < inf && t < best) {
-                best = t;
-                code = 8 + s;
-            }
+        if (!(best <= b1)) {
+            best = b1;
+            code = c1;
         }
     } else {
 #pragma unroll

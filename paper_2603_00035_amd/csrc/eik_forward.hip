@@ -25,6 +25,7 @@
 // along with T, so the level field is settled when T is.
 #include "eik_device.h"
 #include "eik_internal.h"
+#include "eik_queue.h"
 
 namespace eik {
 
@@ -272,22 +273,25 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// One round of tile sweeps.
+// One visit of a tile: load T, levels and codes with a one-node halo, run
+// four-sweep cycles until a full cycle changes nothing (or the cycle budget
+// runs out), write back. Returns the halo bits of the neighbours that must see
+// the new boundary values (OR over the wave) and whether the tile settled.
 // ---------------------------------------------------------------------------
+struct Visit {
+    int bits;
+    bool settled;
+    int sweeps;
+};
+
 template <typename R, int TH, bool FULL>
-__global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
-                                                    const R *__restrict__ Ptall, R *__restrict__ Tall,
-                                                    uint8_t *__restrict__ codeall, int32_t *__restrict__ levall,
-                                                    int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
-                                                    int32_t *__restrict__ count_next,
-                                                    unsigned long long *__restrict__ ctr, R tol, int max_cycles)
+__device__ __forceinline__ Visit visit_tile(const LaunchArgs &a, int t, const R *__restrict__ M,
+                                            const R *__restrict__ om, const R *__restrict__ Ptall, R *Tall,
+                                            uint8_t *codeall, int32_t *levall, R tol, int max_cycles, R *sT,
+                                            int32_t *sL, uint8_t *sC)
 {
     constexpr int LP = TW + 3; // odd pitch: conflict-free column access
-    const int t = blockIdx.x;
-    if (act_in[t] == 0) return;
     const int lane = threadIdx.x;
-    if (lane == 0) act_in[t] = 0;
-
     const TileGeo g = tile_geo<TH>(a, t);
     R *T = Tall + g.gd.off;
     uint8_t *code = codeall + g.gd.off;
@@ -297,9 +301,6 @@ __global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__res
     const R *Pt = Ptall + 5 * g.gd.off, *Pto = Pt + 3 * n;   // column-major copy
     const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
 
-    __shared__ R sT[(TH + 2) * LP];
-    __shared__ int32_t sL[(TH + 2) * LP];
-    __shared__ uint8_t sC[TH * TW];
     load_tile_halo<R, TH, LP>(T, sT, g, inf_v<R>());
     load_tile_halo<int32_t, TH, LP>(level, sL, g, -1);
     for (int idx = lane; idx < TH * TW; idx += TW) {
@@ -322,7 +323,6 @@ __global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__res
         quiet = __ballot(ch) ? 0 : quiet + 1;
     }
 
-    // write back; flag neighbours whose halo moved
     int bits = 0;
     for (int idx = lane; idx < TH * TW; idx += TW) {
         const int r = idx / TW, c = idx - r * TW;
@@ -338,12 +338,113 @@ __global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__res
         code[gc] = sC[idx];
         if (counts_as_change<R>(ov, nv, tol)) bits |= halo_bits(c, r, g.w, g.h);
     }
-    bits = wave_or(bits);
-    if (lane == 0) {
-        flag_neighbours(bits, g, act_out, count_next);
-        if (quiet < 4) flag_tile(act_out, count_next, t); // cycle budget ran out before the tile settled
-        atomicAdd(&ctr[kCtrCellUpdates], (unsigned long long)sweeps * (unsigned long long)(g.w * g.h));
+    Visit v;
+    v.bits = wave_or(bits);
+    v.settled = quiet >= 4;
+    v.sweeps = sweeps * g.w * g.h;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Round scheduler: one launch per round over the flagged tiles.
+// ---------------------------------------------------------------------------
+template <typename R, int TH, bool FULL>
+__global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
+                                                    const R *__restrict__ Ptall, R *__restrict__ Tall,
+                                                    uint8_t *__restrict__ codeall, int32_t *__restrict__ levall,
+                                                    int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
+                                                    int32_t *__restrict__ count_next,
+                                                    unsigned long long *__restrict__ ctr, R tol, int max_cycles)
+{
+    constexpr int LP = TW + 3;
+    const int t = blockIdx.x;
+    if (act_in[t] == 0) return;
+    if (threadIdx.x == 0) act_in[t] = 0;
+    __shared__ R sT[(TH + 2) * LP];
+    __shared__ int32_t sL[(TH + 2) * LP];
+    __shared__ uint8_t sC[TH * TW];
+    const Visit v = visit_tile<R, TH, FULL>(a, t, M, om, Ptall, Tall, codeall, levall, tol, max_cycles, sT, sL, sC);
+    if (threadIdx.x == 0) {
+        const TileGeo g = tile_geo<TH>(a, t);
+        flag_neighbours(v.bits, g, act_out, count_next);
+        if (!v.settled) flag_tile(act_out, count_next, t); // cycle budget ran out before the tile settled
+        atomicAdd(&ctr[kCtrCellUpdates], (unsigned long long)v.sweeps);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Work-queue scheduler: one launch; each wave takes flagged tiles from a
+// device queue, visits them, and puts the neighbours whose halo changed back
+// on the queue. A tile is never visited by two waves at once: its state goes
+// idle -> queued -> running -> idle, and a tile flagged while running is
+// marked and queued again when its visit ends. Information then crosses tile
+// boundaries as soon as the neighbour is visited, with no round barrier.
+//
+// Termination: every wait polls a bounded number of times. A wave leaves when
+// no tile is queued or running (nothing can be flagged any more), when the
+// visit budget is spent, or when a wait exceeds its limit (reported as an
+// error); the visits themselves are bounded by the cycle budget, so every
+// wave reaches the exit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void q_flag_neighbours(const WorkQueue &q, int bits, const TileGeo &g)
+{
+    const int DX[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+    const int DY[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+    for (int b = 0; b < 8; ++b) {
+        if (!(bits & (1 << b))) continue;
+        const int ux = g.tx + DX[b], uy = g.ty + DY[b];
+        if (ux < 0 || ux >= g.gd.ntx || uy < 0 || uy >= g.gd.nty) continue;
+        q_flag(q, g.gd.tile_base + uy * g.gd.ntx + ux);
+    }
+}
+
+template <typename R, int TH>
+__global__ __launch_bounds__(TW) void k_sweep_queue(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
+                                                    const R *__restrict__ Ptall, R *Tall, uint8_t *codeall,
+                                                    int32_t *levall, WorkQueue q, unsigned long long *__restrict__ ctr,
+                                                    R tol, int max_cycles)
+{
+    constexpr int LP = TW + 3;
+    __shared__ R sT[(TH + 2) * LP];
+    __shared__ int32_t sL[(TH + 2) * LP];
+    __shared__ uint8_t sC[TH * TW];
+    unsigned long long updates = 0;
+    for (;;) {
+        int t = threadIdx.x == 0 ? q_take(q) : 0;
+        t = __shfl(t, 0);
+        if (t < 0) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); // the neighbours' written-back values
+        const Visit v =
+            visit_tile<R, TH, true>(a, t, M, om, Ptall, Tall, codeall, levall, tol, max_cycles, sT, sL, sC);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // this tile's values before its flags
+        updates += (unsigned long long)v.sweeps;
+        if (threadIdx.x == 0) {
+            q_flag_neighbours(q, v.bits, tile_geo<TH>(a, t));
+            q_done(q, t, v.settled);
+        }
+        __syncthreads(); // LDS reuse by the next visit
+    }
+    if (threadIdx.x == 0 && updates) atomicAdd(&ctr[kCtrCellUpdates], updates);
+}
+
+// Queue set-up from the flags of round 0 (sources, or every tile for a warm
+// start): flagged tiles are queued and their flags cleared.
+__global__ void k_queue_seed(int n_tiles, int32_t *__restrict__ act, WorkQueue q)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles || act[t] == 0) return;
+    act[t] = 0;
+    q.state[t] = kTileQueued;
+    atomicAdd(&q.ctl[kQPending], 1u);
+    const uint32_t pos = atomicAdd(&q.ctl[kQTail], 1u);
+    q.ring[pos & q.mask] = (uint32_t)(t + 1);
+}
+
+// Control words: cleared, with the visit budget set.
+__global__ void k_queue_reset(WorkQueue q, uint32_t budget)
+{
+    const int i = threadIdx.x;
+    if (i < kQCtlWords) q.ctl[i] = i == kQBudget ? budget : 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -553,6 +654,41 @@ void launch_sweep_round(const LaunchArgs &a, int mode, const void *M, const void
                                                  act_in, act_out, count_next, ctr, R(tol), max_cycles));
 }
 
+void launch_queue_setup(const LaunchArgs &a, int32_t *act, const WorkQueue &q, uint32_t budget, hipStream_t st)
+{
+    launch_fill_i32((int32_t *)q.ring, (int64_t)q.mask + 1, 0, st);
+    launch_fill_i32((int32_t *)q.state, a.n_tiles, kTileIdle, st);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, q, budget);
+    hipLaunchKernelGGL(k_queue_seed, dim3((a.n_tiles + 255) / 256), dim3(256), 0, st, a.n_tiles, act, q);
+}
+
+template <typename R>
+void launch_sweep_queue(const LaunchArgs &a, int n_waves, const void *M, const void *om, const void *Pt, void *T,
+                        uint8_t *code, int32_t *level, const WorkQueue &q, unsigned long long *ctr, double tol,
+                        int max_cycles, hipStream_t st)
+{
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_queue<R, TH>), dim3(n_waves), dim3(TW), 0, st, a,
+                                             (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level, q,
+                                             ctr, R(tol), max_cycles));
+}
+
+int sweep_queue_waves(int th, int dtype)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    hipError_t e;
+    if (dtype == 1)
+        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_queue<double, 64>, TW, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_queue<double, 32>, TW, 0);
+    else
+        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_queue<float, 64>, TW, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_queue<float, 32>, TW, 0);
+    if (e != hipSuccess) return 0;
+    return std::max(1, per_cu) * cus;
+}
+
 template <typename R>
 void launch_parents(const LaunchArgs &a, const void *M, const void *om, const void *T, uint8_t *parent,
                     hipStream_t st)
@@ -598,6 +734,9 @@ void launch_check_feasible(int64_t n, const void *M, const void *om, unsigned lo
     template void launch_sweep_round<R>(const LaunchArgs &, int, const void *, const void *, const void *,       \
                                         void *, uint8_t *, int32_t *, int32_t *, int32_t *, int32_t *,           \
                                         unsigned long long *, double, int, hipStream_t);                         \
+    template void launch_sweep_queue<R>(const LaunchArgs &, int, const void *, const void *, const void *,       \
+                                        void *, uint8_t *, int32_t *, const WorkQueue &, unsigned long long *,   \
+                                        double, int, hipStream_t);                                               \
     template void launch_parents<R>(const LaunchArgs &, const void *, const void *, const void *, uint8_t *,     \
                                     hipStream_t);                                                                \
     template void launch_check_feasible<R>(int64_t, const void *, const void *, unsigned long long *, hipStream_t);
@@ -617,6 +756,19 @@ __global__ void k_note_pending(const int32_t *__restrict__ count, unsigned long 
 void launch_note_pending(const int32_t *count, unsigned long long *slot, hipStream_t st)
 {
     hipLaunchKernelGGL(k_note_pending, dim3(1), dim3(64), 0, st, count, slot);
+}
+
+// tiles still queued or running after the queue kernel (plus 2^32 on a failed wait)
+__global__ void k_note_queue(WorkQueue q, unsigned long long *__restrict__ slot)
+{
+    if (threadIdx.x == 0)
+        *slot = (unsigned long long)q.ctl[kQPending] + (q.ctl[kQFail] ? (1ull << 32) : 0ull) +
+                (q.ctl[kQStop] && !q.ctl[kQPending] ? 1ull : 0ull);
+}
+
+void launch_note_queue(const WorkQueue &q, unsigned long long *slot, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_note_queue, dim3(1), dim3(64), 0, st, q, slot);
 }
 
 } // namespace eik

@@ -42,6 +42,18 @@ enum {
     kCtrCount = 16
 };
 
+// Device work queue of the queue scheduler (workspace memory, reset by
+// kernels before each use).
+enum { kTileIdle = 0, kTileQueued = 1, kTileRunning = 2, kTileAgain = 3 };
+enum { kQHead = 0, kQTail = 1, kQPending = 2, kQStop = 3, kQFail = 4, kQBudget = 5, kQVisits = 6, kQCtlWords = 8 };
+struct WorkQueue {
+    uint32_t *ring;      // mask + 1 slots: tile + 1, or 0 when empty
+    uint32_t *state;     // per tile: kTile*
+    uint32_t *ctl;       // kQCtlWords control words
+    uint32_t mask;       // slots - 1 (a power of two minus one)
+    uint32_t spin_limit; // polls before a wait is declared stuck
+};
+
 constexpr int kMaxRounds = 1 << 16;
 constexpr int kSortChunk = 4096;
 
@@ -49,6 +61,7 @@ enum SweepMode { kModeFast = 0, kModeFull = 1 };
 
 // copies the flagged-tile count of the last round into a counter slot
 void launch_note_pending(const int32_t *count, unsigned long long *slot, hipStream_t st);
+void launch_note_queue(const WorkQueue &q, unsigned long long *slot, hipStream_t st);
 
 // forward
 template <typename R>
@@ -67,6 +80,14 @@ void launch_parents(const LaunchArgs &a, const void *M, const void *om, const vo
 template <typename R>
 void launch_check_feasible(int64_t n, const void *M, const void *om, unsigned long long *ctr, hipStream_t st);
 void launch_all_active(const LaunchArgs &a, int32_t *act, int32_t *act_count, hipStream_t st);
+// queue scheduler: reset + seed from the round-0 flags, then one persistent launch
+void launch_queue_setup(const LaunchArgs &a, int32_t *act, const WorkQueue &q, uint32_t budget, hipStream_t st);
+template <typename R>
+void launch_sweep_queue(const LaunchArgs &a, int n_waves, const void *M, const void *om, const void *Pt, void *T,
+                        uint8_t *code, int32_t *level, const WorkQueue &q, unsigned long long *ctr, double tol,
+                        int max_cycles, hipStream_t st);
+// waves of the queue kernel that fit on the device at once
+int sweep_queue_waves(int th, int dtype);
 void launch_level_round(const LaunchArgs &a, const uint8_t *parent, int32_t *level, int32_t *act_in,
                         int32_t *act_out, int32_t *count_next, int max_cycles, hipStream_t st);
 void launch_max_level(int64_t n, const int32_t *level, unsigned long long *ctr, hipStream_t st);
@@ -83,6 +104,11 @@ template <typename R>
 void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const int32_t *level, const void *w1,
                       const void *dLdT, const int32_t *list, const int32_t *cnt, void *lam, int32_t *act_in,
                       int32_t *act_out, int32_t *count_next, hipStream_t st);
+template <typename R>
+void launch_adj_queue(const LaunchArgs &a, int n_waves, const uint8_t *parent, const int32_t *level, const void *w1,
+                      const void *dLdT, const int32_t *list, const int32_t *cnt, void *lam, const WorkQueue &q,
+                      hipStream_t st);
+int adj_queue_waves(int th, int dtype);
 template <typename R>
 void launch_adj_params(const LaunchArgs &a, const void *M, const uint8_t *parent, const void *w1, const void *lam,
                        void *dM, void *dom, hipStream_t st);

@@ -57,10 +57,11 @@ def workspace(grid: L.EikGrid, dtype_code: int, device) -> torch.Tensor:
 
 
 def tuning(tile_height=0, max_local_cycles=0, rounds_per_check=0, fast_cold_start=-1, adjoint_rounds=0,
-           level_rounds=0):
-    """Scheduling knobs (0 / -1 keep the library default)."""
+           level_rounds=0, scheduler=0):
+    """Scheduling knobs (0 / -1 keep the library default). scheduler: 1 rounds,
+    2 device work queue."""
     return L.EikTuning(tile_height, max_local_cycles, rounds_per_check, fast_cold_start, adjoint_rounds,
-                       level_rounds)
+                       level_rounds, scheduler)
 
 
 def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=4096, check_feasible=False,

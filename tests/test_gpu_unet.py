@@ -28,8 +28,26 @@ def st():
     return L.stream_handle(torch.device("cuda"))
 
 
+_KEEP = []  # device inputs stay referenced until the test ends (a temporary's memory could be reused)
+
+
 def to_dev_bf16(x):
-    return torch.tensor(U.bf16_bits(x).view(np.int16), device="cuda")
+    t = torch.tensor(U.bf16_bits(x).view(np.int16), device="cuda")
+    _KEEP.append(t)
+    return t
+
+
+def to_dev(x):
+    t = torch.tensor(x, device="cuda")
+    _KEEP.append(t)
+    return t
+
+
+@pytest.fixture(autouse=True)
+def _release_inputs():
+    yield
+    torch.cuda.synchronize()
+    _KEEP.clear()
 
 
 def from_dev_bf16(t, shape):
@@ -108,7 +126,7 @@ def test_weight_prep_mirrors_taps_for_the_data_gradient():
     w32 = rng.standard_normal((9, Cout, Cin)).astype(np.float32)
     wf = torch.zeros(9 * Cout * Cin, dtype=torch.int16, device="cuda")
     wb = torch.zeros(9 * Cout * Cin, dtype=torch.int16, device="cuda")
-    assert lib().eiku_prep_weights(0, 9, Cout, Cin, Cin, P(torch.tensor(w32, device="cuda")), P(wf), P(wb), st()) == 0
+    assert lib().eiku_prep_weights(0, 9, Cout, Cin, Cin, P(to_dev(w32)), P(wf), P(wb), st()) == 0
     wfr = from_dev_bf16(wf, (9, Cout, Cin))
     wbr = from_dev_bf16(wb, (9, Cin, Cout))
     assert np.array_equal(wfr, U.bf16_round(w32))
@@ -131,8 +149,8 @@ def test_pool_head_features_and_adam():
     hb = np.array([0.5], np.float32)
     xh = U.bf16_round(rng.standard_normal((B * H * W, 16)))
     out = torch.zeros(B * H * W, device="cuda")
-    assert lib().eiku_head_fwd(B * H * W, P(to_dev_bf16(xh)), 16, 0, 16, P(torch.tensor(hw, device="cuda")),
-                               P(torch.tensor(hb, device="cuda")), P(out), st()) == 0
+    assert lib().eiku_head_fwd(B * H * W, P(to_dev_bf16(xh)), 16, 0, 16, P(to_dev(hw)),
+                               P(to_dev(hb)), P(out), st()) == 0
     ref = U.head(xh, hw.astype(np.float64), 0.5)
     assert np.allclose(out.cpu().numpy(), ref, rtol=1e-5, atol=1e-5)
     # Adam on a quadratic: one step moves every parameter by lr against the gradient sign
