@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"f32": 28, "f64": 56}  # 5 parameters + T read + T write
-KERNEL_SOURCES = ["paper_2603_00035_amd/csrc/eik_forward.hip", "paper_2603_00035_amd/csrc/eik_device.h"]
+KERNEL_SOURCES = ["paper_2603_00035_amd/csrc/eik_forward.hip", "paper_2603_00035_amd/csrc/eik_device.h",
+                  "paper_2603_00035_amd/csrc/eik_tile.h", "paper_2603_00035_amd/csrc/eik_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c3_traffic.json")
 
 WORKLOADS = {
@@ -213,7 +214,7 @@ def main():
     src = torch.tensor(prob.src_idx, dtype=torch.int32, device=dev)
     Mt = torch.tensor(tgt.M, dtype=dt, device=dev)
     omt = torch.tensor(tgt.omega, dtype=dt, device=dev)
-    target, _, _, _ = E.solve(Mt, omt, src, prob.h, tol=args.tol)
+    target, _, _, _ = E.solve(Mt, omt, src, prob.h, tol=args.tol, levels=False)
     mask = torch.isfinite(target)
     mask.view(-1)[src.long()] = False
     n_obs = int(mask.sum())
@@ -295,11 +296,15 @@ def main():
     if not args.no_cpu_baseline:
         cb, T_ora = cpu_baseline(prob, args.tol)
         out["cpu_baseline"] = cb
-        T_gpu, _, _, _ = E.solve(M0, om0, src, prob.h, tol=args.tol)
+        # parity of the timed GPU solve against the oracle's exact fixed point
+        # (the oracle's tol run continued to stationarity, outside the timing)
+        import oracle
+        T_fix, _, _ = oracle.forward(prob.rounded(np.float32), tol=0.0, T_init=T_ora)
+        T_gpu, _, _, _ = E.solve(M0, om0, src, prob.h, tol=args.tol, levels=False)
         Tg = T_gpu.double().cpu().numpy()
-        m = np.isfinite(T_ora)
+        m = np.isfinite(T_fix)
         m.flat[prob.src_idx] = False
-        out["parity_fwd_max_rel_vs_oracle"] = float(np.max(np.abs(Tg[m] - T_ora[m]) / np.abs(T_ora[m])))
+        out["parity_fwd_max_rel_vs_oracle"] = float(np.max(np.abs(Tg[m] - T_fix[m]) / np.abs(T_fix[m])))
     print(json.dumps(out), flush=True)
 
 

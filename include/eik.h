@@ -26,7 +26,9 @@
  *                       (dx,dy)_k = (-1,1) (-1,0) (-1,-1) (0,-1) (1,-1) (1,0) (1,1) (0,1)
  *                       (counter-clockwise from the upper-left neighbour);
  *   level  [ny][nx]     int32 dependency level: 0 at sources, 1 + the largest
- *                       level of the donors elsewhere, -1 where unreached.
+ *                       level of the donors elsewhere, -1 where unreached
+ *                       (optional output of the forward; the adjoint does not
+ *                       need it).
  * Real arrays are float (EIK_F32) or double (EIK_F64) as the dtype argument says.
  * Batched calls pack the grids one after the other: the node arrays of grid g
  * start at node offset off_g = sum over earlier grids of nx*ny, its M planes at
@@ -89,7 +91,7 @@ typedef struct eik_stats {
     int32_t rounds;         /* tile-sweep rounds (forward) or adjoint rounds (backward) */
     int32_t converged;      /* 1 when no node changed by more than tol */
     int64_t cell_updates;   /* local-update evaluations (one per node per sweep) */
-    int32_t n_levels;       /* largest level + 1 */
+    int32_t n_levels;       /* largest level + 1 (0 when levels were not asked for) */
     int32_t status;         /* same as the return value */
     int32_t sweep_launches; /* launches of the tile-sweep kernel */
     int32_t aux_rounds;     /* level rounds (forward) / adjoint rounds (backward) */
@@ -99,7 +101,7 @@ typedef struct eik_stats {
 /* Scheduling knobs; NULL or a field <= 0 keeps the library default. */
 typedef struct eik_tuning {
     int32_t tile_height;      /* 32 or 64 (tiles are 64 nodes wide); default 64 */
-    int32_t max_local_cycles; /* four-sweep cycles a tile may run per round; default 2 */
+    int32_t max_local_cycles; /* four-sweep cycles a tile may run per visit; default 1 */
     int32_t rounds_per_check; /* rounds enqueued between host convergence checks; default 8 */
     int32_t fast_cold_start;  /* 1: restricted-candidate min sweeps before the full ones (cold start); default 0 */
     int32_t adjoint_rounds;   /* fixed adjoint round budget of unsynchronised batched calls; default 64 */
@@ -108,6 +110,10 @@ typedef struct eik_tuning {
                                  batches of rounds; EIK_SCHED_QUEUE: one persistent launch whose waves take
                                  flagged tiles from a device work queue (max_rounds then bounds the tile visits
                                  to max_rounds x tiles); default EIK_SCHED_ROUNDS */
+    int32_t node_lanes;       /* lanes that share one node's update in the round scheduler's sweeps when no
+                                 levels are asked for: 1, 2 or 4 (a tile then runs on that many waves);
+                                 default 4 */
+    int32_t adjoint_cycles;   /* four-sweep cycles a tile may run per adjoint visit; default 1 */
 } eik_tuning;
 
 enum { EIK_SCHED_ROUNDS = 1, EIK_SCHED_QUEUE = 2 };
@@ -126,7 +132,9 @@ size_t eik_workspace_bytes(const eik_grid *grid, int32_t dtype);
  *             four-direction cycle leaves no node changed. tol = 0 asks for
  *             exact stationarity;
  *   max_rounds bound on tile-sweep rounds per phase (EIK_NOT_CONVERGED past it);
- *   T, parent, level outputs; ws/ws_bytes workspace; tuning and stats optional.
+ *   T, parent outputs; level optional output (NULL: not computed, which
+ *             saves the level rounds); ws/ws_bytes workspace; tuning and
+ *             stats optional.
  * The call synchronises the stream between batches of rounds to test for
  * convergence. Out-of-range source indices are ignored on the device and
  * reported as EIK_EINVAL.
@@ -137,13 +145,15 @@ int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *
                 void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
 
 /* Adjoint (Sec. 3.3, Alg. backward): given dL/dT and the saved state
- * (M, omega, T, parent, level) of eik_forward, writes dL/dM [3][ny][nx]
+ * (M, omega, T, parent) of eik_forward, writes dL/dM [3][ny][nx]
  * (derivatives with respect to the stored m11, m12, m22), dL/domega
- * [2][ny][nx] and dL/dt_src [n_src]. Nodes are processed by decreasing level;
- * each node gathers from the nodes it feeds (no atomics). Unreached nodes and
- * the parameters of source nodes get zero gradient. Tiles exchange their
- * border adjoints between rounds (the call synchronises the stream to test
- * that no border changed); stats, when given, receives the round count. */
+ * [2][ny][nx] and dL/dt_src [n_src]. Each tile relaxes the triangular
+ * adjoint equations with directional line sweeps until they hold exactly;
+ * each node gathers from the nodes it feeds (no atomics). Unreached nodes and the
+ * parameters of source nodes get zero gradient. Tiles exchange their border
+ * adjoints between rounds (the call synchronises the stream to test that no
+ * border changed); stats, when given, receives the round count. `level` is
+ * not read and may be NULL. */
 int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
                  const uint8_t *parent, const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega,
                  void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats,

@@ -44,7 +44,8 @@ class EikTuning(ctypes.Structure):
     _fields_ = [("tile_height", ctypes.c_int32), ("max_local_cycles", ctypes.c_int32),
                 ("rounds_per_check", ctypes.c_int32), ("fast_cold_start", ctypes.c_int32),
                 ("adjoint_rounds", ctypes.c_int32), ("level_rounds", ctypes.c_int32),
-                ("scheduler", ctypes.c_int32)]
+                ("scheduler", ctypes.c_int32), ("node_lanes", ctypes.c_int32),
+                ("adjoint_cycles", ctypes.c_int32)]
 
 
 class EikProjectParams(ctypes.Structure):

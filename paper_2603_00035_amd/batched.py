@@ -68,15 +68,17 @@ class Batch:
                 for g in range(self.n_grids)]
 
     # -- calls ------------------------------------------------------------
-    def alloc_forward(self):
+    def alloc_forward(self, levels=False):
         T = torch.empty(self.n_nodes, dtype=self.dtype, device=self.device)
         parent = torch.empty(self.n_nodes, dtype=torch.uint8, device=self.device)
-        level = torch.empty(self.n_nodes, dtype=torch.int32, device=self.device)
+        level = torch.empty(self.n_nodes, dtype=torch.int32, device=self.device) if levels else None
         return T, parent, level
 
     def forward(self, M, om, src_idx, src_t=None, T_init=None, tol=1e-5, out=None, sync=True,
-                time_kernels=False):
-        T, parent, level = out if out is not None else self.alloc_forward()
+                time_kernels=False, levels=False):
+        """Returns (T, parent, level, Stats); level is None unless ``levels``
+        (or an ``out`` triple with a level tensor) asks for it."""
+        T, parent, level = out if out is not None else self.alloc_forward(levels)
         st = L.EikStats() if sync else None
         flags = L.EIK_TIME_KERNELS if (time_kernels and sync) else 0
         rc = L.lib().eik_forward_batched(self.n_grids, self.grids, self.dc, L.ptr(src_idx), L.ptr(src_t),

@@ -48,7 +48,7 @@ struct Extent {
 int64_t tiles_of(int nx, int ny, int th) { return (int64_t)((nx + TW - 1) / TW) * ((ny + th - 1) / th); }
 
 struct Layout {
-    size_t descs, tile_grid, act, act_count, ctr, Pt, lam, w1, list, cnt, qring, qstate, qctl, total;
+    size_t descs, tile_grid, act, act_count, ctr, Pt, lam, w1, qring, qstate, qctl, total;
     uint32_t qslots;
 };
 
@@ -66,7 +66,6 @@ Layout layout(const Extent &e, int dtype)
 {
     const size_t rs = dtype == EIK_F64 ? 8 : 4;
     const size_t NT = (size_t)std::max(e.tiles32, e.tiles64);
-    const size_t list_n = std::max((size_t)e.tiles64 * TW * 64, (size_t)e.tiles32 * TW * 32);
     Layout L;
     size_t o = 0;
     L.descs = o;     o += align256((size_t)e.n_grids * sizeof(GridDesc));
@@ -77,8 +76,7 @@ Layout layout(const Extent &e, int dtype)
     L.Pt = o;        o += align256(5 * (size_t)e.nodes * rs);
     L.lam = o;       o += align256((size_t)e.nodes * rs);
     L.w1 = o;        o += align256((size_t)e.nodes * rs);
-    L.list = o;      o += align256(list_n * 4);
-    L.cnt = o;       o += align256(NT * 4);
+
     L.qslots = queue_slots(NT);
     L.qring = o;     o += align256((size_t)L.qslots * 4);
     L.qstate = o;    o += align256(NT * 4);
@@ -143,7 +141,7 @@ void host_descs(int n_grids, const eik_grid *grids, int th, std::vector<GridDesc
 
 struct Ws {
     GridDesc *descs;
-    int32_t *tile_grid, *act, *act_count, *list, *cnt;
+    int32_t *tile_grid, *act, *act_count;
     unsigned long long *ctr;
     void *Pt, *lam, *w1;
     WorkQueue q;
@@ -163,8 +161,7 @@ int carve(const Extent &e, int dtype, void *ws, size_t ws_bytes, Ws &w)
     w.Pt = b + L.Pt;
     w.lam = b + L.lam;
     w.w1 = b + L.w1;
-    w.list = (int32_t *)(b + L.list);
-    w.cnt = (int32_t *)(b + L.cnt);
+
     w.q.ring = (uint32_t *)(b + L.qring);
     w.q.state = (uint32_t *)(b + L.qstate);
     w.q.ctl = (uint32_t *)(b + L.qctl);
@@ -177,12 +174,14 @@ eik_tuning tuning_or_default(const eik_tuning *t)
 {
     eik_tuning d;
     d.tile_height = kDefaultTH;
-    d.max_local_cycles = 2;
+    d.max_local_cycles = 1;
     d.rounds_per_check = 8;
     d.fast_cold_start = 0;
     d.adjoint_rounds = 64;
     d.level_rounds = 8;
     d.scheduler = EIK_SCHED_ROUNDS;
+    d.node_lanes = 4;
+    d.adjoint_cycles = 1;
     if (t) {
         if (t->tile_height == 32 || t->tile_height == 64) d.tile_height = t->tile_height;
         if (t->max_local_cycles >= 1) d.max_local_cycles = t->max_local_cycles;
@@ -191,6 +190,8 @@ eik_tuning tuning_or_default(const eik_tuning *t)
         if (t->adjoint_rounds >= 1) d.adjoint_rounds = t->adjoint_rounds;
         if (t->level_rounds >= 1) d.level_rounds = t->level_rounds;
         if (t->scheduler == EIK_SCHED_ROUNDS || t->scheduler == EIK_SCHED_QUEUE) d.scheduler = t->scheduler;
+        if (t->node_lanes == 1 || t->node_lanes == 2 || t->node_lanes == 4) d.node_lanes = t->node_lanes;
+        if (t->adjoint_cycles >= 1) d.adjoint_cycles = t->adjoint_cycles;
     }
     return d;
 }
@@ -330,7 +331,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
             w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
                 launch_sweep_round<R>(a, kModeFast, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
-                                      tn.max_local_cycles, st);
+                                      tn.max_local_cycles, 1, st);
             },
             &rounds, &conv, &timer);
         if (rc) return rc;
@@ -341,7 +342,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     int launches = r0;
     if (tn.scheduler == EIK_SCHED_QUEUE) {
         // one persistent launch over a device queue of flagged tiles
-        const int waves = std::min({sweep_queue_waves(a.th, dtype), kMaxQueueWaves, a.n_tiles});
+        const int waves = std::min({sweep_queue_waves(a.th, dtype, level != nullptr), kMaxQueueWaves, a.n_tiles});
         if (waves < 1) return fail(EIK_EDEVICE, "no occupancy for the work-queue sweep kernel");
         const uint32_t budget = (uint32_t)std::min<int64_t>((int64_t)max_rounds * a.n_tiles, INT32_MAX);
         launch_queue_setup(a, w.act + (r0 & 1) * a.n_tiles, w.q, budget, st);
@@ -365,7 +366,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
             w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
                 launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
-                                      tn.max_local_cycles, st);
+                                      tn.max_local_cycles, tn.node_lanes, st);
             },
             &rounds, &conv, &timer);
         if (rc) return rc;
@@ -375,24 +376,27 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         HIP_OK(hipGetLastError());
     }
 
-    // active stencils from the final field, then levels made consistent with them
+    // active stencils from the final field, then (when asked for) levels made
+    // consistent with them
     launch_parents<R>(a, M, om, T, parent, st);
-    launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
-    launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
-    launch_all_active(a, w.act, w.act_count, st);
     int lrounds = 0;
-    bool lconv = false;
-    const int level_budget = sync ? kMaxRounds / 2 : tn.level_rounds;
-    rc = run_rounds(
-        w.act, w.act_count, a.n_tiles, 0, level_budget, tn.rounds_per_check, sync, st,
-        [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-            launch_level_round(a, parent, level, ain, aout, cnt, tn.max_local_cycles, st);
-        },
-        &lrounds, &lconv);
-    if (rc) return rc;
-    if (sync && !lconv) return fail(EIK_EDEVICE, "dependency levels did not settle");
-    launch_note_pending(w.act_count + lrounds, w.ctr + kCtrLevelPending, st);
-    launch_max_level(e.nodes, level, w.ctr, st);
+    if (level) {
+        launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
+        launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
+        launch_all_active(a, w.act, w.act_count, st);
+        bool lconv = false;
+        const int level_budget = sync ? kMaxRounds / 2 : tn.level_rounds;
+        rc = run_rounds(
+            w.act, w.act_count, a.n_tiles, 0, level_budget, tn.rounds_per_check, sync, st,
+            [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
+                launch_level_round(a, parent, level, ain, aout, cnt, tn.max_local_cycles, st);
+            },
+            &lrounds, &lconv);
+        if (rc) return rc;
+        if (sync && !lconv) return fail(EIK_EDEVICE, "dependency levels did not settle");
+        launch_note_pending(w.act_count + lrounds, w.ctr + kCtrLevelPending, st);
+        launch_max_level(e.nodes, level, w.ctr, st);
+    }
     HIP_OK(hipGetLastError());
     if (!sync) return EIK_OK;
 
@@ -406,7 +410,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         stats->rounds = r0;
         stats->converged = conv ? 1 : 0;
         stats->cell_updates = (int64_t)ctr[kCtrCellUpdates];
-        stats->n_levels = (int32_t)ctr[kCtrMaxLevel] + 1;
+        stats->n_levels = level ? (int32_t)ctr[kCtrMaxLevel] + 1 : 0;
         stats->status = status;
         stats->sweep_launches = launches;
         stats->sweep_ms = timer.ms;
@@ -430,8 +434,9 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
     if (rc) return rc;
     const bool sync = single || stats != nullptr;
 
+    (void)level; // the adjoint orders each tile by its own dependency levels
+    launch_fill_u64(w.ctr + kCtrAdjPending, 1, st);
     launch_adj_prep<R>(a, M, om, T, parent, w.w1, w.lam, st);
-    launch_adj_sort(a, level, w.list, w.cnt, st);
     launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
     launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
     launch_all_active(a, w.act, w.act_count, st);
@@ -444,7 +449,7 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
         const int budget_rounds = sync ? kMaxRounds / 2 : tn.adjoint_rounds;
         const uint32_t budget = (uint32_t)std::min<int64_t>((int64_t)budget_rounds * a.n_tiles, INT32_MAX);
         launch_queue_setup(a, w.act, w.q, budget, st);
-        launch_adj_queue<R>(a, waves, parent, level, w.w1, dLdT, w.list, w.cnt, w.lam, w.q, st);
+        launch_adj_queue<R>(a, waves, parent, w.w1, dLdT, w.lam, tn.adjoint_cycles, w.q, st);
         launch_note_queue(w.q, w.ctr + kCtrAdjPending, st);
         HIP_OK(hipGetLastError());
         if (sync) {
@@ -461,7 +466,7 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
             w.act, w.act_count, a.n_tiles, 0, sync ? kMaxRounds / 2 : tn.adjoint_rounds, tn.rounds_per_check, sync,
             st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-                launch_adj_round<R>(a, parent, level, w.w1, dLdT, w.list, w.cnt, w.lam, ain, aout, cnt, st);
+                launch_adj_round<R>(a, parent, w.w1, dLdT, w.lam, tn.adjoint_cycles, ain, aout, cnt, st);
             },
             &rounds, &conv);
         if (rc) return rc;
@@ -480,9 +485,9 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
     return EIK_OK;
 }
 
-int check_ptrs(const void *M, const void *om, const void *T, const void *parent, const void *level)
+int check_ptrs(const void *M, const void *om, const void *T, const void *parent)
 {
-    if (!M || !om || !T || !parent || !level) return fail(EIK_EINVAL, "NULL field or output pointer");
+    if (!M || !om || !T || !parent) return fail(EIK_EINVAL, "NULL field or output pointer");
     return EIK_OK;
 }
 
@@ -533,7 +538,7 @@ int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *
     int rc = check_one(grid, 0);
     if (rc) return rc;
     if (!grid->src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
-    rc = check_ptrs(M, omega, T, parent, level);
+    rc = check_ptrs(M, omega, T, parent);
     if (rc) return rc;
     if (!(tol >= 0.0)) return fail(EIK_EINVAL, "tol must be >= 0");
     if (max_rounds < 1) return fail(EIK_EINVAL, "max_rounds must be >= 1");
@@ -550,7 +555,7 @@ int eik_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, c
                         size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream)
 {
     if (!src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
-    int rc = check_ptrs(M, omega, T, parent, level);
+    int rc = check_ptrs(M, omega, T, parent);
     if (rc) return rc;
     if (!(tol >= 0.0)) return fail(EIK_EINVAL, "tol must be >= 0");
     if (max_rounds < 1) return fail(EIK_EINVAL, "max_rounds must be >= 1");
@@ -573,7 +578,7 @@ int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void 
     int rc = check_one(grid, 0);
     if (rc) return rc;
     if (!grid->src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
-    if (!M || !omega || !T || !parent || !level || !dLdT || !dLdM || !dLdomega || !dLdsrc)
+    if (!M || !omega || !T || !parent || !dLdT || !dLdM || !dLdomega || !dLdsrc)
         return fail(EIK_EINVAL, "NULL pointer argument");
     if (dtype == EIK_F64)
         return backward_impl<double>(1, grid, grid->src_idx, M, omega, T, parent, level, dLdT, dLdM, dLdomega,
@@ -587,7 +592,7 @@ int eik_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, 
                          const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega, void *dLdsrc, void *ws,
                          size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream)
 {
-    if (!src_idx || !M || !omega || !T || !parent || !level || !dLdT || !dLdM || !dLdomega || !dLdsrc)
+    if (!src_idx || !M || !omega || !T || !parent || !dLdT || !dLdM || !dLdomega || !dLdsrc)
         return fail(EIK_EINVAL, "NULL pointer argument");
     if (dtype == EIK_F64)
         return backward_impl<double>(n_grids, grids, src_idx, M, omega, T, parent, level, dLdT, dLdM, dLdomega,
@@ -654,7 +659,7 @@ int eik_batch_pending(int32_t n_grids, const eik_grid *grids, int32_t dtype, con
     Ws w;
     rc = carve(e, dtype, const_cast<void *>(ws), ws_bytes, w);
     if (rc) return rc;
-    unsigned long long c[3];
+    unsigned long long c[3]; // sweep, level, adjoint
     HIP_OK(hipMemcpyAsync(c, w.ctr + kCtrSweepPending, sizeof c, hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     for (int k = 0; k < 3; ++k) pending[k] = (int64_t)c[k];

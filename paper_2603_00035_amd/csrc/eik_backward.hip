@@ -5,21 +5,20 @@
 // (barycentric weight of a two-point update, 1 for a one-point update), so the
 // adjoint system J^T lambda = dL/dT is triangular in the causal order and
 // reads lambda_i = g_i + sum over the nodes j that i feeds of w_ji lambda_j.
-// Instead of sorting by T, nodes are ordered by dependency level: a node's
-// receivers all sit at deeper levels. Each tile keeps its nodes sorted by
-// decreasing level (a counting sort done once) and, holding lambda, the donor
-// weights and the active updates of the tile plus a one-node halo in LDS,
-// processes its levels from the deepest down; all nodes of one level gather
-// from their (at most eight) receivers at once, and nothing is scattered, so
-// no atomics are needed. Receivers in neighbouring tiles are read from the
-// halo; tiles whose halo changed run again in the next round, and the rounds
-// end when no lambda on a tile border changes -- then every lambda satisfies
-// its equation exactly, as a single global level-by-level pass would give.
-// dL/dtheta_i = lambda_i dT_i/dtheta_i (Alg. backward, last loop) follows in
-// one pass over the nodes.
+// Instead of sorting all nodes by T, each tile (holding lambda, the donor
+// weights and the active updates of the tile plus a one-node halo in LDS)
+// relaxes these equations with the same four directional line sweeps as the
+// forward pass, each node gathering from its (at most eight) receivers, so
+// nothing is scattered and no atomics are needed. On the acyclic donor graph a
+// lambda is exact as soon as its receivers are, so the sweeps end at the exact
+// solution. Receivers in neighbouring tiles are read from the halo; tiles
+// whose halo changed are visited again, until no lambda on a tile border
+// changes. dL/dtheta_i = lambda_i dT_i/dtheta_i (Alg. backward, last loop)
+// follows in one pass over the nodes.
 #include "eik_device.h"
 #include "eik_internal.h"
 #include "eik_queue.h"
+#include "eik_tile.h"
 
 namespace eik {
 
@@ -69,7 +68,7 @@ __global__ __launch_bounds__(256) void k_adj_prep(LaunchArgs a, const R *__restr
                 NodeConst<R> k;
                 node_const<R>(Mg[c], Mg[n + c], Mg[2 * n + c], og[c], og[n + c], h, inv_h, k);
                 R t, mu1, mu2;
-                two_point<R>(k, code, T[(size_t)yp * g.gd.nx + xp], T[(size_t)yq * g.gd.nx + xq], t, mu1, mu2);
+                two_point_any<R>(k, code, T[(size_t)yp * g.gd.nx + xp], T[(size_t)yq * g.gd.nx + xq], t, mu1, mu2);
                 w = mu1 / (mu1 + mu2);
             }
         }
@@ -78,193 +77,120 @@ __global__ __launch_bounds__(256) void k_adj_prep(LaunchArgs a, const R *__restr
     }
 }
 
-// Per tile: reached nodes sorted by decreasing level into the tile's segment
-// of `list` (local indices r * 64 + c), count in cnt[tile]. Counting sort in
-// LDS, in chunks of kSortChunk levels.
-template <int TH>
-__global__ __launch_bounds__(256) void k_adj_sort(LaunchArgs a, const int32_t *__restrict__ levall,
-                                                  int32_t *__restrict__ list, int32_t *__restrict__ cnt)
-{
-    __shared__ int32_t hist[kSortChunk];
-    __shared__ int32_t part[256];
-    __shared__ int32_t s_lo, s_hi, s_base;
-    const int t = blockIdx.x;
-    const TileGeoB g = tile_geo_b<TH>(a, t);
-    const int32_t *level = levall + g.gd.off;
-    int32_t *seg = list + (size_t)t * TW * TH;
-    if (threadIdx.x == 0) {
-        s_lo = 0x7fffffff;
-        s_hi = -1;
-        s_base = 0;
-    }
-    __syncthreads();
-    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
-    int lo = 0x7fffffff, hi = -1;
-    for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
-        const int r = idx / TW, c = idx - r * TW;
-        if (r >= g.h || c >= g.w) continue;
-        const int lv = level[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c];
-        if (lv >= 0 && lv < n) {
-            lo = min(lo, lv);
-            hi = max(hi, lv);
-        }
-    }
-    atomicMin(&s_lo, lo);
-    atomicMax(&s_hi, hi);
-    __syncthreads();
-    lo = s_lo;
-    hi = s_hi;
-    if (hi < 0) {
-        if (threadIdx.x == 0) cnt[t] = 0;
-        return;
-    }
-    for (int k0 = 0; k0 <= hi - lo; k0 += kSortChunk) {
-        for (int b = threadIdx.x; b < kSortChunk; b += blockDim.x) hist[b] = 0;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
-            const int r = idx / TW, c = idx - r * TW;
-            if (r >= g.h || c >= g.w) continue;
-            const int lv = level[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c];
-            const int key = hi - lv - k0;
-            if (lv >= 0 && lv < n && key >= 0 && key < kSortChunk) atomicAdd(&hist[key], 1);
-        }
-        __syncthreads();
-        // exclusive scan of hist: 16 entries per thread, then across threads
-        constexpr int PER = kSortChunk / 256;
-        int sum = 0;
-        for (int q = 0; q < PER; ++q) sum += hist[threadIdx.x * PER + q];
-        part[threadIdx.x] = sum;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-            __syncthreads();
-            part[threadIdx.x] += add;
-            __syncthreads();
-        }
-        int run = s_base + part[threadIdx.x] - sum;
-        for (int q = 0; q < PER; ++q) {
-            const int v = hist[threadIdx.x * PER + q];
-            hist[threadIdx.x * PER + q] = run;
-            run += v;
-        }
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
-            const int r = idx / TW, c = idx - r * TW;
-            if (r >= g.h || c >= g.w) continue;
-            const int lv = level[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c];
-            const int key = hi - lv - k0;
-            if (lv >= 0 && lv < n && key >= 0 && key < kSortChunk) seg[atomicAdd(&hist[key], 1)] = r * TW + c;
-        }
-        __syncthreads();
-        if (threadIdx.x == 255) s_base += part[255];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) cnt[t] = s_base;
-}
+// One visit of a tile by directional sweeps: lambda_i = g_i + sum over the
+// tile's and the halo's receivers j of i of (dT_j/dT_i) lambda_j, the sum in
+// neighbour order k = 0..7, relaxed with the four directional line sweeps
+// (Gauss-Seidel, a line of the tile per step) until a full four-sweep cycle
+// changes nothing or the cycle budget runs out. The donor graph is acyclic,
+// so every lambda reaches its exact value once its receivers have theirs, and
+// a quiet cycle means every node satisfies its equation for the current halo.
+// Each node's receivers and weight selectors are gathered once per visit into
+// a 16-bit descriptor (two bits per neighbour: 1 first donor, weight w; 2
+// second donor, weight 1 - w; 3 one-point donor, weight 1).
+struct AdjVisit {
+    int bits;
+    bool settled;
+};
 
-// One visit of a tile: lambda of every reached node of the tile, levels
-// deepest first, from the receivers' lambda (inside the tile, or in the halo
-// as last written back by the neighbours). Returns the halo bits of the
-// neighbours whose halo changed (OR over the wave).
 template <typename R, int TH>
-__device__ __forceinline__ int adj_visit(const LaunchArgs &a, int t, const uint8_t *__restrict__ parall,
-                                         const int32_t *__restrict__ levall, const R *__restrict__ w1all,
-                                         const R *__restrict__ gall, const int32_t *__restrict__ list,
-                                         const int32_t *__restrict__ cnt, R *lamall, R *sLam, R *sW, uint8_t *sP)
+__device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, const uint8_t *__restrict__ parall,
+                                                    const R *__restrict__ w1all, const R *__restrict__ gall,
+                                                    R *lamall, int max_cycles, R *sLam, R *sW, uint8_t *sP,
+                                                    uint16_t *sD, R *sG)
 {
     constexpr int LP = TW + 3;
     const int lane = threadIdx.x;
     const TileGeoB g = tile_geo_b<TH>(a, t);
     const int nx = g.gd.nx, ny = g.gd.ny;
     R *lam = lamall + g.gd.off;
-    const int32_t *level = levall + g.gd.off;
-    const R *gT = gall + g.gd.off;
 
-    for (int idx = lane; idx < (TH + 2) * (TW + 2); idx += TW) {
-        const int r = idx / (TW + 2), c = idx - r * (TW + 2);
-        const int gi = g.i0 + c - 1, gj = g.j0 + r - 1;
-        R lv = R(0), wv = R(1);
-        uint8_t pv = kUnreached;
-        if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
-            const size_t gc = (size_t)gj * nx + gi;
-            lv = lam[gc];
-            wv = w1all[g.gd.off + gc];
-            pv = parall[g.gd.off + gc];
+    load_tile_halo<R, TH, LP>(lam, sLam, nx, ny, g.i0, g.j0, R(0));
+    load_tile_halo<R, TH, LP>(w1all + g.gd.off, sW, nx, ny, g.i0, g.j0, R(1));
+    load_tile_halo<uint8_t, TH, LP>(parall + g.gd.off, sP, nx, ny, g.i0, g.j0, kUnreached);
+    load_block<R, TH, TW, 0>(gall + g.gd.off, sG, nx, ny, g.i0, g.j0, R(0));
+    __syncthreads();
+    for (int idx = lane; idx < TH * TW; idx += TW) {
+        const int r = idx / TW, c = idx - r * TW;
+        uint32_t d = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int pc = sP[(r + 1 + nb_dy(k)) * LP + (c + 1 + nb_dx(k))];
+            const int kk = (k + 4) & 7; // this node seen from the neighbour
+            const uint32_t sel = pc == kk ? 1u : (pc == ((kk + 7) & 7) ? 2u : (pc == 8 + kk ? 3u : 0u));
+            d |= sel << (2 * k);
         }
-        sLam[r * LP + c] = lv;
-        sW[r * LP + c] = wv;
-        sP[r * LP + c] = pv;
+        sD[idx] = (uint16_t)d;
     }
     __syncthreads();
 
-    const int count = cnt[t];
-    const int32_t *seg = list + (size_t)t * TW * TH;
-    // chunk of 64 sorted entries per pass; the next chunk's entry, level and
-    // dL/dT are loaded while the current one is processed
-    auto fetch = [&](int base, int &e, int &lv, R &gv) {
-        const bool have = base + lane < count;
-        e = have ? seg[base + lane] : -1;
-        const int rr = have ? e / TW : 0, cc = have ? e - rr * TW : 0;
-        const size_t gc = (size_t)(g.j0 + rr) * nx + g.i0 + cc;
-        lv = have ? level[gc] : -1;
-        gv = have ? gT[gc] : R(0);
-    };
-    int e_n, lv_n;
-    R g_n;
-    fetch(0, e_n, lv_n, g_n);
-    for (int base = 0; base < count; base += TW) {
-        const int e = e_n;
-        int lv = lv_n;
-        const R gi = g_n;
-        if (base + TW < count) fetch(base + TW, e_n, lv_n, g_n);
-        const bool have = e >= 0;
-        const int r = have ? e / TW : 0, c = have ? e - r * TW : 0;
-        bool done = !have;
-        // levels inside the chunk are non-increasing; take them deepest first
-        while (__ballot(!done)) {
-            int cur = done ? -1 : lv;
-            for (int off = 32; off >= 1; off >>= 1) cur = max(cur, __shfl_xor(cur, off));
-            const bool mine = !done && lv == cur;
-            if (mine) {
-                R acc = gi;
+    int quiet = 0, sweeps = 0;
+    const int max_sweeps = 4 * max_cycles;
+    while (quiet < 4 && sweeps < max_sweeps) {
+        const int dir = sweeps & 3;
+        const bool col = (dir & 1) == 0;
+        const int len = col ? g.w : g.h;
+        const int span = col ? g.h : g.w;
+        bool changed = false;
+        for (int s = 0; s < len; ++s) {
+            const int pos = dir < 2 ? s : len - 1 - s;
+            const int ci = col ? pos : lane;
+            const int cj = col ? lane : pos;
+            if (lane < span) {
+                const uint32_t d = sD[cj * TW + ci];
+                R acc = sG[cj * TW + ci];
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    const int sl = (r + 1 + nb_dy(k)) * LP + (c + 1 + nb_dx(k));
-                    const int pc = sP[sl];
-                    const int kk = (k + 4) & 7; // this node seen from the neighbour
-                    if (pc == kk)
-                        acc += sW[sl] * sLam[sl];
-                    else if (pc == ((kk + 7) & 7))
-                        acc += (R(1) - sW[sl]) * sLam[sl];
-                    else if (pc == 8 + kk)
-                        acc += sLam[sl];
+                    const uint32_t sel = (d >> (2 * k)) & 3u;
+                    if (sel) {
+                        const int sl = (cj + 1 + nb_dy(k)) * LP + (ci + 1 + nb_dx(k));
+                        const R wj = sW[sl];
+                        const R coef = sel == 1u ? wj : (sel == 2u ? R(1) - wj : R(1));
+                        acc += coef * sLam[sl];
+                    }
                 }
-                sLam[(r + 1) * LP + c + 1] = acc;
-                done = true;
+                const int slot = (cj + 1) * LP + ci + 1;
+                changed |= acc != sLam[slot];
+                sLam[slot] = acc;
             }
-            // one-wave workgroup: LDS requests are served in issue order, so
-            // only compiler motion across the level boundary is blocked
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        ++sweeps;
+        quiet = __ballot(changed) ? 0 : quiet + 1;
     }
 
+    // write back (old values re-read in batches), note the neighbours whose
+    // halo changed
     int bits = 0;
-    for (int idx = lane; idx < TH * TW; idx += TW) {
-        const int r = idx / TW, c = idx - r * TW;
-        if (c >= g.w || r >= g.h) continue;
-        const size_t gc = (size_t)(g.j0 + r) * nx + (g.i0 + c);
-        const R nv = sLam[(r + 1) * LP + c + 1];
-        if (nv != lam[gc]) {
-            lam[gc] = nv;
-            const bool W = c == 0, E = c == g.w - 1, S = r == 0, N = r == g.h - 1;
-            bits |= (W ? 1 : 0) | (E ? 2 : 0) | (S ? 4 : 0) | (N ? 8 : 0) | ((S && W) ? 16 : 0) |
-                    ((S && E) ? 32 : 0) | ((N && W) ? 64 : 0) | ((N && E) ? 128 : 0);
+    const int c = lane;
+#pragma unroll 1
+    for (int r0 = 0; r0 < TH; r0 += kLoadBatch) {
+        R ov[kLoadBatch];
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+            const int r = r0 + k;
+            const int rc = r < g.h ? r : g.h - 1, cc = c < g.w ? c : g.w - 1; // in-tile, no branch
+            ov[k] = lam[(size_t)(g.j0 + rc) * nx + g.i0 + cc];
+        }
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+            const int r = r0 + k;
+            if (r >= g.h || c >= g.w) continue;
+            const R nv = sLam[(r + 1) * LP + c + 1];
+            if (nv != ov[k]) {
+                lam[(size_t)(g.j0 + r) * nx + g.i0 + c] = nv;
+                const bool W = c == 0, E = c == g.w - 1, S = r == 0, N = r == g.h - 1;
+                bits |= (W ? 1 : 0) | (E ? 2 : 0) | (S ? 4 : 0) | (N ? 8 : 0) | ((S && W) ? 16 : 0) |
+                        ((S && E) ? 32 : 0) | ((N && W) ? 64 : 0) | ((N && E) ? 128 : 0);
+            }
         }
     }
     for (int off = 32; off >= 1; off >>= 1) bits |= __shfl_xor(bits, off);
-    return bits;
+    AdjVisit v;
+    v.bits = bits;
+    v.settled = quiet >= 4;
+    return v;
 }
 
 // tile index of the neighbour in halo-bit direction b, or -1 outside the grid
@@ -277,14 +203,13 @@ __device__ __forceinline__ int adj_neighbour(const TileGeoB &g, int b)
     return g.gd.tile_base + uy * g.gd.ntx + ux;
 }
 
-// One round of the tile-local level-descending gather.
+// Round scheduler with sweep visits.
 template <typename R, int TH>
-__global__ __launch_bounds__(TW) void k_adj_round(LaunchArgs a, const uint8_t *__restrict__ parall,
-                                                  const int32_t *__restrict__ levall, const R *__restrict__ w1all,
-                                                  const R *__restrict__ gall, const int32_t *__restrict__ list,
-                                                  const int32_t *__restrict__ cnt, R *__restrict__ lamall,
-                                                  int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
-                                                  int32_t *__restrict__ count_next)
+__global__ __launch_bounds__(TW) void k_adj_sweep_round(LaunchArgs a, const uint8_t *__restrict__ parall,
+                                                        const R *__restrict__ w1all, const R *__restrict__ gall,
+                                                        R *__restrict__ lamall, int max_cycles,
+                                                        int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
+                                                        int32_t *__restrict__ count_next)
 {
     constexpr int LP = TW + 3;
     const int t = blockIdx.x;
@@ -293,45 +218,48 @@ __global__ __launch_bounds__(TW) void k_adj_round(LaunchArgs a, const uint8_t *_
     __shared__ R sLam[(TH + 2) * LP];
     __shared__ R sW[(TH + 2) * LP];
     __shared__ uint8_t sP[(TH + 2) * LP];
-    const int bits = adj_visit<R, TH>(a, t, parall, levall, w1all, gall, list, cnt, lamall, sLam, sW, sP);
+    __shared__ uint16_t sD[TH * TW];
+    __shared__ R sG[TH * TW];
+    const AdjVisit v = adj_visit_sweep<R, TH>(a, t, parall, w1all, gall, lamall, max_cycles, sLam, sW, sP, sD, sG);
     if (threadIdx.x == 0) {
         const TileGeoB g = tile_geo_b<TH>(a, t);
         for (int b = 0; b < 8; ++b) {
-            if (!(bits & (1 << b))) continue;
+            if (!(v.bits & (1 << b))) continue;
             const int u = adj_neighbour(g, b);
             if (u >= 0 && atomicExch(&act_out[u], 1) == 0) atomicAdd(count_next, 1);
         }
+        if (!v.settled && atomicExch(&act_out[t], 1) == 0) atomicAdd(count_next, 1);
     }
 }
 
-// Work-queue form: one launch; waves take flagged tiles from the device
-// queue (same protocol as the forward's queue scheduler), visit them and flag
-// the neighbours whose halo changed.
+// Work-queue scheduler with sweep visits.
 template <typename R, int TH>
-__global__ __launch_bounds__(TW) void k_adj_queue(LaunchArgs a, const uint8_t *__restrict__ parall,
-                                                  const int32_t *__restrict__ levall, const R *__restrict__ w1all,
-                                                  const R *__restrict__ gall, const int32_t *__restrict__ list,
-                                                  const int32_t *__restrict__ cnt, R *lamall, WorkQueue q)
+__global__ __launch_bounds__(TW) void k_adj_sweep_queue(LaunchArgs a, const uint8_t *__restrict__ parall,
+                                                        const R *__restrict__ w1all, const R *__restrict__ gall,
+                                                        R *lamall, int max_cycles, WorkQueue q)
 {
     constexpr int LP = TW + 3;
     __shared__ R sLam[(TH + 2) * LP];
     __shared__ R sW[(TH + 2) * LP];
     __shared__ uint8_t sP[(TH + 2) * LP];
+    __shared__ uint16_t sD[TH * TW];
+    __shared__ R sG[TH * TW];
     for (;;) {
         int t = threadIdx.x == 0 ? q_take(q) : 0;
         t = __shfl(t, 0);
         if (t < 0) break;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int bits = adj_visit<R, TH>(a, t, parall, levall, w1all, gall, list, cnt, lamall, sLam, sW, sP);
+        const AdjVisit v =
+            adj_visit_sweep<R, TH>(a, t, parall, w1all, gall, lamall, max_cycles, sLam, sW, sP, sD, sG);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (threadIdx.x == 0) {
             const TileGeoB g = tile_geo_b<TH>(a, t);
             for (int b = 0; b < 8; ++b) {
-                if (!(bits & (1 << b))) continue;
+                if (!(v.bits & (1 << b))) continue;
                 const int u = adj_neighbour(g, b);
                 if (u >= 0) q_flag(q, u);
             }
-            q_done(q, t, true);
+            q_done(q, t, v.settled);
         }
         __syncthreads(); // LDS reuse by the next visit
     }
@@ -400,28 +328,21 @@ void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const v
                                              (const R *)M, (const R *)om, (const R *)T, parent, (R *)w1, (R *)lam));
 }
 
-void launch_adj_sort(const LaunchArgs &a, const int32_t *level, int32_t *list, int32_t *cnt, hipStream_t st)
+template <typename R>
+void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const void *w1, const void *dLdT, void *lam,
+                      int max_cycles, int32_t *act_in, int32_t *act_out, int32_t *count_next, hipStream_t st)
 {
-    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL(k_adj_sort<TH>, dim3(a.n_tiles), dim3(256), 0, st, a, level, list, cnt));
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_sweep_round<R, TH>), dim3(a.n_tiles), dim3(TW), 0, st, a, parent,
+                                             (const R *)w1, (const R *)dLdT, (R *)lam, max_cycles, act_in, act_out,
+                                             count_next));
 }
 
 template <typename R>
-void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const int32_t *level, const void *w1,
-                      const void *dLdT, const int32_t *list, const int32_t *cnt, void *lam, int32_t *act_in,
-                      int32_t *act_out, int32_t *count_next, hipStream_t st)
+void launch_adj_queue(const LaunchArgs &a, int n_waves, const uint8_t *parent, const void *w1, const void *dLdT,
+                      void *lam, int max_cycles, const WorkQueue &q, hipStream_t st)
 {
-    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_round<R, TH>), dim3(a.n_tiles), dim3(TW), 0, st, a, parent,
-                                             level, (const R *)w1, (const R *)dLdT, list, cnt, (R *)lam, act_in,
-                                             act_out, count_next));
-}
-
-template <typename R>
-void launch_adj_queue(const LaunchArgs &a, int n_waves, const uint8_t *parent, const int32_t *level, const void *w1,
-                      const void *dLdT, const int32_t *list, const int32_t *cnt, void *lam, const WorkQueue &q,
-                      hipStream_t st)
-{
-    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_queue<R, TH>), dim3(n_waves), dim3(TW), 0, st, a, parent, level,
-                                             (const R *)w1, (const R *)dLdT, list, cnt, (R *)lam, q));
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_sweep_queue<R, TH>), dim3(n_waves), dim3(TW), 0, st, a, parent,
+                                             (const R *)w1, (const R *)dLdT, (R *)lam, max_cycles, q));
 }
 
 int adj_queue_waves(int th, int dtype)
@@ -432,11 +353,11 @@ int adj_queue_waves(int th, int dtype)
         return 0;
     hipError_t e;
     if (dtype == 1)
-        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_queue<double, 64>, TW, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_queue<double, 32>, TW, 0);
+        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_sweep_queue<double, 64>, TW, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_sweep_queue<double, 32>, TW, 0);
     else
-        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_queue<float, 64>, TW, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_queue<float, 32>, TW, 0);
+        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_sweep_queue<float, 64>, TW, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_sweep_queue<float, 32>, TW, 0);
     if (e != hipSuccess) return 0;
     return std::max(1, per_cu) * cus;
 }
@@ -459,12 +380,10 @@ void launch_dsrc(const LaunchArgs &a, const int32_t *src_idx, const void *lam, v
 #define EIK_INST(R)                                                                                              \
     template void launch_adj_prep<R>(const LaunchArgs &, const void *, const void *, const void *,              \
                                      const uint8_t *, void *, void *, hipStream_t);                             \
-    template void launch_adj_round<R>(const LaunchArgs &, const uint8_t *, const int32_t *, const void *,        \
-                                      const void *, const int32_t *, const int32_t *, void *, int32_t *,         \
-                                      int32_t *, int32_t *, hipStream_t);                                        \
-    template void launch_adj_queue<R>(const LaunchArgs &, int, const uint8_t *, const int32_t *, const void *,  \
-                                      const void *, const int32_t *, const int32_t *, void *, const WorkQueue &, \
-                                      hipStream_t);                                                              \
+    template void launch_adj_round<R>(const LaunchArgs &, const uint8_t *, const void *, const void *, void *,   \
+                                      int, int32_t *, int32_t *, int32_t *, hipStream_t);                        \
+    template void launch_adj_queue<R>(const LaunchArgs &, int, const uint8_t *, const void *, const void *,     \
+                                      void *, int, const WorkQueue &, hipStream_t);                              \
     template void launch_adj_params<R>(const LaunchArgs &, const void *, const uint8_t *, const void *,         \
                                        const void *, void *, void *, hipStream_t);                               \
     template void launch_dsrc<R>(const LaunchArgs &, const int32_t *, const void *, void *, hipStream_t);

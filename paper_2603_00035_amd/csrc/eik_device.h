@@ -28,8 +28,14 @@ __device__ __forceinline__ float inf_v<float>() { return __builtin_huge_valf(); 
 template <>
 __device__ __forceinline__ double inf_v<double>() { return __builtin_huge_val(); }
 
-__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+// FP32 uses the hardware square root and reciprocal (about 1 ulp) instead of
+// the correctly rounded instruction sequences, which cost ten or more
+// instructions each on the sweep's critical path; FP64 keeps the correctly
+// rounded forms.
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float drcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double drcp(double x) { return 1.0 / x; }
 
 // Neighbour k of (i, j) is (i + nb_dx(k), j + nb_dy(k)), counter-clockwise
 // from the upper-left neighbour with +y = +j (Fig. stencil).
@@ -85,8 +91,8 @@ __device__ __forceinline__ void node_const(R m11, R m12, R m22, R bx, R by, R h,
     k.det = m11 * m22 - m12 * m12;
     k.h = h;
     k.inv_h = inv_h;
-    k.inv_m11 = R(1) / m11;
-    k.inv_m22 = R(1) / m22;
+    k.inv_m11 = drcp(m11);
+    k.inv_m22 = drcp(m22);
 }
 
 // Two-point candidate of stencil s (donors s and s+1 with times Tp, Tq).
@@ -112,6 +118,24 @@ __device__ __forceinline__ bool two_point(const NodeConst<R> &k, int s, R Tp, R 
     mu2 = Ep * (tau - s2) - Epq * (tau - s1);
     t = S0 + k.h * tau;
     return mu1 >= R(0) && mu2 >= R(0) && t > Tp && t > Tq;
+}
+
+// two_point for a stencil index known only at run time: one constant-index
+// call per case, so the per-node constants stay in registers (an indexed
+// access into them would go through scratch memory).
+template <typename R>
+__device__ __forceinline__ bool two_point_any(const NodeConst<R> &k, int s, R Tp, R Tq, R &t, R &mu1, R &mu2)
+{
+    switch (s & 7) {
+    case 0: return two_point(k, 0, Tp, Tq, t, mu1, mu2);
+    case 1: return two_point(k, 1, Tp, Tq, t, mu1, mu2);
+    case 2: return two_point(k, 2, Tp, Tq, t, mu1, mu2);
+    case 3: return two_point(k, 3, Tp, Tq, t, mu1, mu2);
+    case 4: return two_point(k, 4, Tp, Tq, t, mu1, mu2);
+    case 5: return two_point(k, 5, Tp, Tq, t, mu1, mu2);
+    case 6: return two_point(k, 6, Tp, Tq, t, mu1, mu2);
+    default: return two_point(k, 7, Tp, Tq, t, mu1, mu2);
+    }
 }
 
 // Minimum over the valid candidates (two-point stencils 0..7 first, then
@@ -173,8 +197,8 @@ __device__ __forceinline__ R local_update_dir(const NodeConst<R> &k, const R Tn[
         int c1 = kUnreached;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const R t = Tn[s] + k.c1[s];
-            if (Tn[s] < inf && t < b1) {
+            const R t = Tn[s] + k.c1[s]; // +inf for an unreached donor, never below b1
+            if (t < b1) {
                 b1 = t;
                 c1 = 8 + s;
             }

@@ -26,6 +26,7 @@
 #include "eik_device.h"
 #include "eik_internal.h"
 #include "eik_queue.h"
+#include "eik_tile.h"
 
 namespace eik {
 
@@ -94,7 +95,7 @@ __global__ void k_init(int64_t n, const R *__restrict__ T_init, R *__restrict__ 
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         T[c] = T_init ? T_init[c] : inf_v<R>();
         code[c] = kUnreached;
-        level[c] = -1;
+        if (level) level[c] = -1;
     }
 }
 
@@ -115,7 +116,7 @@ __global__ void k_sources(LaunchArgs a, const int32_t *__restrict__ src_idx, con
         }
         T[gd.off + c] = src_t ? src_t[gd.src_base + s] : R(0);
         code[gd.off + c] = kSource;
-        level[gd.off + c] = 0;
+        if (level) level[gd.off + c] = 0;
         const int i = c % gd.nx, j = c / gd.nx;
         const int t = gd.tile_base + (j / TH) * gd.ntx + i / TW;
         if (atomicExch(&act[t], 1) == 0) atomicAdd(&act_count[0], 1);
@@ -144,18 +145,6 @@ __global__ void k_all_active(int32_t *__restrict__ act, int n_tiles, int32_t *__
 // ---------------------------------------------------------------------------
 // Tile helpers.
 // ---------------------------------------------------------------------------
-template <typename V, int TH, int LP>
-__device__ __forceinline__ void load_tile_halo(const V *__restrict__ src, V *sT, const TileGeo &g, V outside)
-{
-    for (int idx = threadIdx.x; idx < (TH + 2) * (TW + 2); idx += blockDim.x) {
-        const int r = idx / (TW + 2), c = idx - r * (TW + 2);
-        const int gi = g.i0 + c - 1, gj = g.j0 + r - 1;
-        V v = outside;
-        if (gi >= 0 && gi < g.gd.nx && gj >= 0 && gj < g.gd.ny) v = src[(size_t)gj * g.gd.nx + gi];
-        sT[r * LP + c] = v;
-    }
-}
-
 // Bits of the neighbour tiles that see node (ci, cj) of a w x h tile in their
 // halo: 0 W, 1 E, 2 S (j-1), 3 N (j+1), 4 SW, 5 SE, 6 NW, 7 NE.
 __device__ __forceinline__ int halo_bits(int ci, int cj, int w, int h)
@@ -205,7 +194,8 @@ __device__ __forceinline__ void wave_step_sync()
 // ---------------------------------------------------------------------------
 // Mb: three metric planes, Ob: two drift planes, both of n nodes each, laid out
 // column-major (transposed copy) for column sweeps and row-major otherwise.
-template <typename R, int TH, int DIR, bool FULL>
+// LEV: carry the active update's code and dependency level along with T.
+template <typename R, int TH, int DIR, bool FULL, bool LEV>
 __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict__ Mb, const R *__restrict__ Ob,
                                           R *sT, int32_t *sL, uint8_t *sC, R tol, R h, R inv_h)
 {
@@ -249,23 +239,25 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
                 v = old;
                 newcode = sC[cc];
             }
-            // dependency level of the current active update
-            int lv = -1;
-            if (newcode < 16) {
-                const int kp = newcode < 8 ? newcode : newcode - 8;
-                lv = sL[(cj + 1 + nb_dy(kp)) * LP + ci + 1 + nb_dx(kp)];
-                if (newcode < 8) {
-                    const int kq = (newcode + 1) & 7;
-                    lv = max(lv, sL[(cj + 1 + nb_dy(kq)) * LP + ci + 1 + nb_dx(kq)]);
+            if (LEV) {
+                // dependency level of the current active update
+                int lv = -1;
+                if (newcode < 16) {
+                    const int kp = newcode < 8 ? newcode : newcode - 8;
+                    lv = sL[(cj + 1 + nb_dy(kp)) * LP + ci + 1 + nb_dx(kp)];
+                    if (newcode < 8) {
+                        const int kq = (newcode + 1) & 7;
+                        lv = max(lv, sL[(cj + 1 + nb_dy(kq)) * LP + ci + 1 + nb_dx(kq)]);
+                    }
+                    lv = lv + 1;
                 }
-                lv = lv + 1;
+                sL[slot] = lv;
+                sC[cc] = (uint8_t)newcode;
             }
             // only T decides convergence; levels ride along and are made
             // consistent with the final active updates afterwards
             changed |= counts_as_change<R>(old, v, tol);
             sT[slot] = v;
-            sL[slot] = lv;
-            sC[cc] = (uint8_t)newcode;
         }
         wave_step_sync();
     }
@@ -284,7 +276,7 @@ struct Visit {
     int sweeps;
 };
 
-template <typename R, int TH, bool FULL>
+template <typename R, int TH, bool FULL, bool LEV>
 __device__ __forceinline__ Visit visit_tile(const LaunchArgs &a, int t, const R *__restrict__ M,
                                             const R *__restrict__ om, const R *__restrict__ Ptall, R *Tall,
                                             uint8_t *codeall, int32_t *levall, R tol, int max_cycles, R *sT,
@@ -295,18 +287,15 @@ __device__ __forceinline__ Visit visit_tile(const LaunchArgs &a, int t, const R 
     const TileGeo g = tile_geo<TH>(a, t);
     R *T = Tall + g.gd.off;
     uint8_t *code = codeall + g.gd.off;
-    int32_t *level = levall + g.gd.off;
+    int32_t *level = LEV ? levall + g.gd.off : nullptr;
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
     const R *Mg = M + 3 * g.gd.off, *Og = om + 2 * g.gd.off; // row-major planes
     const R *Pt = Ptall + 5 * g.gd.off, *Pto = Pt + 3 * n;   // column-major copy
     const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
 
-    load_tile_halo<R, TH, LP>(T, sT, g, inf_v<R>());
-    load_tile_halo<int32_t, TH, LP>(level, sL, g, -1);
-    for (int idx = lane; idx < TH * TW; idx += TW) {
-        const int r = idx / TW, c = idx - r * TW;
-        sC[idx] = (c < g.w && r < g.h) ? code[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c] : kSource;
-    }
+    load_tile_halo<R, TH, LP>(T, sT, g.gd.nx, g.gd.ny, g.i0, g.j0, inf_v<R>());
+    if (LEV) load_tile_halo<int32_t, TH, LP>(level, sL, g.gd.nx, g.gd.ny, g.i0, g.j0, -1);
+    load_block<uint8_t, TH, TW, 0>(code, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
     __syncthreads();
 
     int quiet = 0, sweeps = 0;
@@ -314,29 +303,42 @@ __device__ __forceinline__ Visit visit_tile(const LaunchArgs &a, int t, const R 
     while (quiet < 4 && sweeps < max_sweeps) {
         bool ch;
         switch (sweeps & 3) {
-        case 0: ch = sweep_dir<R, TH, 0, FULL>(g, Pt, Pto, sT, sL, sC, tol, h, inv_h); break;
-        case 1: ch = sweep_dir<R, TH, 1, FULL>(g, Mg, Og, sT, sL, sC, tol, h, inv_h); break;
-        case 2: ch = sweep_dir<R, TH, 2, FULL>(g, Pt, Pto, sT, sL, sC, tol, h, inv_h); break;
-        default: ch = sweep_dir<R, TH, 3, FULL>(g, Mg, Og, sT, sL, sC, tol, h, inv_h); break;
+        case 0: ch = sweep_dir<R, TH, 0, FULL, LEV>(g, Pt, Pto, sT, sL, sC, tol, h, inv_h); break;
+        case 1: ch = sweep_dir<R, TH, 1, FULL, LEV>(g, Mg, Og, sT, sL, sC, tol, h, inv_h); break;
+        case 2: ch = sweep_dir<R, TH, 2, FULL, LEV>(g, Pt, Pto, sT, sL, sC, tol, h, inv_h); break;
+        default: ch = sweep_dir<R, TH, 3, FULL, LEV>(g, Mg, Og, sT, sL, sC, tol, h, inv_h); break;
         }
         ++sweeps;
         quiet = __ballot(ch) ? 0 : quiet + 1;
     }
 
+    // write back (old values re-read in batches, see load_block), note the
+    // neighbours whose halo moved
     int bits = 0;
-    for (int idx = lane; idx < TH * TW; idx += TW) {
-        const int r = idx / TW, c = idx - r * TW;
-        if (c >= g.w || r >= g.h) continue;
-        const size_t gc = (size_t)(g.j0 + r) * g.gd.nx + (g.i0 + c);
-        const int sl = (r + 1) * LP + c + 1;
-        const R nv = sT[sl];
-        const R ov = T[gc];
-        const int nl = sL[sl];
-        const int ol = level[gc];
-        if (nv != ov) T[gc] = nv;
-        if (nl != ol) level[gc] = nl;
-        code[gc] = sC[idx];
-        if (counts_as_change<R>(ov, nv, tol)) bits |= halo_bits(c, r, g.w, g.h);
+    const int c = lane;
+#pragma unroll 1
+    for (int r0 = 0; r0 < TH; r0 += kLoadBatch) {
+        R ov[kLoadBatch];
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+            const int r = r0 + k;
+            const int rc = r < g.h ? r : g.h - 1, cc = c < g.w ? c : g.w - 1; // in-tile, no branch
+            ov[k] = T[(size_t)(g.j0 + rc) * g.gd.nx + g.i0 + cc];
+        }
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+            const int r = r0 + k;
+            if (r >= g.h || c >= g.w) continue;
+            const size_t gc = (size_t)(g.j0 + r) * g.gd.nx + (g.i0 + c);
+            const int sl = (r + 1) * LP + c + 1;
+            const R nv = sT[sl];
+            if (nv != ov[k]) T[gc] = nv;
+            if (LEV) {
+                level[gc] = sL[sl];
+                code[gc] = sC[r * TW + c];
+            }
+            if (counts_as_change<R>(ov[k], nv, tol)) bits |= halo_bits(c, r, g.w, g.h);
+        }
     }
     Visit v;
     v.bits = wave_or(bits);
@@ -348,7 +350,7 @@ __device__ __forceinline__ Visit visit_tile(const LaunchArgs &a, int t, const R 
 // ---------------------------------------------------------------------------
 // Round scheduler: one launch per round over the flagged tiles.
 // ---------------------------------------------------------------------------
-template <typename R, int TH, bool FULL>
+template <typename R, int TH, bool FULL, bool LEV>
 __global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
                                                     const R *__restrict__ Ptall, R *__restrict__ Tall,
                                                     uint8_t *__restrict__ codeall, int32_t *__restrict__ levall,
@@ -361,9 +363,10 @@ __global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__res
     if (act_in[t] == 0) return;
     if (threadIdx.x == 0) act_in[t] = 0;
     __shared__ R sT[(TH + 2) * LP];
-    __shared__ int32_t sL[(TH + 2) * LP];
+    __shared__ int32_t sL[LEV ? (TH + 2) * LP : 1];
     __shared__ uint8_t sC[TH * TW];
-    const Visit v = visit_tile<R, TH, FULL>(a, t, M, om, Ptall, Tall, codeall, levall, tol, max_cycles, sT, sL, sC);
+    const Visit v =
+        visit_tile<R, TH, FULL, LEV>(a, t, M, om, Ptall, Tall, codeall, levall, tol, max_cycles, sT, sL, sC);
     if (threadIdx.x == 0) {
         const TileGeo g = tile_geo<TH>(a, t);
         flag_neighbours(v.bits, g, act_out, count_next);
@@ -398,7 +401,7 @@ __device__ __forceinline__ void q_flag_neighbours(const WorkQueue &q, int bits, 
     }
 }
 
-template <typename R, int TH>
+template <typename R, int TH, bool LEV>
 __global__ __launch_bounds__(TW) void k_sweep_queue(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
                                                     const R *__restrict__ Ptall, R *Tall, uint8_t *codeall,
                                                     int32_t *levall, WorkQueue q, unsigned long long *__restrict__ ctr,
@@ -406,7 +409,7 @@ __global__ __launch_bounds__(TW) void k_sweep_queue(LaunchArgs a, const R *__res
 {
     constexpr int LP = TW + 3;
     __shared__ R sT[(TH + 2) * LP];
-    __shared__ int32_t sL[(TH + 2) * LP];
+    __shared__ int32_t sL[LEV ? (TH + 2) * LP : 1];
     __shared__ uint8_t sC[TH * TW];
     unsigned long long updates = 0;
     for (;;) {
@@ -415,7 +418,7 @@ __global__ __launch_bounds__(TW) void k_sweep_queue(LaunchArgs a, const R *__res
         if (t < 0) break;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); // the neighbours' written-back values
         const Visit v =
-            visit_tile<R, TH, true>(a, t, M, om, Ptall, Tall, codeall, levall, tol, max_cycles, sT, sL, sC);
+            visit_tile<R, TH, true, LEV>(a, t, M, om, Ptall, Tall, codeall, levall, tol, max_cycles, sT, sL, sC);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // this tile's values before its flags
         updates += (unsigned long long)v.sweeps;
         if (threadIdx.x == 0) {
@@ -445,6 +448,291 @@ __global__ void k_queue_reset(WorkQueue q, uint32_t budget)
 {
     const int i = threadIdx.x;
     if (i < kQCtlWords) q.ctl[i] = i == kQBudget ? budget : 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Split update: SUB lanes per node, a workgroup of SUB waves per tile. Lane
+// `sub` of a node evaluates the two-point stencils NS sub .. NS sub + NS - 1
+// (NS = 8 / SUB) and the one-point candidates of their first donors, from
+// per-node constants it forms itself; the group's minimum is taken with
+// cross-lane moves inside the group, ordered by value and then by code, which
+// is the canonical order of the one-lane update. A wave then issues a fraction
+// of the instructions per line step, which shortens the chain of dependent
+// steps that bounds a tile visit.
+// ---------------------------------------------------------------------------
+namespace split {
+
+// neighbour offsets, two bits per k holding offset + 1
+constexpr uint32_t kDx = (0u << 0) | (0u << 2) | (0u << 4) | (1u << 6) | (2u << 8) | (2u << 10) | (2u << 12) | (1u << 14);
+constexpr uint32_t kDy = (2u << 0) | (1u << 2) | (0u << 4) | (0u << 6) | (0u << 8) | (1u << 10) | (2u << 12) | (2u << 14);
+__device__ __forceinline__ int odx(int k) { return (int)((kDx >> (2 * k)) & 3u) - 1; }
+__device__ __forceinline__ int ody(int k) { return (int)((kDy >> (2 * k)) & 3u) - 1; }
+
+// data-parallel-primitive moves inside a group of four lanes
+constexpr int kXor1 = 0xB1; // lanes (1, 0, 3, 2)
+constexpr int kXor2 = 0x4E; // lanes (2, 3, 0, 1)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_r(float v)
+{
+    return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_r(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)(b & 0xffffffffull));
+    const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int CTRL, typename R>
+__device__ __forceinline__ void lex_min(R &v, int &c)
+{
+    const R ov = dpp_r<CTRL>(v);
+    const int oc = dpp_i<CTRL>(c);
+    if (ov < v || (ov == v && oc < c)) {
+        v = ov;
+        c = oc;
+    }
+}
+template <int SUB, typename R>
+__device__ __forceinline__ void group_min(R &v, int &c)
+{
+    if (SUB >= 2) lex_min<kXor1>(v, c);
+    if (SUB >= 4) lex_min<kXor2>(v, c);
+}
+
+// The node's full local update from the NS + 1 donors this lane reads
+// (donor k_q = (NS sub + q) mod 8 has time Tq[q]); code as in local_update.
+template <typename R, int SUB>
+__device__ __forceinline__ R update(int sub, R m11, R m12, R m22, R bx, R by, R h, R inv_h, const R *Tq, int &code)
+{
+    constexpr int NS = 8 / SUB;
+    const R inf = inf_v<R>();
+    R mx[NS + 1], my[NS + 1], e[NS + 1], bm[NS + 1];
+#pragma unroll
+    for (int q = 0; q <= NS; ++q) {
+        const int k = (NS * sub + q) & 7;
+        mx[q] = R(-odx(k)); // receiver minus donor
+        my[q] = R(-ody(k));
+        e[q] = mx[q] * (m11 * mx[q] + m12 * my[q]) + my[q] * (m12 * mx[q] + m22 * my[q]);
+        bm[q] = mx[q] * bx + my[q] * by;
+    }
+    // one-point candidates of donors 0..NS-1, then the group's best
+    R b1 = inf;
+    int c1 = kUnreached;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const R t = Tq[q] + h * (bm[q] + dsqrt(e[q]));
+        if (t < b1) {
+            b1 = t;
+            c1 = 8 + ((NS * sub + q) & 7);
+        }
+    }
+    group_min<SUB>(b1, c1);
+    // two-point stencils whose donors are both below the best one-point value
+    const R det = m11 * m22 - m12 * m12;
+    R b2 = inf;
+    int c2 = kUnreached;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const R Tp = Tq[q], Tr = Tq[q + 1];
+        if (Tp < b1 && Tr < b1) {
+            const R Ep = e[q], Er = e[q + 1];
+            const R Epr = mx[q] * (m11 * mx[q + 1] + m12 * my[q + 1]) + my[q] * (m12 * mx[q + 1] + m22 * my[q + 1]);
+            const R dx = mx[q + 1] - mx[q], dy = my[q + 1] - my[q];
+            const R a = dx * dx * m11 + R(2) * dx * dy * m12 + dy * dy * m22; // m11 or m22 exactly
+            const R delta = (Tr - Tp) * inv_h + (bm[q + 1] - bm[q]);
+            const bool base_r = delta < R(0);
+            const R s1 = base_r ? -delta : R(0);
+            const R s2 = base_r ? R(0) : delta;
+            const R S0 = base_r ? Tr + h * bm[q + 1] : Tp + h * bm[q];
+            const R beta = s1 * (Er - Epr) + s2 * (Ep - Epr);
+            const R c = Er * s1 * s1 + Ep * s2 * s2 - det;
+            const R D = beta * beta - a * c;
+            if (D >= R(0)) {
+                const R tau = (beta + dsqrt(D)) * drcp(a);
+                const R mu1 = Er * (tau - s1) - Epr * (tau - s2);
+                const R mu2 = Ep * (tau - s2) - Epr * (tau - s1);
+                const R t = S0 + h * tau;
+                if (mu1 >= R(0) && mu2 >= R(0) && t > Tp && t > Tr && t < b2) {
+                    b2 = t;
+                    c2 = (NS * sub + q) & 7;
+                }
+            }
+        }
+    }
+    group_min<SUB>(b2, c2);
+    if (b2 <= b1) {
+        code = c2;
+        return b2;
+    }
+    code = c1;
+    return b1;
+}
+
+} // namespace split
+
+template <typename R, int TH, int DIR, int SUB>
+__device__ __forceinline__ bool sweep_dir_split(const TileGeo &g, const R *__restrict__ Mb, const R *__restrict__ Ob,
+                                                R *sT, const uint8_t *sC, R tol, R h, R inv_h)
+{
+    constexpr int LP = TW + 3;
+    constexpr int NS = 8 / SUB;
+    constexpr bool COL = (DIR & 1) == 0;
+    const int node = threadIdx.x / SUB, sub = threadIdx.x % SUB;
+    const int len = COL ? g.w : g.h;
+    const int span = COL ? g.h : g.w;
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    const int lc = node < span ? node : span - 1;
+    auto addr = [&](int s) -> size_t {
+        const int pos = DIR < 2 ? s : len - 1 - s;
+        return COL ? (size_t)(g.i0 + pos) * g.gd.ny + (g.j0 + lc) : (size_t)(g.j0 + pos) * g.gd.nx + (g.i0 + lc);
+    };
+    // the parameters of the next PD lines are in flight while a line is
+    // updated (register ring, static indices through the unrolled inner loop;
+    // addresses past the last line are clamped to it)
+    constexpr int PD = 1;
+    R P[PD][5];
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+        const size_t a0 = addr(d < len ? d : len - 1);
+        P[d][0] = Mb[a0]; P[d][1] = Mb[n + a0]; P[d][2] = Mb[2 * n + a0]; P[d][3] = Ob[a0]; P[d][4] = Ob[n + a0];
+    }
+    bool changed = false;
+    for (int s0 = 0; s0 < len; s0 += PD) {
+#pragma unroll
+        for (int d = 0; d < PD; ++d) {
+            const int s = s0 + d;
+            if (s >= len) break; // uniform over the workgroup
+            const R q0 = P[d][0], q1 = P[d][1], q2 = P[d][2], q3 = P[d][3], q4 = P[d][4];
+            {
+                const size_t an = addr(s + PD < len ? s + PD : len - 1);
+                P[d][0] = Mb[an]; P[d][1] = Mb[n + an]; P[d][2] = Mb[2 * n + an]; P[d][3] = Ob[an];
+                P[d][4] = Ob[n + an];
+            }
+            const int pos = DIR < 2 ? s : len - 1 - s;
+            const int ci = COL ? pos : node;
+            const int cj = COL ? node : pos;
+            // the SUB lanes of a node share this test, so groups stay whole
+            if (node < span && sC[cj * TW + ci] != kSource) {
+                R Tq[NS + 1];
+#pragma unroll
+                for (int q = 0; q <= NS; ++q) {
+                    const int k = (NS * sub + q) & 7;
+                    Tq[q] = sT[(cj + 1 + split::ody(k)) * LP + (ci + 1 + split::odx(k))];
+                }
+                int code;
+                const R v = split::update<R, SUB>(sub, q0, q1, q2, q3, q4, h, inv_h, Tq, code);
+                if (sub == 0) {
+                    const int slot = (cj + 1) * LP + ci + 1;
+                    changed |= counts_as_change<R>(sT[slot], v, tol);
+                    sT[slot] = v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return changed;
+}
+
+// One visit of a tile by SUB waves (full update, no levels carried).
+template <typename R, int TH, int SUB>
+__device__ __forceinline__ Visit visit_tile_split(const LaunchArgs &a, int t, const R *__restrict__ M,
+                                                  const R *__restrict__ om, const R *__restrict__ Ptall, R *Tall,
+                                                  const uint8_t *codeall, R tol, int max_cycles, R *sT, uint8_t *sC,
+                                                  int *sbits)
+{
+    constexpr int LP = TW + 3;
+    const TileGeo g = tile_geo<TH>(a, t);
+    R *T = Tall + g.gd.off;
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    const R *Mg = M + 3 * g.gd.off, *Og = om + 2 * g.gd.off;
+    const R *Pt = Ptall + 5 * g.gd.off, *Pto = Pt + 3 * n;
+    const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
+
+    if (threadIdx.x == 0) *sbits = 0;
+    load_tile_halo<R, TH, LP>(T, sT, g.gd.nx, g.gd.ny, g.i0, g.j0, inf_v<R>());
+    load_block<uint8_t, TH, TW, 0>(codeall + g.gd.off, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
+    __syncthreads();
+
+    int quiet = 0, sweeps = 0;
+    const int max_sweeps = 4 * max_cycles;
+    while (quiet < 4 && sweeps < max_sweeps) {
+        bool ch;
+        switch (sweeps & 3) {
+        case 0: ch = sweep_dir_split<R, TH, 0, SUB>(g, Pt, Pto, sT, sC, tol, h, inv_h); break;
+        case 1: ch = sweep_dir_split<R, TH, 1, SUB>(g, Mg, Og, sT, sC, tol, h, inv_h); break;
+        case 2: ch = sweep_dir_split<R, TH, 2, SUB>(g, Pt, Pto, sT, sC, tol, h, inv_h); break;
+        default: ch = sweep_dir_split<R, TH, 3, SUB>(g, Mg, Og, sT, sC, tol, h, inv_h); break;
+        }
+        ++sweeps;
+        quiet = __syncthreads_or(ch) ? 0 : quiet + 1;
+    }
+
+    // write back: each wave takes rows in turn (old values re-read in batches)
+    int bits = 0;
+    const int c = threadIdx.x % TW;
+    const int wave = threadIdx.x / TW;
+#pragma unroll 1
+    for (int r0 = wave * kLoadBatch; r0 < TH; r0 += SUB * kLoadBatch) {
+        R ov[kLoadBatch];
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+            const int r = r0 + k;
+            const int rc = r < g.h ? r : g.h - 1, cc = c < g.w ? c : g.w - 1;
+            ov[k] = T[(size_t)(g.j0 + rc) * g.gd.nx + g.i0 + cc];
+        }
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+            const int r = r0 + k;
+            if (r >= g.h || c >= g.w) continue;
+            const R nv = sT[(r + 1) * LP + c + 1];
+            if (nv != ov[k]) T[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c] = nv;
+            if (counts_as_change<R>(ov[k], nv, tol)) bits |= halo_bits(c, r, g.w, g.h);
+        }
+    }
+    bits = wave_or(bits);
+    if (threadIdx.x % TW == 0 && bits) atomicOr(sbits, bits);
+    __syncthreads();
+    Visit v;
+    v.bits = *sbits;
+    v.settled = quiet >= 4;
+    v.sweeps = sweeps * g.w * g.h;
+    return v;
+}
+
+template <typename R, int TH, int SUB>
+__global__ __launch_bounds__(TW * SUB) void k_sweep_round_split(LaunchArgs a, const R *__restrict__ M,
+                                                                const R *__restrict__ om,
+                                                                const R *__restrict__ Ptall, R *__restrict__ Tall,
+                                                                const uint8_t *__restrict__ codeall,
+                                                                int32_t *__restrict__ act_in,
+                                                                int32_t *__restrict__ act_out,
+                                                                int32_t *__restrict__ count_next,
+                                                                unsigned long long *__restrict__ ctr, R tol,
+                                                                int max_cycles)
+{
+    constexpr int LP = TW + 3;
+    const int t = blockIdx.x;
+    if (act_in[t] == 0) return; // uniform over the workgroup
+    __shared__ R sT[(TH + 2) * LP];
+    __shared__ uint8_t sC[TH * TW];
+    __shared__ int sbits;
+    __syncthreads(); // every wave has read act_in[t] before it is cleared
+    if (threadIdx.x == 0) act_in[t] = 0;
+    const Visit v =
+        visit_tile_split<R, TH, SUB>(a, t, M, om, Ptall, Tall, codeall, tol, max_cycles, sT, sC, &sbits);
+    if (threadIdx.x == 0) {
+        const TileGeo g = tile_geo<TH>(a, t);
+        flag_neighbours(v.bits, g, act_out, count_next);
+        if (!v.settled) flag_tile(act_out, count_next, t);
+        atomicAdd(&ctr[kCtrCellUpdates], (unsigned long long)v.sweeps);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -511,11 +799,8 @@ __global__ __launch_bounds__(TW) void k_level_round(LaunchArgs a, const uint8_t 
 
     __shared__ int32_t sL[(TH + 2) * LP];
     __shared__ uint8_t sP[TH * TW];
-    load_tile_halo<int32_t, TH, LP>(level, sL, g, -1);
-    for (int idx = lane; idx < TH * TW; idx += TW) {
-        const int r = idx / TW, c = idx - r * TW;
-        sP[idx] = (c < g.w && r < g.h) ? parent[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c] : kUnreached;
-    }
+    load_tile_halo<int32_t, TH, LP>(level, sL, g.gd.nx, g.gd.ny, g.i0, g.j0, -1);
+    load_block<uint8_t, TH, TW, 0>(parent, sP, g.gd.nx, g.gd.ny, g.i0, g.j0, kUnreached);
     __syncthreads();
 
     int quiet = 0, sweeps = 0;
@@ -642,16 +927,31 @@ void launch_all_active(const LaunchArgs &a, int32_t *act, int32_t *act_count, hi
 template <typename R>
 void launch_sweep_round(const LaunchArgs &a, int mode, const void *M, const void *om, const void *Pt, void *T,
                         uint8_t *code, int32_t *level, int32_t *act_in, int32_t *act_out, int32_t *count_next,
-                        unsigned long long *ctr, double tol, int max_cycles, hipStream_t st)
+                        unsigned long long *ctr, double tol, int max_cycles, int node_lanes, hipStream_t st)
 {
-    if (mode == kModeFull)
-        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round<R, TH, true>), dim3(a.n_tiles), dim3(TW), 0, st, a,
-                                                 (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level,
-                                                 act_in, act_out, count_next, ctr, R(tol), max_cycles));
-    else
-        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round<R, TH, false>), dim3(a.n_tiles), dim3(TW), 0, st, a,
-                                                 (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level,
-                                                 act_in, act_out, count_next, ctr, R(tol), max_cycles));
+    if (mode == kModeFull && level == nullptr && node_lanes > 1) {
+#define EIK_SWEEP_SPLIT(SUB)                                                                                     \
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round_split<R, TH, SUB>), dim3(a.n_tiles), dim3(TW * SUB), 0,  \
+                                             st, a, (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code,     \
+                                             act_in, act_out, count_next, ctr, R(tol), max_cycles))
+        if (node_lanes >= 4) EIK_SWEEP_SPLIT(4);
+        else EIK_SWEEP_SPLIT(2);
+#undef EIK_SWEEP_SPLIT
+        return;
+    }
+#define EIK_SWEEP_ROUND(FULL, LEV)                                                                               \
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round<R, TH, FULL, LEV>), dim3(a.n_tiles), dim3(TW), 0, st, a, \
+                                             (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level,     \
+                                             act_in, act_out, count_next, ctr, R(tol), max_cycles))
+    const bool lev = level != nullptr;
+    if (mode == kModeFull) {
+        if (lev) EIK_SWEEP_ROUND(true, true);
+        else EIK_SWEEP_ROUND(true, false);
+    } else {
+        if (lev) EIK_SWEEP_ROUND(false, true);
+        else EIK_SWEEP_ROUND(false, false);
+    }
+#undef EIK_SWEEP_ROUND
 }
 
 void launch_queue_setup(const LaunchArgs &a, int32_t *act, const WorkQueue &q, uint32_t budget, hipStream_t st)
@@ -667,24 +967,31 @@ void launch_sweep_queue(const LaunchArgs &a, int n_waves, const void *M, const v
                         uint8_t *code, int32_t *level, const WorkQueue &q, unsigned long long *ctr, double tol,
                         int max_cycles, hipStream_t st)
 {
-    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_queue<R, TH>), dim3(n_waves), dim3(TW), 0, st, a,
-                                             (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level, q,
-                                             ctr, R(tol), max_cycles));
+    if (level)
+        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_queue<R, TH, true>), dim3(n_waves), dim3(TW), 0, st, a,
+                                                 (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level, q,
+                                                 ctr, R(tol), max_cycles));
+    else
+        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_queue<R, TH, false>), dim3(n_waves), dim3(TW), 0, st, a,
+                                                 (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level, q,
+                                                 ctr, R(tol), max_cycles));
 }
 
-int sweep_queue_waves(int th, int dtype)
+int sweep_queue_waves(int th, int dtype, bool lev)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     hipError_t e;
+#define EIK_OCC(R, TH, LEV) hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_queue<R, TH, LEV>, TW, 0)
     if (dtype == 1)
-        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_queue<double, 64>, TW, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_queue<double, 32>, TW, 0);
+        e = th == 64 ? (lev ? EIK_OCC(double, 64, true) : EIK_OCC(double, 64, false))
+                     : (lev ? EIK_OCC(double, 32, true) : EIK_OCC(double, 32, false));
     else
-        e = th == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_queue<float, 64>, TW, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_queue<float, 32>, TW, 0);
+        e = th == 64 ? (lev ? EIK_OCC(float, 64, true) : EIK_OCC(float, 64, false))
+                     : (lev ? EIK_OCC(float, 32, true) : EIK_OCC(float, 32, false));
+#undef EIK_OCC
     if (e != hipSuccess) return 0;
     return std::max(1, per_cu) * cus;
 }
@@ -733,7 +1040,7 @@ void launch_check_feasible(int64_t n, const void *M, const void *om, unsigned lo
                                  bool, hipStream_t);                                                             \
     template void launch_sweep_round<R>(const LaunchArgs &, int, const void *, const void *, const void *,       \
                                         void *, uint8_t *, int32_t *, int32_t *, int32_t *, int32_t *,           \
-                                        unsigned long long *, double, int, hipStream_t);                         \
+                                        unsigned long long *, double, int, int, hipStream_t);                    \
     template void launch_sweep_queue<R>(const LaunchArgs &, int, const void *, const void *, const void *,       \
                                         void *, uint8_t *, int32_t *, const WorkQueue &, unsigned long long *,   \
                                         double, int, hipStream_t);                                               \

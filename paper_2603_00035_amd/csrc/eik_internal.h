@@ -55,7 +55,6 @@ struct WorkQueue {
 };
 
 constexpr int kMaxRounds = 1 << 16;
-constexpr int kSortChunk = 4096;
 
 enum SweepMode { kModeFast = 0, kModeFull = 1 };
 
@@ -73,7 +72,7 @@ void launch_init(const LaunchArgs &a, const void *T_init, void *T, uint8_t *code
 template <typename R>
 void launch_sweep_round(const LaunchArgs &a, int mode, const void *M, const void *om, const void *Pt, void *T,
                         uint8_t *code, int32_t *level, int32_t *act_in, int32_t *act_out, int32_t *count_next,
-                        unsigned long long *ctr, double tol, int max_cycles, hipStream_t st);
+                        unsigned long long *ctr, double tol, int max_cycles, int node_lanes, hipStream_t st);
 template <typename R>
 void launch_parents(const LaunchArgs &a, const void *M, const void *om, const void *T, uint8_t *parent,
                     hipStream_t st);
@@ -87,7 +86,7 @@ void launch_sweep_queue(const LaunchArgs &a, int n_waves, const void *M, const v
                         uint8_t *code, int32_t *level, const WorkQueue &q, unsigned long long *ctr, double tol,
                         int max_cycles, hipStream_t st);
 // waves of the queue kernel that fit on the device at once
-int sweep_queue_waves(int th, int dtype);
+int sweep_queue_waves(int th, int dtype, bool lev);
 void launch_level_round(const LaunchArgs &a, const uint8_t *parent, int32_t *level, int32_t *act_in,
                         int32_t *act_out, int32_t *count_next, int max_cycles, hipStream_t st);
 void launch_max_level(int64_t n, const int32_t *level, unsigned long long *ctr, hipStream_t st);
@@ -99,15 +98,12 @@ void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_gr
 template <typename R>
 void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const void *T, const uint8_t *parent,
                      void *w1, void *lam, hipStream_t st);
-void launch_adj_sort(const LaunchArgs &a, const int32_t *level, int32_t *list, int32_t *cnt, hipStream_t st);
 template <typename R>
-void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const int32_t *level, const void *w1,
-                      const void *dLdT, const int32_t *list, const int32_t *cnt, void *lam, int32_t *act_in,
-                      int32_t *act_out, int32_t *count_next, hipStream_t st);
+void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const void *w1, const void *dLdT, void *lam,
+                      int max_cycles, int32_t *act_in, int32_t *act_out, int32_t *count_next, hipStream_t st);
 template <typename R>
-void launch_adj_queue(const LaunchArgs &a, int n_waves, const uint8_t *parent, const int32_t *level, const void *w1,
-                      const void *dLdT, const int32_t *list, const int32_t *cnt, void *lam, const WorkQueue &q,
-                      hipStream_t st);
+void launch_adj_queue(const LaunchArgs &a, int n_waves, const uint8_t *parent, const void *w1, const void *dLdT,
+                      void *lam, int max_cycles, const WorkQueue &q, hipStream_t st);
 int adj_queue_waves(int th, int dtype);
 template <typename R>
 void launch_adj_params(const LaunchArgs &a, const void *M, const uint8_t *parent, const void *w1, const void *lam,

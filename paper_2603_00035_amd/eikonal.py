@@ -57,16 +57,17 @@ def workspace(grid: L.EikGrid, dtype_code: int, device) -> torch.Tensor:
 
 
 def tuning(tile_height=0, max_local_cycles=0, rounds_per_check=0, fast_cold_start=-1, adjoint_rounds=0,
-           level_rounds=0, scheduler=0):
+           level_rounds=0, scheduler=0, node_lanes=0, adjoint_cycles=0):
     """Scheduling knobs (0 / -1 keep the library default). scheduler: 1 rounds,
-    2 device work queue."""
+    2 device work queue; node_lanes: 1, 2 or 4 lanes per node update."""
     return L.EikTuning(tile_height, max_local_cycles, rounds_per_check, fast_cold_start, adjoint_rounds,
-                       level_rounds, scheduler)
+                       level_rounds, scheduler, node_lanes, adjoint_cycles)
 
 
 def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=4096, check_feasible=False,
-          tune=None, ws=None, time_kernels=False):
-    """Forward solve. Returns (T, parent, level, Stats)."""
+          tune=None, ws=None, time_kernels=False, levels=True):
+    """Forward solve. Returns (T, parent, level, Stats); level is None when
+    ``levels`` is False (the adjoint does not need it)."""
     _check_fields(M, omega)
     ny, nx = M.shape[1:]
     dev = M.device
@@ -80,7 +81,7 @@ def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=40
         tune = autotune.lookup(nx * ny, autotune.dtype_name(M.dtype))
     T = torch.empty((ny, nx), dtype=M.dtype, device=dev)
     parent = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
-    level = torch.empty((ny, nx), dtype=torch.int32, device=dev)
+    level = torch.empty((ny, nx), dtype=torch.int32, device=dev) if levels else None
     if T_init is not None:
         T_init = T_init.to(device=dev, dtype=M.dtype).contiguous()
     st = L.EikStats()
@@ -97,7 +98,7 @@ def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=40
 
 def adjoint(M, omega, T, parent, level, src_idx, h, dLdT, src_t=None, tune=None, ws=None, stats_out=None):
     """Backward pass. Returns (dL/dM, dL/domega, dL/dt_src); ``stats_out`` (a
-    list) receives the call's Stats."""
+    list) receives the call's Stats. ``level`` is not needed (may be None)."""
     _check_fields(M, omega)
     ny, nx = M.shape[1:]
     dev = M.device
@@ -125,31 +126,35 @@ class EikonalFn(torch.autograd.Function):
     """T = eikonal(M, omega, src_t); gradients by implicit differentiation."""
 
     @staticmethod
-    def forward(ctx, M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink=None, time_kernels=False):
+    def forward(ctx, M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink=None, time_kernels=False,
+                levels=False):
         M = M.contiguous()
         omega = omega.contiguous()
         T, parent, level, stats = solve(M, omega, src_idx, h, src_t=src_t, tol=tol, max_rounds=max_rounds,
-                                        time_kernels=time_kernels)
+                                        time_kernels=time_kernels, levels=levels)
         if stats_sink is not None:
             stats_sink.append(stats)
-        ctx.save_for_backward(M, omega, T, parent, level, src_idx)
+        ctx.save_for_backward(M, omega, T, parent, src_idx)
         ctx.h = h
         ctx.has_src_t = src_t is not None
         ctx.stats = stats
-        ctx.mark_non_differentiable(parent, level)
+        ctx.mark_non_differentiable(parent)
+        if level is not None:
+            ctx.mark_non_differentiable(level)
         return T, parent, level
 
     @staticmethod
     def backward(ctx, gT, _gp=None, _gl=None):
-        M, omega, T, parent, level, src_idx = ctx.saved_tensors
-        dM, dom, ds = adjoint(M, omega, T, parent, level, src_idx, ctx.h, gT)
-        return dM, dom, (ds if ctx.has_src_t else None), None, None, None, None, None, None
+        M, omega, T, parent, src_idx = ctx.saved_tensors
+        dM, dom, ds = adjoint(M, omega, T, parent, None, src_idx, ctx.h, gT)
+        return dM, dom, (ds if ctx.has_src_t else None), None, None, None, None, None, None, None
 
 
-def eikonal(M, omega, src_idx, h, src_t=None, tol=1e-5, max_rounds=4096, stats_sink=None, time_kernels=False):
-    """Differentiable solve; returns (T, parent, level). ``stats_sink`` (a list)
-    receives the forward's Stats."""
-    return EikonalFn.apply(M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink, time_kernels)
+def eikonal(M, omega, src_idx, h, src_t=None, tol=1e-5, max_rounds=4096, stats_sink=None, time_kernels=False,
+            levels=False):
+    """Differentiable solve; returns (T, parent, level) with level None unless
+    ``levels`` is set. ``stats_sink`` (a list) receives the forward's Stats."""
+    return EikonalFn.apply(M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink, time_kernels, levels)
 
 
 def _proj_params(eig_min, eig_max, eucl_clip, rho_max):

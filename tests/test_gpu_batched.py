@@ -45,7 +45,7 @@ def test_batched_fp64_matches_oracle_per_grid(th):
     say(f"[batched fp64] {len(probs)} grids, tile height {th}")
     B = make_batch(probs, torch.float64, tune=E.tuning(tile_height=th))
     M, om, src = packed_inputs(B, probs, torch.float64)
-    T, par, lev, st = B.forward(M, om, src, tol=0.0)
+    T, par, lev, st = B.forward(M, om, src, tol=0.0, levels=True)
     assert st.converged
     Ts, ps, ls = B.unpack_nodes(T), B.unpack_nodes(par), B.unpack_nodes(lev)
     gs = []
@@ -58,7 +58,7 @@ def test_batched_fp64_matches_oracle_per_grid(th):
         assert np.array_equal(ls[g].cpu().numpy(), lo), g
         gs.append(np.random.default_rng(g).uniform(-1, 1, To.shape))
     gT = torch.tensor(np.concatenate([x.ravel() for x in gs]), dtype=torch.float64, device=B.device)
-    dM, dom, ds, rounds = B.backward(M, om, T, par, lev, src, gT)
+    dM, dom, ds, rounds = B.backward(M, om, T, par, None, src, gT)  # the adjoint needs no levels
     dMs, doms = B.unpack_planes(dM, 3), B.unpack_planes(dom, 2)
     for g, p in enumerate(probs):
         To, _, _ = oracle.forward(p)

@@ -25,7 +25,7 @@ def test_stress_2048_forward_and_gradient():
     src = torch.tensor(p.src_idx, device=dev)
     # a fixed loss target independent of either solver: a smooth field in [0, 3]
     target = 3.0 * fourier_field(np.random.default_rng(7), p.nx, p.ny, p.h)
-    T, par, lev = E.eikonal(M, om, src, p.h, tol=1e-5)
+    T, par, lev = E.eikonal(M, om, src, p.h, tol=1e-5, levels=True)
     mask = np.isfinite(target)
     mask.flat[p.src_idx] = False
     n_obs = mask.sum()
