@@ -304,7 +304,11 @@ def main():
         Tg = T_gpu.double().cpu().numpy()
         m = np.isfinite(T_fix)
         m.flat[prob.src_idx] = False
-        out["parity_fwd_max_rel_vs_oracle"] = float(np.max(np.abs(Tg[m] - T_fix[m]) / np.abs(T_fix[m])))
+        rel = np.abs(Tg[m] - T_fix[m]) / np.abs(T_fix[m])
+        out["parity_fwd_max_rel_vs_oracle"] = float(rel.max())
+        # nodes past 1e-5 lie downstream of causality tests decided within FP32
+        # rounding of a tie (checked node by node in the full-size parity test)
+        out["parity_nodes_over_1e-5"] = int((rel > 1e-5).sum())
     print(json.dumps(out), flush=True)
 
 

@@ -56,6 +56,8 @@ def lib():
         L.ora_two_point.restype = i
         L.ora_one_point.argtypes = [dp, dp, d, i, d]
         L.ora_one_point.restype = d
+        L.ora_local_update_all.argtypes = [i, i, d, dp, dp, dp, dp, up]
+        L.ora_local_update_all.restype = None
         L.ora_candidate.argtypes = [i, i, d, dp, dp, dp, i, i, ip]
         L.ora_candidate.restype = d
         L.ora_parents_levels.argtypes = [i, i, d, dp, dp, i, ip, dp, up, ip]
@@ -137,6 +139,16 @@ def local_update(prob, T, c, one_point_only=False):
     v = lib().ora_local_update(prob.nx, prob.ny, prob.h, _dp(M), _dp(om), _dp(T), int(c),
                                int(one_point_only), ctypes.byref(code))
     return v, code.value
+
+
+def local_update_all(prob, T):
+    """The local update evaluated at every node of T (a Jacobi evaluation that
+    changes nothing): (values [ny,nx], codes [ny,nx] uint8)."""
+    M, om, T = _d(prob.M), _d(prob.omega), _d(T)
+    v = np.empty((prob.ny, prob.nx))
+    code = np.empty((prob.ny, prob.nx), np.uint8)
+    lib().ora_local_update_all(prob.nx, prob.ny, prob.h, _dp(M), _dp(om), _dp(T), _dp(v), _p(code, ctypes.c_ubyte))
+    return v, code
 
 
 def candidate(prob, T, c, code):

@@ -234,6 +234,21 @@ double ora_local_update(int nx, int ny, double h, const double *M, const double 
     return local_update(&f, T, c % nx, c / nx, one_point_only, code);
 }
 
+/* The local update evaluated at every node of the field T (no node is
+ * changed), for tests that check whether a field is a fixed point of the
+ * update: out_v[c] and out_code[c] are the minimum candidate and its code. */
+void ora_local_update_all(int nx, int ny, double h, const double *M, const double *om, const double *T,
+                          double *out_v, unsigned char *out_code)
+{
+    ora_field f = {nx, ny, h, M, om};
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int code;
+            out_v[(size_t)j * nx + i] = local_update(&f, T, i, j, 0, &code);
+            out_code[(size_t)j * nx + i] = (unsigned char)code;
+        }
+}
+
 /* Two-point solve exposed for tests: returns validity, candidate, lambda. */
 int ora_two_point(const double g[3], const double b[2], double h, int kp, int kq,
                   double Tp, double Tq, double *T0, double lam[2])

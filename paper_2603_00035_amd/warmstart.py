@@ -30,18 +30,18 @@ def _pack_sources(src):
 
 def solve_batch(M, om, src, h, tol=1e-5, T_init=None, max_rounds=256, tune=None):
     """Equal-size grids M (B,3,ny,nx), omega (B,2,ny,nx), sources (B,max_src).
-    Returns T (B,ny,nx), parent, level, Stats, seconds (synchronised)."""
+    Returns T (B,ny,nx), parent (B,ny,nx), Stats, seconds (synchronised)."""
     B, _, ny, nx = M.shape
     counts, packed = _pack_sources(src)
     batch = Batch([(nx, ny, h, c) for c in counts], dtype=M.dtype, device=M.device, tune=tune,
                   max_rounds=max_rounds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    T, par, lev, st = batch.forward(M.reshape(-1), om.reshape(-1), packed,
-                                    T_init=None if T_init is None else T_init.reshape(-1), tol=tol)
+    T, par, _, st = batch.forward(M.reshape(-1), om.reshape(-1), packed,
+                                  T_init=None if T_init is None else T_init.reshape(-1), tol=tol)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return T.reshape(B, ny, nx), par.reshape(B, ny, nx), lev.reshape(B, ny, nx), st, dt
+    return T.reshape(B, ny, nx), par.reshape(B, ny, nx), st, dt
 
 
 def make_training_set(n, seed0=0, chunk=256, device="cuda"):
@@ -51,7 +51,7 @@ def make_training_set(n, seed0=0, chunk=256, device="cuda"):
     for k in range(0, n, chunk):
         b = min(chunk, n - k)
         M, om, src, h = random_batch(seed0 + k, b, device=device)
-        T, _, _, st, _ = solve_batch(M, om, src, h)
+        T, _, st, _ = solve_batch(M, om, src, h)
         assert st.converged
         Ms.append(M)
         oms.append(om)
@@ -115,17 +115,17 @@ def evaluate(net, seeds, chunk=250, tol=1e-5, log=print):
             src[b, :p.src_idx.size] = torch.tensor(p.src_idx)
         src = src.to(dev)
         h = ps[0].h
-        Tc, _, _, stc, tc = solve_batch(M, om, src, h, tol=tol)
+        Tc, _, stc, tc = solve_batch(M, om, src, h, tol=tol)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         Tinit = predict(net, M, om, src, h)
         torch.cuda.synchronize()
         ti = time.perf_counter() - t0
         budget = stc.rounds + 8
-        Tw, _, _, stw, tw = solve_batch(M, om, src, h, tol=tol, T_init=Tinit, max_rounds=budget)
+        Tw, _, stw, tw = solve_batch(M, om, src, h, tol=tol, T_init=Tinit, max_rounds=budget)
         if not stw.converged:
             res["fallbacks"] += B
-            Tw, _, _, stw2, tw2 = solve_batch(M, om, src, h, tol=tol)
+            Tw, _, stw2, tw2 = solve_batch(M, om, src, h, tol=tol)
             tw += tw2
         m = torch.isfinite(Tc) & (Tc > 0)
         rel = ((Tw - Tc).abs()[m] / Tc[m]).max().item()

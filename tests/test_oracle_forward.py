@@ -177,6 +177,14 @@ def test_fixed_point_is_stationary_and_c1_converges():
             continue
         v, code = oracle.local_update(p, T, c)
         assert v == T.flat[c] and code < 16
+    # the all-node evaluation agrees with the one-node one and leaves a zero
+    # residual at every reached non-source node
+    va, ca = oracle.local_update_all(p, T)
+    m = np.isfinite(T)
+    m.flat[p.src_idx] = False
+    assert np.array_equal(va[m], T[m])
+    for c in np.random.default_rng(1).choice(p.n, 50, replace=False):
+        assert (va.flat[c], int(ca.flat[c])) == oracle.local_update(p, T, c)
 
 
 def test_grid_spacing_scaling_and_homogeneity():
