@@ -42,6 +42,8 @@ WORKLOADS = {
     "c2": "512x512 FP32, eigenvalue ratio 4, drift 0.7, 4 sources, fwd to 1e-5 + adjoint",
     "c4": "256 grids with sides U{64..512} FP32, eigenvalue ratio 4, drift 0.5, 1-4 sources each, "
           "fwd to 1e-5 + adjoint, one HIP graph replay per step",
+    "c5": "256x256 FP32 forward to 1e-5 on held-out seeds, batches of 250: cold start vs the learned BF16 "
+          "U-Net warm start (inference included) with and without the fixed-budget fallback",
 }
 
 
@@ -82,6 +84,35 @@ def cpu_baseline(prob, tol):
     return {"value": prob.n * sweeps / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"one full {prob.nx}x{prob.ny} solve to {tol:g} ({sweeps} Gauss-Seidel sweeps, FP64) "
                       f"+ stencil/level pass + VJP, single thread, {dt:.1f} s"}, T
+
+
+def bench_warm(args):
+    """The learned warm start against the cold start on held-out seeds (the
+    committed weights), each side timed over whole batched solves."""
+    import torch
+
+    from paper_2603_00035_amd import warmstart as W
+    from paper_2603_00035_amd.unet import UNet
+
+    net = UNet()
+    net.load_state_dict(torch.load(W.WEIGHTS, weights_only=True))
+    seeds = list(range(1_000_000 + args.seed, 1_000_000 + args.seed + 250 * args.steps))
+    W.evaluate(net, seeds[:250], chunk=250, tol=args.tol, log=lambda s: None)  # warm-up
+    r = W.evaluate(net, seeds, chunk=250, tol=args.tol, log=lambda s: None)
+    n = r["grids"]
+    return {
+        "metric": "cell-updates/s; fwd+adjoint ms to 1e-5 at 2048^2; learned warm vs cold",
+        "value": r["cold_updates"] / r["cold_s"], "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * r["cold_s"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c5: {WORKLOADS['c5']}", "grids": n, "tol": args.tol},
+        "cold_ms_per_grid": 1e3 * r["cold_s"] / n, "warm_ms_per_grid": 1e3 * r["warm_s"] / n,
+        "warm_with_fallback_ms_per_grid": 1e3 * r["warm_fb_s"] / n, "inference_ms_per_grid": 1e3 * r["infer_s"] / n,
+        "cold_sweeps_per_node": r["cold_sweeps_per_node"], "warm_sweeps_per_node": r["warm_sweeps_per_node"],
+        "warm_speedup": r["speedup_warm"], "warm_with_fallback_speedup": r["speedup_warm_with_fallback"],
+        "prediction_rel_err_mean": sum(r["pred_rel_err_mean"]) / len(r["pred_rel_err_mean"]),
+        "max_rel_warm_vs_cold": r["max_rel_warm_vs_cold"], "roofline": None, "cpu_baseline": None,
+    }
 
 
 def bench_batched(args):
@@ -203,6 +234,9 @@ def main():
 
     if args.workload == "c4":
         print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(bench_warm(args)), flush=True)
         return
 
     dev = torch.device("cuda:0")

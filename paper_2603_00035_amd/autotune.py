@@ -34,9 +34,15 @@ DEFAULTS = {"tile_height": 64, "max_local_cycles": 1, "rounds_per_check": 8, "fa
 CANDIDATES = {"tile_height": (32, 64), "max_local_cycles": (1, 2, 3), "rounds_per_check": (4, 8, 16),
               "fast_cold_start": (0, 1), "adjoint_rounds": (16, 64, 256), "level_rounds": (4, 8, 16),
               "scheduler": (1, 2), "node_lanes": (1, 2, 4), "adjoint_cycles": (1, 2)}
-# size classes by node count: (upper bound, representative side, problem recipe)
+# knobs timed by the tuner (the unsynchronised round budgets are sized for
+# correctness, not speed, and keep their defaults)
+TUNED = ("tile_height", "max_local_cycles", "rounds_per_check", "fast_cold_start", "scheduler", "node_lanes",
+         "adjoint_cycles")
+# single-grid size classes by node count: (upper bound, representative side, problem recipe)
 CLASSES = ((96 * 96, 64, "c1"), (384 * 384, 256, "c1"), (768 * 768, 512, "c2"), (1536 * 1536, 1024, "c3"),
            (1 << 62, 2048, "c3"))
+# batch classes by total node count: (upper bound, grids in the representative batch)
+BATCH_CLASSES = ((8 << 20, 64), (1 << 62, 256))
 
 _cache = {}
 
@@ -51,15 +57,16 @@ def _load(path=TABLE):
     return _cache[path]
 
 
-def lookup(n_nodes, dtype_name, path=TABLE):
-    """EikTuning for a grid of ``n_nodes`` nodes in dtype "f32"/"f64", or None
-    when the table is absent or has no entry for that dtype."""
+def lookup(n_nodes, dtype_name, kind="single", path=TABLE):
+    """EikTuning for a grid (kind "single") or a batch (kind "batch") of
+    ``n_nodes`` nodes in dtype "f32"/"f64", or None when the table is absent or
+    has no entry for that dtype and kind."""
     table = _load(path)
     if not table:
         return None
     best = None
     for e in table.get("entries", []):
-        if e["dtype"] != dtype_name:
+        if e["dtype"] != dtype_name or e.get("kind", "single") != kind:
             continue
         if n_nodes <= e["max_nodes"] and (best is None or e["max_nodes"] < best["max_nodes"]):
             best = e
@@ -87,10 +94,48 @@ def _problem(recipe, side, seed, dtype):
     return M, om, src, p.h, g
 
 
+def _batch_problem(n_grids, seed0, dtype):
+    import numpy as np
+    import torch
+    from synthetic.fields import batched_set
+    probs = batched_set(n_grids, seed0)
+    dev = torch.device("cuda")
+    cat = lambda xs: torch.tensor(np.concatenate([x.reshape(-1) for x in xs]), dtype=dtype, device=dev)
+    M, om = cat([p.M for p in probs]), cat([p.omega for p in probs])
+    src = torch.tensor(np.concatenate([p.src_idx for p in probs]), dtype=torch.int32, device=dev)
+    shapes = [(p.nx, p.ny, p.h, p.src_idx.size) for p in probs]
+    g = torch.rand(M.numel() // 3, generator=torch.Generator(device=dev).manual_seed(seed0), device=dev, dtype=dtype)
+    return ("batch", shapes, M, om, src, g)
+
+
+def time_batch(prob, knobs, tol, reps=3):
+    """Median wall time (ms) of one batched forward + adjoint with these knobs."""
+    import torch
+    from .batched import Batch
+    _, shapes, M, om, src, g = prob
+    tn = L.EikTuning(*[int(knobs[k]) for k in KNOBS])
+    B = Batch(shapes, dtype=M.dtype, device=M.device, tune=tn, max_rounds=4096)
+    times = []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T, par, _, st = B.forward(M, om, src, tol=tol)
+        B.backward(M, om, T, par, None, src, g)
+        torch.cuda.synchronize()
+        if r:
+            times.append(1e3 * (time.perf_counter() - t0))
+        if not st.converged:
+            return float("inf")
+    times.sort()
+    return times[len(times) // 2]
+
+
 def time_fwd_adj(prob, knobs, tol, reps=3):
     """Median wall time (ms) of one forward + adjoint with these knobs."""
     import torch
     from . import eikonal as E
+    if prob[0] == "batch":
+        return time_batch(prob, knobs, tol, reps)
     M, om, src, h, g = prob
     tn = L.EikTuning(*[int(knobs[k]) for k in KNOBS])
     ws = E.workspace(E.make_grid(M.shape[2], M.shape[1], h, src), L.dtype_code(M), M.device)
@@ -98,8 +143,8 @@ def time_fwd_adj(prob, knobs, tol, reps=3):
     for r in range(reps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        T, par, lev, st = E.solve(M, om, src, h, tol=tol, tune=tn, ws=ws)
-        E.adjoint(M, om, T, par, lev, src, h, g, tune=tn, ws=ws)
+        T, par, _, st = E.solve(M, om, src, h, tol=tol, tune=tn, ws=ws, levels=False)
+        E.adjoint(M, om, T, par, None, src, h, g, tune=tn, ws=ws)
         torch.cuda.synchronize()
         if r:
             times.append(1e3 * (time.perf_counter() - t0))
@@ -115,7 +160,7 @@ def tune_class(prob, tol, passes=2, log=print):
     best_t = base
     for _ in range(passes):
         changed = False
-        for k in KNOBS:
+        for k in TUNED:
             for v in CANDIDATES[k]:
                 if v == cur[k]:
                     continue
@@ -147,8 +192,17 @@ def main():
             print(f"[tune] {dn} {side}x{side} ({recipe})", flush=True)
             knobs, t, base = tune_class(prob, args.tol)
             print(f"[tune] {dn} {side}x{side}: {base:.3f} ms -> {t:.3f} ms with {knobs}", flush=True)
-            entries.append({"dtype": dn, "max_nodes": max_nodes, "side": side, "recipe": recipe,
+            entries.append({"kind": "single", "dtype": dn, "max_nodes": max_nodes, "side": side, "recipe": recipe,
                             "tuning": knobs, "ms_fwd_adj": round(t, 4), "ms_default": round(base, 4)})
+        if dn == "f32":
+            for max_nodes, n_grids in BATCH_CLASSES:
+                prob = _batch_problem(n_grids, 1000, dtype)
+                print(f"[tune] {dn} batch of {n_grids} grids", flush=True)
+                knobs, t, base = tune_class(prob, args.tol)
+                print(f"[tune] {dn} batch of {n_grids}: {base:.3f} ms -> {t:.3f} ms with {knobs}", flush=True)
+                entries.append({"kind": "batch", "dtype": dn, "max_nodes": max_nodes, "grids": n_grids,
+                                "recipe": "c4", "tuning": knobs, "ms_fwd_adj": round(t, 4),
+                                "ms_default": round(base, 4)})
     out = {"device": torch.cuda.get_device_name(0), "tol": args.tol, "knobs": list(KNOBS), "entries": entries}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)

@@ -32,7 +32,8 @@ class Batch:
         self.device = torch.device(device)
         self.dc = L.dtype_code(torch.empty(0, dtype=dtype))
         if tune is None:
-            tune = autotune.lookup(max(nx * ny for nx, ny, _, _ in self.shapes), autotune.dtype_name(dtype))
+            tune = autotune.lookup(sum(nx * ny for nx, ny, _, _ in self.shapes), autotune.dtype_name(dtype),
+                                   kind="batch")
         self.tune = tune
         self.max_rounds = max_rounds
         G = L.EikGrid * self.n_grids

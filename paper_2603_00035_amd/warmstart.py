@@ -98,13 +98,19 @@ def predict(net, M, om, src, h):
 
 
 def evaluate(net, seeds, chunk=250, tol=1e-5, log=print):
-    """Warm vs cold on held-out seeds of the numpy generator. A warm solve that
-    does not reach tol within the cold solve's round count plus a margin falls
-    back to a cold solve (its time is then charged to the warm side)."""
+    """Warm vs cold on held-out seeds of the numpy generator, batched.
+
+    cold: the cold-start solve. warm: inference + the solve from the network's
+    field, run to convergence (its sweeps, time and distance to the cold
+    result). warm_fb: the deployable policy -- the warm solve gets a round
+    budget fixed in advance (twice the tiles across plus 8, far above what a
+    cold solve of this size needs); if it has not converged by then, the cold
+    solve runs and both are charged."""
     from synthetic.fields import make_problem
     dev = torch.device("cuda")
-    res = {"grids": 0, "cold_s": 0.0, "warm_s": 0.0, "infer_s": 0.0, "cold_updates": 0, "warm_updates": 0,
-           "cold_rounds": [], "warm_rounds": [], "fallbacks": 0, "max_rel_diff": 0.0}
+    res = {"grids": 0, "cold_s": 0.0, "warm_s": 0.0, "warm_fb_s": 0.0, "infer_s": 0.0, "cold_updates": 0,
+           "warm_updates": 0, "cold_rounds": [], "warm_rounds": [], "fallback_batches": 0, "batches": 0,
+           "max_rel_warm_vs_cold": 0.0, "pred_rel_err_mean": [], "pred_rel_err_p99": []}
     for k in range(0, len(seeds), chunk):
         ps = [make_problem("c5", int(s)) for s in seeds[k:k + chunk]]
         B = len(ps)
@@ -115,35 +121,45 @@ def evaluate(net, seeds, chunk=250, tol=1e-5, log=print):
             src[b, :p.src_idx.size] = torch.tensor(p.src_idx)
         src = src.to(dev)
         h = ps[0].h
+        ny, nx = M.shape[2], M.shape[3]
         Tc, _, stc, tc = solve_batch(M, om, src, h, tol=tol)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         Tinit = predict(net, M, om, src, h)
         torch.cuda.synchronize()
         ti = time.perf_counter() - t0
-        budget = stc.rounds + 8
-        Tw, _, stw, tw = solve_batch(M, om, src, h, tol=tol, T_init=Tinit, max_rounds=budget)
-        if not stw.converged:
-            res["fallbacks"] += B
-            Tw, _, stw2, tw2 = solve_batch(M, om, src, h, tol=tol)
-            tw += tw2
         m = torch.isfinite(Tc) & (Tc > 0)
+        perr = ((Tinit - Tc).abs()[m] / Tc[m]).float()
+        Tw, _, stw, tw = solve_batch(M, om, src, h, tol=tol, T_init=Tinit, max_rounds=4096)
+        budget = 2 * ((nx + 63) // 64 + (ny + 63) // 64) + 8
+        _, _, stb, tb = solve_batch(M, om, src, h, tol=tol, T_init=Tinit, max_rounds=budget)
+        t_fb = ti + tb
+        if not stb.converged:
+            res["fallback_batches"] += 1
+            t_fb += tc
         rel = ((Tw - Tc).abs()[m] / Tc[m]).max().item()
         res["grids"] += B
+        res["batches"] += 1
         res["cold_s"] += tc
         res["warm_s"] += tw + ti
+        res["warm_fb_s"] += t_fb
         res["infer_s"] += ti
         res["cold_updates"] += stc.cell_updates
         res["warm_updates"] += stw.cell_updates
         res["cold_rounds"].append(stc.rounds)
         res["warm_rounds"].append(stw.rounds)
-        res["max_rel_diff"] = max(res["max_rel_diff"], rel)
-        log(f"eval {k + B}/{len(seeds)}: cold {tc * 1e3:.1f} ms ({stc.rounds} rounds), warm {tw * 1e3:.1f} ms "
-            f"+ inference {ti * 1e3:.1f} ms ({stw.rounds} rounds), max rel diff {rel:.2e}")
+        res["max_rel_warm_vs_cold"] = max(res["max_rel_warm_vs_cold"], rel)
+        res["pred_rel_err_mean"].append(perr.mean().item())
+        res["pred_rel_err_p99"].append(torch.quantile(perr[:1 << 24], 0.99).item())
+        log(f"eval {k + B}/{len(seeds)}: cold {tc * 1e3:.1f} ms ({stc.rounds} rounds, "
+            f"{stc.cell_updates / (B * nx * ny):.1f} sweeps/node); warm {tw * 1e3:.1f} ms + inference {ti * 1e3:.1f} ms "
+            f"({stw.rounds} rounds, {stw.cell_updates / (B * nx * ny):.1f} sweeps/node); prediction rel err mean "
+            f"{perr.mean().item():.2e}; warm vs cold max rel diff {rel:.2e}")
     n_cells = res["grids"] * 256 * 256
     res["cold_sweeps_per_node"] = res["cold_updates"] / n_cells
     res["warm_sweeps_per_node"] = res["warm_updates"] / n_cells
-    res["speedup"] = res["cold_s"] / res["warm_s"]
+    res["speedup_warm"] = res["cold_s"] / res["warm_s"]
+    res["speedup_warm_with_fallback"] = res["cold_s"] / res["warm_fb_s"]
     return res
 
 
