@@ -2,22 +2,28 @@
 """Benchmark of the hot path on one MI355X.
 
 One step = feasibility projection (eik_project) -> forward fast-sweeping solve
-to 1e-5 relative change (eik_forward: sweeps, convergence test, active stencils,
-dependency levels) -> dense mean-squared loss against a target field -> adjoint
-(eik_backward: level bucketing, level-scheduled gather, parameter gradients)
--> projection VJP, all through the torch.autograd.Function wrappers.
+to 1e-5 relative change (eik_forward_mixed: FP32 sweeps, then FP64 sweeps from
+that field; active stencils) -> dense mean-squared loss against a fixed target
+field -> adjoint (eik_backward_mixed: donor weights, directional relaxation of
+the adjoint equations, parameter gradients) -> projection VJP, all through the
+torch.autograd.Function wrappers. --precision f32 times the plain FP32 path
+(eik_forward / eik_backward in FP32); by default the other precision is timed
+beside the headline one and reported under "compare".
 
-Workload (default): 2048 x 2048 FP32 stress case -- eigenvalue ratio 10, drift
-norm up to 0.9, 4 sharp-edged regions with rotated principal directions,
-16 random sources; target from the seed+1 fields. Inputs are seeded synthetic
-fields resident in HBM before timing starts.
+Workload (default): 2048 x 2048 stress case -- eigenvalue ratio 10, drift norm
+up to 0.9, 4 sharp-edged regions with rotated principal directions, 16 random
+sources, parameters rounded to FP32; the loss target is a smooth random field
+in [0, 3] that no solver produced. Inputs are seeded synthetic fields resident
+in HBM before timing starts.
 
 Prints one JSON line: value = cell-updates per second over the timed steps
-(all local-update evaluations of the forward divided by the whole step time,
-adjoint included); ms_per_step = forward + adjoint ms; roofline = achieved
-algorithmic bandwidth of the tile-sweep kernel (28 bytes per FP32 cell-update)
-against the 8 TB/s HBM peak, its launches timed with HIP events on the stream
-they run on; cpu_baseline = the FP64 oracle timed on the host.
+(all local-update evaluations of both forward phases divided by the whole step
+time, adjoint included); ms_per_step = forward + adjoint ms; roofline =
+achieved algorithmic bandwidth of the FP32 tile-sweep kernel (28 bytes per
+FP32 cell-update) against the 8 TB/s HBM peak, its launches timed with HIP
+events on the stream they run on; cpu_baseline = the FP64 oracle timed on the
+host; parity_* = the timed solve's field and gradient against the oracle's
+exact fixed point and its gradient of the same loss.
 """
 from __future__ import annotations
 
@@ -44,6 +50,13 @@ WORKLOADS = {
           "fwd to 1e-5 + adjoint, one HIP graph replay per step",
     "c5": "256x256 FP32 forward to 1e-5 on held-out seeds, batches of 250: cold start vs the learned BF16 "
           "U-Net warm start (inference included) with and without the fixed-budget fallback",
+}
+
+
+PRECISIONS = {
+    "mixed": "FP32 sweeps to tol, FP64 sweeps from that field to tol, adjoint with FP64 weights and parameter "
+             "derivatives and an FP32 relaxation",
+    "f32": "FP32 throughout",
 }
 
 
@@ -216,6 +229,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--precision", default="mixed", choices=sorted(PRECISIONS))
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after the steps, copy a 1 GiB buffer once (a plain copy kernel of known size that "
@@ -230,7 +245,7 @@ def main():
     import torch
 
     from paper_2603_00035_amd import eikonal as E
-    from synthetic.fields import make_problem
+    from synthetic.fields import fourier_field, make_problem
 
     if args.workload == "c4":
         print(json.dumps(bench_batched(args)), flush=True)
@@ -241,84 +256,112 @@ def main():
 
     dev = torch.device("cuda:0")
     prob = make_problem(args.workload, args.seed)
-    tgt = make_problem(args.workload, args.seed + 1)
-    dt = torch.float32
-    M0 = torch.tensor(prob.M, dtype=dt, device=dev)
-    om0 = torch.tensor(prob.omega, dtype=dt, device=dev)
+    q = prob.rounded(np.float32)  # FP32-representable inputs, shared by both precisions and the oracle
     src = torch.tensor(prob.src_idx, dtype=torch.int32, device=dev)
-    Mt = torch.tensor(tgt.M, dtype=dt, device=dev)
-    omt = torch.tensor(tgt.omega, dtype=dt, device=dev)
-    target, _, _, _ = E.solve(Mt, omt, src, prob.h, tol=args.tol, levels=False)
-    mask = torch.isfinite(target)
-    mask.view(-1)[src.long()] = False
-    n_obs = int(mask.sum())
-    torch.cuda.synchronize()
+    # a fixed loss target independent of any solver: a smooth field in [0, 3]
+    target_np = 3.0 * fourier_field(np.random.default_rng(args.seed + 7), prob.nx, prob.ny, prob.h)
+    mask_np = np.isfinite(target_np)
+    mask_np.flat[prob.src_idx] = False
+    n_obs = int(mask_np.sum())
+    mask = torch.tensor(mask_np, device=dev)
 
-    def step(sink, t_ev):
-        M = M0.detach().requires_grad_(True)
-        om = om0.detach().requires_grad_(True)
-        t_ev[0].record()
-        Mp, omp = E.ProjectFn.apply(M, om)
-        T, _, _ = E.eikonal(Mp, omp, src, prob.h, tol=args.tol, stats_sink=sink, time_kernels=True)
-        d = torch.where(mask, T - target, torch.zeros_like(T))
-        loss = (d * d).sum() / n_obs
-        t_ev[1].record()
-        loss.backward()
-        t_ev[2].record()
-        return M.grad, om.grad
+    def run(precision):
+        dt = torch.float64 if precision == "mixed" else torch.float32
+        M0 = torch.tensor(q.M, dtype=dt, device=dev)
+        om0 = torch.tensor(q.omega, dtype=dt, device=dev)
+        target = torch.tensor(target_np, dtype=dt, device=dev)
+        torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
-        step([], [torch.cuda.Event(enable_timing=True) for _ in range(3)])
-    torch.cuda.synchronize()
+        def step(sink, t_ev):
+            M = M0.detach().requires_grad_(True)
+            om = om0.detach().requires_grad_(True)
+            t_ev[0].record()
+            Mp, omp = E.ProjectFn.apply(M, om)
+            T, _, _ = E.eikonal(Mp, omp, src, prob.h, tol=args.tol, stats_sink=sink, time_kernels=True,
+                                precision=None if precision == "f32" else precision)
+            d = torch.where(mask, T - target, torch.zeros_like(T))
+            loss = (d * d).sum() / n_obs
+            t_ev[1].record()
+            loss.backward()
+            t_ev[2].record()
+            return T, M.grad, om.grad
 
-    sink = []
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        gM, gom = step(sink, evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    updates = sum(s.cell_updates for s in sink)
-    sweep_ms = sum(s.sweep_ms for s in sink)
-    launches = sum(s.sweep_launches for s in sink)
-    assert all(s.converged for s in sink), "solve did not reach the tolerance"
-    assert torch.isfinite(gM).all() and torch.isfinite(gom).all()
+        for _ in range(args.warmup):
+            step([], [torch.cuda.Event(enable_timing=True) for _ in range(3)])
+        torch.cuda.synchronize()
+        sink = []
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            T, gM, gom = step(sink, evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        assert all(s.converged for s in sink[(1 if precision == "mixed" else 0)::(2 if precision == "mixed" else 1)]), \
+            "solve did not reach the tolerance"
+        assert torch.isfinite(gM).all() and torch.isfinite(gom).all()
+        # FP32 sweep launches: every stats entry of the FP32 path, the first
+        # phase of each mixed solve
+        s32 = sink[0::2] if precision == "mixed" else sink
+        s64 = sink[1::2] if precision == "mixed" else []
+        return dict(wall=wall, sink=sink, s32=s32, s64=s64,
+                    fwd_ms=float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+                    adj_ms=float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
+                    T=T.detach().double().cpu().numpy(), gM=gM.double().cpu().numpy(), gom=gom.double().cpu().numpy())
 
+    head = run(args.precision)
+    other = None if args.no_compare else run("f32" if args.precision == "mixed" else "mixed")
+
+    def figures(r):
+        updates = sum(s.cell_updates for s in r["sink"])
+        return dict(value=updates / r["wall"], ms_per_step=1e3 * r["wall"] / args.steps, fwd_ms=round(r["fwd_ms"], 3),
+                    adj_ms=round(r["adj_ms"], 3), sweeps_per_cell=round(updates / args.steps / prob.n, 2),
+                    rounds=[s.rounds for s in r["sink"][-(2 if r["s64"] else 1):]])
+
+    fh = figures(head)
+    u32 = sum(s.cell_updates for s in head["s32"])
+    ms32 = sum(s.sweep_ms for s in head["s32"])
     bpu = BYTES_PER_UPDATE["f32"]
-    achieved = bpu * updates / (sweep_ms / 1e3) / 1e9 if sweep_ms > 0 else 0.0
-    tb = traffic_bytes()
+    achieved = bpu * u32 / (ms32 / 1e3) / 1e9 if ms32 > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": tb, "kernel": "k_sweep_round",
-            "launches": launches, "kernel_ms": round(sweep_ms / args.steps, 3),
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic_bytes(), "kernel": "k_sweep_round_split<float>",
+            "launches": sum(s.sweep_launches for s in head["s32"]), "kernel_ms": round(ms32 / args.steps, 3),
             "algorithmic_bytes_per_update": bpu}
+    if head["s64"]:
+        u64 = sum(s.cell_updates for s in head["s64"])
+        ms64 = sum(s.sweep_ms for s in head["s64"])
+        roof["fp64_phase"] = {"kernel": "k_sweep_round_split<double>", "kernel_ms": round(ms64 / args.steps, 3),
+                              "updates_per_cell": round(u64 / args.steps / prob.n, 2),
+                              "achieved_GBs": round(BYTES_PER_UPDATE["f64"] * u64 / (ms64 / 1e3) / 1e9, 2)
+                              if ms64 > 0 else 0.0}
 
     out = {
         "metric": "cell-updates/s; fwd+adjoint ms to 1e-5 at 2048^2; learned warm vs cold",
-        "value": updates / wall,
+        "value": fh["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": fh["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+f64" if args.precision == "mixed" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "nx": prob.nx, "ny": prob.ny,
-                   "n_src": int(prob.src_idx.size), "tol": args.tol, "seed": args.seed},
-        "fwd_ms": round(fwd_ms, 3),
-        "adj_ms": round(adj_ms, 3),
-        "sweeps_per_cell": round(updates / args.steps / prob.n, 2),
-        "rounds": sink[-1].rounds,
-        "n_levels": sink[-1].n_levels,
+                   "n_src": int(prob.src_idx.size), "tol": args.tol, "seed": args.seed,
+                   "precision": PRECISIONS[args.precision]},
+        "fwd_ms": fh["fwd_ms"],
+        "adj_ms": fh["adj_ms"],
+        "sweeps_per_cell": fh["sweeps_per_cell"],
+        "rounds": fh["rounds"],
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if other is not None:
+        fo = figures(other)
+        out["compare"] = {"precision": PRECISIONS["f32" if args.precision == "mixed" else "mixed"],
+                          **{k: (round(v, 3) if isinstance(v, float) and k != "value" else v) for k, v in fo.items()}}
     if args.copy_calib:
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -328,21 +371,31 @@ def main():
         out["copy_calib_bytes"] = {"read": a.numel() * 4, "write": b.numel() * 4}
         del a, b
     if not args.no_cpu_baseline:
+        import oracle
         cb, T_ora = cpu_baseline(prob, args.tol)
         out["cpu_baseline"] = cb
-        # parity of the timed GPU solve against the oracle's exact fixed point
-        # (the oracle's tol run continued to stationarity, outside the timing)
-        import oracle
-        T_fix, _, _ = oracle.forward(prob.rounded(np.float32), tol=0.0, T_init=T_ora)
-        T_gpu, _, _, _ = E.solve(M0, om0, src, prob.h, tol=args.tol, levels=False)
-        Tg = T_gpu.double().cpu().numpy()
+        # parity of the timed GPU solves against the oracle's exact fixed point
+        # (the oracle's tol run continued to stationarity) and its gradient of
+        # the same loss, outside the timing; the projection is inactive on
+        # this workload, so the oracle's gradient is the parameters' gradient
+        T_fix, _, _ = oracle.forward(q, tol=0.0, T_init=T_ora)
+        par_fix, _ = oracle.parents_levels(q, T_fix)
+        g = np.zeros_like(T_fix)
+        g[mask_np] = 2.0 * (T_fix[mask_np] - target_np[mask_np]) / n_obs
+        dMo, domo, _ = oracle.vjp(q, T_fix, par_fix, g)
         m = np.isfinite(T_fix)
         m.flat[prob.src_idx] = False
-        rel = np.abs(Tg[m] - T_fix[m]) / np.abs(T_fix[m])
-        out["parity_fwd_max_rel_vs_oracle"] = float(rel.max())
-        # nodes past 1e-5 lie downstream of causality tests decided within FP32
-        # rounding of a tie (checked node by node in the full-size parity test)
-        out["parity_nodes_over_1e-5"] = int((rel > 1e-5).sum())
+
+        def parity(r):
+            rel = np.abs(r["T"][m] - T_fix[m]) / np.abs(T_fix[m])
+            num = float(np.sum((r["gM"] - dMo) ** 2) + np.sum((r["gom"] - domo) ** 2))
+            den = float(np.sum(dMo ** 2) + np.sum(domo ** 2))
+            return {"parity_fwd_max_rel_vs_oracle": float(rel.max()), "parity_nodes_over_1e-5": int((rel > 1e-5).sum()),
+                    "parity_grad_rel_l2_vs_oracle": (num / den) ** 0.5}
+
+        out.update(parity(head))
+        if other is not None:
+            out["compare"].update(parity(other))
     print(json.dumps(out), flush=True)
 
 

@@ -124,9 +124,10 @@ size_t eik_workspace_bytes(const eik_grid *grid, int32_t dtype);
 
 /* Forward solve (Sec. 3.2, Alg. forward).
  *   M, omega  inputs as laid out above;
- *   T_init    optional [ny][nx] initial field (warm start) or NULL for the
- *             cold start (+inf away from the sources); the update overwrites
- *             T rather than taking a minimum with the previous value;
+ *   T_init    optional [ny][nx] initial field (warm start; may be T itself)
+ *             or NULL for the cold start (+inf away from the sources); the
+ *             update overwrites T rather than taking a minimum with the
+ *             previous value;
  *   tol       a node counts as changed when |dT| > tol |T| (or it changes
  *             between finite and infinite); the solve ends when a full
  *             four-direction cycle leaves no node changed. tol = 0 asks for
@@ -144,6 +145,27 @@ int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *
                 double tol, int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level,
                 void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
 
+/* Mixed-precision forward: the solve of eik_forward on FP64 parameters in two
+ * phases. FP32 sweeps from the cold start, on FP32-rounded copies of M, omega
+ * and the source times, run to tol32 (EIK_NOT_CONVERGED there is not an
+ * error); FP64 sweeps then continue from that field, in place in T, to tol.
+ * The FP32 phase carries the front across the grid at FP32 cost; the FP64
+ * phase removes the FP32 rounding that the arrival times accumulate along
+ * their characteristics, to which the adjoint's local derivatives are
+ * sensitive. M, omega, grid->src_t (or NULL), T are double; parent and level
+ * as in eik_forward, both written by the FP64 phase. max_rounds bounds each
+ * phase. EIK_CHECK_FEASIBLE tests the FP32 copies. tuning32 and tuning
+ * (each optional) drive the two phases; stats is NULL or an array of two
+ * (FP32 phase, FP64 phase). The workspace comes from
+ * eik_mixed_workspace_bytes. The FP64 state it returns feeds eik_backward
+ * with EIK_F64. Errors as eik_forward; the status is that of the FP64 phase
+ * unless the FP32 phase failed. */
+size_t eik_mixed_workspace_bytes(const eik_grid *grid);
+int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega, double tol32, double tol,
+                      int32_t max_rounds, int32_t flags, double *T, uint8_t *parent, int32_t *level, void *ws,
+                      size_t ws_bytes, const eik_tuning *tuning32, const eik_tuning *tuning, eik_stats *stats,
+                      hipStream_t stream);
+
 /* Adjoint (Sec. 3.3, Alg. backward): given dL/dT and the saved state
  * (M, omega, T, parent) of eik_forward, writes dL/dM [3][ny][nx]
  * (derivatives with respect to the stored m11, m12, m22), dL/domega
@@ -158,6 +180,17 @@ int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void 
                  const uint8_t *parent, const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega,
                  void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats,
                  hipStream_t stream);
+
+/* Adjoint of the mixed-precision forward's FP64 state: the eik_backward
+ * computation with the donor weights and the parameter derivatives in FP64
+ * from (M, omega, T), and the adjoint relaxation itself in FP32 (lambda is a
+ * sum of weight-times-lambda terms, which FP32 carries to about 1e-6
+ * relative; the sensitivity of the gradient to T sits in the weights, which
+ * stay FP64-derived). All real arrays double, laid out as in eik_backward;
+ * the workspace comes from eik_mixed_workspace_bytes. Errors as eik_backward. */
+int eik_backward_mixed(const eik_grid *grid, const double *M, const double *omega, const double *T,
+                       const uint8_t *parent, const double *dLdT, double *dLdM, double *dLdomega, double *dLdsrc,
+                       void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
 
 /* Batched solving (n_grids independent grids, packed as described above).
  * eik_batch_workspace_bytes sizes the workspace; eik_batch_plan writes the

@@ -26,7 +26,8 @@ SOURCE, UNREACHED = 0xFE, 0xFF
 
 EXPORTS = ["eik_workspace_bytes", "eik_forward", "eik_backward", "eik_project", "eik_project_backward",
            "eik_last_error", "eik_batch_workspace_bytes", "eik_batch_plan", "eik_forward_batched",
-           "eik_backward_batched", "eik_batch_pending"]
+           "eik_backward_batched", "eik_batch_pending", "eik_mixed_workspace_bytes", "eik_forward_mixed",
+           "eik_backward_mixed"]
 
 
 class EikGrid(ctypes.Structure):
@@ -96,6 +97,12 @@ def lib():
         L.eik_backward_batched.restype = ctypes.c_int
         L.eik_batch_pending.argtypes = [i32, gp, i32, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64), vp]
         L.eik_batch_pending.restype = ctypes.c_int
+        L.eik_mixed_workspace_bytes.argtypes = [gp]
+        L.eik_mixed_workspace_bytes.restype = ctypes.c_size_t
+        L.eik_forward_mixed.argtypes = [gp, vp, vp, d, d, i32, i32, vp, vp, vp, vp, ctypes.c_size_t, tp, tp, sp, vp]
+        L.eik_forward_mixed.restype = ctypes.c_int
+        L.eik_backward_mixed.argtypes = [gp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, tp, sp, vp]
+        L.eik_backward_mixed.restype = ctypes.c_int
         L.eik_last_error.argtypes = []
         L.eik_last_error.restype = ctypes.c_char_p
         _lib = L

@@ -419,11 +419,83 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     return status;
 }
 
+// Workspace of the mixed-precision calls: FP32 copies of the parameters, the
+// FP32 field and source times, then the workspace of the FP64 solve, which the
+// FP32 solve uses before it. The mixed adjoint keeps its FP32 weights, dL/dT
+// and lambda in the first three regions.
+struct MixedLayout {
+    size_t M32, om32, T32, src32, base, total;
+};
+
+MixedLayout mixed_layout(const Extent &e)
+{
+    const size_t n = (size_t)e.nodes;
+    MixedLayout L;
+    size_t o = 0;
+    L.M32 = o;   o += align256(3 * n * 4);
+    L.om32 = o;  o += align256(2 * n * 4);
+    L.T32 = o;   o += align256(n * 4);
+    L.src32 = o; o += align256((size_t)e.n_src * 4);
+    L.base = o;
+    L.total = o + layout(e, EIK_F64).total;
+    return L;
+}
+
+// The adjoint relaxation (round or queue scheduler) on lambda of type RL.
+template <typename RL>
+int relax(const LaunchArgs &a, Ws &w, const eik_tuning &tn, bool sync, const uint8_t *parent, const void *w1,
+          const void *g, void *lam, hipStream_t st, int &rounds, bool &conv)
+{
+    const int dtype = sizeof(RL) == 8 ? EIK_F64 : EIK_F32;
+    launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
+    launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
+    launch_all_active(a, w.act, w.act_count, st);
+    HIP_OK(hipGetLastError());
+    rounds = 0;
+    conv = false;
+    if (tn.scheduler == EIK_SCHED_QUEUE) {
+        const int waves = std::min({adj_queue_waves(a.th, dtype), kMaxQueueWaves, a.n_tiles});
+        if (waves < 1) return fail(EIK_EDEVICE, "no occupancy for the work-queue adjoint kernel");
+        const int budget_rounds = sync ? kMaxRounds / 2 : tn.adjoint_rounds;
+        const uint32_t budget = (uint32_t)std::min<int64_t>((int64_t)budget_rounds * a.n_tiles, INT32_MAX);
+        launch_queue_setup(a, w.act, w.q, budget, st);
+        launch_adj_queue<RL>(a, waves, parent, w1, g, lam, tn.adjoint_cycles, w.q, st);
+        launch_note_queue(w.q, w.ctr + kCtrAdjPending, st);
+        HIP_OK(hipGetLastError());
+        if (sync) {
+            uint32_t ctl[kQCtlWords];
+            HIP_OK(hipMemcpyAsync(ctl, w.q.ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            if (ctl[kQFail]) return fail(EIK_EDEVICE, "work queue: a wait exceeded its poll limit");
+            conv = ctl[kQPending] == 0 && !ctl[kQStop];
+            rounds = (int)(((int64_t)ctl[kQVisits] + a.n_tiles - 1) / a.n_tiles);
+            if (!conv) return fail(EIK_EDEVICE, "adjoint visits did not settle");
+        }
+    } else {
+        int rc = run_rounds(
+            w.act, w.act_count, a.n_tiles, 0, sync ? kMaxRounds / 2 : tn.adjoint_rounds, tn.rounds_per_check, sync,
+            st,
+            [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
+                launch_adj_round<RL>(a, parent, w1, g, lam, tn.adjoint_cycles, ain, aout, cnt, st);
+            },
+            &rounds, &conv);
+        if (rc) return rc;
+        if (sync && !conv) return fail(EIK_EDEVICE, "adjoint rounds did not settle");
+        launch_note_pending(w.act_count + rounds, w.ctr + kCtrAdjPending, st);
+    }
+    return EIK_OK;
+}
+
+// FP32 buffers of the mixed-precision adjoint (donor weights, dL/dT, lambda).
+struct Relax32 {
+    float *w1, *g, *lam;
+};
+
 template <typename R>
 int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, const void *M, const void *om,
                   const void *T, const uint8_t *parent, const int32_t *level, const void *dLdT, void *dLdM,
                   void *dLdom, void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tun, bool single,
-                  eik_stats *stats, hipStream_t st)
+                  eik_stats *stats, hipStream_t st, const Relax32 *r32 = nullptr)
 {
     const int dtype = sizeof(R) == 8 ? EIK_F64 : EIK_F32;
     const eik_tuning tn = tuning_or_default(tun);
@@ -437,41 +509,18 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
     (void)level; // the adjoint orders each tile by its own dependency levels
     launch_fill_u64(w.ctr + kCtrAdjPending, 1, st);
     launch_adj_prep<R>(a, M, om, T, parent, w.w1, w.lam, st);
-    launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
-    launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
-    launch_all_active(a, w.act, w.act_count, st);
-    HIP_OK(hipGetLastError());
     int rounds = 0;
     bool conv = false;
-    if (tn.scheduler == EIK_SCHED_QUEUE) {
-        const int waves = std::min({adj_queue_waves(a.th, dtype), kMaxQueueWaves, a.n_tiles});
-        if (waves < 1) return fail(EIK_EDEVICE, "no occupancy for the work-queue adjoint kernel");
-        const int budget_rounds = sync ? kMaxRounds / 2 : tn.adjoint_rounds;
-        const uint32_t budget = (uint32_t)std::min<int64_t>((int64_t)budget_rounds * a.n_tiles, INT32_MAX);
-        launch_queue_setup(a, w.act, w.q, budget, st);
-        launch_adj_queue<R>(a, waves, parent, w.w1, dLdT, w.lam, tn.adjoint_cycles, w.q, st);
-        launch_note_queue(w.q, w.ctr + kCtrAdjPending, st);
-        HIP_OK(hipGetLastError());
-        if (sync) {
-            uint32_t ctl[kQCtlWords];
-            HIP_OK(hipMemcpyAsync(ctl, w.q.ctl, sizeof ctl, hipMemcpyDeviceToHost, st));
-            HIP_OK(hipStreamSynchronize(st));
-            if (ctl[kQFail]) return fail(EIK_EDEVICE, "work queue: a wait exceeded its poll limit");
-            conv = ctl[kQPending] == 0 && !ctl[kQStop];
-            rounds = (int)(((int64_t)ctl[kQVisits] + a.n_tiles - 1) / a.n_tiles);
-            if (!conv) return fail(EIK_EDEVICE, "adjoint visits did not settle");
-        }
-    } else {
-        rc = run_rounds(
-            w.act, w.act_count, a.n_tiles, 0, sync ? kMaxRounds / 2 : tn.adjoint_rounds, tn.rounds_per_check, sync,
-            st,
-            [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-                launch_adj_round<R>(a, parent, w.w1, dLdT, w.lam, tn.adjoint_cycles, ain, aout, cnt, st);
-            },
-            &rounds, &conv);
+    if (r32) { // weights from the state in R, lambda relaxed in FP32, then widened
+        launch_cast_f64_f32(e.nodes, (const double *)w.w1, r32->w1, st);
+        launch_cast_f64_f32(e.nodes, (const double *)dLdT, r32->g, st);
+        launch_fill_i32((int32_t *)r32->lam, e.nodes, 0, st); // +0.0f
+        rc = relax<float>(a, w, tn, sync, parent, r32->w1, r32->g, r32->lam, st, rounds, conv);
         if (rc) return rc;
-        if (sync && !conv) return fail(EIK_EDEVICE, "adjoint rounds did not settle");
-        launch_note_pending(w.act_count + rounds, w.ctr + kCtrAdjPending, st);
+        launch_cast_f32_f64(e.nodes, r32->lam, (double *)w.lam, st);
+    } else {
+        rc = relax<R>(a, w, tn, sync, parent, w.w1, dLdT, w.lam, st, rounds, conv);
+        if (rc) return rc;
     }
     launch_adj_params<R>(a, M, parent, w.w1, w.lam, dLdM, dLdom, st);
     launch_dsrc<R>(a, src_idx, w.lam, dLdsrc, st);
@@ -549,6 +598,55 @@ int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *
                                parent, level, ws, ws_bytes, tuning, stats, true, stream);
 }
 
+size_t eik_mixed_workspace_bytes(const eik_grid *grid)
+{
+    if (!grid || !grid->src_idx) return 0;
+    Extent e;
+    if (extent_of(1, grid, EIK_F64, e)) return 0;
+    return mixed_layout(e).total;
+}
+
+int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega, double tol32, double tol,
+                      int32_t max_rounds, int32_t flags, double *T, uint8_t *parent, int32_t *level, void *ws,
+                      size_t ws_bytes, const eik_tuning *tuning32, const eik_tuning *tuning, eik_stats *stats,
+                      hipStream_t stream)
+{
+    if (!grid) return fail(EIK_EINVAL, "grid is NULL");
+    int rc = check_one(grid, 0);
+    if (rc) return rc;
+    if (!grid->src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
+    rc = check_ptrs(M, omega, T, parent);
+    if (rc) return rc;
+    if (!(tol >= 0.0) || !(tol32 >= 0.0)) return fail(EIK_EINVAL, "tolerances must be >= 0");
+    if (max_rounds < 1) return fail(EIK_EINVAL, "max_rounds must be >= 1");
+    Extent e;
+    rc = extent_of(1, grid, EIK_F64, e);
+    if (rc) return rc;
+    const MixedLayout L = mixed_layout(e);
+    if (!ws || ws_bytes < L.total)
+        return fail(EIK_EWORKSPACE, "workspace %zu bytes, %zu needed", ws_bytes, L.total);
+    char *b = (char *)ws;
+    float *M32 = (float *)(b + L.M32), *om32 = (float *)(b + L.om32), *T32 = (float *)(b + L.T32);
+    launch_cast_f64_f32(3 * e.nodes, M, M32, stream);
+    launch_cast_f64_f32(2 * e.nodes, omega, om32, stream);
+    eik_grid g32 = *grid;
+    if (grid->src_t) {
+        g32.src_t = b + L.src32;
+        launch_cast_f64_f32(grid->n_src, (const double *)grid->src_t, (float *)(b + L.src32), stream);
+    }
+    HIP_OK(hipGetLastError());
+    // FP32 sweeps from the cold start; not reaching tol32 is no error here
+    rc = forward_impl<float>(1, &g32, g32.src_idx, g32.src_t, M32, om32, nullptr, tol32, max_rounds, flags, T32,
+                             parent, nullptr, b + L.base, ws_bytes - L.base, tuning32, stats, true, stream);
+    if (rc < 0) return rc;
+    // FP64 sweeps from that field, in place in T
+    launch_cast_f32_f64(e.nodes, T32, T, stream);
+    HIP_OK(hipGetLastError());
+    return forward_impl<double>(1, grid, grid->src_idx, grid->src_t, M, omega, T, tol, max_rounds,
+                                flags & ~EIK_CHECK_FEASIBLE, T, parent, level, b + L.base, ws_bytes - L.base,
+                                tuning, stats ? stats + 1 : nullptr, true, stream);
+}
+
 int eik_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
                         const void *src_t, const void *M, const void *omega, const void *T_init, double tol,
                         int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level, void *ws,
@@ -585,6 +683,28 @@ int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void 
                                      dLdsrc, ws, ws_bytes, tuning, true, stats, stream);
     return backward_impl<float>(1, grid, grid->src_idx, M, omega, T, parent, level, dLdT, dLdM, dLdomega, dLdsrc,
                                 ws, ws_bytes, tuning, true, stats, stream);
+}
+
+int eik_backward_mixed(const eik_grid *grid, const double *M, const double *omega, const double *T,
+                       const uint8_t *parent, const double *dLdT, double *dLdM, double *dLdomega, double *dLdsrc,
+                       void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream)
+{
+    if (!grid) return fail(EIK_EINVAL, "grid is NULL");
+    int rc = check_one(grid, 0);
+    if (rc) return rc;
+    if (!grid->src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
+    if (!M || !omega || !T || !parent || !dLdT || !dLdM || !dLdomega || !dLdsrc)
+        return fail(EIK_EINVAL, "NULL pointer argument");
+    Extent e;
+    rc = extent_of(1, grid, EIK_F64, e);
+    if (rc) return rc;
+    const MixedLayout L = mixed_layout(e);
+    if (!ws || ws_bytes < L.total)
+        return fail(EIK_EWORKSPACE, "workspace %zu bytes, %zu needed", ws_bytes, L.total);
+    char *b = (char *)ws;
+    const Relax32 r32 = {(float *)(b + L.M32), (float *)(b + L.om32), (float *)(b + L.T32)};
+    return backward_impl<double>(1, grid, grid->src_idx, M, omega, T, parent, nullptr, dLdT, dLdM, dLdomega, dLdsrc,
+                                 b + L.base, ws_bytes - L.base, tuning, true, stats, stream, &r32);
 }
 
 int eik_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,

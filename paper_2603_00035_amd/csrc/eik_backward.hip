@@ -87,6 +87,55 @@ __global__ __launch_bounds__(256) void k_adj_prep(LaunchArgs a, const R *__restr
 // Each node's receivers and weight selectors are gathered once per visit into
 // a 16-bit descriptor (two bits per neighbour: 1 first donor, weight w; 2
 // second donor, weight 1 - w; 3 one-point donor, weight 1).
+// One directional sweep of the adjoint relaxation over the tile in LDS (a
+// line of the tile per step; DIR as in the forward sweeps).
+template <typename R, int TH, int DIR>
+__device__ __forceinline__ bool adj_sweep_dir(const TileGeoB &g, R *sLam, const R *sW, const uint16_t *sD,
+                                              const R *sG)
+{
+    constexpr int LP = TW + 3;
+    constexpr bool COL = (DIR & 1) == 0;
+    const int lane = threadIdx.x;
+    const int len = COL ? g.w : g.h;
+    const int span = COL ? g.h : g.w;
+    bool changed = false;
+    for (int s = 0; s < len; ++s) {
+        const int pos = DIR < 2 ? s : len - 1 - s;
+        const int ci = COL ? pos : lane;
+        const int cj = COL ? lane : pos;
+        if (lane < span) {
+            const uint32_t d = sD[cj * TW + ci];
+            R acc = sG[cj * TW + ci];
+            // all neighbour reads are issued at once and the receivers
+            // selected afterwards (no branch per neighbour); non-receivers add
+            // an exact zero, so the sum is the same, in the same order
+            R lam[8], wn[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int sl = (cj + 1 + nb_dy(k)) * LP + (ci + 1 + nb_dx(k));
+                lam[k] = sLam[sl];
+                wn[k] = sW[sl];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t sel = (d >> (2 * k)) & 3u;
+                // sequential selects (no branches): 0, w, 1 - w or 1
+                R coef = sel == 3u ? R(1) : R(0);
+                coef = sel == 2u ? R(1) - wn[k] : coef;
+                coef = sel == 1u ? wn[k] : coef;
+                acc += coef * lam[k];
+            }
+            const int slot = (cj + 1) * LP + ci + 1;
+            changed |= acc != sLam[slot];
+            sLam[slot] = acc;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    return changed;
+}
+
 struct AdjVisit {
     int bits;
     bool settled;
@@ -126,35 +175,12 @@ __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, 
     int quiet = 0, sweeps = 0;
     const int max_sweeps = 4 * max_cycles;
     while (quiet < 4 && sweeps < max_sweeps) {
-        const int dir = sweeps & 3;
-        const bool col = (dir & 1) == 0;
-        const int len = col ? g.w : g.h;
-        const int span = col ? g.h : g.w;
-        bool changed = false;
-        for (int s = 0; s < len; ++s) {
-            const int pos = dir < 2 ? s : len - 1 - s;
-            const int ci = col ? pos : lane;
-            const int cj = col ? lane : pos;
-            if (lane < span) {
-                const uint32_t d = sD[cj * TW + ci];
-                R acc = sG[cj * TW + ci];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const uint32_t sel = (d >> (2 * k)) & 3u;
-                    if (sel) {
-                        const int sl = (cj + 1 + nb_dy(k)) * LP + (ci + 1 + nb_dx(k));
-                        const R wj = sW[sl];
-                        const R coef = sel == 1u ? wj : (sel == 2u ? R(1) - wj : R(1));
-                        acc += coef * sLam[sl];
-                    }
-                }
-                const int slot = (cj + 1) * LP + ci + 1;
-                changed |= acc != sLam[slot];
-                sLam[slot] = acc;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        bool changed;
+        switch (sweeps & 3) {
+        case 0: changed = adj_sweep_dir<R, TH, 0>(g, sLam, sW, sD, sG); break;
+        case 1: changed = adj_sweep_dir<R, TH, 1>(g, sLam, sW, sD, sG); break;
+        case 2: changed = adj_sweep_dir<R, TH, 2>(g, sLam, sW, sD, sG); break;
+        default: changed = adj_sweep_dir<R, TH, 3>(g, sLam, sW, sD, sG); break;
         }
         ++sweeps;
         quiet = __ballot(changed) ? 0 : quiet + 1;

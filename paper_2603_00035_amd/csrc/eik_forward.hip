@@ -89,9 +89,8 @@ __global__ __launch_bounds__(256) void k_stage(LaunchArgs a, const R *__restrict
 // Initialisation: T, codes (source marks), levels, first active tiles.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void k_init(int64_t n, const R *__restrict__ T_init, R *__restrict__ T, uint8_t *__restrict__ code,
-                       int32_t *__restrict__ level)
-{
+__global__ void k_init(int64_t n, const R *T_init, R *T, uint8_t *__restrict__ code, int32_t *__restrict__ level)
+{ // T_init may be T itself (in-place warm start): each element is read before it is written
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         T[c] = T_init ? T_init[c] : inf_v<R>();
         code[c] = kUnreached;
@@ -133,6 +132,14 @@ __global__ void k_fill_u64(unsigned long long *__restrict__ p, int64_t n)
 {
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
         p[c] = 0ull;
+}
+
+// Element-wise precision change (round to nearest; infinities kept).
+template <typename S, typename D>
+__global__ void k_cast(int64_t n, const S *__restrict__ src, D *__restrict__ dst)
+{
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        dst[c] = (D)src[c];
 }
 
 __global__ void k_all_active(int32_t *__restrict__ act, int n_tiles, int32_t *__restrict__ act_count)
@@ -494,10 +501,9 @@ __device__ __forceinline__ void lex_min(R &v, int &c)
 {
     const R ov = dpp_r<CTRL>(v);
     const int oc = dpp_i<CTRL>(c);
-    if (ov < v || (ov == v && oc < c)) {
-        v = ov;
-        c = oc;
-    }
+    const bool take = (ov < v) | ((ov == v) & (oc < c)); // selects, no branch
+    v = take ? ov : v;
+    c = take ? oc : c;
 }
 template <int SUB, typename R>
 __device__ __forceinline__ void group_min(R &v, int &c)
@@ -528,10 +534,9 @@ __device__ __forceinline__ R update(int sub, R m11, R m12, R m22, R bx, R by, R 
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         const R t = Tq[q] + h * (bm[q] + dsqrt(e[q]));
-        if (t < b1) {
-            b1 = t;
-            c1 = 8 + ((NS * sub + q) & 7);
-        }
+        const bool take = t < b1;
+        b1 = take ? t : b1;
+        c1 = take ? 8 + ((NS * sub + q) & 7) : c1;
     }
     group_min<SUB>(b1, c1);
     // two-point stencils whose donors are both below the best one-point value
@@ -1024,6 +1029,16 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
 void launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+}
+
+void launch_cast_f64_f32(int64_t n, const double *src, float *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(blocks_for(n, 256)), dim3(256), 0, st, n, src, dst);
+}
+
+void launch_cast_f32_f64(int64_t n, const float *src, double *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(blocks_for(n, 256)), dim3(256), 0, st, n, src, dst);
 }
 
 template <typename R>

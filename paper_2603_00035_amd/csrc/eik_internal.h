@@ -92,6 +92,8 @@ void launch_level_round(const LaunchArgs &a, const uint8_t *parent, int32_t *lev
 void launch_max_level(int64_t n, const int32_t *level, unsigned long long *ctr, hipStream_t st);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st);
+void launch_cast_f64_f32(int64_t n, const double *src, float *dst, hipStream_t st);
+void launch_cast_f32_f64(int64_t n, const float *src, double *dst, hipStream_t st);
 void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_grid, int n_tiles, hipStream_t st);
 
 // backward

@@ -96,6 +96,51 @@ def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=40
                                    st.sweep_launches, st.sweep_ms, st.aux_rounds)
 
 
+def _stats(st):
+    return Stats(st.rounds, bool(st.converged), st.cell_updates, st.n_levels, st.status, st.sweep_launches,
+                 st.sweep_ms, st.aux_rounds)
+
+
+def mixed_workspace(grid: L.EikGrid, device) -> torch.Tensor:
+    nbytes = L.lib().eik_mixed_workspace_bytes(ctypes.byref(grid))
+    if nbytes == 0:
+        L.check("eik_mixed_workspace_bytes", L.EIK_EINVAL)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def solve_mixed(M, omega, src_idx, h, src_t=None, tol=1e-5, tol32=None, max_rounds=4096, check_feasible=False,
+                tune32=None, tune=None, ws=None, time_kernels=False, levels=True):
+    """Mixed-precision forward (eik_forward_mixed): FP32 sweeps from the cold
+    start to ``tol32`` (default ``tol``) on FP32-rounded copies of the FP64
+    fields, then FP64 sweeps from that field to ``tol``. Returns (T, parent,
+    level, (Stats of the FP32 phase, Stats of the FP64 phase)) with T FP64."""
+    _check_fields(M, omega)
+    if M.dtype != torch.float64:
+        raise TypeError("the mixed-precision solve takes FP64 fields")
+    ny, nx = M.shape[1:]
+    dev = M.device
+    if src_t is not None:
+        src_t = src_t.to(device=dev, dtype=torch.float64).contiguous()
+    grid = make_grid(nx, ny, h, src_idx, src_t)
+    if ws is None:
+        ws = mixed_workspace(grid, dev)
+    if tune32 is None:
+        tune32 = autotune.lookup(nx * ny, "f32")
+    T = torch.empty((ny, nx), dtype=torch.float64, device=dev)
+    parent = torch.empty((ny, nx), dtype=torch.uint8, device=dev)
+    level = torch.empty((ny, nx), dtype=torch.int32, device=dev) if levels else None
+    st = (L.EikStats * 2)()
+    rc = L.lib().eik_forward_mixed(ctypes.byref(grid), L.ptr(M), L.ptr(omega), float(tol if tol32 is None else tol32),
+                                   float(tol), int(max_rounds),
+                                   (L.EIK_CHECK_FEASIBLE if check_feasible else 0) |
+                                   (L.EIK_TIME_KERNELS if time_kernels else 0),
+                                   L.ptr(T), L.ptr(parent), L.ptr(level), L.ptr(ws), ws.numel(),
+                                   None if tune32 is None else ctypes.byref(tune32),
+                                   None if tune is None else ctypes.byref(tune), st, L.stream_handle(dev))
+    L.check("eik_forward_mixed", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
+    return T, parent, level, (_stats(st[0]), _stats(st[1]))
+
+
 def adjoint(M, omega, T, parent, level, src_idx, h, dLdT, src_t=None, tune=None, ws=None, stats_out=None):
     """Backward pass. Returns (dL/dM, dL/domega, dL/dt_src); ``stats_out`` (a
     list) receives the call's Stats. ``level`` is not needed (may be None)."""
@@ -122,20 +167,57 @@ def adjoint(M, omega, T, parent, level, src_idx, h, dLdT, src_t=None, tune=None,
     return dM, dom, ds
 
 
+def adjoint_mixed(M, omega, T, parent, src_idx, h, dLdT, src_t=None, tune=None, ws=None, stats_out=None):
+    """Backward pass of the mixed-precision state (eik_backward_mixed): FP64
+    weights and parameter derivatives, FP32 adjoint relaxation. Returns FP64
+    (dL/dM, dL/domega, dL/dt_src)."""
+    _check_fields(M, omega)
+    if M.dtype != torch.float64 or T.dtype != torch.float64:
+        raise TypeError("the mixed-precision adjoint takes the FP64 fields and field T")
+    ny, nx = M.shape[1:]
+    dev = M.device
+    grid = make_grid(nx, ny, h, src_idx, src_t)
+    if ws is None:
+        ws = mixed_workspace(grid, dev)
+    if tune is None:
+        tune = autotune.lookup(nx * ny, "f32")
+    dLdT = dLdT.to(dtype=torch.float64).contiguous()
+    dM = torch.empty_like(M)
+    dom = torch.empty_like(omega)
+    ds = torch.empty(src_idx.numel(), dtype=torch.float64, device=dev)
+    st = L.EikStats()
+    rc = L.lib().eik_backward_mixed(ctypes.byref(grid), L.ptr(M), L.ptr(omega), L.ptr(T), L.ptr(parent),
+                                    L.ptr(dLdT), L.ptr(dM), L.ptr(dom), L.ptr(ds), L.ptr(ws), ws.numel(),
+                                    None if tune is None else ctypes.byref(tune), ctypes.byref(st),
+                                    L.stream_handle(dev))
+    L.check("eik_backward_mixed", rc)
+    if stats_out is not None:
+        stats_out.append(Stats(st.rounds, bool(st.converged), 0, 0, rc, 0, 0.0, st.aux_rounds))
+    return dM, dom, ds
+
+
 class EikonalFn(torch.autograd.Function):
     """T = eikonal(M, omega, src_t); gradients by implicit differentiation."""
 
     @staticmethod
     def forward(ctx, M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink=None, time_kernels=False,
-                levels=False):
+                levels=False, mixed=False, tol32=None):
         M = M.contiguous()
         omega = omega.contiguous()
-        T, parent, level, stats = solve(M, omega, src_idx, h, src_t=src_t, tol=tol, max_rounds=max_rounds,
-                                        time_kernels=time_kernels, levels=levels)
-        if stats_sink is not None:
-            stats_sink.append(stats)
+        if mixed:
+            T, parent, level, st = solve_mixed(M, omega, src_idx, h, src_t=src_t, tol=tol, tol32=tol32,
+                                               max_rounds=max_rounds, time_kernels=time_kernels, levels=levels)
+            stats = st[1]
+            if stats_sink is not None:
+                stats_sink.extend(st)
+        else:
+            T, parent, level, stats = solve(M, omega, src_idx, h, src_t=src_t, tol=tol, max_rounds=max_rounds,
+                                            time_kernels=time_kernels, levels=levels)
+            if stats_sink is not None:
+                stats_sink.append(stats)
         ctx.save_for_backward(M, omega, T, parent, src_idx)
         ctx.h = h
+        ctx.mixed = mixed
         ctx.has_src_t = src_t is not None
         ctx.stats = stats
         ctx.mark_non_differentiable(parent)
@@ -146,15 +228,33 @@ class EikonalFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gT, _gp=None, _gl=None):
         M, omega, T, parent, src_idx = ctx.saved_tensors
-        dM, dom, ds = adjoint(M, omega, T, parent, None, src_idx, ctx.h, gT)
-        return dM, dom, (ds if ctx.has_src_t else None), None, None, None, None, None, None, None
+        if ctx.mixed:
+            dM, dom, ds = adjoint_mixed(M, omega, T, parent, src_idx, ctx.h, gT)
+        else:
+            dM, dom, ds = adjoint(M, omega, T, parent, None, src_idx, ctx.h, gT)
+        return dM, dom, (ds if ctx.has_src_t else None), None, None, None, None, None, None, None, None, None
 
 
 def eikonal(M, omega, src_idx, h, src_t=None, tol=1e-5, max_rounds=4096, stats_sink=None, time_kernels=False,
-            levels=False):
+            levels=False, precision=None, tol32=None):
     """Differentiable solve; returns (T, parent, level) with level None unless
-    ``levels`` is set. ``stats_sink`` (a list) receives the forward's Stats."""
-    return EikonalFn.apply(M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink, time_kernels, levels)
+    ``levels`` is set. ``stats_sink`` (a list) receives the forward's Stats.
+
+    precision None solves and differentiates in the dtype of M; "mixed" runs
+    the mixed-precision forward (FP32 sweeps to ``tol32``, then FP64 sweeps to
+    ``tol``) and the mixed adjoint (FP64 weights, FP32 relaxation): M, omega
+    and src_t enter in FP64 (their
+    gradients return in their own dtype), T is FP64, and ``stats_sink``
+    receives the Stats of both phases."""
+    if precision not in (None, "mixed"):
+        raise ValueError(f"precision {precision!r}: None or 'mixed'")
+    mixed = precision == "mixed"
+    if mixed:
+        M, omega = M.to(torch.float64), omega.to(torch.float64)
+        if src_t is not None:
+            src_t = src_t.to(torch.float64)
+    return EikonalFn.apply(M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink, time_kernels, levels, mixed,
+                           tol32)
 
 
 def _proj_params(eig_min, eig_max, eucl_clip, rho_max):

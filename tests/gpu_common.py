@@ -78,20 +78,43 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def check_parent_choices(q, To, po, pg, rtol):
+def check_parent_choices(q, To, po, pg, rtol, Tg=None):
     """Where the GPU picked another active update than the oracle, that update
     must reach the oracle's minimum within rtol (a near-tie between candidates:
-    either choice is a correct minimiser). Returns the number of such nodes."""
+    either choice is a correct minimiser), or -- when the GPU field Tg is given
+    -- one of the two choices must pass its causality test by no more than rtol
+    relative on its own field: both fields are fixed only to rtol, so such a
+    decision is taken by differences inside the tolerance. Returns the number
+    of such nodes."""
+    tie = rtol
     bad = np.flatnonzero(pg.ravel() != po.ravel())
     for c in bad:
         code = int(pg.flat[c])
         assert code < 16, f"node {c}: GPU code {code} vs oracle {po.flat[c]}"
         v, _ = oracle.candidate(q, To, c, code)
-        assert abs(v - To.flat[c]) <= rtol * abs(To.flat[c]), (c, code, int(po.flat[c]), v, To.flat[c])
+        if abs(v - To.flat[c]) <= rtol * abs(To.flat[c]):
+            continue
+        assert Tg is not None and (causality_margin(q, Tg, int(c), code) <= tie or
+                                   causality_margin(q, To, int(c), int(po.flat[c])) <= tie), \
+            (c, code, int(po.flat[c]), v, To.flat[c])
     return int(bad.size)
 
 
 FP32_EPS = 2.0 ** -24
+
+
+def causality_margin(q, T, c, code):
+    """min(t - Tp, t - Tq) / t of two-point candidate `code` at node c of T
+    (+inf for one-point codes): how close its causality test is to a tie."""
+    if code >= 8 or code < 0:
+        return np.inf
+    nx = T.shape[1]
+    t, _ = oracle.candidate(q, T, c, code)
+    j, i = divmod(c, nx)
+    kq = (code + 1) % 8
+    tp = T[j + oracle.NBY[code], i + oracle.NBX[code]]
+    tq = T[j + oracle.NBY[kq], i + oracle.NBX[kq]]
+    return abs(min(t - tp, t - tq)) / abs(t)
 
 
 def near_tie_analysis(q, Tg, parent_g, To, skip, tol=1e-5, fp_rel=1e-6, tie_ulps=8):
@@ -118,14 +141,7 @@ def near_tie_analysis(q, Tg, parent_g, To, skip, tol=1e-5, fp_rel=1e-6, tie_ulps
     po, _ = oracle.parents_levels(q, To)
 
     def margin(T, c, code):
-        if code >= 8 or code < 0:
-            return np.inf
-        t, _ = oracle.candidate(q, T, c, code)
-        j, i = divmod(c, nx)
-        kq = (code + 1) % 8
-        tp = T[j + oracle.NBY[code], i + oracle.NBX[code]]
-        tq = T[j + oracle.NBY[kq], i + oracle.NBX[kq]]
-        return abs(min(t - tp, t - tq)) / abs(t)
+        return causality_margin(q, T, c, code)
 
     def near_tie(c):
         return margin(Tg, c, int(parent_g.flat[c])) <= tie or margin(To, c, int(po.flat[c])) <= tie

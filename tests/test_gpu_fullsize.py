@@ -1,7 +1,8 @@
-"""Full-size parity: the 2048 x 2048 FP32 stress workload (eigenvalue ratio 10,
-drift 0.9, 4 sharp regions, 16 sources) through the autograd wrapper, in the
-configuration the benchmark times, against the FP64 oracle run to exact
-stationarity on the same FP32-rounded inputs."""
+"""Full-size parity: the 2048 x 2048 stress workload (eigenvalue ratio 10,
+drift 0.9, 4 sharp regions, 16 sources, FP32-rounded inputs) through the
+autograd wrapper, against the FP64 oracle run to exact stationarity on the
+same inputs: the mixed-precision path the benchmark times, and the plain FP32
+path."""
 import numpy as np
 import pytest
 
@@ -12,52 +13,92 @@ from tests.gpu_common import check_parent_choices, near_tie_analysis, rel_l2, sa
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
+# Gradient rel-L2 floor of any solve that stores T in FP32, on this workload:
+# the oracle's own Gauss-Seidel sweeps with every stored value rounded to FP32
+# (exact FP64 updates otherwise) reach 1.43e-4 against the exact FP64 state,
+# and random relative perturbations s of the exact field move the gradient by
+# about 1000 s. The plain FP32 path is held to twice that floor.
+FP32_STORAGE_GRAD_FLOOR = 1.43e-4
 
-@pytest.mark.timeout(600)
-def test_stress_2048_forward_and_gradient():
-    from paper_2603_00035_amd import eikonal as E
+
+@pytest.fixture(scope="module")
+def case():
     p = make_problem("c3", 0)
     q = p.rounded(np.float32)
-    say("[full] 2048x2048 stress: GPU solve to 1e-5 and adjoint")
-    dev = torch.device("cuda:0")
-    M = torch.tensor(p.M, dtype=torch.float32, device=dev).requires_grad_(True)
-    om = torch.tensor(p.omega, dtype=torch.float32, device=dev).requires_grad_(True)
-    src = torch.tensor(p.src_idx, device=dev)
-    # a fixed loss target independent of either solver: a smooth field in [0, 3]
-    target = 3.0 * fourier_field(np.random.default_rng(7), p.nx, p.ny, p.h)
-    T, par, _ = E.eikonal(M, om, src, p.h, tol=1e-5)  # the configuration the benchmark times
-    mask = np.isfinite(target)
-    mask.flat[p.src_idx] = False
-    n_obs = mask.sum()
-    tgt = torch.tensor(target, dtype=torch.float32, device=dev)
-    mk = torch.tensor(mask, device=dev)
-    d = torch.where(mk, T - tgt, torch.zeros_like(T))
-    ((d * d).sum() / n_obs).backward()
-    torch.cuda.synchronize()
-    Tg = T.detach().double().cpu().numpy()
-    pg = par.cpu().numpy()
     say("[full] oracle solve (about 20-40 s)")
     To, sweeps, st = oracle.forward(q)
     assert st == 0
-    # 1e-5 everywhere except downstream of causality decisions that sit within
-    # FP32 rounding of a tie (where FP32 and FP64 may both be right); the GPU
-    # field must satisfy the oracle's local equations to the solve tolerance
-    info = near_tie_analysis(q, Tg, pg, To, p.src_idx, tol=1e-5, fp_rel=1e-5)
-    say(f"[full] forward: max rel err {info['max_rel']:.3e} (oracle {sweeps} sweeps); "
-        f"{info['nodes_over_tol']} nodes over 1e-5, all downstream of {info['decision_nodes']} near-tie decisions")
-    assert info["nodes_over_tol"] <= p.n // 10000
     po, _ = oracle.parents_levels(q, To)
+    # a fixed loss target independent of either solver: a smooth field in [0, 3]
+    target = 3.0 * fourier_field(np.random.default_rng(7), p.nx, p.ny, p.h)
+    mask = np.isfinite(target)
+    mask.flat[p.src_idx] = False
+    n_obs = int(mask.sum())
+    g = np.zeros_like(To)
+    g[mask] = 2.0 * (To[mask] - target[mask]) / n_obs
+    dMo, domo, _ = oracle.vjp(q, To, po, g)
+    return dict(p=p, q=q, To=To, sweeps=sweeps, po=po, target=target, mask=mask, n_obs=n_obs, dMo=dMo, domo=domo)
+
+
+def gpu_run(c, precision):
+    from paper_2603_00035_amd import eikonal as E
+    p, q = c["p"], c["q"]
+    dev = torch.device("cuda:0")
+    M = torch.tensor(q.M, dtype=torch.float32, device=dev).requires_grad_(True)
+    om = torch.tensor(q.omega, dtype=torch.float32, device=dev).requires_grad_(True)
+    src = torch.tensor(p.src_idx, device=dev)
+    T, par, _ = E.eikonal(M, om, src, p.h, tol=1e-5, precision=precision)
+    tgt = torch.tensor(c["target"], dtype=T.dtype, device=dev)
+    mk = torch.tensor(c["mask"], device=dev)
+    d = torch.where(mk, T - tgt, torch.zeros_like(T))
+    ((d * d).sum() / c["n_obs"]).backward()
+    torch.cuda.synchronize()
+    r = rel_l2([M.grad.double().cpu().numpy(), om.grad.double().cpu().numpy()], [c["dMo"], c["domo"]])
+    return T.detach().double().cpu().numpy(), par.cpu().numpy(), r
+
+
+@pytest.mark.timeout(600)
+def test_stress_2048_mixed_precision(case):
+    """The configuration the benchmark times: FP32 sweeps to 1e-5, FP64 sweeps
+    from there to 1e-5, mixed adjoint. Both bars hold at every node."""
+    c = case
+    p = c["p"]
+    say("[full] 2048x2048 stress, mixed precision: GPU solve to 1e-5 and adjoint")
+    Tg, pg, r = gpu_run(c, "mixed")
+    To = c["To"]
+    m = np.isfinite(To)
+    m.flat[p.src_idx] = False
+    assert np.array_equal(np.isfinite(Tg), np.isfinite(To))
+    err = float(np.max(np.abs(Tg[m] - To[m]) / To[m]))
+    mism = int(np.sum(pg != c["po"]))
+    say(f"[full] mixed: forward max rel err {err:.3e} (oracle {c['sweeps']} sweeps), parent differences {mism}, "
+        f"gradient rel L2 {r:.3e}")
+    assert err <= 1e-5
+    check_parent_choices(c["q"], To, c["po"], pg, 1e-5, Tg=Tg)
+    assert r <= 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_stress_2048_fp32(case):
+    """The plain FP32 path: 1e-5 everywhere except downstream of causality
+    decisions that sit within FP32 rounding of a tie (where FP32 and FP64 may
+    both be right); the GPU field must satisfy the oracle's local equations to
+    the solve tolerance. The gradient is held to twice the FP32-storage floor."""
+    c = case
+    p, q, To, po = c["p"], c["q"], c["To"], c["po"]
+    say("[full] 2048x2048 stress, FP32: GPU solve to 1e-5 and adjoint")
+    Tg, pg, r = gpu_run(c, None)
+    info = near_tie_analysis(q, Tg, pg, To, p.src_idx, tol=1e-5, fp_rel=1e-5)
+    say(f"[full] fp32: forward max rel err {info['max_rel']:.3e}; {info['nodes_over_tol']} nodes over 1e-5, "
+        f"all downstream of {info['decision_nodes']} near-tie decisions")
+    assert info["nodes_over_tol"] <= p.n // 10000
     mism = int(np.sum(pg != po))
-    say(f"[full] parent differences {mism}")
-    sample = np.array([c for c in np.flatnonzero((pg != po).ravel()) if c not in info["excluded"]], dtype=np.int64)
+    say(f"[full] fp32: parent differences {mism}, gradient rel L2 {r:.3e} "
+        f"(FP32-storage floor {FP32_STORAGE_GRAD_FLOOR:.2e})")
+    sample = np.array([x for x in np.flatnonzero((pg != po).ravel()) if x not in info["excluded"]], dtype=np.int64)
     if sample.size > 2000:  # the oracle checks a sample of the differing nodes one by one
         sample = np.random.default_rng(0).choice(sample, 2000, replace=False)
     pg_s = po.copy()
     pg_s.flat[sample] = pg.flat[sample]
-    check_parent_choices(q, To, po, pg_s, 1e-5)
-    g = np.zeros_like(To)
-    g[mask] = 2.0 * (To[mask] - target[mask]) / n_obs
-    dMo, domo, _ = oracle.vjp(q, To, po, g)
-    r = rel_l2([M.grad.double().cpu().numpy(), om.grad.double().cpu().numpy()], [dMo, domo])
-    say(f"[full] gradient rel L2 {r:.3e}")
-    assert r <= 1e-4
+    check_parent_choices(q, To, po, pg_s, 1e-5, Tg=Tg)
+    assert r <= 2 * FP32_STORAGE_GRAD_FLOOR
