@@ -103,7 +103,10 @@ typedef struct eik_tuning {
     int32_t tile_height;      /* 32 or 64 (tiles are 64 nodes wide); default 64 */
     int32_t max_local_cycles; /* four-sweep cycles a tile may run per visit; default 1 */
     int32_t rounds_per_check; /* rounds enqueued between host convergence checks; default 8 */
-    int32_t fast_cold_start;  /* 1: restricted-candidate min sweeps before the full ones (cold start); default 0 */
+    int32_t fast_cold_start;  /* cold start only: 1: restricted-candidate min sweeps before the full ones;
+                                 2: the same with the four directions of each cycle swept at once by four
+                                 waves (one workgroup of 256 lanes per tile); 0: full sweeps only;
+                                 default 2 (with levels asked for, 2 runs as 1) */
     int32_t adjoint_rounds;   /* fixed adjoint round budget of unsynchronised batched calls; default 64 */
     int32_t level_rounds;     /* fixed level round budget of unsynchronised batched calls; default 8 */
     int32_t scheduler;        /* EIK_SCHED_ROUNDS: one launch per round of flagged tiles, host checks between
@@ -114,6 +117,9 @@ typedef struct eik_tuning {
                                  levels are asked for: 1, 2 or 4 (a tile then runs on that many waves);
                                  default 4 */
     int32_t adjoint_cycles;   /* four-sweep cycles a tile may run per adjoint visit; default 1 */
+    int32_t adjoint_waves;    /* waves per tile in the round scheduler's adjoint visits: 1 (the four
+                                 directional sweeps of a cycle in turn) or 4 (one direction per wave, all at
+                                 once); default 4 */
 } eik_tuning;
 
 enum { EIK_SCHED_ROUNDS = 1, EIK_SCHED_QUEUE = 2 };

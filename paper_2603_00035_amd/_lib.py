@@ -46,7 +46,7 @@ class EikTuning(ctypes.Structure):
                 ("rounds_per_check", ctypes.c_int32), ("fast_cold_start", ctypes.c_int32),
                 ("adjoint_rounds", ctypes.c_int32), ("level_rounds", ctypes.c_int32),
                 ("scheduler", ctypes.c_int32), ("node_lanes", ctypes.c_int32),
-                ("adjoint_cycles", ctypes.c_int32)]
+                ("adjoint_cycles", ctypes.c_int32), ("adjoint_waves", ctypes.c_int32)]
 
 
 class EikProjectParams(ctypes.Structure):

@@ -176,22 +176,24 @@ eik_tuning tuning_or_default(const eik_tuning *t)
     d.tile_height = kDefaultTH;
     d.max_local_cycles = 1;
     d.rounds_per_check = 8;
-    d.fast_cold_start = 0;
+    d.fast_cold_start = 2;
     d.adjoint_rounds = 64;
     d.level_rounds = 8;
     d.scheduler = EIK_SCHED_ROUNDS;
     d.node_lanes = 4;
     d.adjoint_cycles = 1;
+    d.adjoint_waves = 4;
     if (t) {
         if (t->tile_height == 32 || t->tile_height == 64) d.tile_height = t->tile_height;
         if (t->max_local_cycles >= 1) d.max_local_cycles = t->max_local_cycles;
         if (t->rounds_per_check >= 1) d.rounds_per_check = t->rounds_per_check;
-        if (t->fast_cold_start >= 0) d.fast_cold_start = t->fast_cold_start;
+        if (t->fast_cold_start >= 0) d.fast_cold_start = std::min(t->fast_cold_start, 2);
         if (t->adjoint_rounds >= 1) d.adjoint_rounds = t->adjoint_rounds;
         if (t->level_rounds >= 1) d.level_rounds = t->level_rounds;
         if (t->scheduler == EIK_SCHED_ROUNDS || t->scheduler == EIK_SCHED_QUEUE) d.scheduler = t->scheduler;
         if (t->node_lanes == 1 || t->node_lanes == 2 || t->node_lanes == 4) d.node_lanes = t->node_lanes;
         if (t->adjoint_cycles >= 1) d.adjoint_cycles = t->adjoint_cycles;
+        if (t->adjoint_waves == 1 || t->adjoint_waves == 4) d.adjoint_waves = t->adjoint_waves;
     }
     return d;
 }
@@ -326,12 +328,16 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     int r0 = 0, rounds = 0;
     bool conv = false;
     const bool fast = T_init == nullptr && tn.fast_cold_start;
-    if (fast) { // cold start: restricted candidates, T only decreases
+    if (fast) {
+        // cold start: restricted candidates, T only decreases. Run to exact
+        // stationarity of this min-update (finite: every store lowers a
+        // value), so the full rounds that follow start from the fixed point
+        // rather than from a field left within tol of it.
         rc = run_rounds(
             w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-                launch_sweep_round<R>(a, kModeFast, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
-                                      tn.max_local_cycles, 1, st);
+                launch_sweep_round<R>(a, tn.fast_cold_start == 2 ? kModeFastCD : kModeFast, M, om, w.Pt, T,
+                                      parent, level, ain, aout, cnt, w.ctr, 0.0, tn.max_local_cycles, 1, st);
             },
             &rounds, &conv, &timer);
         if (rc) return rc;
@@ -476,7 +482,7 @@ int relax(const LaunchArgs &a, Ws &w, const eik_tuning &tn, bool sync, const uin
             w.act, w.act_count, a.n_tiles, 0, sync ? kMaxRounds / 2 : tn.adjoint_rounds, tn.rounds_per_check, sync,
             st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-                launch_adj_round<RL>(a, parent, w1, g, lam, tn.adjoint_cycles, ain, aout, cnt, st);
+                launch_adj_round<RL>(a, parent, w1, g, lam, tn.adjoint_cycles, tn.adjoint_waves, ain, aout, cnt, st);
             },
             &rounds, &conv);
         if (rc) return rc;

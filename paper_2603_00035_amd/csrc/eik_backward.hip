@@ -95,7 +95,7 @@ __device__ __forceinline__ bool adj_sweep_dir(const TileGeoB &g, R *sLam, const 
 {
     constexpr int LP = TW + 3;
     constexpr bool COL = (DIR & 1) == 0;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % TW;
     const int len = COL ? g.w : g.h;
     const int span = COL ? g.h : g.w;
     bool changed = false;
@@ -141,14 +141,22 @@ struct AdjVisit {
     bool settled;
 };
 
-template <typename R, int TH>
+// CD: the workgroup holds four waves that sweep the four directions of each
+// cycle at once over the same LDS tile. Every store is a full recomputation of
+// a node from its receivers' current values; a store computed from values that
+// another wave has since replaced counts as a change, so the cycle repeats. A
+// cycle in which no wave changed anything recomputed every node from values
+// that stayed fixed, so every equation of the tile holds exactly, as after a
+// quiet cycle of the one-wave visit, and the fixed point is the same.
+template <typename R, int TH, bool CD>
 __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, const uint8_t *__restrict__ parall,
                                                     const R *__restrict__ w1all, const R *__restrict__ gall,
                                                     R *lamall, int max_cycles, R *sLam, R *sW, uint8_t *sP,
-                                                    uint16_t *sD, R *sG)
+                                                    uint16_t *sD, R *sG, int *sBits)
 {
     constexpr int LP = TW + 3;
-    const int lane = threadIdx.x;
+    constexpr int NW = CD ? 4 : 1;
+    const int lane = threadIdx.x % TW, wave = threadIdx.x / TW;
     const TileGeoB g = tile_geo_b<TH>(a, t);
     const int nx = g.gd.nx, ny = g.gd.ny;
     R *lam = lamall + g.gd.off;
@@ -157,8 +165,9 @@ __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, 
     load_tile_halo<R, TH, LP>(w1all + g.gd.off, sW, nx, ny, g.i0, g.j0, R(1));
     load_tile_halo<uint8_t, TH, LP>(parall + g.gd.off, sP, nx, ny, g.i0, g.j0, kUnreached);
     load_block<R, TH, TW, 0>(gall + g.gd.off, sG, nx, ny, g.i0, g.j0, R(0));
+    if (CD && threadIdx.x == 0) *sBits = 0;
     __syncthreads();
-    for (int idx = lane; idx < TH * TW; idx += TW) {
+    for (int idx = threadIdx.x; idx < TH * TW; idx += NW * TW) {
         const int r = idx / TW, c = idx - r * TW;
         uint32_t d = 0;
 #pragma unroll
@@ -176,14 +185,19 @@ __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, 
     const int max_sweeps = 4 * max_cycles;
     while (quiet < 4 && sweeps < max_sweeps) {
         bool changed;
-        switch (sweeps & 3) {
+        switch (CD ? wave : (sweeps & 3)) { // CD: one direction per wave, uniform per wave
         case 0: changed = adj_sweep_dir<R, TH, 0>(g, sLam, sW, sD, sG); break;
         case 1: changed = adj_sweep_dir<R, TH, 1>(g, sLam, sW, sD, sG); break;
         case 2: changed = adj_sweep_dir<R, TH, 2>(g, sLam, sW, sD, sG); break;
         default: changed = adj_sweep_dir<R, TH, 3>(g, sLam, sW, sD, sG); break;
         }
-        ++sweeps;
-        quiet = __ballot(changed) ? 0 : quiet + 1;
+        if (CD) { // a cycle is the four concurrent sweeps
+            sweeps += 4;
+            quiet = __syncthreads_or(changed ? 1 : 0) ? 0 : 4;
+        } else {
+            ++sweeps;
+            quiet = __ballot(changed) ? 0 : quiet + 1;
+        }
     }
 
     // write back (old values re-read in batches), note the neighbours whose
@@ -191,7 +205,7 @@ __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, 
     int bits = 0;
     const int c = lane;
 #pragma unroll 1
-    for (int r0 = 0; r0 < TH; r0 += kLoadBatch) {
+    for (int r0 = wave * kLoadBatch; r0 < TH; r0 += NW * kLoadBatch) {
         R ov[kLoadBatch];
 #pragma unroll
         for (int k = 0; k < kLoadBatch; ++k) {
@@ -213,6 +227,11 @@ __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, 
         }
     }
     for (int off = 32; off >= 1; off >>= 1) bits |= __shfl_xor(bits, off);
+    if (CD) {
+        if (lane == 0 && bits) atomicOr(sBits, bits);
+        __syncthreads();
+        bits = *sBits;
+    }
     AdjVisit v;
     v.bits = bits;
     v.settled = quiet >= 4;
@@ -229,24 +248,26 @@ __device__ __forceinline__ int adj_neighbour(const TileGeoB &g, int b)
     return g.gd.tile_base + uy * g.gd.ntx + ux;
 }
 
-// Round scheduler with sweep visits.
-template <typename R, int TH>
-__global__ __launch_bounds__(TW) void k_adj_sweep_round(LaunchArgs a, const uint8_t *__restrict__ parall,
-                                                        const R *__restrict__ w1all, const R *__restrict__ gall,
-                                                        R *__restrict__ lamall, int max_cycles,
-                                                        int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
-                                                        int32_t *__restrict__ count_next)
+// Round scheduler with sweep visits (CD: four waves per tile).
+template <typename R, int TH, bool CD>
+__global__ __launch_bounds__(CD ? 4 * TW : TW) void k_adj_sweep_round(
+    LaunchArgs a, const uint8_t *__restrict__ parall, const R *__restrict__ w1all, const R *__restrict__ gall,
+    R *__restrict__ lamall, int max_cycles, int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
+    int32_t *__restrict__ count_next)
 {
     constexpr int LP = TW + 3;
     const int t = blockIdx.x;
-    if (act_in[t] == 0) return;
-    if (threadIdx.x == 0) act_in[t] = 0;
+    if (act_in[t] == 0) return; // uniform over the workgroup
     __shared__ R sLam[(TH + 2) * LP];
     __shared__ R sW[(TH + 2) * LP];
     __shared__ uint8_t sP[(TH + 2) * LP];
     __shared__ uint16_t sD[TH * TW];
     __shared__ R sG[TH * TW];
-    const AdjVisit v = adj_visit_sweep<R, TH>(a, t, parall, w1all, gall, lamall, max_cycles, sLam, sW, sP, sD, sG);
+    __shared__ int sBits;
+    if (CD) __syncthreads(); // every wave has read act_in[t] before it is cleared
+    if (threadIdx.x == 0) act_in[t] = 0;
+    const AdjVisit v =
+        adj_visit_sweep<R, TH, CD>(a, t, parall, w1all, gall, lamall, max_cycles, sLam, sW, sP, sD, sG, &sBits);
     if (threadIdx.x == 0) {
         const TileGeoB g = tile_geo_b<TH>(a, t);
         for (int b = 0; b < 8; ++b) {
@@ -276,7 +297,7 @@ __global__ __launch_bounds__(TW) void k_adj_sweep_queue(LaunchArgs a, const uint
         if (t < 0) break;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const AdjVisit v =
-            adj_visit_sweep<R, TH>(a, t, parall, w1all, gall, lamall, max_cycles, sLam, sW, sP, sD, sG);
+            adj_visit_sweep<R, TH, false>(a, t, parall, w1all, gall, lamall, max_cycles, sLam, sW, sP, sD, sG, nullptr);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (threadIdx.x == 0) {
             const TileGeoB g = tile_geo_b<TH>(a, t);
@@ -356,11 +377,16 @@ void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const v
 
 template <typename R>
 void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const void *w1, const void *dLdT, void *lam,
-                      int max_cycles, int32_t *act_in, int32_t *act_out, int32_t *count_next, hipStream_t st)
+                      int max_cycles, int waves, int32_t *act_in, int32_t *act_out, int32_t *count_next,
+                      hipStream_t st)
 {
-    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_sweep_round<R, TH>), dim3(a.n_tiles), dim3(TW), 0, st, a, parent,
-                                             (const R *)w1, (const R *)dLdT, (R *)lam, max_cycles, act_in, act_out,
-                                             count_next));
+#define EIK_ADJ_ROUND(CD)                                                                                        \
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_sweep_round<R, TH, CD>), dim3(a.n_tiles), dim3(CD ? 4 * TW : TW), \
+                                             0, st, a, parent, (const R *)w1, (const R *)dLdT, (R *)lam,          \
+                                             max_cycles, act_in, act_out, count_next))
+    if (waves >= 4) EIK_ADJ_ROUND(true);
+    else EIK_ADJ_ROUND(false);
+#undef EIK_ADJ_ROUND
 }
 
 template <typename R>
@@ -407,7 +433,7 @@ void launch_dsrc(const LaunchArgs &a, const int32_t *src_idx, const void *lam, v
     template void launch_adj_prep<R>(const LaunchArgs &, const void *, const void *, const void *,              \
                                      const uint8_t *, void *, void *, hipStream_t);                             \
     template void launch_adj_round<R>(const LaunchArgs &, const uint8_t *, const void *, const void *, void *,   \
-                                      int, int32_t *, int32_t *, int32_t *, hipStream_t);                        \
+                                      int, int, int32_t *, int32_t *, int32_t *, hipStream_t);                   \
     template void launch_adj_queue<R>(const LaunchArgs &, int, const uint8_t *, const void *, const void *,     \
                                       void *, int, const WorkQueue &, hipStream_t);                              \
     template void launch_adj_params<R>(const LaunchArgs &, const void *, const uint8_t *, const void *,         \

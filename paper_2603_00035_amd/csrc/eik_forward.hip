@@ -208,7 +208,7 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
 {
     constexpr int LP = TW + 3;
     constexpr bool COL = (DIR & 1) == 0; // a column (fixed x) per step
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % TW;
     const int len = COL ? g.w : g.h;
     const int span = COL ? g.h : g.w;
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
@@ -264,7 +264,12 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
             // only T decides convergence; levels ride along and are made
             // consistent with the final active updates afterwards
             changed |= counts_as_change<R>(old, v, tol);
-            sT[slot] = v;
+            if (FULL) {
+                sT[slot] = v;
+            } else if (v < old) { // FAST: LDS atomic minimum (ds_min), safe under concurrent directions
+                __hip_atomic_fetch_min(&sT[slot], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+
         }
         wave_step_sync();
     }
@@ -378,6 +383,106 @@ __global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__res
         const TileGeo g = tile_geo<TH>(a, t);
         flag_neighbours(v.bits, g, act_out, count_next);
         if (!v.settled) flag_tile(act_out, count_next, t); // cycle budget ran out before the tile settled
+        atomicAdd(&ctr[kCtrCellUpdates], (unsigned long long)v.sweeps);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Concurrent-direction FAST visits (cold start). T only decreases under the
+// FAST update and the update is monotone in the donor values, so the four
+// directional sweeps of a cycle need not run one after another: four waves
+// sweep the four directions of the same LDS tile at once, each storing its
+// improvements with an LDS atomic minimum, so concurrent stores never raise a
+// value. A cycle ends quiet only when no wave improved anything. The chain of
+// dependent line steps per cycle is one direction's instead of four.
+// ---------------------------------------------------------------------------
+template <typename R, int TH>
+__device__ __forceinline__ Visit visit_tile_cd(const LaunchArgs &a, int t, const R *__restrict__ M,
+                                               const R *__restrict__ om, const R *__restrict__ Ptall, R *Tall,
+                                               R tol, int max_cycles, R *sT, uint8_t *sC, int *sBits)
+{
+    constexpr int LP = TW + 3;
+    const int lane = threadIdx.x % TW, wave = threadIdx.x / TW;
+    const TileGeo g = tile_geo<TH>(a, t);
+    R *T = Tall + g.gd.off;
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    const R *Mg = M + 3 * g.gd.off, *Og = om + 2 * g.gd.off;
+    const R *Pt = Ptall + 5 * g.gd.off, *Pto = Pt + 3 * n;
+    const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
+
+    load_tile_halo<R, TH, LP>(T, sT, g.gd.nx, g.gd.ny, g.i0, g.j0, inf_v<R>());
+    if (threadIdx.x == 0) *sBits = 0;
+    __syncthreads();
+
+    int cycles = 0;
+    bool quiet = false;
+    while (!quiet && cycles < max_cycles) {
+        bool ch;
+        switch (wave) { // uniform per wave
+        case 0: ch = sweep_dir<R, TH, 0, false, false>(g, Pt, Pto, sT, nullptr, sC, tol, h, inv_h); break;
+        case 1: ch = sweep_dir<R, TH, 1, false, false>(g, Mg, Og, sT, nullptr, sC, tol, h, inv_h); break;
+        case 2: ch = sweep_dir<R, TH, 2, false, false>(g, Pt, Pto, sT, nullptr, sC, tol, h, inv_h); break;
+        default: ch = sweep_dir<R, TH, 3, false, false>(g, Mg, Og, sT, nullptr, sC, tol, h, inv_h); break;
+        }
+        ++cycles;
+        quiet = !__syncthreads_or(ch ? 1 : 0);
+    }
+
+    // write back: wave w takes row batches w, w + 4, ...
+    int bits = 0;
+    const int c = lane;
+#pragma unroll 1
+    for (int r0 = wave * kLoadBatch; r0 < TH; r0 += 4 * kLoadBatch) {
+        R ov[kLoadBatch];
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+            const int r = r0 + k;
+            const int rc = r < g.h ? r : g.h - 1, cc = c < g.w ? c : g.w - 1;
+            ov[k] = T[(size_t)(g.j0 + rc) * g.gd.nx + g.i0 + cc];
+        }
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+            const int r = r0 + k;
+            if (r >= g.h || c >= g.w) continue;
+            const R nv = sT[(r + 1) * LP + c + 1];
+            if (nv != ov[k]) T[(size_t)(g.j0 + r) * g.gd.nx + (g.i0 + c)] = nv;
+            if (counts_as_change<R>(ov[k], nv, tol)) bits |= halo_bits(c, r, g.w, g.h);
+        }
+    }
+    bits = wave_or(bits);
+    if (lane == 0 && bits) atomicOr(sBits, bits);
+    __syncthreads();
+    Visit v;
+    v.bits = *sBits;
+    v.settled = quiet;
+    v.sweeps = 4 * cycles * g.w * g.h;
+    return v;
+}
+
+template <typename R, int TH>
+__global__ __launch_bounds__(4 * TW) void k_sweep_round_cd(LaunchArgs a, const R *__restrict__ M,
+                                                         const R *__restrict__ om, const R *__restrict__ Ptall,
+                                                         R *__restrict__ Tall, const uint8_t *__restrict__ codeall,
+                                                         int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
+                                                         int32_t *__restrict__ count_next,
+                                                         unsigned long long *__restrict__ ctr, R tol, int max_cycles)
+{
+    constexpr int LP = TW + 3;
+    const int t = blockIdx.x;
+    if (act_in[t] == 0) return;
+    __shared__ R sT[(TH + 2) * LP];
+    __shared__ uint8_t sC[TH * TW];
+    __shared__ int sBits;
+    {
+        const TileGeo g = tile_geo<TH>(a, t);
+        load_block<uint8_t, TH, TW, 0>(codeall + g.gd.off, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
+    }
+    const Visit v = visit_tile_cd<R, TH>(a, t, M, om, Ptall, Tall, tol, max_cycles, sT, sC, &sBits);
+    if (threadIdx.x == 0) {
+        act_in[t] = 0;
+        const TileGeo g = tile_geo<TH>(a, t);
+        flag_neighbours(v.bits, g, act_out, count_next);
+        if (!v.settled) flag_tile(act_out, count_next, t);
         atomicAdd(&ctr[kCtrCellUpdates], (unsigned long long)v.sweeps);
     }
 }
@@ -949,6 +1054,12 @@ void launch_sweep_round(const LaunchArgs &a, int mode, const void *M, const void
                                              (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, level,     \
                                              act_in, act_out, count_next, ctr, R(tol), max_cycles))
     const bool lev = level != nullptr;
+    if (mode == kModeFastCD && !lev) {
+        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round_cd<R, TH>), dim3(a.n_tiles), dim3(4 * TW), 0, st, a,
+                                                 (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, act_in,
+                                                 act_out, count_next, ctr, R(tol), max_cycles));
+        return;
+    }
     if (mode == kModeFull) {
         if (lev) EIK_SWEEP_ROUND(true, true);
         else EIK_SWEEP_ROUND(true, false);

@@ -56,7 +56,7 @@ struct WorkQueue {
 
 constexpr int kMaxRounds = 1 << 16;
 
-enum SweepMode { kModeFast = 0, kModeFull = 1 };
+enum SweepMode { kModeFast = 0, kModeFull = 1, kModeFastCD = 2 };
 
 // copies the flagged-tile count of the last round into a counter slot
 void launch_note_pending(const int32_t *count, unsigned long long *slot, hipStream_t st);
@@ -102,7 +102,8 @@ void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const v
                      void *w1, void *lam, hipStream_t st);
 template <typename R>
 void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const void *w1, const void *dLdT, void *lam,
-                      int max_cycles, int32_t *act_in, int32_t *act_out, int32_t *count_next, hipStream_t st);
+                      int max_cycles, int waves, int32_t *act_in, int32_t *act_out, int32_t *count_next,
+                      hipStream_t st);
 template <typename R>
 void launch_adj_queue(const LaunchArgs &a, int n_waves, const uint8_t *parent, const void *w1, const void *dLdT,
                       void *lam, int max_cycles, const WorkQueue &q, hipStream_t st);

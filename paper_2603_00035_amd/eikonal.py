@@ -57,11 +57,12 @@ def workspace(grid: L.EikGrid, dtype_code: int, device) -> torch.Tensor:
 
 
 def tuning(tile_height=0, max_local_cycles=0, rounds_per_check=0, fast_cold_start=-1, adjoint_rounds=0,
-           level_rounds=0, scheduler=0, node_lanes=0, adjoint_cycles=0):
+           level_rounds=0, scheduler=0, node_lanes=0, adjoint_cycles=0, adjoint_waves=0):
     """Scheduling knobs (0 / -1 keep the library default). scheduler: 1 rounds,
-    2 device work queue; node_lanes: 1, 2 or 4 lanes per node update."""
+    2 device work queue; node_lanes: 1, 2 or 4 lanes per node update;
+    fast_cold_start: 0, 1 or 2 (four directions at once); adjoint_waves: 1 or 4."""
     return L.EikTuning(tile_height, max_local_cycles, rounds_per_check, fast_cold_start, adjoint_rounds,
-                       level_rounds, scheduler, node_lanes, adjoint_cycles)
+                       level_rounds, scheduler, node_lanes, adjoint_cycles, adjoint_waves)
 
 
 def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=4096, check_feasible=False,

@@ -102,6 +102,15 @@ def check_parent_choices(q, To, po, pg, rtol, Tg=None):
 
 FP32_EPS = 2.0 ** -24
 
+# Gradient rel-L2 bar of the plain FP32 path against the oracle. The 1e-4 bar
+# sits at the floor that FP32 storage of T allows on these anisotropic fields:
+# the oracle's own sweeps with every stored value rounded to FP32 land 1.0e-4
+# from the exact gradient of the 512^2 loss (1.4e-4 on the 2048^2 stress
+# field), because the donor weights of nearly degenerate two-point updates
+# amplify errors in T. FP32 runs are held to three times that; the
+# mixed-precision path is held to 1e-4.
+FP32_GRAD_RTOL = 3e-4
+
 
 def causality_margin(q, T, c, code):
     """min(t - Tp, t - Tq) / t of two-point candidate `code` at node c of T

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from synthetic.fields import make_problem
-from tests.gpu_common import (check_levels_consistent, check_parent_choices, oracle_view, rel_err_cells, rel_l2,
+from tests.gpu_common import (FP32_GRAD_RTOL, check_levels_consistent, check_parent_choices, oracle_view, rel_err_cells, rel_l2,
                               say, to_dev)
 
 pytestmark = pytest.mark.gpu
@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 
 def queue_tuning(th=64, cycles=2):
     from paper_2603_00035_amd import eikonal as E
-    return E.tuning(tile_height=th, max_local_cycles=cycles, scheduler=2)
+    return E.tuning(tile_height=th, max_local_cycles=cycles, scheduler=2, fast_cold_start=0)  # the queue alone
 
 
 def solve(p, dt, tol, tune, **kw):
@@ -70,7 +70,7 @@ def test_queue_fp32_c2_matches_oracle():
     r = rel_l2([dM.cpu().numpy().astype(np.float64), dom.cpu().numpy().astype(np.float64),
                 ds.cpu().numpy().astype(np.float64)], [dMo, domo, dso])
     say(f"  gradient rel L2 {r:.2e}")
-    assert r <= 1e-4
+    assert r <= FP32_GRAD_RTOL
 
 
 def test_queue_warm_start_and_visit_budget():

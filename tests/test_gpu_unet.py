@@ -177,7 +177,7 @@ def test_network_gradient_matches_finite_differences_of_its_loss():
     src = torch.tensor([[5 * W + 7, -1, -1, -1]], dtype=torch.int32, device="cuda")
     hv = torch.full((B,), 1.0 / 31, device="cuda")
     net.features(M, om, src, hv)
-    target = torch.rand(B * H * W, device="cuda")
+    target = torch.rand(B * H * W, device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
 
     def loss():
         pred = net.forward(B, H, W)
@@ -201,8 +201,11 @@ def test_network_gradient_matches_finite_differences_of_its_loss():
         net.refresh_weights()
         return (lp - lm) / (2 * eps)
 
-    for key, idx in [("head.b", 0), ("d0b.b", 3), ("bb.b", 7), ("e1a.b", 5), ("u0.b", 2)]:
+    # each tensor at its largest-gradient entry: small entries are sums with
+    # heavy cancellation, where BF16 rounding of the backward dominates
+    for key in ["head.b", "d0b.b", "bb.b", "e1a.b", "u0.b"]:
         p = net.params[key]
+        idx = int(net.grads[key].view(-1).abs().argmax())
         # the bf16 activations make the loss a step function at fine scales:
         # the spread of two step sizes measures that noise in the difference
         fd1, fd2 = central(p, idx, 0.05), central(p, idx, 0.025)
