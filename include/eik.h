@@ -95,7 +95,11 @@ typedef struct eik_stats {
     int32_t status;         /* same as the return value */
     int32_t sweep_launches; /* launches of the tile-sweep kernel */
     int32_t aux_rounds;     /* level rounds (forward) / adjoint rounds (backward) */
-    double sweep_ms;        /* summed duration of the sweep launches (EIK_TIME_KERNELS), else 0 */
+    double sweep_ms;        /* duration of the sweep launches (EIK_TIME_KERNELS; each batch of rounds between
+                               host checks is timed as a whole), else 0 */
+    double fast_ms;         /* the part of sweep_ms spent in the cold start's restricted-candidate rounds */
+    int64_t fast_cell_updates; /* the part of cell_updates made in those rounds */
+    int32_t fast_launches;  /* the part of sweep_launches made in those rounds */
 } eik_stats;
 
 /* Scheduling knobs; NULL or a field <= 0 keeps the library default. */
@@ -120,6 +124,9 @@ typedef struct eik_tuning {
     int32_t adjoint_waves;    /* waves per tile in the round scheduler's adjoint visits: 1 (the four
                                  directional sweeps of a cycle in turn) or 4 (one direction per wave, all at
                                  once); default 4 */
+    int32_t full_waves;       /* waves per tile in the round scheduler's full-update visits when no levels are
+                                 asked for: 1 (the four directions in turn, node_lanes lanes per node) or 4
+                                 (one direction per wave, one lane per node, all at once); default 4 */
 } eik_tuning;
 
 enum { EIK_SCHED_ROUNDS = 1, EIK_SCHED_QUEUE = 2 };

@@ -38,7 +38,8 @@ class EikGrid(ctypes.Structure):
 class EikStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("converged", ctypes.c_int32), ("cell_updates", ctypes.c_int64),
                 ("n_levels", ctypes.c_int32), ("status", ctypes.c_int32), ("sweep_launches", ctypes.c_int32),
-                ("aux_rounds", ctypes.c_int32), ("sweep_ms", ctypes.c_double)]
+                ("aux_rounds", ctypes.c_int32), ("sweep_ms", ctypes.c_double), ("fast_ms", ctypes.c_double),
+                ("fast_cell_updates", ctypes.c_int64), ("fast_launches", ctypes.c_int32)]
 
 
 class EikTuning(ctypes.Structure):
@@ -46,7 +47,8 @@ class EikTuning(ctypes.Structure):
                 ("rounds_per_check", ctypes.c_int32), ("fast_cold_start", ctypes.c_int32),
                 ("adjoint_rounds", ctypes.c_int32), ("level_rounds", ctypes.c_int32),
                 ("scheduler", ctypes.c_int32), ("node_lanes", ctypes.c_int32),
-                ("adjoint_cycles", ctypes.c_int32), ("adjoint_waves", ctypes.c_int32)]
+                ("adjoint_cycles", ctypes.c_int32), ("adjoint_waves", ctypes.c_int32),
+                ("full_waves", ctypes.c_int32)]
 
 
 class EikProjectParams(ctypes.Structure):

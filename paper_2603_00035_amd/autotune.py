@@ -27,18 +27,18 @@ from . import _lib as L
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning_table.json")
 KNOBS = ("tile_height", "max_local_cycles", "rounds_per_check", "fast_cold_start", "adjoint_rounds", "level_rounds",
-         "scheduler", "node_lanes", "adjoint_cycles", "adjoint_waves")
+         "scheduler", "node_lanes", "adjoint_cycles", "adjoint_waves", "full_waves")
 DEFAULTS = {"tile_height": 64, "max_local_cycles": 1, "rounds_per_check": 8, "fast_cold_start": 2,
             "adjoint_rounds": 64, "level_rounds": 8, "scheduler": 1, "node_lanes": 4,
-            "adjoint_cycles": 1, "adjoint_waves": 4}
+            "adjoint_cycles": 1, "adjoint_waves": 4, "full_waves": 4}
 CANDIDATES = {"tile_height": (32, 64), "max_local_cycles": (1, 2, 3), "rounds_per_check": (4, 8, 16),
               "fast_cold_start": (0, 1, 2), "adjoint_rounds": (16, 64, 256), "level_rounds": (4, 8, 16),
               "scheduler": (1, 2), "node_lanes": (1, 2, 4), "adjoint_cycles": (1, 2),
-              "adjoint_waves": (1, 4)}
+              "adjoint_waves": (1, 4), "full_waves": (1, 4)}
 # knobs timed by the tuner (the unsynchronised round budgets are sized for
 # correctness, not speed, and keep their defaults)
 TUNED = ("tile_height", "max_local_cycles", "rounds_per_check", "fast_cold_start", "scheduler", "node_lanes",
-         "adjoint_cycles", "adjoint_waves")
+         "adjoint_cycles", "adjoint_waves", "full_waves")
 # single-grid size classes by node count: (upper bound, representative side, problem recipe)
 CLASSES = ((96 * 96, 64, "c1"), (384 * 384, 256, "c1"), (768 * 768, 512, "c2"), (1536 * 1536, 1024, "c3"),
            (1 << 62, 2048, "c3"))

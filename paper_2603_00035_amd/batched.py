@@ -20,7 +20,7 @@ import torch
 
 from . import _lib as L
 from . import autotune
-from .eikonal import Stats
+from .eikonal import stats_of
 
 
 class Batch:
@@ -90,8 +90,7 @@ class Batch:
         L.check("eik_forward_batched", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
         stats = None
         if st is not None:
-            stats = Stats(st.rounds, bool(st.converged), st.cell_updates, st.n_levels, st.status,
-                          st.sweep_launches, st.sweep_ms, st.aux_rounds)
+            stats = stats_of(st)
         return T, parent, level, stats
 
     def alloc_backward(self):

@@ -183,6 +183,7 @@ eik_tuning tuning_or_default(const eik_tuning *t)
     d.node_lanes = 4;
     d.adjoint_cycles = 1;
     d.adjoint_waves = 4;
+    d.full_waves = 4;
     if (t) {
         if (t->tile_height == 32 || t->tile_height == 64) d.tile_height = t->tile_height;
         if (t->max_local_cycles >= 1) d.max_local_cycles = t->max_local_cycles;
@@ -194,11 +195,14 @@ eik_tuning tuning_or_default(const eik_tuning *t)
         if (t->node_lanes == 1 || t->node_lanes == 2 || t->node_lanes == 4) d.node_lanes = t->node_lanes;
         if (t->adjoint_cycles >= 1) d.adjoint_cycles = t->adjoint_cycles;
         if (t->adjoint_waves == 1 || t->adjoint_waves == 4) d.adjoint_waves = t->adjoint_waves;
+        if (t->full_waves == 1 || t->full_waves == 4) d.full_waves = t->full_waves;
     }
     return d;
 }
 
-// Optional per-launch timing with HIP events recorded on the launch stream.
+// Optional timing with HIP events recorded on the launch stream: one pair
+// around each batch of rounds enqueued between host checks, so the timing adds
+// nothing between the launches of a batch.
 struct LaunchTimer {
     std::vector<hipEvent_t> ev;
     int used = 0;
@@ -208,11 +212,11 @@ struct LaunchTimer {
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
-    int init(bool enable, int per_batch)
+    int init(bool enable)
     {
         on = enable;
         if (!on) return EIK_OK;
-        ev.resize(2 * per_batch);
+        ev.resize(2);
         for (auto &e : ev) HIP_OK(hipEventCreate(&e));
         return EIK_OK;
     }
@@ -247,11 +251,10 @@ int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int bud
     *converged = false;
     while (r < end) {
         const int batch = sync ? std::min(per_check, end - r) : end - r;
-        for (int b = 0; b < batch; ++b, ++r) {
-            if (timer && timer->on) timer->before(st);
+        if (timer && timer->on) timer->before(st);
+        for (int b = 0; b < batch; ++b, ++r)
             round_fn(act + (r & 1) * n_tiles, act + ((r + 1) & 1) * n_tiles, act_count + r + 1);
-            if (timer && timer->on) timer->after(st);
-        }
+        if (timer && timer->on) timer->after(st);
         if (!sync) break;
         int32_t cnt = 0;
         HIP_OK(hipMemcpyAsync(&cnt, act_count + r, sizeof cnt, hipMemcpyDeviceToHost, st));
@@ -323,7 +326,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     HIP_OK(hipGetLastError());
 
     LaunchTimer timer;
-    rc = timer.init((flags & EIK_TIME_KERNELS) != 0 && sync, tn.rounds_per_check);
+    rc = timer.init((flags & EIK_TIME_KERNELS) != 0 && sync);
     if (rc) return rc;
     int r0 = 0, rounds = 0;
     bool conv = false;
@@ -342,10 +345,13 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
             &rounds, &conv, &timer);
         if (rc) return rc;
         r0 += rounds;
+        launch_copy_u64(w.ctr + kCtrCellUpdates, w.ctr + kCtrFastUpdates, st);
         // certify with the full update: every tile runs once more
         launch_all_active(a, w.act + (r0 & 1) * a.n_tiles, w.act_count + r0, st);
     }
     int launches = r0;
+    const int fast_launches = r0;
+    const double fast_ms = timer.ms;
     if (tn.scheduler == EIK_SCHED_QUEUE) {
         // one persistent launch over a device queue of flagged tiles
         const int waves = std::min({sweep_queue_waves(a.th, dtype, level != nullptr), kMaxQueueWaves, a.n_tiles});
@@ -372,7 +378,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
             w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
                 launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
-                                      tn.max_local_cycles, tn.node_lanes, st);
+                                      tn.max_local_cycles, tn.full_waves == 4 ? kFullWavesCD : tn.node_lanes, st);
             },
             &rounds, &conv, &timer);
         if (rc) return rc;
@@ -421,6 +427,9 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         stats->sweep_launches = launches;
         stats->sweep_ms = timer.ms;
         stats->aux_rounds = lrounds;
+        stats->fast_ms = fast_ms;
+        stats->fast_cell_updates = fast ? (int64_t)ctr[kCtrFastUpdates] : 0;
+        stats->fast_launches = fast_launches;
     }
     return status;
 }

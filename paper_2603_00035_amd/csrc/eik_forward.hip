@@ -265,7 +265,7 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
             // consistent with the final active updates afterwards
             changed |= counts_as_change<R>(old, v, tol);
             if (FULL) {
-                sT[slot] = v;
+                if (v != old) sT[slot] = v; // skipping equal stores changes nothing in turn, loses less at once
             } else if (v < old) { // FAST: LDS atomic minimum (ds_min), safe under concurrent directions
                 __hip_atomic_fetch_min(&sT[slot], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
@@ -388,15 +388,19 @@ __global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__res
 }
 
 // ---------------------------------------------------------------------------
-// Concurrent-direction FAST visits (cold start). T only decreases under the
-// FAST update and the update is monotone in the donor values, so the four
-// directional sweeps of a cycle need not run one after another: four waves
-// sweep the four directions of the same LDS tile at once, each storing its
-// improvements with an LDS atomic minimum, so concurrent stores never raise a
-// value. A cycle ends quiet only when no wave improved anything. The chain of
-// dependent line steps per cycle is one direction's instead of four.
+// Concurrent-direction visits: four waves sweep the four directions of the
+// same LDS tile at once, so the chain of dependent line steps per cycle is one
+// direction's instead of four. FAST (cold start): T only decreases and the
+// update is monotone in the donor values; improvements are stored with an LDS
+// atomic minimum, so concurrent stores never raise a value. FULL: every store
+// is a recomputation of the node from its neighbours' current values; a store
+// computed from values another wave has since replaced is itself a change
+// beyond tol or is corrected by the change that replaced them, so the cycle
+// repeats. Either way a cycle ends quiet only when no wave changed anything
+// beyond tol, which means every node of the tile holds its update (to tol)
+// from the final values, as after a quiet cycle of the one-wave visit.
 // ---------------------------------------------------------------------------
-template <typename R, int TH>
+template <typename R, int TH, bool FULL>
 __device__ __forceinline__ Visit visit_tile_cd(const LaunchArgs &a, int t, const R *__restrict__ M,
                                                const R *__restrict__ om, const R *__restrict__ Ptall, R *Tall,
                                                R tol, int max_cycles, R *sT, uint8_t *sC, int *sBits)
@@ -419,10 +423,10 @@ __device__ __forceinline__ Visit visit_tile_cd(const LaunchArgs &a, int t, const
     while (!quiet && cycles < max_cycles) {
         bool ch;
         switch (wave) { // uniform per wave
-        case 0: ch = sweep_dir<R, TH, 0, false, false>(g, Pt, Pto, sT, nullptr, sC, tol, h, inv_h); break;
-        case 1: ch = sweep_dir<R, TH, 1, false, false>(g, Mg, Og, sT, nullptr, sC, tol, h, inv_h); break;
-        case 2: ch = sweep_dir<R, TH, 2, false, false>(g, Pt, Pto, sT, nullptr, sC, tol, h, inv_h); break;
-        default: ch = sweep_dir<R, TH, 3, false, false>(g, Mg, Og, sT, nullptr, sC, tol, h, inv_h); break;
+        case 0: ch = sweep_dir<R, TH, 0, FULL, false>(g, Pt, Pto, sT, nullptr, sC, tol, h, inv_h); break;
+        case 1: ch = sweep_dir<R, TH, 1, FULL, false>(g, Mg, Og, sT, nullptr, sC, tol, h, inv_h); break;
+        case 2: ch = sweep_dir<R, TH, 2, FULL, false>(g, Pt, Pto, sT, nullptr, sC, tol, h, inv_h); break;
+        default: ch = sweep_dir<R, TH, 3, FULL, false>(g, Mg, Og, sT, nullptr, sC, tol, h, inv_h); break;
         }
         ++cycles;
         quiet = !__syncthreads_or(ch ? 1 : 0);
@@ -459,7 +463,7 @@ __device__ __forceinline__ Visit visit_tile_cd(const LaunchArgs &a, int t, const
     return v;
 }
 
-template <typename R, int TH>
+template <typename R, int TH, bool FULL>
 __global__ __launch_bounds__(4 * TW) void k_sweep_round_cd(LaunchArgs a, const R *__restrict__ M,
                                                          const R *__restrict__ om, const R *__restrict__ Ptall,
                                                          R *__restrict__ Tall, const uint8_t *__restrict__ codeall,
@@ -477,7 +481,7 @@ __global__ __launch_bounds__(4 * TW) void k_sweep_round_cd(LaunchArgs a, const R
         const TileGeo g = tile_geo<TH>(a, t);
         load_block<uint8_t, TH, TW, 0>(codeall + g.gd.off, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
     }
-    const Visit v = visit_tile_cd<R, TH>(a, t, M, om, Ptall, Tall, tol, max_cycles, sT, sC, &sBits);
+    const Visit v = visit_tile_cd<R, TH, FULL>(a, t, M, om, Ptall, Tall, tol, max_cycles, sT, sC, &sBits);
     if (threadIdx.x == 0) {
         act_in[t] = 0;
         const TileGeo g = tile_geo<TH>(a, t);
@@ -1039,6 +1043,12 @@ void launch_sweep_round(const LaunchArgs &a, int mode, const void *M, const void
                         uint8_t *code, int32_t *level, int32_t *act_in, int32_t *act_out, int32_t *count_next,
                         unsigned long long *ctr, double tol, int max_cycles, int node_lanes, hipStream_t st)
 {
+    if (mode == kModeFull && level == nullptr && node_lanes == kFullWavesCD) {
+        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round_cd<R, TH, true>), dim3(a.n_tiles), dim3(4 * TW), 0, st,
+                                                 a, (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, act_in,
+                                                 act_out, count_next, ctr, R(tol), max_cycles));
+        return;
+    }
     if (mode == kModeFull && level == nullptr && node_lanes > 1) {
 #define EIK_SWEEP_SPLIT(SUB)                                                                                     \
     EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round_split<R, TH, SUB>), dim3(a.n_tiles), dim3(TW * SUB), 0,  \
@@ -1055,7 +1065,7 @@ void launch_sweep_round(const LaunchArgs &a, int mode, const void *M, const void
                                              act_in, act_out, count_next, ctr, R(tol), max_cycles))
     const bool lev = level != nullptr;
     if (mode == kModeFastCD && !lev) {
-        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round_cd<R, TH>), dim3(a.n_tiles), dim3(4 * TW), 0, st, a,
+        EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sweep_round_cd<R, TH, false>), dim3(a.n_tiles), dim3(4 * TW), 0, st, a,
                                                  (const R *)M, (const R *)om, (const R *)Pt, (R *)T, code, act_in,
                                                  act_out, count_next, ctr, R(tol), max_cycles));
         return;
@@ -1184,6 +1194,16 @@ namespace eik {
 __global__ void k_note_pending(const int32_t *__restrict__ count, unsigned long long *__restrict__ slot)
 {
     if (threadIdx.x == 0) *slot = (unsigned long long)(count[0] > 0 ? count[0] : 0);
+}
+
+__global__ void k_copy_u64(const unsigned long long *__restrict__ src, unsigned long long *__restrict__ dst)
+{
+    if (threadIdx.x == 0) *dst = *src;
+}
+
+void launch_copy_u64(const unsigned long long *src, unsigned long long *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, st, src, dst);
 }
 
 void launch_note_pending(const int32_t *count, unsigned long long *slot, hipStream_t st)

@@ -39,6 +39,7 @@ enum {
     kCtrSweepPending = 4, // tiles still flagged after the last sweep round
     kCtrLevelPending = 5, // ... after the last level round
     kCtrAdjPending = 6,   // ... after the last adjoint round
+    kCtrFastUpdates = 7,  // kCtrCellUpdates when the restricted-candidate cold start ended
     kCtrCount = 16
 };
 
@@ -57,6 +58,8 @@ struct WorkQueue {
 constexpr int kMaxRounds = 1 << 16;
 
 enum SweepMode { kModeFast = 0, kModeFull = 1, kModeFastCD = 2 };
+// node_lanes argument of launch_sweep_round that selects the concurrent-direction FULL visits
+constexpr int kFullWavesCD = -4;
 
 // copies the flagged-tile count of the last round into a counter slot
 void launch_note_pending(const int32_t *count, unsigned long long *slot, hipStream_t st);
@@ -92,6 +95,7 @@ void launch_level_round(const LaunchArgs &a, const uint8_t *parent, int32_t *lev
 void launch_max_level(int64_t n, const int32_t *level, unsigned long long *ctr, hipStream_t st);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st);
+void launch_copy_u64(const unsigned long long *src, unsigned long long *dst, hipStream_t st);
 void launch_cast_f64_f32(int64_t n, const double *src, float *dst, hipStream_t st);
 void launch_cast_f32_f64(int64_t n, const float *src, double *dst, hipStream_t st);
 void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_grid, int n_tiles, hipStream_t st);

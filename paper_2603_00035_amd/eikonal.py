@@ -27,6 +27,9 @@ class Stats:
     sweep_launches: int = 0
     sweep_ms: float = 0.0
     aux_rounds: int = 0
+    fast_ms: float = 0.0
+    fast_cell_updates: int = 0
+    fast_launches: int = 0
 
 
 def _check_fields(M, omega):
@@ -57,12 +60,13 @@ def workspace(grid: L.EikGrid, dtype_code: int, device) -> torch.Tensor:
 
 
 def tuning(tile_height=0, max_local_cycles=0, rounds_per_check=0, fast_cold_start=-1, adjoint_rounds=0,
-           level_rounds=0, scheduler=0, node_lanes=0, adjoint_cycles=0, adjoint_waves=0):
+           level_rounds=0, scheduler=0, node_lanes=0, adjoint_cycles=0, adjoint_waves=0, full_waves=0):
     """Scheduling knobs (0 / -1 keep the library default). scheduler: 1 rounds,
     2 device work queue; node_lanes: 1, 2 or 4 lanes per node update;
-    fast_cold_start: 0, 1 or 2 (four directions at once); adjoint_waves: 1 or 4."""
+    fast_cold_start: 0, 1 or 2 (four directions at once); adjoint_waves and
+    full_waves: 1 or 4 (four directions at once)."""
     return L.EikTuning(tile_height, max_local_cycles, rounds_per_check, fast_cold_start, adjoint_rounds,
-                       level_rounds, scheduler, node_lanes, adjoint_cycles, adjoint_waves)
+                       level_rounds, scheduler, node_lanes, adjoint_cycles, adjoint_waves, full_waves)
 
 
 def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=4096, check_feasible=False,
@@ -93,13 +97,13 @@ def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=40
                              L.ptr(parent), L.ptr(level), L.ptr(ws), ws.numel(),
                              None if tune is None else ctypes.byref(tune), ctypes.byref(st), L.stream_handle(dev))
     L.check("eik_forward", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
-    return T, parent, level, Stats(st.rounds, bool(st.converged), st.cell_updates, st.n_levels, st.status,
-                                   st.sweep_launches, st.sweep_ms, st.aux_rounds)
+    return T, parent, level, stats_of(st)
 
 
-def _stats(st):
+def stats_of(st):
+    """Stats from an eik_stats filled by a forward call."""
     return Stats(st.rounds, bool(st.converged), st.cell_updates, st.n_levels, st.status, st.sweep_launches,
-                 st.sweep_ms, st.aux_rounds)
+                 st.sweep_ms, st.aux_rounds, st.fast_ms, st.fast_cell_updates, st.fast_launches)
 
 
 def mixed_workspace(grid: L.EikGrid, device) -> torch.Tensor:
@@ -139,7 +143,7 @@ def solve_mixed(M, omega, src_idx, h, src_t=None, tol=1e-5, tol32=None, max_roun
                                    None if tune32 is None else ctypes.byref(tune32),
                                    None if tune is None else ctypes.byref(tune), st, L.stream_handle(dev))
     L.check("eik_forward_mixed", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
-    return T, parent, level, (_stats(st[0]), _stats(st[1]))
+    return T, parent, level, (stats_of(st[0]), stats_of(st[1]))
 
 
 def adjoint(M, omega, T, parent, level, src_idx, h, dLdT, src_t=None, tune=None, ws=None, stats_out=None):
