@@ -104,8 +104,8 @@ __device__ __forceinline__ bool adj_sweep_dir(const TileGeoB &g, R *sLam, const 
         const int ci = COL ? pos : lane;
         const int cj = COL ? lane : pos;
         if (lane < span) {
-            const uint32_t d = sD[cj * TW + ci];
-            R acc = sG[cj * TW + ci];
+            const uint32_t d = sD[cj * kHalfPitch + ci];
+            R acc = sG[cj * kWordPitch + ci];
             // all neighbour reads are issued at once and the receivers
             // selected afterwards (no branch per neighbour); non-receivers add
             // an exact zero, so the sum is the same, in the same order
@@ -164,7 +164,7 @@ __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, 
     load_tile_halo<R, TH, LP>(lam, sLam, nx, ny, g.i0, g.j0, R(0));
     load_tile_halo<R, TH, LP>(w1all + g.gd.off, sW, nx, ny, g.i0, g.j0, R(1));
     load_tile_halo<uint8_t, TH, LP>(parall + g.gd.off, sP, nx, ny, g.i0, g.j0, kUnreached);
-    load_block<R, TH, TW, 0>(gall + g.gd.off, sG, nx, ny, g.i0, g.j0, R(0));
+    load_block<R, TH, kWordPitch, 0>(gall + g.gd.off, sG, nx, ny, g.i0, g.j0, R(0));
     if (CD && threadIdx.x == 0) *sBits = 0;
     __syncthreads();
     for (int idx = threadIdx.x; idx < TH * TW; idx += NW * TW) {
@@ -177,7 +177,7 @@ __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, 
             const uint32_t sel = pc == kk ? 1u : (pc == ((kk + 7) & 7) ? 2u : (pc == 8 + kk ? 3u : 0u));
             d |= sel << (2 * k);
         }
-        sD[idx] = (uint16_t)d;
+        sD[r * kHalfPitch + c] = (uint16_t)d;
     }
     __syncthreads();
 
@@ -261,8 +261,8 @@ __global__ __launch_bounds__(CD ? 4 * TW : TW) void k_adj_sweep_round(
     __shared__ R sLam[(TH + 2) * LP];
     __shared__ R sW[(TH + 2) * LP];
     __shared__ uint8_t sP[(TH + 2) * LP];
-    __shared__ uint16_t sD[TH * TW];
-    __shared__ R sG[TH * TW];
+    __shared__ uint16_t sD[TH * kHalfPitch];
+    __shared__ R sG[TH * kWordPitch];
     __shared__ int sBits;
     if (CD) __syncthreads(); // every wave has read act_in[t] before it is cleared
     if (threadIdx.x == 0) act_in[t] = 0;
@@ -289,8 +289,8 @@ __global__ __launch_bounds__(TW) void k_adj_sweep_queue(LaunchArgs a, const uint
     __shared__ R sLam[(TH + 2) * LP];
     __shared__ R sW[(TH + 2) * LP];
     __shared__ uint8_t sP[(TH + 2) * LP];
-    __shared__ uint16_t sD[TH * TW];
-    __shared__ R sG[TH * TW];
+    __shared__ uint16_t sD[TH * kHalfPitch];
+    __shared__ R sG[TH * kWordPitch];
     for (;;) {
         int t = threadIdx.x == 0 ? q_take(q) : 0;
         t = __shfl(t, 0);

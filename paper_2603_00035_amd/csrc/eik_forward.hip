@@ -213,30 +213,27 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
     const int span = COL ? g.h : g.w;
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
     const int lc = lane < span ? lane : span - 1; // clamped lane for loads
-    // parameter address of the node this lane updates at step s
-    auto addr = [&](int s) -> size_t {
+    // parameters of the node this lane updates at step s (steps past the last
+    // line are clamped to it)
+    auto load = [&](int s, R *p) {
+        s = s < len ? s : len - 1;
         const int pos = DIR < 2 ? s : len - 1 - s;
-        return COL ? (size_t)(g.i0 + pos) * g.gd.ny + (g.j0 + lc) : (size_t)(g.j0 + pos) * g.gd.nx + (g.i0 + lc);
+        const size_t ad =
+            COL ? (size_t)(g.i0 + pos) * g.gd.ny + (g.j0 + lc) : (size_t)(g.j0 + pos) * g.gd.nx + (g.i0 + lc);
+        p[0] = Mb[ad]; p[1] = Mb[n + ad]; p[2] = Mb[2 * n + ad]; p[3] = Ob[ad]; p[4] = Ob[n + ad];
     };
-    size_t ad = addr(0);
-    R p0 = Mb[ad], p1 = Mb[n + ad], p2 = Mb[2 * n + ad], p3 = Ob[ad], p4 = Ob[n + ad];
     bool changed = false;
-    for (int s = 0; s < len; ++s) {
-        R q0 = p0, q1 = p1, q2 = p2, q3 = p3, q4 = p4;
-        if (s + 1 < len) { // prefetch the next line's parameters
-            ad = addr(s + 1);
-            p0 = Mb[ad]; p1 = Mb[n + ad]; p2 = Mb[2 * n + ad]; p3 = Ob[ad]; p4 = Ob[n + ad];
-        }
+    auto step = [&](int s, const R *q) {
         const int pos = DIR < 2 ? s : len - 1 - s;
         const int ci = COL ? pos : lane;
         const int cj = COL ? lane : pos;
-        const int cc = cj * TW + ci;
+        const int cc = cj * kBytePitch + ci;
         if (lane < span && sC[cc] != kSource) {
             NodeConst<R> k;
-            node_const<R>(q0, q1, q2, q3, q4, h, inv_h, k);
+            node_const<R>(q[0], q[1], q[2], q[3], q[4], h, inv_h, k);
             R Tn[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) Tn[q] = sT[(cj + 1 + nb_dy(q)) * LP + (ci + 1 + nb_dx(q))];
+            for (int d = 0; d < 8; ++d) Tn[d] = sT[(cj + 1 + nb_dy(d)) * LP + (ci + 1 + nb_dx(d))];
             int code;
             R v = local_update_dir<R, DIR, FULL>(k, Tn, code);
             const int slot = (cj + 1) * LP + ci + 1;
@@ -269,9 +266,21 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
             } else if (v < old) { // FAST: LDS atomic minimum (ds_min), safe under concurrent directions
                 __hip_atomic_fetch_min(&sT[slot], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-
         }
         wave_step_sync();
+    };
+    // Double-buffered parameters: the next line's five values load while a
+    // line is updated. Two steps per iteration alternate the buffers, and each
+    // buffer is refilled only after its last use, so no register copy (and no
+    // wait for the loads in flight) sits between steps.
+    R X[5], Y[5];
+    load(0, X);
+    for (int s = 0; s < len; s += 2) {
+        load(s + 1, Y);
+        step(s, X);
+        if (s + 1 >= len) break; // uniform over the wave
+        load(s + 2, X);
+        step(s + 1, Y);
     }
     return changed;
 }
@@ -307,7 +316,7 @@ __device__ __forceinline__ Visit visit_tile(const LaunchArgs &a, int t, const R 
 
     load_tile_halo<R, TH, LP>(T, sT, g.gd.nx, g.gd.ny, g.i0, g.j0, inf_v<R>());
     if (LEV) load_tile_halo<int32_t, TH, LP>(level, sL, g.gd.nx, g.gd.ny, g.i0, g.j0, -1);
-    load_block<uint8_t, TH, TW, 0>(code, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
+    load_block<uint8_t, TH, kBytePitch, 0>(code, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
     __syncthreads();
 
     int quiet = 0, sweeps = 0;
@@ -347,7 +356,7 @@ __device__ __forceinline__ Visit visit_tile(const LaunchArgs &a, int t, const R 
             if (nv != ov[k]) T[gc] = nv;
             if (LEV) {
                 level[gc] = sL[sl];
-                code[gc] = sC[r * TW + c];
+                code[gc] = sC[r * kBytePitch + c];
             }
             if (counts_as_change<R>(ov[k], nv, tol)) bits |= halo_bits(c, r, g.w, g.h);
         }
@@ -376,7 +385,7 @@ __global__ __launch_bounds__(TW) void k_sweep_round(LaunchArgs a, const R *__res
     if (threadIdx.x == 0) act_in[t] = 0;
     __shared__ R sT[(TH + 2) * LP];
     __shared__ int32_t sL[LEV ? (TH + 2) * LP : 1];
-    __shared__ uint8_t sC[TH * TW];
+    __shared__ uint8_t sC[TH * kBytePitch];
     const Visit v =
         visit_tile<R, TH, FULL, LEV>(a, t, M, om, Ptall, Tall, codeall, levall, tol, max_cycles, sT, sL, sC);
     if (threadIdx.x == 0) {
@@ -475,11 +484,11 @@ __global__ __launch_bounds__(4 * TW) void k_sweep_round_cd(LaunchArgs a, const R
     const int t = blockIdx.x;
     if (act_in[t] == 0) return;
     __shared__ R sT[(TH + 2) * LP];
-    __shared__ uint8_t sC[TH * TW];
+    __shared__ uint8_t sC[TH * kBytePitch];
     __shared__ int sBits;
     {
         const TileGeo g = tile_geo<TH>(a, t);
-        load_block<uint8_t, TH, TW, 0>(codeall + g.gd.off, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
+        load_block<uint8_t, TH, kBytePitch, 0>(codeall + g.gd.off, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
     }
     const Visit v = visit_tile_cd<R, TH, FULL>(a, t, M, om, Ptall, Tall, tol, max_cycles, sT, sC, &sBits);
     if (threadIdx.x == 0) {
@@ -526,7 +535,7 @@ __global__ __launch_bounds__(TW) void k_sweep_queue(LaunchArgs a, const R *__res
     constexpr int LP = TW + 3;
     __shared__ R sT[(TH + 2) * LP];
     __shared__ int32_t sL[LEV ? (TH + 2) * LP : 1];
-    __shared__ uint8_t sC[TH * TW];
+    __shared__ uint8_t sC[TH * kBytePitch];
     unsigned long long updates = 0;
     for (;;) {
         int t = threadIdx.x == 0 ? q_take(q) : 0;
@@ -733,7 +742,7 @@ __device__ __forceinline__ bool sweep_dir_split(const TileGeo &g, const R *__res
             const int ci = COL ? pos : node;
             const int cj = COL ? node : pos;
             // the SUB lanes of a node share this test, so groups stay whole
-            if (node < span && sC[cj * TW + ci] != kSource) {
+            if (node < span && sC[cj * kBytePitch + ci] != kSource) {
                 R Tq[NS + 1];
 #pragma unroll
                 for (int q = 0; q <= NS; ++q) {
@@ -771,7 +780,7 @@ __device__ __forceinline__ Visit visit_tile_split(const LaunchArgs &a, int t, co
 
     if (threadIdx.x == 0) *sbits = 0;
     load_tile_halo<R, TH, LP>(T, sT, g.gd.nx, g.gd.ny, g.i0, g.j0, inf_v<R>());
-    load_block<uint8_t, TH, TW, 0>(codeall + g.gd.off, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
+    load_block<uint8_t, TH, kBytePitch, 0>(codeall + g.gd.off, sC, g.gd.nx, g.gd.ny, g.i0, g.j0, kSource);
     __syncthreads();
 
     int quiet = 0, sweeps = 0;
@@ -835,7 +844,7 @@ __global__ __launch_bounds__(TW * SUB) void k_sweep_round_split(LaunchArgs a, co
     const int t = blockIdx.x;
     if (act_in[t] == 0) return; // uniform over the workgroup
     __shared__ R sT[(TH + 2) * LP];
-    __shared__ uint8_t sC[TH * TW];
+    __shared__ uint8_t sC[TH * kBytePitch];
     __shared__ int sbits;
     __syncthreads(); // every wave has read act_in[t] before it is cleared
     if (threadIdx.x == 0) act_in[t] = 0;
@@ -912,9 +921,9 @@ __global__ __launch_bounds__(TW) void k_level_round(LaunchArgs a, const uint8_t 
     int32_t *level = levall + g.gd.off;
 
     __shared__ int32_t sL[(TH + 2) * LP];
-    __shared__ uint8_t sP[TH * TW];
+    __shared__ uint8_t sP[TH * kBytePitch];
     load_tile_halo<int32_t, TH, LP>(level, sL, g.gd.nx, g.gd.ny, g.i0, g.j0, -1);
-    load_block<uint8_t, TH, TW, 0>(parent, sP, g.gd.nx, g.gd.ny, g.i0, g.j0, kUnreached);
+    load_block<uint8_t, TH, kBytePitch, 0>(parent, sP, g.gd.nx, g.gd.ny, g.i0, g.j0, kUnreached);
     __syncthreads();
 
     int quiet = 0, sweeps = 0;
@@ -929,7 +938,7 @@ __global__ __launch_bounds__(TW) void k_level_round(LaunchArgs a, const uint8_t 
             const int pos = dir < 2 ? s : len - 1 - s;
             const int ci = col ? pos : lane;
             const int cj = col ? lane : pos;
-            const int code = lane < span ? sP[cj * TW + ci] : kUnreached;
+            const int code = lane < span ? sP[cj * kBytePitch + ci] : kUnreached;
             int32_t *slot = &sL[(cj + 1) * LP + ci + 1];
             int nv = code == kSource ? 0 : -1;
             if (code < 16) {

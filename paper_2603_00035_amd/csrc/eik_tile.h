@@ -11,6 +11,14 @@ namespace eik {
 
 constexpr int kLoadBatch = 16;
 
+// Row pitches of the per-node LDS arrays (no halo), padded so that the 64
+// lanes of a column sweep, which step through one row each, fall in distinct
+// banks: 68 bytes (17 dwords) for byte arrays, 66 halves (33 dwords) for
+// 16-bit arrays, 65 elements for 32-bit ones (an odd dword stride each).
+constexpr int kBytePitch = TW + 4;
+constexpr int kHalfPitch = TW + 2;
+constexpr int kWordPitch = TW + 1;
+
 // dst[row * PITCH + OFF + lane] = src[(jstart + row) * nx + i0 + lane] for
 // row in [0, ROWS); `outside` where that node is not in the nx x ny grid.
 // The block may hold several waves (blockDim.x a multiple of 64); they take
