@@ -31,7 +31,7 @@ KNOBS = ("tile_height", "max_local_cycles", "rounds_per_check", "fast_cold_start
 DEFAULTS = {"tile_height": 64, "max_local_cycles": 1, "rounds_per_check": 8, "fast_cold_start": 2,
             "adjoint_rounds": 64, "level_rounds": 8, "scheduler": 1, "node_lanes": 4,
             "adjoint_cycles": 1, "adjoint_waves": 4, "full_waves": 4}
-CANDIDATES = {"tile_height": (32, 64), "max_local_cycles": (1, 2, 3), "rounds_per_check": (4, 8, 16),
+CANDIDATES = {"tile_height": (32, 64), "max_local_cycles": (1, 2, 3), "rounds_per_check": (4, 8, 16, 32),
               "fast_cold_start": (0, 1, 2), "adjoint_rounds": (16, 64, 256), "level_rounds": (4, 8, 16),
               "scheduler": (1, 2), "node_lanes": (1, 2, 4), "adjoint_cycles": (1, 2),
               "adjoint_waves": (1, 4), "full_waves": (1, 4)}

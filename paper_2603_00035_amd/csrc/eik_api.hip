@@ -240,17 +240,21 @@ struct LaunchTimer {
 
 // Rounds until a round flags nothing (converged) or the budget runs out.
 // Without a host check (sync = false) exactly `budget` rounds are enqueued;
-// rounds after convergence find no flagged tile and exit at once.
-// round_fn(act_in, act_out, count_next) enqueues one round.
+// rounds after convergence find no flagged tile and exit at once. With host
+// checks, the first check comes after `first_batch` rounds (a phase that
+// starts near its fixed point settles in one or two), the others every
+// `per_check` rounds. round_fn(act_in, act_out, count_next) enqueues one round.
 template <typename F>
 int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int budget, int per_check, bool sync,
-               hipStream_t st, F round_fn, int *rounds_done, bool *converged, LaunchTimer *timer = nullptr)
+               hipStream_t st, F round_fn, int *rounds_done, bool *converged, LaunchTimer *timer = nullptr,
+               int first_batch = 0)
 {
     int r = first;
     const int end = std::min(first + budget, kMaxRounds);
     *converged = false;
     while (r < end) {
-        const int batch = sync ? std::min(per_check, end - r) : end - r;
+        const int want = (r == first && first_batch > 0) ? std::min(first_batch, per_check) : per_check;
+        const int batch = sync ? std::min(want, end - r) : end - r;
         if (timer && timer->on) timer->before(st);
         for (int b = 0; b < batch; ++b, ++r)
             round_fn(act + (r & 1) * n_tiles, act + ((r + 1) & 1) * n_tiles, act_count + r + 1);
@@ -380,7 +384,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
                 launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
                                       tn.max_local_cycles, tn.full_waves == 4 ? kFullWavesCD : tn.node_lanes, st);
             },
-            &rounds, &conv, &timer);
+            &rounds, &conv, &timer, (fast || T_init) ? 2 : 0);
         if (rc) return rc;
         r0 += rounds;
         launches = r0;
