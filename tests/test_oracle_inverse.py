@@ -1,0 +1,99 @@
+"""Pins of the inverse-problem oracle (CPU): closed forms of the total
+variation, finite differences of every gradient, and the optimiser's known
+trajectories."""
+import numpy as np
+import pytest
+
+from oracle import inverse_ref as I
+
+
+def test_tv_of_a_step_edge_is_jump_times_length():
+    ny, nx, k = 7, 9, 4
+    F = np.ones((1, ny, nx))
+    F[:, :, k:] = 3.0
+    val, _ = I.tv(F, [1.0])
+    assert val == pytest.approx(2.0 * ny)  # one jump of 2 per row, between columns k-1 and k
+
+
+def test_tv_of_a_ramp_closed_form():
+    ny, nx, a, b = 6, 8, 0.3, -0.7
+    j, i = np.mgrid[0:ny, 0:nx]
+    F = (a * i + b * j)[None].astype(np.float64)
+    val, _ = I.tv(F, [1.0])
+    want = (nx - 1) * (ny - 1) * np.hypot(a, b) + (ny - 1) * abs(b) + (nx - 1) * abs(a)
+    assert val == pytest.approx(want, rel=1e-12)
+
+
+def test_plane_weight_scales_its_norm():
+    rng = np.random.default_rng(0)
+    P = rng.normal(size=(1, 5, 6))
+    Z = np.zeros_like(P)
+    G = np.concatenate([Z, P, Z])  # only the off-diagonal varies
+    vG, _ = I.tv(G, [1.0, 2.0, 1.0])
+    vP, _ = I.tv(P, [1.0])
+    assert vG == pytest.approx(np.sqrt(2.0) * vP, rel=1e-12)
+
+
+@pytest.mark.parametrize("planes,weights", [(1, [1.0]), (2, [1.0, 1.0]), (3, [1.0, 2.0, 1.0])])
+def test_tv_gradient_matches_central_differences(planes, weights):
+    rng = np.random.default_rng(planes)
+    F = rng.normal(size=(planes, 5, 7))
+    _, g = I.tv(F, weights)
+    eps = 1e-6
+    for c, jj, ii in [(0, 0, 0), (planes - 1, 4, 6), (0, 2, 3), (planes - 1, 1, 5), (planes // 2, 4, 0)]:
+        Fp, Fm = F.copy(), F.copy()
+        Fp[c, jj, ii] += eps
+        Fm[c, jj, ii] -= eps
+        fd = (I.tv(Fp, weights)[0] - I.tv(Fm, weights)[0]) / (2 * eps)
+        assert g[c, jj, ii] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_tv_subgradient_is_zero_on_flat_regions():
+    F = np.full((2, 4, 5), 1.5)
+    val, g = I.tv(F, [1.0, 1.0])
+    assert val == 0.0 and not np.any(g)
+
+
+def test_obs_loss_value_gradient_and_mask():
+    rng = np.random.default_rng(3)
+    T = rng.uniform(0, 2, (4, 6))
+    To = rng.uniform(0, 2, (4, 6))
+    mask = (rng.uniform(size=(4, 6)) < 0.5).astype(np.uint8)
+    T[0, 0], mask[0, 0] = np.inf, 1  # an unreached observed node contributes nothing
+    val, g = I.obs_loss(T, To, mask)
+    use = (mask != 0) & np.isfinite(T)
+    assert val == pytest.approx(0.5 * np.sum((T[use] - To[use]) ** 2))
+    assert np.all(g[~use] == 0)
+    k = tuple(np.argwhere(use)[0])
+    Tp, Tm = T.copy(), T.copy()
+    Tp[k] += 1e-6
+    Tm[k] -= 1e-6
+    fd = (I.obs_loss(Tp, To, mask)[0] - I.obs_loss(Tm, To, mask)[0]) / 2e-6
+    assert g[k] == pytest.approx(fd, rel=1e-6)
+
+
+def test_gradient_descent_step():
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.5, 1.0, -4.0])
+    q, _, _ = I.param_step(0, p, g, None, None, lr=0.1)
+    assert np.allclose(q, [0.95, -2.1, 0.9])
+
+
+def test_adam_moves_lr_per_step_under_a_constant_gradient():
+    # with bias correction, m_hat = g and v_hat = g^2 at every step of a
+    # constant gradient, so each step moves by lr * g / (|g| + eps)
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.5, 1e-3, -4.0])
+    m = np.zeros(3)
+    v = np.zeros(3)
+    for t in range(1, 6):
+        p, m, v = I.param_step(1, p, g, m, v, lr=0.01, t=t, eps=0.0)
+    assert np.allclose(p, np.array([1.0, -2.0, 0.5]) - 5 * 0.01 * np.sign(g), rtol=0, atol=1e-12)
+
+
+def test_clipping_caps_the_global_norm():
+    g = np.array([3.0, 4.0])  # norm 5
+    q, _, _ = I.param_step(0, np.zeros(2), g, None, None, lr=1.0, max_norm=1.0, grad_sq=25.0)
+    assert np.linalg.norm(q) == pytest.approx(1.0)
+    q, _, _ = I.param_step(0, np.zeros(2), g, None, None, lr=1.0, max_norm=10.0, grad_sq=25.0)
+    assert np.allclose(-q, g)
