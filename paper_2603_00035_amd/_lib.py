@@ -27,7 +27,7 @@ SOURCE, UNREACHED = 0xFE, 0xFF
 EXPORTS = ["eik_workspace_bytes", "eik_forward", "eik_backward", "eik_project", "eik_project_backward",
            "eik_last_error", "eik_batch_workspace_bytes", "eik_batch_plan", "eik_forward_batched",
            "eik_backward_batched", "eik_batch_pending", "eik_mixed_workspace_bytes", "eik_forward_mixed",
-           "eik_backward_mixed"]
+           "eik_backward_mixed", "eik_inv_scratch_bytes", "eik_tv", "eik_obs_loss", "eik_sum_sq", "eik_param_step"]
 
 
 class EikGrid(ctypes.Structure):
@@ -105,6 +105,16 @@ def lib():
         L.eik_forward_mixed.restype = ctypes.c_int
         L.eik_backward_mixed.argtypes = [gp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, tp, sp, vp]
         L.eik_backward_mixed.restype = ctypes.c_int
+        L.eik_inv_scratch_bytes.argtypes = []
+        L.eik_inv_scratch_bytes.restype = ctypes.c_size_t
+        L.eik_tv.argtypes = [i32, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), d, vp, vp, vp, vp]
+        L.eik_tv.restype = ctypes.c_int
+        L.eik_obs_loss.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.eik_obs_loss.restype = ctypes.c_int
+        L.eik_sum_sq.argtypes = [i64, i32, vp, vp, vp, vp]
+        L.eik_sum_sq.restype = ctypes.c_int
+        L.eik_param_step.argtypes = [i64, i32, i32, vp, vp, vp, vp, d, d, d, d, i32, d, vp, vp]
+        L.eik_param_step.restype = ctypes.c_int
         L.eik_last_error.argtypes = []
         L.eik_last_error.restype = ctypes.c_char_p
         _lib = L

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/eik.h"
+#include "../../include/eik_inverse.h"
 #include "eik_internal.h"
 
 using namespace eik;
@@ -802,6 +803,75 @@ int eik_batch_pending(int32_t n_grids, const eik_grid *grids, int32_t dtype, con
     HIP_OK(hipMemcpyAsync(c, w.ctr + kCtrSweepPending, sizeof c, hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
     for (int k = 0; k < 3; ++k) pending[k] = (int64_t)c[k];
+    return EIK_OK;
+}
+
+size_t eik_inv_scratch_bytes(void) { return (size_t)kInvBlocks * sizeof(double); }
+
+int eik_tv(int32_t nx, int32_t ny, int32_t n_planes, int32_t dtype, const void *F, const double *weights,
+           double scale, void *grad, double *value, void *scratch, hipStream_t stream)
+{
+    if (nx < 1 || ny < 1 || n_planes < 1 || n_planes > 4) return fail(EIK_EINVAL, "sizes %d x %d x %d", nx, ny, n_planes);
+    if ((int64_t)nx * ny >= ((int64_t)1 << 40)) return fail(EIK_EINVAL, "field too large");
+    if (!F || !weights || !grad || !value || !scratch) return fail(EIK_EINVAL, "NULL pointer argument");
+    for (int c = 0; c < n_planes; ++c)
+        if (!(weights[c] >= 0.0)) return fail(EIK_EINVAL, "plane weight %d is negative", c);
+    if (dtype == EIK_F64)
+        launch_tv<double>(nx, ny, n_planes, F, weights, scale, grad, value, (double *)scratch, stream);
+    else if (dtype == EIK_F32)
+        launch_tv<float>(nx, ny, n_planes, F, weights, scale, grad, value, (double *)scratch, stream);
+    else
+        return fail(EIK_EINVAL, "dtype %d", dtype);
+    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+int eik_obs_loss(int64_t n, int32_t dtype, const void *T, const void *T_obs, const uint8_t *mask, void *dLdT,
+                 double *value, void *scratch, hipStream_t stream)
+{
+    if (n < 1) return fail(EIK_EINVAL, "n < 1");
+    if (!T || !T_obs || !mask || !dLdT || !value || !scratch) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        launch_obs_loss<double>(n, T, T_obs, mask, dLdT, value, (double *)scratch, stream);
+    else if (dtype == EIK_F32)
+        launch_obs_loss<float>(n, T, T_obs, mask, dLdT, value, (double *)scratch, stream);
+    else
+        return fail(EIK_EINVAL, "dtype %d", dtype);
+    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+int eik_sum_sq(int64_t n, int32_t dtype, const void *x, double *acc, void *scratch, hipStream_t stream)
+{
+    if (n < 1) return fail(EIK_EINVAL, "n < 1");
+    if (!x || !acc || !scratch) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        launch_sum_sq<double>(n, x, acc, (double *)scratch, stream);
+    else if (dtype == EIK_F32)
+        launch_sum_sq<float>(n, x, acc, (double *)scratch, stream);
+    else
+        return fail(EIK_EINVAL, "dtype %d", dtype);
+    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+int eik_param_step(int64_t n, int32_t dtype, int32_t method, void *p, const void *g, void *m, void *v, double lr,
+                   double beta1, double beta2, double eps, int32_t t, double max_norm, const double *grad_sq,
+                   hipStream_t stream)
+{
+    if (n < 1) return fail(EIK_EINVAL, "n < 1");
+    if (method != 0 && method != 1) return fail(EIK_EINVAL, "method %d", method);
+    if (!p || !g) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (method == 1 && (!m || !v || t < 1 || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0)))
+        return fail(EIK_EINVAL, "Adam needs state arrays, t >= 1, betas in [0, 1) and eps >= 0");
+    if (max_norm > 0 && !grad_sq) return fail(EIK_EINVAL, "clipping needs grad_sq");
+    if (dtype == EIK_F64)
+        launch_param_step<double>(n, method, p, g, m, v, lr, beta1, beta2, eps, t, max_norm, grad_sq, stream);
+    else if (dtype == EIK_F32)
+        launch_param_step<float>(n, method, p, g, m, v, lr, beta1, beta2, eps, t, max_norm, grad_sq, stream);
+    else
+        return fail(EIK_EINVAL, "dtype %d", dtype);
+    HIP_OK(hipGetLastError());
     return EIK_OK;
 }
 

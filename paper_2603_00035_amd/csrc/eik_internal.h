@@ -96,6 +96,21 @@ void launch_max_level(int64_t n, const int32_t *level, unsigned long long *ctr, 
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t st);
 void launch_copy_u64(const unsigned long long *src, unsigned long long *dst, hipStream_t st);
+
+// Inverse-problem passes (eik_inverse.hip); reductions use kInvBlocks
+// double partials in the caller's scratch.
+constexpr int kInvBlocks = 1024;
+template <typename R>
+void launch_tv(int nx, int ny, int C, const void *F, const double *weights, double scale, void *grad,
+               double *value, double *partial, hipStream_t st);
+template <typename R>
+void launch_obs_loss(int64_t n, const void *T, const void *To, const uint8_t *mask, void *g, double *value,
+                     double *partial, hipStream_t st);
+template <typename R>
+void launch_sum_sq(int64_t n, const void *x, double *acc, double *partial, hipStream_t st);
+template <typename R>
+void launch_param_step(int64_t n, int method, void *p, const void *g, void *m, void *v, double lr, double b1,
+                       double b2, double eps, int t, double max_norm, const double *grad_sq, hipStream_t st);
 void launch_cast_f64_f32(int64_t n, const double *src, float *dst, hipStream_t st);
 void launch_cast_f32_f64(int64_t n, const float *src, double *dst, hipStream_t st);
 void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_grid, int n_tiles, hipStream_t st);

@@ -1,5 +1,5 @@
-"""The C-ABI library loads and exports every entry point include/eik.h
-declares; host-side argument checks reject bad calls before any launch.
+"""The C-ABI library loads and exports every entry point include/eik.h and
+include/eik_inverse.h declare; host-side argument checks reject bad calls before any launch.
 No kernel runs here (CPU only)."""
 import ctypes
 import os
@@ -11,9 +11,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "eik.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(eik_[a-z_]+)\s*\(", src)))
+    """eik_* functions declared in include/*.h (the solver and the inverse-problem headers)."""
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(eik_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():

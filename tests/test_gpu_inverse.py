@@ -1,0 +1,175 @@
+"""GPU parity of the inverse-problem kernels (total variation, data term, sum
+of squares, parameter step) against the oracle, and of whole recovery
+iterations against the same iterations composed from the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import inverse_ref as I
+from synthetic.fields import Problem
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def lib():
+    from paper_2603_00035_amd import _lib as L
+    return L, L.lib()
+
+
+def scratch(dev):
+    L, lb = lib()
+    return torch.empty(lb.eik_inv_scratch_bytes(), dtype=torch.uint8, device=dev)
+
+
+@pytest.mark.parametrize("dt,rtol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+@pytest.mark.parametrize("C,ny,nx", [(1, 1, 70), (2, 65, 1), (3, 37, 53), (4, 480, 600), (3, 1, 1)])
+def test_tv_matches_oracle(dt, rtol, C, ny, nx):
+    L, lb = lib()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(C * 1000 + nx)
+    F = rng.normal(size=(C, ny, nx))
+    F[:, : ny // 3, : nx // 3] = 0.25  # a flat block: zero norms take the subgradient 0
+    w = rng.uniform(0.5, 2.0, C)
+    g0 = rng.normal(size=F.shape)
+    say(f"[tv] {C} planes {nx}x{ny} {dt}")
+    Fd = torch.tensor(F, dtype=dt, device=dev)
+    if dt == torch.float32:
+        F = Fd.double().cpu().numpy()
+    gd = torch.tensor(g0, dtype=dt, device=dev)
+    val = torch.zeros(1, dtype=torch.float64, device=dev)
+    wc = (ctypes.c_double * C)(*w)
+    rc = lb.eik_tv(nx, ny, C, L.dtype_code(Fd), L.ptr(Fd), wc, 0.3, L.ptr(gd), val.data_ptr(),
+                   L.ptr(scratch(dev)), L.stream_handle(dev))
+    assert rc == 0
+    vo, go = I.tv(F, w)
+    torch.cuda.synchronize()
+    assert float(val) == pytest.approx(0.3 * vo, rel=rtol, abs=1e-12)
+    want = g0.astype(np.float64) + 0.3 * go
+    if dt == torch.float32:
+        want = torch.tensor(g0, dtype=dt).double().numpy() + 0.3 * go
+    got = gd.double().cpu().numpy()
+    assert np.max(np.abs(got - want)) <= rtol * (1 + np.max(np.abs(want))) * (1 if dt == torch.float64 else 10)
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_obs_loss_and_sum_sq_match_oracle(dt):
+    L, lb = lib()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    n = 300_001  # more than one pass of the fixed grid
+    T = rng.uniform(0, 3, n)
+    To = rng.uniform(0, 3, n)
+    T[::97] = np.inf
+    To[::101] = np.inf
+    mask = (rng.uniform(size=n) < 0.3).astype(np.uint8)
+    Td, Tod = torch.tensor(T, dtype=dt, device=dev), torch.tensor(To, dtype=dt, device=dev)
+    md = torch.tensor(mask, device=dev)
+    g = torch.empty_like(Td)
+    val = torch.zeros(2, dtype=torch.float64, device=dev)
+    sc = scratch(dev)
+    st = L.stream_handle(dev)
+    say(f"[obs loss] n={n} {dt}")
+    assert lb.eik_obs_loss(n, L.dtype_code(Td), L.ptr(Td), L.ptr(Tod), L.ptr(md), L.ptr(g), val.data_ptr(),
+                           L.ptr(sc), st) == 0
+    assert lb.eik_sum_sq(n, L.dtype_code(g), L.ptr(g), val.data_ptr() + 8, L.ptr(sc), st) == 0
+    assert lb.eik_sum_sq(n, L.dtype_code(g), L.ptr(g), val.data_ptr() + 8, L.ptr(sc), st) == 0  # accumulates
+    torch.cuda.synchronize()
+    vo, go = I.obs_loss(Td.double().cpu().numpy(), Tod.double().cpu().numpy(), mask)
+    tol = 1e-12 if dt == torch.float64 else 1e-6
+    assert float(val[0]) == pytest.approx(vo, rel=tol)
+    assert np.allclose(g.double().cpu().numpy(), go, rtol=tol, atol=0)
+    assert float(val[1]) == pytest.approx(2 * float(np.sum(g.double().cpu().numpy() ** 2)), rel=1e-12)
+
+
+@pytest.mark.parametrize("method,max_norm", [(0, 0.0), (1, 0.0), (1, 0.5), (0, 0.5)])
+def test_param_step_matches_oracle(method, max_norm):
+    L, lb = lib()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(method * 10 + int(max_norm * 10))
+    n = 5000
+    p = rng.normal(size=n)
+    m = np.zeros(n)
+    v = np.zeros(n)
+    pd_, md_, vd_ = (torch.tensor(x, device=dev) for x in (p, m, v))
+    gsq = torch.zeros(1, dtype=torch.float64, device=dev)
+    say(f"[param step] method={method} max_norm={max_norm}")
+    for t in range(1, 5):
+        g = rng.normal(size=n) * (0.1 if t % 2 else 3.0)
+        gd = torch.tensor(g, device=dev)
+        gsq.fill_(float(np.sum(g * g)))
+        assert lb.eik_param_step(n, L.dtype_code(pd_), method, L.ptr(pd_), L.ptr(gd), L.ptr(md_), L.ptr(vd_), 0.01,
+                                 0.9, 0.999, 1e-8, t, max_norm, gsq.data_ptr(), L.stream_handle(dev)) == 0
+        p, m, v = I.param_step(method, p, g, m, v, 0.01, 0.9, 0.999, 1e-8, t, max_norm, float(np.sum(g * g)))
+    torch.cuda.synchronize()
+    assert np.allclose(pd_.cpu().numpy(), p, rtol=1e-13, atol=1e-15)
+
+
+def _isotropic_case(nx, ny, obs_frac, seed):
+    """The paper's isotropic recovery problem: G = g I with g = 1 on the left
+    half and 2 on the right, one source at the centre, zero drift."""
+    h = 1.0 / (nx - 1)
+    g = np.where(np.arange(nx)[None, :] < nx // 2, 1.0, 2.0) * np.ones((ny, 1))
+    M = np.stack([g, np.zeros_like(g), g])
+    om = np.zeros((2, ny, nx))
+    src = np.array([(ny // 2) * nx + nx // 2], np.int32)
+    truth = Problem(nx, ny, h, M, om, src, np.zeros(1))
+    T_obs, _, st = oracle.forward(truth)
+    assert st == 0
+    mask = (np.random.default_rng(seed).uniform(size=(ny, nx)) < obs_frac).astype(np.uint8)
+    M0 = np.stack([np.full_like(g, 1.5), np.zeros_like(g), np.full_like(g, 1.5)])
+    return truth, T_obs, mask, M0, om
+
+
+def _oracle_iterations(truth, T_obs, mask, M0, om0, cfg, iters):
+    from paper_2603_00035_amd import inverse as V
+    M, om = M0.copy(), om0.copy()
+    mM, vM, mo, vo = (np.zeros_like(M), np.zeros_like(M), np.zeros_like(om), np.zeros_like(om))
+    for k in range(iters):
+        prob = Problem(truth.nx, truth.ny, truth.h, M, om, truth.src_idx, truth.src_t)
+        T, _, _ = oracle.forward(prob, tol=cfg.tol)
+        par, _ = oracle.parents_levels(prob, T)
+        _, g = I.obs_loss(T, T_obs, mask)
+        gM, gom, _ = oracle.vjp(prob, T, par, g)
+        gM = gM + cfg.lam_G * I.tv(M, V.G_WEIGHTS)[1]
+        gom = gom + cfg.lam_b * I.tv(om, V.B_WEIGHTS)[1]
+        gsq = float(np.sum(gM * gM) + np.sum(gom * gom))
+        method = 1 if cfg.method == "adam" else 0
+        M, mM, vM = I.param_step(method, M, gM, mM, vM, V.lr_at(cfg, cfg.lr_G, k, iters), cfg.beta1, cfg.beta2,
+                                 cfg.eps, k + 1, cfg.max_norm, gsq)
+        om, mo, vo = I.param_step(method, om, gom, mo, vo, V.lr_at(cfg, cfg.lr_b, k, iters), cfg.beta1, cfg.beta2,
+                                  cfg.eps, k + 1, cfg.max_norm, gsq)
+        M, om = oracle.project(M, om, eig_min=cfg.eig_min, eig_max=cfg.eig_max, eucl_clip=cfg.eucl_clip,
+                               rho_max=cfg.rho_max)
+    return M, om
+
+
+# Whole iterations are compared where their outcome is a smooth function of
+# the arithmetic: the TV subgradient of a nearly flat field points wherever
+# rounding puts it, and Adam turns any such direction into a full step, so TV
+# enters only from a rough initial field (its kernel is checked exactly above).
+@pytest.mark.parametrize("method,max_norm,lam_G,rough", [("adam", 0.5, 0.0, False), ("gd", 0.0, 0.0, False),
+                                                          ("gd", 0.0, 1e-2, True), ("adam", 0.0, 1e-2, True)])
+def test_recovery_iterations_match_the_oracle(method, max_norm, lam_G, rough):
+    from paper_2603_00035_amd import inverse as V
+    truth, T_obs, mask, M0, om0 = _isotropic_case(41, 37, 0.4, 1)
+    if rough:
+        M0 = M0 * np.random.default_rng(2).uniform(0.8, 1.2, M0.shape)
+        M0[1] = 0.0
+    cfg = V.InverseConfig(method=method, max_norm=max_norm, lam_G=lam_G, lam_b=0.0, lr_G=0.05, lr_b=0.02)
+    iters = 4
+    say(f"[recovery] {method} clip={max_norm} lam_G={lam_G} rough={rough} 41x37, {iters} iterations vs the oracle")
+    dev = torch.device("cuda:0")
+    R = V.Recovery(torch.tensor(M0, device=dev), torch.tensor(om0, device=dev),
+                   torch.tensor(truth.src_idx, device=dev), truth.h, torch.tensor(T_obs, device=dev),
+                   torch.tensor(mask, device=dev), cfg)
+    hist = R.run(iters)
+    Mo, oo = _oracle_iterations(truth, T_obs, mask, M0, om0, cfg, iters)
+    rel = max(np.max(np.abs(R.M.cpu().numpy() - Mo)) / np.max(np.abs(Mo)),
+              np.max(np.abs(R.om.cpu().numpy() - oo)) / max(1e-30, np.max(np.abs(oo))))
+    say(f"  max rel difference {rel:.2e}; data loss {float(hist[0, 0]):.3e} -> {float(hist[-1, 0]):.3e}")
+    assert rel <= 1e-8
+    assert float(hist[-1, 0]) < float(hist[0, 0])
