@@ -73,3 +73,12 @@ def param_step(method, p, g, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-8, t=1, ma
     mh = m / (1.0 - beta1 ** t)
     vh = v / (1.0 - beta2 ** t)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def tie_isotropic(M):
+    """Projection onto isotropic metrics G = g I (the constraint of the
+    isotropic recovery experiment, Sec. 5): the Frobenius-nearest g I to G is
+    g = (m11 + m22) / 2, with m12 = 0."""
+    M = np.asarray(M, dtype=np.float64)
+    g = 0.5 * (M[0] + M[2])
+    return np.stack([g, np.zeros_like(g), g])

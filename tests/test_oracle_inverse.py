@@ -97,3 +97,17 @@ def test_clipping_caps_the_global_norm():
     assert np.linalg.norm(q) == pytest.approx(1.0)
     q, _, _ = I.param_step(0, np.zeros(2), g, None, None, lr=1.0, max_norm=10.0, grad_sq=25.0)
     assert np.allclose(-q, g)
+
+
+def test_isotropic_tie_is_the_frobenius_nearest_isotropic_metric():
+    rng = np.random.default_rng(11)
+    M = rng.normal(size=(3, 4, 5))
+    P = I.tie_isotropic(M)
+    assert np.array_equal(I.tie_isotropic(P), P)  # a projection
+    gs = np.linspace(-4, 4, 80001)
+    for j, i in [(0, 0), (3, 4), (2, 1)]:
+        m11, m12, m22 = M[:, j, i]
+        # brute force over g of || G - g I ||_F^2 (the off-diagonal counts twice)
+        d = (m11 - gs) ** 2 + 2 * m12 ** 2 + (m22 - gs) ** 2
+        assert P[0, j, i] == pytest.approx(gs[np.argmin(d)], abs=1e-4)
+        assert P[1, j, i] == 0.0 and P[0, j, i] == P[2, j, i]
