@@ -66,6 +66,12 @@ int eik_param_step(int64_t n, int32_t dtype, int32_t method, void *p, const void
                    double beta1, double beta2, double eps, int32_t t, double max_norm, const double *grad_sq,
                    hipStream_t stream);
 
+/* Projection of n nodes of metric planes M [3][n] onto isotropic metrics
+ * G = g I, in place: m11 = m22 = (m11 + m22) / 2, m12 = 0 (the Frobenius-
+ * nearest isotropic tensor; the constraint of the isotropic recovery of
+ * Sec. 5). */
+int eik_tie_isotropic(int64_t n, int32_t dtype, void *M, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

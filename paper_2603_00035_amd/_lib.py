@@ -27,7 +27,8 @@ SOURCE, UNREACHED = 0xFE, 0xFF
 EXPORTS = ["eik_workspace_bytes", "eik_forward", "eik_backward", "eik_project", "eik_project_backward",
            "eik_last_error", "eik_batch_workspace_bytes", "eik_batch_plan", "eik_forward_batched",
            "eik_backward_batched", "eik_batch_pending", "eik_mixed_workspace_bytes", "eik_forward_mixed",
-           "eik_backward_mixed", "eik_inv_scratch_bytes", "eik_tv", "eik_obs_loss", "eik_sum_sq", "eik_param_step"]
+           "eik_backward_mixed", "eik_inv_scratch_bytes", "eik_tv", "eik_obs_loss", "eik_sum_sq", "eik_param_step",
+           "eik_tie_isotropic"]
 
 
 class EikGrid(ctypes.Structure):
@@ -115,6 +116,8 @@ def lib():
         L.eik_sum_sq.restype = ctypes.c_int
         L.eik_param_step.argtypes = [i64, i32, i32, vp, vp, vp, vp, d, d, d, d, i32, d, vp, vp]
         L.eik_param_step.restype = ctypes.c_int
+        L.eik_tie_isotropic.argtypes = [i64, i32, vp, vp]
+        L.eik_tie_isotropic.restype = ctypes.c_int
         L.eik_last_error.argtypes = []
         L.eik_last_error.restype = ctypes.c_char_p
         _lib = L

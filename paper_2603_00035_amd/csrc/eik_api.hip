@@ -875,6 +875,20 @@ int eik_param_step(int64_t n, int32_t dtype, int32_t method, void *p, const void
     return EIK_OK;
 }
 
+int eik_tie_isotropic(int64_t n, int32_t dtype, void *M, hipStream_t stream)
+{
+    if (n < 1) return fail(EIK_EINVAL, "n < 1");
+    if (!M) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        launch_tie_isotropic<double>(n, M, stream);
+    else if (dtype == EIK_F32)
+        launch_tie_isotropic<float>(n, M, stream);
+    else
+        return fail(EIK_EINVAL, "dtype %d", dtype);
+    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
 const char *eik_last_error(void) { return g_last_error.c_str(); }
 
 } // extern "C"

@@ -109,6 +109,8 @@ void launch_obs_loss(int64_t n, const void *T, const void *To, const uint8_t *ma
 template <typename R>
 void launch_sum_sq(int64_t n, const void *x, double *acc, double *partial, hipStream_t st);
 template <typename R>
+void launch_tie_isotropic(int64_t n, void *M, hipStream_t st);
+template <typename R>
 void launch_param_step(int64_t n, int method, void *p, const void *g, void *m, void *v, double lr, double b1,
                        double b2, double eps, int t, double max_norm, const double *grad_sq, hipStream_t st);
 void launch_cast_f64_f32(int64_t n, const double *src, float *dst, hipStream_t st);

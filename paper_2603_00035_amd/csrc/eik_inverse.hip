@@ -153,7 +153,24 @@ __global__ __launch_bounds__(kInvThreads) void k_param_step(int64_t n, int metho
     }
 }
 
+template <typename R>
+__global__ void k_tie_isotropic(int64_t n, R *__restrict__ M)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const R g = R(0.5) * (M[k] + M[2 * n + k]);
+        M[k] = g;
+        M[n + k] = R(0);
+        M[2 * n + k] = g;
+    }
+}
+
 // ---------------------------------------------------------------------------
+template <typename R>
+void launch_tie_isotropic(int64_t n, void *M, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tie_isotropic<R>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, (R *)M);
+}
+
 template <typename R>
 void launch_tv(int nx, int ny, int C, const void *F, const double *weights, double scale, void *grad,
                double *value, double *partial, hipStream_t st)
@@ -197,7 +214,8 @@ void launch_param_step(int64_t n, int method, void *p, const void *g, void *m, v
                                      double *, hipStream_t);                                                     \
     template void launch_sum_sq<R>(int64_t, const void *, double *, double *, hipStream_t);                      \
     template void launch_param_step<R>(int64_t, int, void *, const void *, void *, void *, double, double,       \
-                                       double, double, int, double, const double *, hipStream_t);
+                                       double, double, int, double, const double *, hipStream_t);               \
+    template void launch_tie_isotropic<R>(int64_t, void *, hipStream_t);
 EIK_INV_INSTANTIATE(float)
 EIK_INV_INSTANTIATE(double)
 

@@ -11,7 +11,8 @@ onto the feasible set (SPD metric, |b|_{G^-1} < 1).
 
 Every step of an iteration is a library call (include/eik.h,
 include/eik_inverse.h): eik_forward, eik_obs_loss, eik_backward, eik_tv,
-eik_sum_sq, eik_param_step, eik_project. This module only sequences them and
+eik_sum_sq, eik_param_step, eik_tie_isotropic (isotropic recovery),
+eik_project. This module only sequences them and
 holds the optimiser state.
 """
 from __future__ import annotations
@@ -44,6 +45,7 @@ class InverseConfig:
     lr_min_frac: float = 0.1
     free_metric: bool = True
     free_drift: bool = True
+    isotropic: bool = False       # constrain the metric to G = g I (projection after each step)
     tol: float = 0.0              # forward solve tolerance of every iteration
     eig_min: float = 1e-3         # projection (eik_project)
     eig_max: float = 1e3
@@ -123,6 +125,8 @@ class Recovery:
                     lib.eik_param_step(p.numel(), self.dc, method, L.ptr(p), L.ptr(g), L.ptr(m), L.ptr(v),
                                        lr_at(c, lr, k, iters), c.beta1, c.beta2, c.eps, self.t, c.max_norm,
                                        self._sp(3), st))
+        if c.isotropic:
+            L.check("eik_tie_isotropic", lib.eik_tie_isotropic(n, self.dc, L.ptr(self.M), st))
         self.M, self.om = E.project(self.M, self.om, c.eig_min, c.eig_max, c.eucl_clip, c.rho_max)
         out = self.scalars.clone()
         return out
