@@ -3,12 +3,13 @@
 
 One step = feasibility projection (eik_project) -> forward fast-sweeping solve
 to 1e-5 relative change (eik_forward_mixed: FP32 sweeps, then FP64 sweeps from
-that field; active stencils) -> dense mean-squared loss against a fixed target
-field -> adjoint (eik_backward_mixed: donor weights, directional relaxation of
-the adjoint equations, parameter gradients) -> projection VJP, all through the
-torch.autograd.Function wrappers. --precision f32 times the plain FP32 path
-(eik_forward / eik_backward in FP32); by default the other precision is timed
-beside the headline one and reported under "compare".
+that field; active stencils) -> data term 1/2 sum (T - target)^2 over the
+observed nodes and its gradient (eik_obs_loss) -> adjoint (eik_backward_mixed:
+donor weights, directional relaxation of the adjoint equations, parameter
+gradients) -> projection VJP (eik_project_backward), each a library call.
+--precision f32 times the plain FP32 path (eik_forward / eik_backward in FP32);
+by default the other precision is timed beside the headline one and reported
+under "compare".
 
 Workload (default): 2048 x 2048 stress case -- eigenvalue ratio 10, drift norm
 up to 0.9, 4 sharp-edged regions with rotated principal directions, 16 random
@@ -305,6 +306,7 @@ def main():
     import numpy as np
     import torch
 
+    from paper_2603_00035_amd import _lib as L
     from paper_2603_00035_amd import eikonal as E
     from synthetic.fields import fourier_field, make_problem
 
@@ -330,25 +332,40 @@ def main():
     mask = torch.tensor(mask_np, device=dev)
 
     def run(precision):
-        dt = torch.float64 if precision == "mixed" else torch.float32
+        from paper_2603_00035_amd import inverse as V
+        mixed = precision == "mixed"
+        dt = torch.float64 if mixed else torch.float32
         M0 = torch.tensor(q.M, dtype=dt, device=dev)
         om0 = torch.tensor(q.omega, dtype=dt, device=dev)
         target = torch.tensor(target_np, dtype=dt, device=dev)
+        mask_u8 = mask.to(torch.uint8)
+        grid = E.make_grid(prob.nx, prob.ny, prob.h, src)
+        ws = E.mixed_workspace(grid, dev) if mixed else E.workspace(grid, L.dtype_code(M0), dev)
+        scratch = torch.empty(L.lib().eik_inv_scratch_bytes(), dtype=torch.uint8, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
 
         def step(sink, t_ev):
-            M = M0.detach().requires_grad_(True)
-            om = om0.detach().requires_grad_(True)
+            # one pass of the hot path, every stage a library call: projection,
+            # forward, data term, adjoint, projection VJP
             t_ev[0].record()
-            Mp, omp = E.ProjectFn.apply(M, om)
-            T, _, _ = E.eikonal(Mp, omp, src, prob.h, tol=args.tol, stats_sink=sink, time_kernels=True,
-                                precision=None if precision == "f32" else precision)
-            d = torch.where(mask, T - target, torch.zeros_like(T))
-            loss = (d * d).sum() / n_obs
+            Mp, omp = E.project(M0, om0)
+            if mixed:
+                T, par, _, st = E.solve_mixed(Mp, omp, src, prob.h, tol=args.tol, levels=False, ws=ws,
+                                              time_kernels=True)
+                sink.extend(st)
+            else:
+                T, par, _, st = E.solve(Mp, omp, src, prob.h, tol=args.tol, levels=False, ws=ws, time_kernels=True)
+                sink.append(st)
+            dLdT = V.obs_loss(T, target, mask_u8, scratch, loss)
             t_ev[1].record()
-            loss.backward()
+            if mixed:
+                gMp, gomp, _ = E.adjoint_mixed(Mp, omp, T, par, src, prob.h, dLdT, ws=ws)
+            else:
+                gMp, gomp, _ = E.adjoint(Mp, omp, T, par, None, src, prob.h, dLdT, ws=ws)
+            gM, gom = E.project_backward(M0, om0, gMp, gomp)
             t_ev[2].record()
-            return T, M.grad, om.grad
+            return T, gM, gom
 
         for _ in range(args.warmup):
             step([], [torch.cuda.Event(enable_timing=True) for _ in range(3)])
@@ -458,7 +475,7 @@ def main():
         T_fix, _, _ = oracle.forward(q, tol=0.0, T_init=T_ora)
         par_fix, _ = oracle.parents_levels(q, T_fix)
         g = np.zeros_like(T_fix)
-        g[mask_np] = 2.0 * (T_fix[mask_np] - target_np[mask_np]) / n_obs
+        g[mask_np] = T_fix[mask_np] - target_np[mask_np]  # dL/dT of L = 1/2 sum over observed nodes
         dMo, domo, _ = oracle.vjp(q, T_fix, par_fix, g)
         m = np.isfinite(T_fix)
         m.flat[prob.src_idx] = False

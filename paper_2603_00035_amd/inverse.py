@@ -61,6 +61,16 @@ def lr_at(cfg: InverseConfig, lr: float, k: int, iters: int) -> float:
     return lo + 0.5 * (lr - lo) * (1.0 + math.cos(math.pi * k / (iters - 1)))
 
 
+def obs_loss(T, T_obs, mask, scratch, value):
+    """eik_obs_loss: returns dL/dT of L = 1/2 sum over observed nodes of
+    (T - T_obs)^2 and writes L into the device double `value`."""
+    dLdT = torch.empty_like(T)
+    L.check("eik_obs_loss", L.lib().eik_obs_loss(T.numel(), L.dtype_code(T), L.ptr(T), L.ptr(T_obs), L.ptr(mask),
+                                                 L.ptr(dLdT), value.data_ptr(), L.ptr(scratch),
+                                                 L.stream_handle(T.device)))
+    return dLdT
+
+
 class Recovery:
     """State of one recovery run: parameters M (3, ny, nx) and omega (2, ny,
     nx) on the GPU, observations T_obs (ny, nx) with a uint8 mask, sources."""
