@@ -219,11 +219,24 @@ __device__ __forceinline__ R local_update_dir(const NodeConst<R> &k, const R Tn[
             code = c1;
         }
     } else {
+        // restricted candidates of direction DIR, with the same one-point-first
+        // pruning and the same canonical order as the full update
+        R b1 = inf;
+        int c1 = kUnreached;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int s = (7 + 2 * DIR + q) & 7;
+            const R t = Tn[s] + k.c1[s]; // +inf for an unreached donor
+            if (t < b1) {
+                b1 = t;
+                c1 = 8 + s;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int s = (7 + 2 * DIR + q) & 7;
             const R Tp = Tn[s], Tq = Tn[(s + 1) & 7];
-            if (Tp < inf && Tq < inf) {
+            if (Tp < b1 && Tq < b1) {
                 R t, m1, m2;
                 if (two_point(k, s, Tp, Tq, t, m1, m2) && t < best) {
                     best = t;
@@ -231,14 +244,9 @@ __device__ __forceinline__ R local_update_dir(const NodeConst<R> &k, const R Tn[
                 }
             }
         }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            const int s = (7 + 2 * DIR + q) & 7;
-            const R t = Tn[s] + k.c1[s];
-            if (Tn[s] < inf && t < best) {
-                best = t;
-                code = 8 + s;
-            }
+        if (!(best <= b1)) {
+            best = b1;
+            code = c1;
         }
     }
     return best;
