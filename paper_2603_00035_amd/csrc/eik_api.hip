@@ -49,7 +49,7 @@ struct Extent {
 int64_t tiles_of(int nx, int ny, int th) { return (int64_t)((nx + TW - 1) / TW) * ((ny + th - 1) / th); }
 
 struct Layout {
-    size_t descs, tile_grid, act, act_count, ctr, Pt, lam, w1, qring, qstate, qctl, total;
+    size_t descs, tile_grid, act, act_count, ctr, Pt, lam, w1, adjD, adjDT, adjGT, qring, qstate, qctl, total;
     uint32_t qslots;
 };
 
@@ -77,6 +77,9 @@ Layout layout(const Extent &e, int dtype)
     L.Pt = o;        o += align256(5 * (size_t)e.nodes * rs);
     L.lam = o;       o += align256((size_t)e.nodes * rs);
     L.w1 = o;        o += align256((size_t)e.nodes * rs);
+    L.adjD = o;      o += align256((size_t)e.nodes * 2);
+    L.adjDT = o;     o += align256((size_t)e.nodes * 2);
+    L.adjGT = o;     o += align256((size_t)e.nodes * rs);
 
     L.qslots = queue_slots(NT);
     L.qring = o;     o += align256((size_t)L.qslots * 4);
@@ -145,6 +148,8 @@ struct Ws {
     int32_t *tile_grid, *act, *act_count;
     unsigned long long *ctr;
     void *Pt, *lam, *w1;
+    uint16_t *adjD, *adjDT;
+    void *adjGT;
     WorkQueue q;
 };
 
@@ -162,6 +167,9 @@ int carve(const Extent &e, int dtype, void *ws, size_t ws_bytes, Ws &w)
     w.Pt = b + L.Pt;
     w.lam = b + L.lam;
     w.w1 = b + L.w1;
+    w.adjD = (uint16_t *)(b + L.adjD);
+    w.adjDT = (uint16_t *)(b + L.adjDT);
+    w.adjGT = b + L.adjGT;
 
     w.q.ring = (uint32_t *)(b + L.qring);
     w.q.state = (uint32_t *)(b + L.qstate);
@@ -463,8 +471,8 @@ MixedLayout mixed_layout(const Extent &e)
 
 // The adjoint relaxation (round or queue scheduler) on lambda of type RL.
 template <typename RL>
-int relax(const LaunchArgs &a, Ws &w, const eik_tuning &tn, bool sync, const uint8_t *parent, const void *w1,
-          const void *g, void *lam, hipStream_t st, int &rounds, bool &conv)
+int relax(const LaunchArgs &a, Ws &w, const eik_tuning &tn, bool sync, const AdjNodes &nd, const void *w1, void *lam,
+          hipStream_t st, int &rounds, bool &conv)
 {
     const int dtype = sizeof(RL) == 8 ? EIK_F64 : EIK_F32;
     launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
@@ -479,7 +487,7 @@ int relax(const LaunchArgs &a, Ws &w, const eik_tuning &tn, bool sync, const uin
         const int budget_rounds = sync ? kMaxRounds / 2 : tn.adjoint_rounds;
         const uint32_t budget = (uint32_t)std::min<int64_t>((int64_t)budget_rounds * a.n_tiles, INT32_MAX);
         launch_queue_setup(a, w.act, w.q, budget, st);
-        launch_adj_queue<RL>(a, waves, parent, w1, g, lam, tn.adjoint_cycles, w.q, st);
+        launch_adj_queue<RL>(a, waves, nd, w1, lam, tn.adjoint_cycles, w.q, st);
         launch_note_queue(w.q, w.ctr + kCtrAdjPending, st);
         HIP_OK(hipGetLastError());
         if (sync) {
@@ -496,7 +504,7 @@ int relax(const LaunchArgs &a, Ws &w, const eik_tuning &tn, bool sync, const uin
             w.act, w.act_count, a.n_tiles, 0, sync ? kMaxRounds / 2 : tn.adjoint_rounds, tn.rounds_per_check, sync,
             st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-                launch_adj_round<RL>(a, parent, w1, g, lam, tn.adjoint_cycles, tn.adjoint_waves, ain, aout, cnt, st);
+                launch_adj_round<RL>(a, nd, w1, lam, tn.adjoint_cycles, tn.adjoint_waves, ain, aout, cnt, st);
             },
             &rounds, &conv);
         if (rc) return rc;
@@ -535,11 +543,15 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
         launch_cast_f64_f32(e.nodes, (const double *)w.w1, r32->w1, st);
         launch_cast_f64_f32(e.nodes, (const double *)dLdT, r32->g, st);
         launch_fill_i32((int32_t *)r32->lam, e.nodes, 0, st); // +0.0f
-        rc = relax<float>(a, w, tn, sync, parent, r32->w1, r32->g, r32->lam, st, rounds, conv);
+        launch_adj_stage<float>(a, parent, r32->g, w.adjD, w.adjDT, w.adjGT, st);
+        const AdjNodes nd = {w.adjD, w.adjDT, r32->g, w.adjGT};
+        rc = relax<float>(a, w, tn, sync, nd, r32->w1, r32->lam, st, rounds, conv);
         if (rc) return rc;
         launch_cast_f32_f64(e.nodes, r32->lam, (double *)w.lam, st);
     } else {
-        rc = relax<R>(a, w, tn, sync, parent, w.w1, dLdT, w.lam, st, rounds, conv);
+        launch_adj_stage<R>(a, parent, dLdT, w.adjD, w.adjDT, w.adjGT, st);
+        const AdjNodes nd = {w.adjD, w.adjDT, dLdT, w.adjGT};
+        rc = relax<R>(a, w, tn, sync, nd, w.w1, w.lam, st, rounds, conv);
         if (rc) return rc;
     }
     launch_adj_params<R>(a, M, parent, w.w1, w.lam, dLdM, dLdom, st);

@@ -15,6 +15,12 @@
 // whose halo changed are visited again, until no lambda on a tile border
 // changes. dL/dtheta_i = lambda_i dT_i/dtheta_i (Alg. backward, last loop)
 // follows in one pass over the nodes.
+//
+// LDS holds only lambda and the donor weights of a tile with its halo; the
+// 16-bit receiver descriptor and dL/dT of each node are built once per
+// adjoint (k_adj_stage) and read by the sweeps from global memory, one line
+// ahead, from row-major arrays in row sweeps and transposed copies in column
+// sweeps, so every load is coalesced and four tiles fit in a CU's LDS.
 #include "eik_device.h"
 #include "eik_internal.h"
 #include "eik_queue.h"
@@ -90,22 +96,32 @@ __global__ __launch_bounds__(256) void k_adj_prep(LaunchArgs a, const R *__restr
 // One directional sweep of the adjoint relaxation over the tile in LDS (a
 // line of the tile per step; DIR as in the forward sweeps).
 template <typename R, int TH, int DIR>
-__device__ __forceinline__ bool adj_sweep_dir(const TileGeoB &g, R *sLam, const R *sW, const uint16_t *sD,
-                                              const R *sG)
+__device__ __forceinline__ bool adj_sweep_dir(const TileGeoB &g, R *sLam, const R *sW,
+                                              const uint16_t *__restrict__ Dsrc, const R *__restrict__ Gsrc)
 {
     constexpr int LP = TW + 3;
     constexpr bool COL = (DIR & 1) == 0;
     const int lane = threadIdx.x % TW;
     const int len = COL ? g.w : g.h;
     const int span = COL ? g.h : g.w;
+    const int lc = lane < span ? lane : span - 1; // clamped lane for loads
+    // descriptor and dL/dT of the node this lane updates at step s (steps past
+    // the last line are clamped to it): Dsrc / Gsrc are the transposed arrays
+    // of the grid in column sweeps, the row-major ones in row sweeps
+    auto load = [&](int s, uint32_t &d, R &gv) {
+        s = s < len ? s : len - 1;
+        const int pos = DIR < 2 ? s : len - 1 - s;
+        const size_t ad =
+            COL ? (size_t)(g.i0 + pos) * g.gd.ny + (g.j0 + lc) : (size_t)(g.j0 + pos) * g.gd.nx + (g.i0 + lc);
+        d = Dsrc[ad];
+        gv = Gsrc[ad];
+    };
     bool changed = false;
-    for (int s = 0; s < len; ++s) {
+    auto step = [&](int s, uint32_t d, R acc) {
         const int pos = DIR < 2 ? s : len - 1 - s;
         const int ci = COL ? pos : lane;
         const int cj = COL ? lane : pos;
         if (lane < span) {
-            const uint32_t d = sD[cj * kHalfPitch + ci];
-            R acc = sG[cj * kWordPitch + ci];
             // all neighbour reads are issued at once and the receivers
             // selected afterwards (no branch per neighbour); non-receivers add
             // an exact zero, so the sum is the same, in the same order
@@ -132,6 +148,17 @@ __device__ __forceinline__ bool adj_sweep_dir(const TileGeoB &g, R *sLam, const 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // double-buffered: the next line's inputs load while a line is updated
+    uint32_t dX, dY;
+    R gX, gY;
+    load(0, dX, gX);
+    for (int s = 0; s < len; s += 2) {
+        load(s + 1, dY, gY);
+        step(s, dX, gX);
+        if (s + 1 >= len) break; // uniform over the wave
+        load(s + 2, dX, gX);
+        step(s + 1, dY, gY);
     }
     return changed;
 }
@@ -149,10 +176,9 @@ struct AdjVisit {
 // that stayed fixed, so every equation of the tile holds exactly, as after a
 // quiet cycle of the one-wave visit, and the fixed point is the same.
 template <typename R, int TH, bool CD>
-__device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, const uint8_t *__restrict__ parall,
-                                                    const R *__restrict__ w1all, const R *__restrict__ gall,
-                                                    R *lamall, int max_cycles, R *sLam, R *sW, uint8_t *sP,
-                                                    uint16_t *sD, R *sG, int *sBits)
+__device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, const AdjNodes &nd,
+                                                    const R *__restrict__ w1all, R *lamall, int max_cycles, R *sLam,
+                                                    R *sW, int *sBits)
 {
     constexpr int LP = TW + 3;
     constexpr int NW = CD ? 4 : 1;
@@ -163,33 +189,20 @@ __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, 
 
     load_tile_halo<R, TH, LP>(lam, sLam, nx, ny, g.i0, g.j0, R(0));
     load_tile_halo<R, TH, LP>(w1all + g.gd.off, sW, nx, ny, g.i0, g.j0, R(1));
-    load_tile_halo<uint8_t, TH, LP>(parall + g.gd.off, sP, nx, ny, g.i0, g.j0, kUnreached);
-    load_block<R, TH, kWordPitch, 0>(gall + g.gd.off, sG, nx, ny, g.i0, g.j0, R(0));
     if (CD && threadIdx.x == 0) *sBits = 0;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < TH * TW; idx += NW * TW) {
-        const int r = idx / TW, c = idx - r * TW;
-        uint32_t d = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int pc = sP[(r + 1 + nb_dy(k)) * LP + (c + 1 + nb_dx(k))];
-            const int kk = (k + 4) & 7; // this node seen from the neighbour
-            const uint32_t sel = pc == kk ? 1u : (pc == ((kk + 7) & 7) ? 2u : (pc == 8 + kk ? 3u : 0u));
-            d |= sel << (2 * k);
-        }
-        sD[r * kHalfPitch + c] = (uint16_t)d;
-    }
-    __syncthreads();
+    const uint16_t *D = nd.D + g.gd.off, *DT = nd.DT + g.gd.off;
+    const R *G = (const R *)nd.g + g.gd.off, *GT = (const R *)nd.gT + g.gd.off;
 
     int quiet = 0, sweeps = 0;
     const int max_sweeps = 4 * max_cycles;
     while (quiet < 4 && sweeps < max_sweeps) {
         bool changed;
         switch (CD ? wave : (sweeps & 3)) { // CD: one direction per wave, uniform per wave
-        case 0: changed = adj_sweep_dir<R, TH, 0>(g, sLam, sW, sD, sG); break;
-        case 1: changed = adj_sweep_dir<R, TH, 1>(g, sLam, sW, sD, sG); break;
-        case 2: changed = adj_sweep_dir<R, TH, 2>(g, sLam, sW, sD, sG); break;
-        default: changed = adj_sweep_dir<R, TH, 3>(g, sLam, sW, sD, sG); break;
+        case 0: changed = adj_sweep_dir<R, TH, 0>(g, sLam, sW, DT, GT); break;
+        case 1: changed = adj_sweep_dir<R, TH, 1>(g, sLam, sW, D, G); break;
+        case 2: changed = adj_sweep_dir<R, TH, 2>(g, sLam, sW, DT, GT); break;
+        default: changed = adj_sweep_dir<R, TH, 3>(g, sLam, sW, D, G); break;
         }
         if (CD) { // a cycle is the four concurrent sweeps
             sweeps += 4;
@@ -250,24 +263,22 @@ __device__ __forceinline__ int adj_neighbour(const TileGeoB &g, int b)
 
 // Round scheduler with sweep visits (CD: four waves per tile).
 template <typename R, int TH, bool CD>
-__global__ __launch_bounds__(CD ? 4 * TW : TW) void k_adj_sweep_round(
-    LaunchArgs a, const uint8_t *__restrict__ parall, const R *__restrict__ w1all, const R *__restrict__ gall,
-    R *__restrict__ lamall, int max_cycles, int32_t *__restrict__ act_in, int32_t *__restrict__ act_out,
-    int32_t *__restrict__ count_next)
+__global__ __launch_bounds__(CD ? 4 * TW : TW) void k_adj_sweep_round(LaunchArgs a, AdjNodes nd,
+                                                                      const R *__restrict__ w1all,
+                                                                      R *__restrict__ lamall, int max_cycles,
+                                                                      int32_t *__restrict__ act_in,
+                                                                      int32_t *__restrict__ act_out,
+                                                                      int32_t *__restrict__ count_next)
 {
     constexpr int LP = TW + 3;
     const int t = blockIdx.x;
     if (act_in[t] == 0) return; // uniform over the workgroup
     __shared__ R sLam[(TH + 2) * LP];
     __shared__ R sW[(TH + 2) * LP];
-    __shared__ uint8_t sP[(TH + 2) * LP];
-    __shared__ uint16_t sD[TH * kHalfPitch];
-    __shared__ R sG[TH * kWordPitch];
     __shared__ int sBits;
     if (CD) __syncthreads(); // every wave has read act_in[t] before it is cleared
     if (threadIdx.x == 0) act_in[t] = 0;
-    const AdjVisit v =
-        adj_visit_sweep<R, TH, CD>(a, t, parall, w1all, gall, lamall, max_cycles, sLam, sW, sP, sD, sG, &sBits);
+    const AdjVisit v = adj_visit_sweep<R, TH, CD>(a, t, nd, w1all, lamall, max_cycles, sLam, sW, &sBits);
     if (threadIdx.x == 0) {
         const TileGeoB g = tile_geo_b<TH>(a, t);
         for (int b = 0; b < 8; ++b) {
@@ -281,23 +292,19 @@ __global__ __launch_bounds__(CD ? 4 * TW : TW) void k_adj_sweep_round(
 
 // Work-queue scheduler with sweep visits.
 template <typename R, int TH>
-__global__ __launch_bounds__(TW) void k_adj_sweep_queue(LaunchArgs a, const uint8_t *__restrict__ parall,
-                                                        const R *__restrict__ w1all, const R *__restrict__ gall,
+__global__ __launch_bounds__(TW) void k_adj_sweep_queue(LaunchArgs a, AdjNodes nd, const R *__restrict__ w1all,
                                                         R *lamall, int max_cycles, WorkQueue q)
 {
     constexpr int LP = TW + 3;
     __shared__ R sLam[(TH + 2) * LP];
     __shared__ R sW[(TH + 2) * LP];
-    __shared__ uint8_t sP[(TH + 2) * LP];
-    __shared__ uint16_t sD[TH * kHalfPitch];
-    __shared__ R sG[TH * kWordPitch];
     for (;;) {
         int t = threadIdx.x == 0 ? q_take(q) : 0;
         t = __shfl(t, 0);
         if (t < 0) break;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const AdjVisit v =
-            adj_visit_sweep<R, TH, false>(a, t, parall, w1all, gall, lamall, max_cycles, sLam, sW, sP, sD, sG, nullptr);
+            adj_visit_sweep<R, TH, false>(a, t, nd, w1all, lamall, max_cycles, sLam, sW, nullptr);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (threadIdx.x == 0) {
             const TileGeoB g = tile_geo_b<TH>(a, t);
@@ -309,6 +316,51 @@ __global__ __launch_bounds__(TW) void k_adj_sweep_queue(LaunchArgs a, const uint
             q_done(q, t, v.settled);
         }
         __syncthreads(); // LDS reuse by the next visit
+    }
+}
+
+// Per-node inputs of the relaxation sweeps, once per adjoint: the receiver
+// descriptor of each node (two bits per neighbour k: 1 if k's active update is
+// the two-point stencil whose first donor is this node (weight w of k), 2 if
+// it is the one whose second donor is this node (weight 1 - w), 3 if it is the
+// one-point update from this node (weight 1), 0 otherwise; neighbours outside
+// the grid count as unreached), row-major D and transposed DT, and the
+// transposed copy GT of dL/dT.
+template <typename R, int TH>
+__global__ __launch_bounds__(256) void k_adj_stage(LaunchArgs a, const uint8_t *__restrict__ parall,
+                                                   const R *__restrict__ gall, uint16_t *__restrict__ D,
+                                                   uint16_t *__restrict__ DT, R *__restrict__ GT)
+{
+    __shared__ uint16_t bd[TH][TW + 2];
+    __shared__ R bg[TH][TW + 1];
+    const TileGeoB g = tile_geo_b<TH>(a, blockIdx.x);
+    const int nx = g.gd.nx, ny = g.gd.ny;
+    const uint8_t *par = parall + g.gd.off;
+    for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+        const int r = idx / TW, c = idx - r * TW;
+        if (r >= g.h || c >= g.w) continue;
+        const int i = g.i0 + c, j = g.j0 + r;
+        uint32_t d = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int x = i + nb_dx(k), y = j + nb_dy(k);
+            const int pc = (x >= 0 && x < nx && y >= 0 && y < ny) ? (int)par[(size_t)y * nx + x] : (int)kUnreached;
+            const int kk = (k + 4) & 7; // this node seen from the neighbour
+            const uint32_t sel = pc == kk ? 1u : (pc == ((kk + 7) & 7) ? 2u : (pc == 8 + kk ? 3u : 0u));
+            d |= sel << (2 * k);
+        }
+        const size_t c0 = (size_t)j * nx + i;
+        D[g.gd.off + c0] = (uint16_t)d;
+        bd[r][c] = (uint16_t)d;
+        bg[r][c] = gall[g.gd.off + c0];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+        const int c = idx / TH, r = idx - c * TH;
+        if (r >= g.h || c >= g.w) continue;
+        const size_t t0 = (size_t)(g.i0 + c) * ny + g.j0 + r;
+        DT[g.gd.off + t0] = bd[r][c];
+        GT[g.gd.off + t0] = bg[r][c];
     }
 }
 
@@ -376,25 +428,32 @@ void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const v
 }
 
 template <typename R>
-void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const void *w1, const void *dLdT, void *lam,
-                      int max_cycles, int waves, int32_t *act_in, int32_t *act_out, int32_t *count_next,
+void launch_adj_stage(const LaunchArgs &a, const uint8_t *parent, const void *g, uint16_t *D, uint16_t *DT, void *gT,
                       hipStream_t st)
+{
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_stage<R, TH>), dim3(a.n_tiles), dim3(256), 0, st, a, parent,
+                                             (const R *)g, D, DT, (R *)gT));
+}
+
+template <typename R>
+void launch_adj_round(const LaunchArgs &a, const AdjNodes &nd, const void *w1, void *lam, int max_cycles, int waves,
+                      int32_t *act_in, int32_t *act_out, int32_t *count_next, hipStream_t st)
 {
 #define EIK_ADJ_ROUND(CD)                                                                                        \
     EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_sweep_round<R, TH, CD>), dim3(a.n_tiles), dim3(CD ? 4 * TW : TW), \
-                                             0, st, a, parent, (const R *)w1, (const R *)dLdT, (R *)lam,          \
-                                             max_cycles, act_in, act_out, count_next))
+                                             0, st, a, nd, (const R *)w1, (R *)lam, max_cycles, act_in, act_out,  \
+                                             count_next))
     if (waves >= 4) EIK_ADJ_ROUND(true);
     else EIK_ADJ_ROUND(false);
 #undef EIK_ADJ_ROUND
 }
 
 template <typename R>
-void launch_adj_queue(const LaunchArgs &a, int n_waves, const uint8_t *parent, const void *w1, const void *dLdT,
-                      void *lam, int max_cycles, const WorkQueue &q, hipStream_t st)
+void launch_adj_queue(const LaunchArgs &a, int n_waves, const AdjNodes &nd, const void *w1, void *lam,
+                      int max_cycles, const WorkQueue &q, hipStream_t st)
 {
-    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_sweep_queue<R, TH>), dim3(n_waves), dim3(TW), 0, st, a, parent,
-                                             (const R *)w1, (const R *)dLdT, (R *)lam, max_cycles, q));
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_sweep_queue<R, TH>), dim3(n_waves), dim3(TW), 0, st, a, nd,
+                                             (const R *)w1, (R *)lam, max_cycles, q));
 }
 
 int adj_queue_waves(int th, int dtype)
@@ -432,10 +491,12 @@ void launch_dsrc(const LaunchArgs &a, const int32_t *src_idx, const void *lam, v
 #define EIK_INST(R)                                                                                              \
     template void launch_adj_prep<R>(const LaunchArgs &, const void *, const void *, const void *,              \
                                      const uint8_t *, void *, void *, hipStream_t);                             \
-    template void launch_adj_round<R>(const LaunchArgs &, const uint8_t *, const void *, const void *, void *,   \
-                                      int, int, int32_t *, int32_t *, int32_t *, hipStream_t);                   \
-    template void launch_adj_queue<R>(const LaunchArgs &, int, const uint8_t *, const void *, const void *,     \
-                                      void *, int, const WorkQueue &, hipStream_t);                              \
+    template void launch_adj_stage<R>(const LaunchArgs &, const uint8_t *, const void *, uint16_t *, uint16_t *, \
+                                      void *, hipStream_t);                                                      \
+    template void launch_adj_round<R>(const LaunchArgs &, const AdjNodes &, const void *, void *, int, int,     \
+                                      int32_t *, int32_t *, int32_t *, hipStream_t);                             \
+    template void launch_adj_queue<R>(const LaunchArgs &, int, const AdjNodes &, const void *, void *, int,     \
+                                      const WorkQueue &, hipStream_t);                                           \
     template void launch_adj_params<R>(const LaunchArgs &, const void *, const uint8_t *, const void *,         \
                                        const void *, void *, void *, hipStream_t);                               \
     template void launch_dsrc<R>(const LaunchArgs &, const int32_t *, const void *, void *, hipStream_t);

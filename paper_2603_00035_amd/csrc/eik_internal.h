@@ -121,13 +121,22 @@ void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_gr
 template <typename R>
 void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const void *T, const uint8_t *parent,
                      void *w1, void *lam, hipStream_t st);
+// Per-node inputs of the adjoint relaxation sweeps, per grid at its node
+// offset: receiver descriptors and dL/dT, row-major (D, g) and transposed
+// (DT, gT, [nx][ny] per grid) for the column sweeps.
+struct AdjNodes {
+    const uint16_t *D, *DT;
+    const void *g, *gT;
+};
 template <typename R>
-void launch_adj_round(const LaunchArgs &a, const uint8_t *parent, const void *w1, const void *dLdT, void *lam,
-                      int max_cycles, int waves, int32_t *act_in, int32_t *act_out, int32_t *count_next,
+void launch_adj_stage(const LaunchArgs &a, const uint8_t *parent, const void *g, uint16_t *D, uint16_t *DT, void *gT,
                       hipStream_t st);
 template <typename R>
-void launch_adj_queue(const LaunchArgs &a, int n_waves, const uint8_t *parent, const void *w1, const void *dLdT,
-                      void *lam, int max_cycles, const WorkQueue &q, hipStream_t st);
+void launch_adj_round(const LaunchArgs &a, const AdjNodes &nd, const void *w1, void *lam, int max_cycles, int waves,
+                      int32_t *act_in, int32_t *act_out, int32_t *count_next, hipStream_t st);
+template <typename R>
+void launch_adj_queue(const LaunchArgs &a, int n_waves, const AdjNodes &nd, const void *w1, void *lam,
+                      int max_cycles, const WorkQueue &q, hipStream_t st);
 int adj_queue_waves(int th, int dtype);
 template <typename R>
 void launch_adj_params(const LaunchArgs &a, const void *M, const uint8_t *parent, const void *w1, const void *lam,

@@ -99,10 +99,13 @@ def test_batched_fp32_matches_oracle_and_single_solves():
 def test_graph_capture_replays_match_eager():
     """The unsynchronised batched forward + backward captured once in a HIP
     graph and replayed three times on changed inputs, with eager work between
-    the replays; every replay equals the eager (synchronised) result."""
+    the replays; every replay equals the eager (synchronised) result bit for
+    bit. The solves run to exact stationarity: at a positive tolerance the
+    concurrent-direction visits fix the field only to within that tolerance
+    (which store of a sub-tolerance change lands last depends on timing)."""
     probs = uneven_set(16, 1300)
     say(f"[graph] {len(probs)} grids")
-    B = make_batch(probs, torch.float32, max_rounds=96)
+    B = make_batch(probs, torch.float32, max_rounds=256)
     M, om, src = packed_inputs(B, probs, torch.float32)
     Ms, oms = M.clone(), om.clone()
     gT = torch.rand(B.n_nodes, device=B.device)
@@ -111,13 +114,13 @@ def test_graph_capture_replays_match_eager():
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):  # warm-up outside capture
-        B.forward(Ms, oms, src, tol=1e-5, out=fo, sync=False)
+        B.forward(Ms, oms, src, tol=0.0, out=fo, sync=False)
         B.backward(Ms, oms, fo[0], fo[1], fo[2], src, gT, out=bo, sync=False)
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        B.forward(Ms, oms, src, tol=1e-5, out=fo, sync=False)
+        B.forward(Ms, oms, src, tol=0.0, out=fo, sync=False)
         B.backward(Ms, oms, fo[0], fo[1], fo[2], src, gT, out=bo, sync=False)
     torch.cuda.synchronize()
     for rep in range(3):
@@ -129,7 +132,7 @@ def test_graph_capture_replays_match_eager():
         assert B.pending() == (0, 0, 0)
         Tr, dMr = fo[0].clone(), bo[0].clone()
         x = torch.randn(1000, device=B.device).sum()  # eager work between replays
-        Te, pe, le, st = B.forward(Ms, oms, src, tol=1e-5)
+        Te, pe, le, st = B.forward(Ms, oms, src, tol=0.0)
         dMe, dome, dse, _ = B.backward(Ms, oms, Te, pe, le, src, gT)
         torch.cuda.synchronize()
         assert torch.isfinite(x)
