@@ -52,6 +52,9 @@ WORKLOADS = {
           "fwd to 1e-5 + adjoint, one HIP graph replay per step",
     "c5": "256x256 FP32 forward to 1e-5 on held-out seeds, batches of 250: cold start vs the learned BF16 "
           "U-Net warm start (inference included) with and without the fixed-budget fallback",
+    "gradcheck": "64x64 FP64 gradient checks of the validation section: pointwise central differences at 20 "
+                 "interior nodes per configuration (isotropic, anisotropic, drift), 100 random directions, "
+                 "1 % metric noise",
     "inverse": "80x80 FP64 isotropic metric recovery (g = 1 | 2, one central source): 300 projected Adam "
                "iterations of forward + data term + adjoint + TV + step + projections, full and 7 % observations",
 }
@@ -178,6 +181,35 @@ def bench_inverse(args):
                    "lr_G": 1e-2, "lam_G": 1e-3, "optimizer": "Adam, cosine schedule, isotropic projection"},
         "recovery": runs,
         "paper_rel_err": {"full": 0.056, "obs7pct": 0.212, "note": "the paper's own figures, other machine"},
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
+def bench_gradcheck(args):
+    """The paper's gradient checks (Sec. 4 and App. gradient verification) on
+    the FP64 path; the paper's figures are quoted beside ours."""
+    from paper_2603_00035_amd import gradcheck as C
+
+    t0 = time.perf_counter()
+    pointwise = {}
+    for name in C.CONFIGS:
+        chk = C.Check(name, n=64, seed=args.seed + 1)
+        err, tested, skipped = chk.pointwise(points=20, planes=C.PLANES[name])
+        pointwise[name] = {"max_rel_err": err, "points": tested, "skipped_at_stencil_switches": skipped}
+    chk = C.Check("anisotropic", n=64, seed=args.seed + 2)
+    f10, f1, med = chk.random_directions(count=100)
+    stab = chk.stability(trials=10)
+    wall = time.perf_counter() - t0
+    return {
+        "metric": "cell-updates/s; fwd+adjoint ms to 1e-5 at 2048^2; learned warm vs cold",
+        "value": None, "unit": "cell-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * wall,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"gradcheck: {WORKLOADS['gradcheck']}", "n": 64, "eps": 1e-5},
+        "pointwise": pointwise,
+        "random_directions": {"within_10pct": f10, "within_1pct": f1, "median_rel_err": med, "count": 100},
+        "noise_1pct_gradient_change": stab,
+        "paper": {"pointwise_max_rel_err": "< 1e-6", "random_directions_within_10pct": 0.20,
+                  "noise_1pct_mean_gradient_change_interior": 0.0048, "note": "the paper's own figures"},
         "roofline": None, "cpu_baseline": None,
     }
 
@@ -318,6 +350,9 @@ def main():
         return
     if args.workload == "inverse":
         print(json.dumps(bench_inverse(args)), flush=True)
+        return
+    if args.workload == "gradcheck":
+        print(json.dumps(bench_gradcheck(args)), flush=True)
         return
 
     dev = torch.device("cuda:0")
