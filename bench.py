@@ -54,7 +54,7 @@ WORKLOADS = {
           "U-Net warm start (inference included) with and without the fixed-budget fallback",
     "gradcheck": "64x64 FP64 gradient checks of the validation section: pointwise central differences at 20 "
                  "interior nodes per configuration (isotropic, anisotropic, drift), 100 random directions, "
-                 "1 % metric noise",
+                 "1 % and 0.1 % metric noise, plain and averaged over 16 jittered copies",
     "inverse": "80x80 FP64 isotropic metric recovery (g = 1 | 2, one central source): 300 projected Adam "
                "iterations of forward + data term + adjoint + TV + step + projections, full and 7 % observations",
 }
@@ -199,6 +199,9 @@ def bench_gradcheck(args):
     chk = C.Check("anisotropic", n=64, seed=args.seed + 2)
     f10, f1, med = chk.random_directions(count=100)
     stab = chk.stability(trials=10)
+    stab_small = chk.stability(trials=10, noise=0.001)
+    smooth = {"K": 16, "sigma": 0.01}
+    smooth.update(chk.stability(trials=10, grad=chk.smoothed(K=16, sigma=0.01)))
     wall = time.perf_counter() - t0
     return {
         "metric": "cell-updates/s; fwd+adjoint ms to 1e-5 at 2048^2; learned warm vs cold",
@@ -208,6 +211,8 @@ def bench_gradcheck(args):
         "pointwise": pointwise,
         "random_directions": {"within_10pct": f10, "within_1pct": f1, "median_rel_err": med, "count": 100},
         "noise_1pct_gradient_change": stab,
+        "noise_1pct_gradient_change_jitter_averaged": smooth,
+        "noise_0.1pct_gradient_change": stab_small,
         "paper": {"pointwise_max_rel_err": "< 1e-6", "random_directions_within_10pct": 0.20,
                   "noise_1pct_mean_gradient_change_interior": 0.0048, "note": "the paper's own figures"},
         "roofline": None, "cpu_baseline": None,
