@@ -28,7 +28,8 @@ EXPORTS = ["eik_workspace_bytes", "eik_forward", "eik_backward", "eik_project", 
            "eik_last_error", "eik_batch_workspace_bytes", "eik_batch_plan", "eik_forward_batched",
            "eik_backward_batched", "eik_batch_pending", "eik_mixed_workspace_bytes", "eik_forward_mixed",
            "eik_backward_mixed", "eik_inv_scratch_bytes", "eik_tv", "eik_obs_loss", "eik_sum_sq", "eik_param_step",
-           "eik_tie_isotropic"]
+           "eik_tie_isotropic", "eik_enc_dense", "eik_enc_dense_backward", "eik_enc_combine",
+           "eik_enc_scratch_bytes", "eik_enc_combine_backward"]
 
 
 class EikGrid(ctypes.Structure):
@@ -118,6 +119,16 @@ def lib():
         L.eik_param_step.restype = ctypes.c_int
         L.eik_tie_isotropic.argtypes = [i64, i32, vp, vp]
         L.eik_tie_isotropic.restype = ctypes.c_int
+        L.eik_enc_dense.argtypes = [i32, i32, i32, vp, vp, vp, i32, vp, vp]
+        L.eik_enc_dense.restype = ctypes.c_int
+        L.eik_enc_dense_backward.argtypes = [i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.eik_enc_dense_backward.restype = ctypes.c_int
+        L.eik_enc_combine.argtypes = [i64, i32, d, vp, vp, vp, vp, vp]
+        L.eik_enc_combine.restype = ctypes.c_int
+        L.eik_enc_scratch_bytes.argtypes = []
+        L.eik_enc_scratch_bytes.restype = ctypes.c_size_t
+        L.eik_enc_combine_backward.argtypes = [i64, i32, d, vp, vp, vp, vp, vp, vp]
+        L.eik_enc_combine_backward.restype = ctypes.c_int
         L.eik_last_error.argtypes = []
         L.eik_last_error.restype = ctypes.c_char_p
         _lib = L

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/eik.h"
+#include "../../include/eik_encoder.h"
 #include "../../include/eik_inverse.h"
 #include "eik_internal.h"
 
@@ -895,6 +896,62 @@ int eik_tie_isotropic(int64_t n, int32_t dtype, void *M, hipStream_t stream)
         launch_tie_isotropic<double>(n, M, stream);
     else if (dtype == EIK_F32)
         launch_tie_isotropic<float>(n, M, stream);
+    else
+        return fail(EIK_EINVAL, "dtype %d", dtype);
+    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Covariate encoder (include/eik_encoder.h)
+
+int eik_enc_dense(int32_t B, int32_t Cin, int32_t Cout, const float *x, const float *W, const float *b, int32_t relu,
+                  float *y, hipStream_t stream)
+{
+    if (B < 1 || Cin < 1 || Cout < 1 || (int64_t)B * Cout > (1 << 24)) return fail(EIK_EINVAL, "dense sizes");
+    if (!x || !W || !y) return fail(EIK_EINVAL, "NULL pointer argument");
+    launch_enc_dense(B, Cin, Cout, x, W, b, relu, y, stream);
+    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+int eik_enc_dense_backward(int32_t B, int32_t Cin, int32_t Cout, const float *x, const float *W, const float *y,
+                           int32_t relu, const float *dy, float *dx, float *dW, float *db, hipStream_t stream)
+{
+    if (B < 1 || Cin < 1 || Cout < 1 || (int64_t)B * Cin > (1 << 24) || (int64_t)Cout * (Cin + 1) > (1 << 24))
+        return fail(EIK_EINVAL, "dense sizes");
+    if (!x || !W || !y || !dy || !dW) return fail(EIK_EINVAL, "NULL pointer argument");
+    launch_enc_dense_backward(B, Cin, Cout, x, W, y, relu, dy, dx, dW, db, stream);
+    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+int eik_enc_combine(int64_t n, int32_t dtype, double alpha, const float *base, const float *local, void *M,
+                    void *omega, hipStream_t stream)
+{
+    if (n < 1) return fail(EIK_EINVAL, "n < 1");
+    if (!base || !local || !M || !omega) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        launch_enc_combine<double>(n, alpha, base, local, M, omega, stream);
+    else if (dtype == EIK_F32)
+        launch_enc_combine<float>(n, alpha, base, local, M, omega, stream);
+    else
+        return fail(EIK_EINVAL, "dtype %d", dtype);
+    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+size_t eik_enc_scratch_bytes(void) { return sizeof(double) * kEncPlanes * kInvBlocks; }
+
+int eik_enc_combine_backward(int64_t n, int32_t dtype, double alpha, const void *dM, const void *domega,
+                             float *dlocal, float *dbase, void *scratch, hipStream_t stream)
+{
+    if (n < 1) return fail(EIK_EINVAL, "n < 1");
+    if (!dM || !domega || !dlocal || !dbase || !scratch) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        launch_enc_combine_backward<double>(n, alpha, dM, domega, dlocal, dbase, (double *)scratch, stream);
+    else if (dtype == EIK_F32)
+        launch_enc_combine_backward<float>(n, alpha, dM, domega, dlocal, dbase, (double *)scratch, stream);
     else
         return fail(EIK_EINVAL, "dtype %d", dtype);
     HIP_OK(hipGetLastError());
