@@ -309,9 +309,11 @@ template <typename R>
 int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, const void *src_t, const void *M,
                  const void *om, const void *T_init, double tol, int max_rounds, int flags, void *T,
                  uint8_t *parent, int32_t *level, void *ws, size_t ws_bytes, const eik_tuning *tun,
-                 eik_stats *stats, bool single, hipStream_t st)
+                 eik_stats *stats, bool single, hipStream_t st, bool certify = true)
 {
     const int dtype = sizeof(R) == 8 ? EIK_F64 : EIK_F32;
+    // the sweeps keep the source marks in the parent array
+    if (!T || !parent) return fail(EIK_EINVAL, "T and parent arrays are required");
     const eik_tuning tn = tuning_or_default(tun);
     Extent e;
     Ws w;
@@ -361,12 +363,16 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         r0 += rounds;
         launch_copy_u64(w.ctr + kCtrCellUpdates, w.ctr + kCtrFastUpdates, st);
         // certify with the full update: every tile runs once more
-        launch_all_active(a, w.act + (r0 & 1) * a.n_tiles, w.act_count + r0, st);
+        if (certify) launch_all_active(a, w.act + (r0 & 1) * a.n_tiles, w.act_count + r0, st);
     }
     int launches = r0;
     const int fast_launches = r0;
     const double fast_ms = timer.ms;
-    if (tn.scheduler == EIK_SCHED_QUEUE) {
+    if (fast && !certify) {
+        // no full rounds: the caller continues from this field with full
+        // updates of its own (the mixed path's FP64 phase), which converge to
+        // the full update's fixed point from any start
+    } else if (tn.scheduler == EIK_SCHED_QUEUE) {
         // one persistent launch over a device queue of flagged tiles
         const int waves = std::min({sweep_queue_waves(a.th, dtype, level != nullptr), kMaxQueueWaves, a.n_tiles});
         if (waves < 1) return fail(EIK_EDEVICE, "no occupancy for the work-queue sweep kernel");
@@ -402,9 +408,10 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         HIP_OK(hipGetLastError());
     }
 
-    // active stencils from the final field, then (when asked for) levels made
-    // consistent with them
-    launch_parents<R>(a, M, om, T, parent, st);
+    // active stencils from the final field (skipped without certification:
+    // the mixed path's FP32 phase, whose stencils the FP64 phase recomputes),
+    // then (when asked for) levels made consistent with them
+    if (certify) launch_parents<R>(a, M, om, T, parent, st);
     int lrounds = 0;
     if (level) {
         launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
@@ -527,6 +534,8 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
                   eik_stats *stats, hipStream_t st, const Relax32 *r32 = nullptr)
 {
     const int dtype = sizeof(R) == 8 ? EIK_F64 : EIK_F32;
+    // the sweeps keep the source marks in the parent array
+    if (!T || !parent) return fail(EIK_EINVAL, "T and parent arrays are required");
     const eik_tuning tn = tuning_or_default(tun);
     Extent e;
     Ws w;
@@ -670,7 +679,8 @@ int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega
     HIP_OK(hipGetLastError());
     // FP32 sweeps from the cold start; not reaching tol32 is no error here
     rc = forward_impl<float>(1, &g32, g32.src_idx, g32.src_t, M32, om32, nullptr, tol32, max_rounds, flags, T32,
-                             parent, nullptr, b + L.base, ws_bytes - L.base, tuning32, stats, true, stream);
+                             parent, nullptr, b + L.base, ws_bytes - L.base, tuning32, stats, true, stream,
+                             /*certify=*/false);
     if (rc < 0) return rc;
     // FP64 sweeps from that field, in place in T
     launch_cast_f32_f64(e.nodes, T32, T, stream);
