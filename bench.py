@@ -64,7 +64,7 @@ WORKLOADS = {
 
 
 PRECISIONS = {
-    "mixed": "FP32 restricted-candidate sweeps to their stationarity, FP64 full-update sweeps from that field to tol, adjoint with FP64 weights and parameter "
+    "mixed": "FP32 restricted-candidate sweeps until no change exceeds tol, FP64 full-update sweeps from that field to tol, adjoint with FP64 weights and parameter "
              "derivatives and an FP32 relaxation",
     "f32": "FP32 throughout",
 }

@@ -161,10 +161,10 @@ int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *
 /* Mixed-precision forward: the solve of eik_forward on FP64 parameters in two
  * phases. FP32 sweeps from the cold start, on FP32-rounded copies of M, omega
  * and the source times: with the restricted-candidate cold start on
- * (tuning32->fast_cold_start, default) they run to that update's exact
- * stationarity and stop there, the full update being left to the FP64 phase;
- * with it off they run the full update to tol32 (EIK_NOT_CONVERGED there is
- * not an error). FP64 full-update sweeps then continue from that field, in
+ * (tuning32->fast_cold_start, default) they run that update until no tile
+ * changes a value by more than tol32 and stop there, the full update being
+ * left to the FP64 phase; with it off they run the full update to tol32
+ * (EIK_NOT_CONVERGED there is not an error). FP64 full-update sweeps then continue from that field, in
  * place in T, to tol, visiting every tile first.
  * The FP32 phase carries the front across the grid at FP32 cost; the FP64
  * phase removes the FP32 rounding that the arrival times accumulate along

@@ -347,6 +347,10 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     int r0 = 0, rounds = 0;
     bool conv = false;
     const bool fast = T_init == nullptr && tn.fast_cold_start;
+    // exact stationarity before certification here; without it (the mixed
+    // path's FP32 phase) the caller's tolerance, its FP64 phase converging
+    // from any start
+    const double fast_tol = certify ? 0.0 : tol;
     if (fast) {
         // cold start: restricted candidates, T only decreases. Run to exact
         // stationarity of this min-update (finite: every store lowers a
@@ -356,7 +360,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
             w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
                 launch_sweep_round<R>(a, tn.fast_cold_start == 2 ? kModeFastCD : kModeFast, M, om, w.Pt, T,
-                                      parent, level, ain, aout, cnt, w.ctr, 0.0, tn.max_local_cycles, 1, st);
+                                      parent, level, ain, aout, cnt, w.ctr, fast_tol, tn.max_local_cycles, 1, st);
             },
             &rounds, &conv, &timer);
         if (rc) return rc;
