@@ -12,8 +12,9 @@ onto the feasible set (SPD metric, |b|_{G^-1} < 1).
 Every step of an iteration is a library call (include/eik.h,
 include/eik_inverse.h): eik_forward, eik_obs_loss, eik_backward, eik_tv,
 eik_sum_sq, eik_param_step, eik_tie_isotropic (isotropic recovery),
-eik_project. This module only sequences them and
-holds the optimiser state.
+eik_project. This module only sequences them and holds the optimiser state;
+with several fires (MultiRecovery) it also replicates the parameter planes
+for the batched launch and sums the per-fire gradients.
 """
 from __future__ import annotations
 
@@ -100,9 +101,9 @@ class Recovery:
     def _sp(self, k):
         return self.scalars.data_ptr() + 8 * k
 
-    def step(self, k: int = 0, iters: int = 1):
-        """One iteration; returns the device tensor (data loss, lam_G R(G),
-        lam_b R(b), squared gradient norm) of the parameters it started from."""
+    def _data_gradient(self):
+        """Gradients (dL/dM, dL/domega) of the data term at the current
+        parameters; the data loss goes to scalars[0]."""
         c = self.cfg
         lib, st = L.lib(), self._stream
         n = self.nx * self.ny
@@ -111,6 +112,15 @@ class Recovery:
         L.check("eik_obs_loss", lib.eik_obs_loss(n, self.dc, L.ptr(T), L.ptr(self.T_obs), L.ptr(self.mask),
                                                  L.ptr(dLdT), self._sp(0), L.ptr(self.scratch), st))
         gM, gom, _ = E.adjoint(self.M, self.om, T, par, None, self.src, self.h, dLdT, src_t=self.src_t)
+        return gM, gom
+
+    def step(self, k: int = 0, iters: int = 1):
+        """One iteration; returns the device tensor (data loss, lam_G R(G),
+        lam_b R(b), squared gradient norm) of the parameters it started from."""
+        c = self.cfg
+        lib, st = L.lib(), self._stream
+        n = self.nx * self.ny
+        gM, gom = self._data_gradient()
         self.scalars[1:].zero_()
         if c.free_metric and c.lam_G > 0:
             w = (ctypes.c_double * 3)(*G_WEIGHTS)
@@ -146,3 +156,38 @@ class Recovery:
         per-iteration (data loss, lam_G R(G), lam_b R(b), |g|^2)."""
         hist = [self.step(k, iters) for k in range(iters)]
         return torch.stack(hist).cpu()
+
+
+class MultiRecovery(Recovery):
+    """Joint recovery from K fires on one grid (Sec. 5, multi-source recovery):
+    fire f has its own ignition src[f] and observations T_obs[f] with mask
+    mask[f], and the data term is the sum over the fires. The K forward
+    solves and adjoints run as one batched launch (eik_forward_batched,
+    eik_backward_batched over K copies of the parameter planes), then the
+    per-fire gradients are summed; the rest of the iteration is Recovery's."""
+
+    def __init__(self, M0, om0, srcs, h, T_obs, mask, cfg: InverseConfig | None = None):
+        from .batched import Batch
+        super().__init__(M0, om0, srcs[0], h, T_obs[0], mask[0], cfg)
+        self.K = len(srcs)
+        if T_obs.shape[0] != self.K or mask.shape[0] != self.K:
+            raise ValueError("one observation field and one mask per fire")
+        self.T_obs = T_obs.to(device=self.M.device, dtype=self.M.dtype).contiguous()
+        self.mask = mask.to(device=self.M.device, dtype=torch.uint8).contiguous()
+        self.src_all = torch.cat([s.to(device=self.M.device, dtype=torch.int32).reshape(-1) for s in srcs])
+        self.batch = Batch([(self.nx, self.ny, self.h, int(s.numel())) for s in srcs], dtype=self.M.dtype,
+                           device=self.M.device, max_rounds=4096)
+
+    def _data_gradient(self):
+        K, n = self.K, self.nx * self.ny
+        lib, st = L.lib(), self._stream
+        Mp = self.M.reshape(1, -1).expand(K, -1).contiguous().reshape(-1)
+        op = self.om.reshape(1, -1).expand(K, -1).contiguous().reshape(-1)
+        T, par, _, _ = self.batch.forward(Mp, op, self.src_all, tol=self.cfg.tol)
+        dLdT = torch.empty_like(T)
+        L.check("eik_obs_loss", lib.eik_obs_loss(K * n, self.dc, L.ptr(T), L.ptr(self.T_obs), L.ptr(self.mask),
+                                                 L.ptr(dLdT), self._sp(0), L.ptr(self.scratch), st))
+        dM, dom, _, _ = self.batch.backward(Mp, op, T, par, None, self.src_all, dLdT)
+        gM = dM.view(K, 3, self.ny, self.nx).sum(0)
+        gom = dom.view(K, 2, self.ny, self.nx).sum(0)
+        return gM.contiguous(), gom.contiguous()
