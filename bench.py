@@ -61,7 +61,7 @@ WORKLOADS = {
     "inverse": "80x80 FP64 isotropic metric recovery (g = 1 | 2, one central source): 300 projected Adam "
                "iterations of forward + data term + adjoint + TV + step + projections, full and 7 % observations; "
                "joint recovery from 1, 2, 3 and 5 fires with 286 observed nodes each; TV-weight and observation-density "
-               "ablations on noisy observations",
+               "ablations on noisy observations; drift recovery from 1 and 5 fires",
 }
 
 
@@ -216,6 +216,31 @@ def bench_inverse(args):
     ablation = {"noise": "1 % relative Gaussian on the observed times",
                 "tv_weight": {str(lam): recover(1.0, lam, args.seed + 20) for lam in (0.0, 1e-4, 1e-3, 1e-2)},
                 "density": {str(fr): recover(fr, 1e-3, args.seed + 30) for fr in (0.05, 0.1, 0.25, 0.5, 0.75, 1.0)}}
+    # drift recovery (G = I known, constant b = (0.15, 0.08) as a free field from
+    # b = 0, full observations) from 1 and 5 fires, at the paper's step size and
+    # TV weight and at a larger pair
+    Mi = torch.zeros(3, ny, nx, dtype=torch.float64, device=dev)
+    Mi[0] = 1.0
+    Mi[2] = 1.0
+    bt = torch.zeros(2, ny, nx, dtype=torch.float64, device=dev)
+    bt[0], bt[1] = 0.15, 0.08
+    drift = {}
+    for K in (1, 5):
+        srcs, Tos = [], []
+        for (i, j) in sites[:K]:
+            s_ = torch.tensor([j * nx + i], dtype=torch.int32, device=dev)
+            To, _, _, _ = E.solve(Mi, bt, s_, h, tol=0.0, levels=False)
+            srcs.append(s_)
+            Tos.append(To)
+        full = torch.ones(K, ny, nx, dtype=torch.uint8, device=dev)
+        for lr_b, lam_b in ((5e-3, 1e-3), (3e-2, 1e-1)):
+            cfg = V.InverseConfig(lam_b=lam_b, lr_b=lr_b, free_metric=False, free_drift=True)
+            R = V.MultiRecovery(Mi, torch.zeros_like(bt), srcs, h, torch.stack(Tos), full, cfg)
+            R.run(iters)
+            b = R.om.cpu().numpy()
+            drift[f"{K}_fires_lr{lr_b}_tv{lam_b}"] = {
+                "err_b1": float(np.linalg.norm(b[0] - 0.15) / (0.15 * np.sqrt(b[0].size))),
+                "err_b2": float(np.linalg.norm(b[1] - 0.08) / (0.08 * np.sqrt(b[1].size)))}
     r = runs["full"]
     return {
         "metric": "cell-updates/s; fwd+adjoint ms to 1e-5 at 2048^2; learned warm vs cold",
@@ -227,8 +252,10 @@ def bench_inverse(args):
         "recovery": runs,
         "multi_source": multi,
         "ablation": ablation,
+        "drift": drift,
         "paper_rel_err": {"full": 0.056, "obs7pct": 0.212, "multi_source": {"1": 0.186, "2": 0.175, "3": 0.124,
                                                                              "5": 0.101},
+                          "drift": {"err_b1": 0.028, "err_b2": 0.020},
                           "ablation": {"no_tv": 0.224, "tv_1e-3": 0.081,
                                        "density": "about 21 % below 50 % coverage, about 6 % above"},
                           "note": "the paper's own figures, other machine"},
