@@ -480,7 +480,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the method here runs one grid (or one batch of grids) per GPU "
-              "and this build has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+              "and the library has no multi-GPU path (the sharding plan is a design note); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
