@@ -114,19 +114,21 @@ def make_case(seed, n):
     return sc, To, mask, enc
 
 
-def test_encoder_forward_matches_oracle():
+@pytest.mark.parametrize("H,W", [(48, 48), (37, 70), (65, 23)])
+def test_encoder_forward_matches_oracle(H, W):
     from paper_2603_00035_amd.encoder import CONV_NAMES
-    sc, _, _, enc = make_case(21, 48)
+    sc, _, _, enc = make_case(21, 72)
+    X = np.ascontiguousarray(sc.X[:, :H, :W])  # non-square and ragged grids from a larger scene
     # random, larger heads so that the spatial pathway carries weight in (M, omega)
     g = torch.Generator().manual_seed(5)
     for k in range(5):
         enc.params[f"head{k}.w"].copy_(torch.randn(16, generator=g) * 0.2)
-    say("[encoder] forward 48x48")
-    enc.set_inputs(torch.tensor(sc.X), torch.tensor(sc.y))
+    say(f"[encoder] forward {H}x{W}")
+    enc.set_inputs(torch.tensor(X), torch.tensor(sc.y))
     M, om = enc.forward()
     P = {k: torch.tensor(v.numpy(), dtype=torch.float64) for k, v in enc.state_dict().items()}
-    X16 = np.zeros((16, 48, 48))
-    X16[:4] = sc.X
+    X16 = np.zeros((16, H, W))
+    X16[:4] = X
     rM, rom = R.network(P, torch.tensor(X16), torch.tensor(sc.y), enc.alpha, CONV_NAMES)
     loc = enc.local.cpu().numpy()
     rloc = (np.concatenate([rM.detach().numpy(), rom.detach().numpy()]) -
