@@ -42,22 +42,27 @@ int eik_enc_dense(int32_t B, int32_t Cin, int32_t Cout, const float *x, const fl
 int eik_enc_dense_backward(int32_t B, int32_t Cin, int32_t Cout, const float *x, const float *W, const float *y,
                            int32_t relu, const float *dy, float *dx, float *dW, float *db, hipStream_t stream);
 
-/* Combination of the global baseline base[5] = (g11, g12, g22, b1, b2) with
- * the spatial residual planes local [5][n] (FP32) into the metric planes
- * M [3][n] and drift planes omega [2][n] of type dtype (EIK_F32 / EIK_F64):
- *   M[c][k] = base[c] + alpha local[c][k],  omega[c][k] = base[3 + c] + alpha local[3 + c][k],
- * evaluated in double and rounded once to dtype. */
-int eik_enc_combine(int64_t n, int32_t dtype, double alpha, const float *base, const float *local, void *M,
-                    void *omega, hipStream_t stream);
+/* Combination, for B scenes of n nodes each, of the global baselines
+ * base [B][5] (per scene g11, g12, g22, b1, b2) with the spatial residual
+ * planes local [5][B][n] (FP32; the layout 1x1 heads write over the B n
+ * pixels of a batch) into the metric planes M [B][3][n] and drift planes
+ * omega [B][2][n] of type dtype (EIK_F32 / EIK_F64; the packing of the
+ * batched solve):
+ *   M[b][c][k] = base[b][c] + alpha local[c][b][k],
+ *   omega[b][c][k] = base[b][3 + c] + alpha local[3 + c][b][k],
+ * evaluated in double and rounded once to dtype. 1 <= B <= 4096. */
+int eik_enc_combine(int32_t B, int64_t n, int32_t dtype, double alpha, const float *base, const float *local,
+                    void *M, void *omega, hipStream_t stream);
 
-/* Bytes of scratch eik_enc_combine_backward needs (independent of n). */
-size_t eik_enc_scratch_bytes(void);
+/* Bytes of scratch eik_enc_combine_backward needs for B scenes (independent
+ * of n; 0 for B outside 1..4096). */
+size_t eik_enc_scratch_bytes(int32_t B);
 
-/* Backward of eik_enc_combine given dM [3][n] and domega [2][n] (dtype):
- *   dlocal[c][k] = alpha d[c][k]  (written, FP32),
- *   dbase[c] += sum_k d[c][k]     (accumulated; the sum in double, fixed order),
- * with d = (dM, domega) stacked as five planes. */
-int eik_enc_combine_backward(int64_t n, int32_t dtype, double alpha, const void *dM, const void *domega,
+/* Backward of eik_enc_combine given dM [B][3][n] and domega [B][2][n] (dtype):
+ *   dlocal[c][b][k] = alpha d[b][c][k]  (written, FP32),
+ *   dbase[b][c] += sum_k d[b][c][k]      (accumulated; the sum in double, fixed order),
+ * with d = (dM, domega) stacked as five planes per scene. */
+int eik_enc_combine_backward(int32_t B, int64_t n, int32_t dtype, double alpha, const void *dM, const void *domega,
                              float *dlocal, float *dbase, void *scratch, hipStream_t stream);
 
 #ifdef __cplusplus

@@ -123,11 +123,11 @@ def lib():
         L.eik_enc_dense.restype = ctypes.c_int
         L.eik_enc_dense_backward.argtypes = [i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp]
         L.eik_enc_dense_backward.restype = ctypes.c_int
-        L.eik_enc_combine.argtypes = [i64, i32, d, vp, vp, vp, vp, vp]
+        L.eik_enc_combine.argtypes = [i32, i64, i32, d, vp, vp, vp, vp, vp]
         L.eik_enc_combine.restype = ctypes.c_int
-        L.eik_enc_scratch_bytes.argtypes = []
+        L.eik_enc_scratch_bytes.argtypes = [i32]
         L.eik_enc_scratch_bytes.restype = ctypes.c_size_t
-        L.eik_enc_combine_backward.argtypes = [i64, i32, d, vp, vp, vp, vp, vp, vp]
+        L.eik_enc_combine_backward.argtypes = [i32, i64, i32, d, vp, vp, vp, vp, vp, vp]
         L.eik_enc_combine_backward.restype = ctypes.c_int
         L.eik_last_error.argtypes = []
         L.eik_last_error.restype = ctypes.c_char_p

@@ -940,32 +940,36 @@ int eik_enc_dense_backward(int32_t B, int32_t Cin, int32_t Cout, const float *x,
     return EIK_OK;
 }
 
-int eik_enc_combine(int64_t n, int32_t dtype, double alpha, const float *base, const float *local, void *M,
-                    void *omega, hipStream_t stream)
+int eik_enc_combine(int32_t B, int64_t n, int32_t dtype, double alpha, const float *base, const float *local,
+                    void *M, void *omega, hipStream_t stream)
 {
-    if (n < 1) return fail(EIK_EINVAL, "n < 1");
+    if (B < 1 || B > kEncMaxScenes || n < 1) return fail(EIK_EINVAL, "B = %d, n = %lld", B, (long long)n);
     if (!base || !local || !M || !omega) return fail(EIK_EINVAL, "NULL pointer argument");
     if (dtype == EIK_F64)
-        launch_enc_combine<double>(n, alpha, base, local, M, omega, stream);
+        launch_enc_combine<double>(B, n, alpha, base, local, M, omega, stream);
     else if (dtype == EIK_F32)
-        launch_enc_combine<float>(n, alpha, base, local, M, omega, stream);
+        launch_enc_combine<float>(B, n, alpha, base, local, M, omega, stream);
     else
         return fail(EIK_EINVAL, "dtype %d", dtype);
     HIP_OK(hipGetLastError());
     return EIK_OK;
 }
 
-size_t eik_enc_scratch_bytes(void) { return sizeof(double) * kEncPlanes * kInvBlocks; }
+size_t eik_enc_scratch_bytes(int32_t B)
+{
+    if (B < 1 || B > kEncMaxScenes) return 0;
+    return sizeof(double) * (size_t)kEncPlanes * (size_t)B * kInvBlocks;
+}
 
-int eik_enc_combine_backward(int64_t n, int32_t dtype, double alpha, const void *dM, const void *domega,
+int eik_enc_combine_backward(int32_t B, int64_t n, int32_t dtype, double alpha, const void *dM, const void *domega,
                              float *dlocal, float *dbase, void *scratch, hipStream_t stream)
 {
-    if (n < 1) return fail(EIK_EINVAL, "n < 1");
+    if (B < 1 || B > kEncMaxScenes || n < 1) return fail(EIK_EINVAL, "B = %d, n = %lld", B, (long long)n);
     if (!dM || !domega || !dlocal || !dbase || !scratch) return fail(EIK_EINVAL, "NULL pointer argument");
     if (dtype == EIK_F64)
-        launch_enc_combine_backward<double>(n, alpha, dM, domega, dlocal, dbase, (double *)scratch, stream);
+        launch_enc_combine_backward<double>(B, n, alpha, dM, domega, dlocal, dbase, (double *)scratch, stream);
     else if (dtype == EIK_F32)
-        launch_enc_combine_backward<float>(n, alpha, dM, domega, dlocal, dbase, (double *)scratch, stream);
+        launch_enc_combine_backward<float>(B, n, alpha, dM, domega, dlocal, dbase, (double *)scratch, stream);
     else
         return fail(EIK_EINVAL, "dtype %d", dtype);
     HIP_OK(hipGetLastError());

@@ -68,16 +68,24 @@ __global__ __launch_bounds__(kEncThreads) void k_dense_dw(int B, int Cin, int Co
         db[o] += s;
 }
 
+// B scenes: base [B][5], local [5][B][n], M [B][3][n], om [B][2][n]
 template <typename R>
-__global__ __launch_bounds__(kEncThreads) void k_combine(int64_t n, double alpha, const float *__restrict__ base,
+__global__ __launch_bounds__(kEncThreads) void k_combine(int B, int64_t n, double alpha,
+                                                         const float *__restrict__ base,
                                                          const float *__restrict__ local, R *__restrict__ M,
                                                          R *__restrict__ om)
 {
-    double b[kEncPlanes];
-    for (int c = 0; c < kEncPlanes; ++c) b[c] = (double)base[c];
-    for (int64_t k = blockIdx.x * (int64_t)kEncThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kEncThreads) {
-        for (int c = 0; c < 3; ++c) M[c * n + k] = R(b[c] + alpha * (double)local[c * n + k]);
-        for (int c = 0; c < 2; ++c) om[c * n + k] = R(b[3 + c] + alpha * (double)local[(3 + c) * n + k]);
+    const int64_t total = (int64_t)B * n;
+    for (int64_t e = blockIdx.x * (int64_t)kEncThreads + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kEncThreads) {
+        const int b = (int)(e / n);
+        const int64_t k = e - (int64_t)b * n;
+        const float *bb = base + kEncPlanes * b;
+        for (int c = 0; c < 3; ++c)
+            M[(3 * (int64_t)b + c) * n + k] = R((double)bb[c] + alpha * (double)local[((int64_t)c * B + b) * n + k]);
+        for (int c = 0; c < 2; ++c)
+            om[(2 * (int64_t)b + c) * n + k] =
+                R((double)bb[3 + c] + alpha * (double)local[((int64_t)(3 + c) * B + b) * n + k]);
     }
 }
 
@@ -93,36 +101,39 @@ __device__ __forceinline__ double enc_block_sum(double v, double *sh)
     return sh[0];
 }
 
-// grid (kInvBlocks, 5): plane c of (dM, dom); writes alpha d and one double
-// partial per block.
+// grid (kInvBlocks, 5 B): plane c of scene b (blockIdx.y = 5 b + c) of
+// (dM, dom); writes alpha d into dlocal [5][B][n] and one double partial per
+// block.
 template <typename R>
-__global__ __launch_bounds__(kEncThreads) void k_combine_bwd(int64_t n, double alpha, const R *__restrict__ dM,
-                                                             const R *__restrict__ dom, float *__restrict__ dlocal,
-                                                             double *__restrict__ partial)
+__global__ __launch_bounds__(kEncThreads) void k_combine_bwd(int B, int64_t n, double alpha,
+                                                             const R *__restrict__ dM, const R *__restrict__ dom,
+                                                             float *__restrict__ dlocal, double *__restrict__ partial)
 {
     __shared__ double sh[kEncThreads];
-    const int c = blockIdx.y;
-    const R *d = c < 3 ? dM + c * n : dom + (c - 3) * n;
+    const int pc = blockIdx.y, b = pc / kEncPlanes, c = pc - kEncPlanes * b;
+    const R *d = c < 3 ? dM + (3 * (int64_t)b + c) * n : dom + (2 * (int64_t)b + c - 3) * n;
+    float *dl = dlocal + ((int64_t)c * B + b) * n;
     double acc = 0.0;
     for (int64_t k = blockIdx.x * (int64_t)kEncThreads + threadIdx.x; k < n; k += (int64_t)kInvBlocks * kEncThreads) {
         const double v = (double)d[k];
-        dlocal[c * n + k] = (float)(alpha * v);
+        dl[k] = (float)(alpha * v);
         acc += v;
     }
     const double s = enc_block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[c * kInvBlocks + blockIdx.x] = s;
+    if (threadIdx.x == 0) partial[(int64_t)pc * kInvBlocks + blockIdx.x] = s;
 }
 
-// one block per plane: dbase[c] += sum of its partials in a fixed order
+// one block per (scene, plane): dbase[5 b + c] += sum of its partials in a
+// fixed order
 __global__ __launch_bounds__(kEncThreads) void k_combine_bwd_finish(const double *__restrict__ partial,
                                                                     float *__restrict__ dbase)
 {
     __shared__ double sh[kEncThreads];
-    const int c = blockIdx.x;
+    const int pc = blockIdx.x;
     double x = 0.0;
-    for (int b = threadIdx.x; b < kInvBlocks; b += kEncThreads) x += partial[c * kInvBlocks + b];
+    for (int b = threadIdx.x; b < kInvBlocks; b += kEncThreads) x += partial[(int64_t)pc * kInvBlocks + b];
     const double s = enc_block_sum(x, sh);
-    if (threadIdx.x == 0) dbase[c] = (float)((double)dbase[c] + s);
+    if (threadIdx.x == 0) dbase[pc] = (float)((double)dbase[pc] + s);
 }
 
 // ---------------------------------------------------------------------------
@@ -144,27 +155,29 @@ void launch_enc_dense_backward(int B, int Cin, int Cout, const float *x, const f
 }
 
 template <typename R>
-void launch_enc_combine(int64_t n, double alpha, const float *base, const float *local, void *M, void *om,
+void launch_enc_combine(int B, int64_t n, double alpha, const float *base, const float *local, void *M, void *om,
                         hipStream_t st)
 {
-    hipLaunchKernelGGL(k_combine<R>, dim3(blocks_for(n, kEncThreads)), dim3(kEncThreads), 0, st, n, alpha, base,
-                       local, (R *)M, (R *)om);
+    hipLaunchKernelGGL(k_combine<R>, dim3(blocks_for((int64_t)B * n, kEncThreads)), dim3(kEncThreads), 0, st, B, n,
+                       alpha, base, local, (R *)M, (R *)om);
 }
 
 template <typename R>
-void launch_enc_combine_backward(int64_t n, double alpha, const void *dM, const void *dom, float *dlocal,
+void launch_enc_combine_backward(int B, int64_t n, double alpha, const void *dM, const void *dom, float *dlocal,
                                  float *dbase, double *partial, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_combine_bwd<R>, dim3(kInvBlocks, kEncPlanes), dim3(kEncThreads), 0, st, n, alpha,
+    hipLaunchKernelGGL(k_combine_bwd<R>, dim3(kInvBlocks, kEncPlanes * B), dim3(kEncThreads), 0, st, B, n, alpha,
                        (const R *)dM, (const R *)dom, dlocal, partial);
-    hipLaunchKernelGGL(k_combine_bwd_finish, dim3(kEncPlanes), dim3(kEncThreads), 0, st, partial, dbase);
+    hipLaunchKernelGGL(k_combine_bwd_finish, dim3(kEncPlanes * B), dim3(kEncThreads), 0, st, partial, dbase);
 }
 
-template void launch_enc_combine<float>(int64_t, double, const float *, const float *, void *, void *, hipStream_t);
-template void launch_enc_combine<double>(int64_t, double, const float *, const float *, void *, void *, hipStream_t);
-template void launch_enc_combine_backward<float>(int64_t, double, const void *, const void *, float *, float *,
+template void launch_enc_combine<float>(int, int64_t, double, const float *, const float *, void *, void *,
+                                        hipStream_t);
+template void launch_enc_combine<double>(int, int64_t, double, const float *, const float *, void *, void *,
+                                         hipStream_t);
+template void launch_enc_combine_backward<float>(int, int64_t, double, const void *, const void *, float *, float *,
                                                  double *, hipStream_t);
-template void launch_enc_combine_backward<double>(int64_t, double, const void *, const void *, float *, float *,
-                                                  double *, hipStream_t);
+template void launch_enc_combine_backward<double>(int, int64_t, double, const void *, const void *, float *,
+                                                  float *, double *, hipStream_t);
 
 } // namespace eik

@@ -113,19 +113,21 @@ void launch_tie_isotropic(int64_t n, void *M, hipStream_t st);
 template <typename R>
 void launch_param_step(int64_t n, int method, void *p, const void *g, void *m, void *v, double lr, double b1,
                        double b2, double eps, int t, double max_norm, const double *grad_sq, hipStream_t st);
-// Covariate encoder passes (eik_encoder.hip); the combination's backward uses
-// kEncPlanes * kInvBlocks double partials in the caller's scratch.
+// Covariate encoder passes (eik_encoder.hip); the combination's backward over B
+// scenes uses B * kEncPlanes * kInvBlocks double partials in the caller's
+// scratch.
 constexpr int kEncPlanes = 5;
 void launch_enc_dense(int B, int Cin, int Cout, const float *x, const float *W, const float *b, int relu, float *y,
                       hipStream_t st);
 void launch_enc_dense_backward(int B, int Cin, int Cout, const float *x, const float *W, const float *y, int relu,
                                const float *dy, float *dx, float *dW, float *db, hipStream_t st);
 template <typename R>
-void launch_enc_combine(int64_t n, double alpha, const float *base, const float *local, void *M, void *om,
+void launch_enc_combine(int B, int64_t n, double alpha, const float *base, const float *local, void *M, void *om,
                         hipStream_t st);
 template <typename R>
-void launch_enc_combine_backward(int64_t n, double alpha, const void *dM, const void *dom, float *dlocal,
+void launch_enc_combine_backward(int B, int64_t n, double alpha, const void *dM, const void *dom, float *dlocal,
                                  float *dbase, double *partial, hipStream_t st);
+constexpr int kEncMaxScenes = 4096;
 void launch_cast_f64_f32(int64_t n, const double *src, float *dst, hipStream_t st);
 void launch_cast_f32_f64(int64_t n, const float *src, double *dst, hipStream_t st);
 void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_grid, int n_tiles, hipStream_t st);

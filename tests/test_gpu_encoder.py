@@ -61,43 +61,49 @@ def test_dense_forward_and_backward(B, Cin, Cout, relu):
     assert np.all(np.abs(db.cpu().numpy() - (db0 + rdb)) <= (B + 1) * 2.0 ** -23 * (np.abs(g).sum(0) + np.abs(db0)))
 
 
-@pytest.mark.parametrize("dtype,n", [(torch.float32, 4097), (torch.float64, 1), (torch.float64, 300 * 257)])
-def test_combine_forward_and_backward(dtype, n):
+@pytest.mark.parametrize("dtype,B,n", [(torch.float32, 1, 4097), (torch.float64, 1, 1), (torch.float64, 1, 300 * 257),
+                                       (torch.float32, 3, 1000), (torch.float64, 5, 257)])
+def test_combine_forward_and_backward(dtype, B, n):
+    """B scenes: base [B][5], local [5][B][n], M [B][3][n], omega [B][2][n];
+    the oracle runs scene by scene."""
     L = lib()
-    rng = np.random.default_rng(n)
-    base = rng.normal(size=5).astype(np.float32).astype(np.float64)
-    local = rng.normal(size=(5, n)).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(n + B)
+    base = rng.normal(size=(B, 5)).astype(np.float32).astype(np.float64)
+    local = rng.normal(size=(5, B, n)).astype(np.float32).astype(np.float64)
     alpha = 0.37
-    say(f"[encoder] combine n={n} {dtype}")
-    M = torch.empty(3, n, dtype=dtype, device="cuda")
-    om = torch.empty(2, n, dtype=dtype, device="cuda")
+    say(f"[encoder] combine B={B} n={n} {dtype}")
+    M = torch.empty(B, 3, n, dtype=dtype, device="cuda")
+    om = torch.empty(B, 2, n, dtype=dtype, device="cuda")
     st = L.stream_handle(torch.device("cuda"))
     based, locald = dev(base), dev(local)  # referenced until the kernel has run
-    L.check("combine", L.lib().eik_enc_combine(n, L.dtype_code(M), alpha, L.ptr(based), L.ptr(locald),
+    L.check("combine", L.lib().eik_enc_combine(B, n, L.dtype_code(M), alpha, L.ptr(based), L.ptr(locald),
                                                L.ptr(M), L.ptr(om), st))
-    rM, rom = R.combine(base, local, alpha)
-    ref = np.concatenate([rM, rom])
-    got = np.concatenate([M.cpu().numpy(), om.cpu().numpy()]).astype(np.float64)
+    got = np.concatenate([M.cpu().numpy(), om.cpu().numpy()], axis=1).astype(np.float64)
     # one rounding of the result, plus the product's rounding in the reference
     # (the kernel fuses the multiply-add), relative to the terms
     ulp = 2.0 ** -23 if dtype == torch.float32 else 2.0 ** -52
-    terms = np.abs(base)[:, None] + alpha * np.abs(local)
-    assert np.all(np.abs(got - ref) <= ulp * np.abs(ref) + 2.0 ** -52 * terms + 1e-300)
-    d = rng.normal(size=(5, n))
+    for b in range(B):
+        rM, rom = R.combine(base[b], local[:, b], alpha)
+        ref = np.concatenate([rM, rom])
+        terms = np.abs(base[b])[:, None] + alpha * np.abs(local[:, b])
+        assert np.all(np.abs(got[b] - ref) <= ulp * np.abs(ref) + 2.0 ** -52 * terms + 1e-300)
+    d = rng.normal(size=(B, 5, n))
     if dtype == torch.float32:
         d = d.astype(np.float32).astype(np.float64)
-    dM, dom = dev(d[:3], dtype), dev(d[3:], dtype)
-    dl = torch.empty(5, n, device="cuda")
-    dbase0 = rng.normal(size=5).astype(np.float32)
+    dM, dom = dev(d[:, :3], dtype), dev(d[:, 3:], dtype)
+    dl = torch.empty(5, B, n, device="cuda")
+    dbase0 = rng.normal(size=(B, 5)).astype(np.float32)
     dbase = dev(dbase0)
-    scratch = torch.empty(L.lib().eik_enc_scratch_bytes(), dtype=torch.uint8, device="cuda")
-    L.check("combine_bwd", L.lib().eik_enc_combine_backward(n, L.dtype_code(dM), alpha, L.ptr(dM), L.ptr(dom),
+    scratch = torch.empty(L.lib().eik_enc_scratch_bytes(B), dtype=torch.uint8, device="cuda")
+    L.check("combine_bwd", L.lib().eik_enc_combine_backward(B, n, L.dtype_code(dM), alpha, L.ptr(dM), L.ptr(dom),
                                                             L.ptr(dl), L.ptr(dbase), L.ptr(scratch), st))
-    rdl, rdb = R.combine_backward(d[:3], d[3:], alpha)
-    assert np.array_equal(dl.cpu().numpy(), rdl.astype(np.float32))
-    tot = dbase0 + rdb
-    bound = n * 2.0 ** -52 * np.abs(d).sum(1) + 2.0 ** -23 * np.abs(tot)
-    assert np.all(np.abs(dbase.cpu().numpy() - tot) <= bound)
+    dlg, dbg = dl.cpu().numpy(), dbase.cpu().numpy()
+    for b in range(B):
+        rdl, rdb = R.combine_backward(d[b, :3], d[b, 3:], alpha)
+        assert np.array_equal(dlg[:, b], rdl.astype(np.float32))
+        tot = dbase0[b] + rdb
+        bound = n * 2.0 ** -52 * np.abs(d[b]).sum(1) + 2.0 ** -23 * np.abs(tot)
+        assert np.all(np.abs(dbg[b] - tot) <= bound)
 
 
 def make_case(seed, n):
@@ -166,6 +172,40 @@ def test_hybrid_gradient_matches_oracle():
         say(f"[encoder]   d{k}: rel-L2 {e:.2e}")
         assert e <= 1e-2, k
     say(f"[encoder] worst parameter-gradient rel-L2 {worst:.2e}")
+
+
+def test_batched_hybrid_gradient_is_the_sum_over_scenes():
+    """Three scenes in one step (batched network, one batched solve and
+    adjoint) against the sum of the oracle's per-scene hybrid gradients."""
+    from paper_2603_00035_amd.encoder import CONV_NAMES, Trainer
+    cases = [make_case(s, 40) for s in (31, 32, 33)]
+    enc = cases[0][3]
+    g = torch.Generator().manual_seed(7)
+    for k in range(5):
+        enc.params[f"head{k}.w"].copy_(torch.randn(16, generator=g) * 0.1)
+    say("[encoder] batched hybrid gradient, 3 scenes of 40x40")
+    tr = Trainer(enc, tol=0.0)
+    enc.zero_grads()
+    X = torch.stack([torch.tensor(c[0].X) for c in cases])
+    y = torch.stack([torch.tensor(c[0].y) for c in cases])
+    srcs = [torch.tensor(c[0].src_idx, dtype=torch.int32, device="cuda") for c in cases]
+    To = dev(np.stack([c[1] for c in cases]))
+    mk = dev(np.stack([c[2] for c in cases]), torch.uint8)
+    T, s = tr.gradients_batch(X, y, srcs, cases[0][0].h, To, mk)
+    params = {k: v.numpy().astype(np.float64) for k, v in enc.state_dict().items()}
+    tot, Ltot = None, 0.0
+    for sc, Tc, mask, _ in cases:
+        X16 = np.zeros((16, 40, 40))
+        X16[:4] = sc.X
+        go, Lo, _, _ = R.hybrid_gradient(params, X16, sc.y, enc.alpha, CONV_NAMES, sc.h, sc.src_idx, np.zeros(1), Tc,
+                                         mask.astype(bool))
+        tot = go if tot is None else {k: tot[k] + go[k] for k in tot}
+        Ltot += Lo
+    say(f"[encoder] data term GPU {float(s[0]):.6e} oracle {Ltot:.6e}")
+    assert abs(float(s[0]) - Ltot) <= 1e-3 * Ltot
+    worst = max(rel_l2([enc.grads[k].cpu().numpy()], [tot[k]]) for k in tot)
+    say(f"[encoder] worst parameter-gradient rel-L2 {worst:.2e}")
+    assert worst <= 1e-2
 
 
 def test_training_lowers_the_loss():
