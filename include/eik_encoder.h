@@ -61,7 +61,8 @@ size_t eik_enc_scratch_bytes(int32_t B);
 /* Backward of eik_enc_combine given dM [B][3][n] and domega [B][2][n] (dtype):
  *   dlocal[c][b][k] = alpha d[b][c][k]  (written, FP32),
  *   dbase[b][c] += sum_k d[b][c][k]      (accumulated; the sum in double, fixed order),
- * with d = (dM, domega) stacked as five planes per scene. */
+ * with d = (dM, domega) stacked as five planes per scene. scratch holds at
+ * least eik_enc_scratch_bytes(B) bytes of device memory. */
 int eik_enc_combine_backward(int32_t B, int64_t n, int32_t dtype, double alpha, const void *dM, const void *domega,
                              float *dlocal, float *dbase, void *scratch, hipStream_t stream);
 
