@@ -172,16 +172,30 @@ __global__ __launch_bounds__(64) void k_wgrad(WgradArgs a)
 // ---------------------------------------------------------------------------
 // Elementwise and small kernels.
 // ---------------------------------------------------------------------------
-__global__ void k_bias_grad(int64_t npix, const bf16 *__restrict__ dy, int cs, int co, int C, float *__restrict__ db)
+// db[c] += sum over pixels of dy(p, c). A block of 256 threads takes a chunk
+// of kBiasChunk pixels as R = 256 / C pixel lanes times C channels (reads of
+// one pixel's channels are contiguous), adds the lanes in shared memory, and
+// adds one value per channel to db.
+constexpr int kBiasChunk = 128;
+__global__ __launch_bounds__(256) void k_bias_grad(int64_t npix, const bf16 *__restrict__ dy, int cs, int co, int C,
+                                                   float *__restrict__ db)
 {
-    const int c = threadIdx.x;
-    if (c >= C) return;
-    const int64_t chunk = 1024;
-    const int64_t pb = (int64_t)blockIdx.x * chunk;
-    const int64_t pe = pb + chunk < npix ? pb + chunk : npix;
+    __shared__ float sh[256];
+    const int t = threadIdx.x, R = 256 / C;
+    const int c = t % C, r = t / C;
     float s = 0.f;
-    for (int64_t p = pb; p < pe; ++p) s += bf2f(dy[p * cs + co + c]);
-    atomicAdd(&db[c], s);
+    if (r < R) {
+        const int64_t pb = (int64_t)blockIdx.x * kBiasChunk;
+        const int64_t pe = pb + kBiasChunk < npix ? pb + kBiasChunk : npix;
+        for (int64_t p = pb + r; p < pe; p += R) s += bf2f(dy[p * cs + co + c]);
+    }
+    sh[t] = s;
+    __syncthreads();
+    if (t < C) {
+        float tot = 0.f;
+        for (int k = 0; k < R; ++k) tot += sh[k * C + t];
+        atomicAdd(&db[t], tot);
+    }
 }
 
 __global__ void k_relu_mask(int64_t n, const bf16 *__restrict__ y, int ycs, int yco, bf16 *__restrict__ g, int gcs,
@@ -281,9 +295,22 @@ __global__ void k_head_bwd(int64_t n, const bf16 *__restrict__ x, int cs, int co
         sdb += __shfl_xor(sdb, off);
         for (int c = 0; c < 16; ++c) sdw[c] += __shfl_xor(sdw[c], off);
     }
+    // the block's waves add their sums in shared memory; one atomic per value
+    // and block (instead of per wave) keeps the contention on the 17 targets low
+    __shared__ float sw[4][17];
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(db, sdb);
-        for (int c = 0; c < C && c < 16; ++c) atomicAdd(&dw[c], sdw[c]);
+        for (int c = 0; c < 16; ++c) sw[wv][c] = sdw[c];
+        sw[wv][16] = sdb;
+    }
+    __syncthreads();
+    if (threadIdx.x < 17) {
+        const int c = threadIdx.x;
+        const float v = sw[0][c] + sw[1][c] + sw[2][c] + sw[3][c];
+        if (c == 16)
+            atomicAdd(db, v);
+        else if (c < C)
+            atomicAdd(&dw[c], v);
     }
 }
 
@@ -432,8 +459,8 @@ int eiku_conv_wgrad(int32_t mode, int32_t B, int32_t H, int32_t W, const uint16_
 int eiku_bias_grad(int64_t npix, const uint16_t *dy, int32_t cs, int32_t co, int32_t C, float *db, hipStream_t st)
 {
     if (npix < 1 || C < 1 || C > 256 || !dy || !db || co + C > cs) return -1;
-    hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)((npix + 1023) / 1024)), dim3(256), 0, st, npix, dy, cs, co, C,
-                       db);
+    hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)((npix + kBiasChunk - 1) / kBiasChunk)), dim3(256), 0, st, npix, dy,
+                       cs, co, C, db);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -212,3 +212,43 @@ def test_network_gradient_matches_finite_differences_of_its_loss():
         an = float(net.grads[key].view(-1)[idx])
         say(f"  {key}[{idx}]: analytic {an:.4e} fd {fd1:.4e} / {fd2:.4e}")
         assert abs(an - fd1) <= 3 * abs(fd1 - fd2) + 0.1 * abs(fd1) + 1e-5
+
+
+@pytest.mark.parametrize("npix,cs,co,C", [(4096, 64, 0, 64), (65536 + 37, 32, 16, 16), (1000, 128, 0, 128),
+                                          (777, 48, 0, 48), (5, 16, 0, 16)])
+def test_bias_gradient_matches_the_sum(npix, cs, co, C):
+    """db[c] += sum_p dy(p, c) over a channel slice, accumulated onto a
+    nonzero start; FP32 partial sums in any order are within
+    npix 2^-24 sum|dy| of the exact sum."""
+    rng = np.random.default_rng(npix + C)
+    dy = U.bf16_round(rng.standard_normal((npix, cs)))
+    db0 = rng.standard_normal(C).astype(np.float32)
+    db = torch.tensor(db0, device="cuda")
+    say(f"[unet] bias grad npix={npix} slice {co}:{co + C} of {cs}")
+    assert lib().eiku_bias_grad(npix, P(to_dev_bf16(dy)), cs, co, C, P(db), st()) == 0
+    ref = db0 + dy[:, co:co + C].sum(0)
+    tol = (npix + 1) * 2.0 ** -23 * (np.abs(dy[:, co:co + C]).sum(0) + np.abs(db0)) + 1e-30
+    assert np.all(np.abs(db.cpu().numpy() - ref) <= tol)
+
+
+@pytest.mark.parametrize("npix,C", [(4096, 16), (65536 * 2 + 13, 16), (300, 7)])
+def test_head_backward_matches_its_definition(npix, C):
+    """dx(p, c) = w[c] g(p) (bfloat16), dw[c] += sum_p g(p) x(p, c),
+    db += sum_p g(p)."""
+    rng = np.random.default_rng(npix * 3 + C)
+    x = U.bf16_round(rng.standard_normal((npix, 16)))
+    w = rng.standard_normal(C).astype(np.float32)
+    g = rng.standard_normal(npix).astype(np.float32)
+    dx = torch.zeros(npix * 16, dtype=torch.int16, device="cuda")
+    dw0 = rng.standard_normal(C).astype(np.float32)
+    dw, dbt = torch.tensor(dw0, device="cuda"), torch.zeros(1, device="cuda")
+    say(f"[unet] head backward npix={npix} C={C}")
+    assert lib().eiku_head_bwd(npix, P(to_dev_bf16(x)), 16, 0, C, P(to_dev(w)), P(to_dev(g)), P(dx), 16, 0, P(dw),
+                               P(dbt), st()) == 0
+    dxg = from_dev_bf16(dx, (npix, 16))[:, :C]
+    ref_dx = U.bf16_round(g.astype(np.float64)[:, None] * w.astype(np.float64)[None, :])
+    assert np.array_equal(dxg, ref_dx)
+    gx = g.astype(np.float64)[:, None] * x[:, :C]
+    ref_dw = dw0 + gx.sum(0)
+    assert np.all(np.abs(dw.cpu().numpy() - ref_dw) <= (npix + 1) * 2.0 ** -23 * (np.abs(gx).sum(0) + np.abs(dw0)))
+    assert abs(float(dbt.cpu()[0]) - g.astype(np.float64).sum()) <= (npix + 1) * 2.0 ** -23 * np.abs(g).sum()
