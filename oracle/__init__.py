@@ -86,7 +86,12 @@ def _ip(a):
 def forward(prob, mode="gs", one_point_only=False, tol=0.0, max_sweeps=100000, T_init=None):
     """Solve to stationarity (tol=0) or to the relative-change tolerance.
 
+    mode "gs" (Gauss-Seidel four-ordering sweeps), "jacobi", or "gs_f32": the
+    Gauss-Seidel sweeps with every stored value rounded to single precision
+    (updates evaluated exactly in double), the best field a solve that stores
+    T in single precision can reach; for measuring that storage's effect only.
     Returns (T[ny,nx], sweeps, status) with status 0 when converged."""
+    modes = {"gs": 0, "jacobi": 1, "gs_f32": 2}
     M, om = _d(prob.M), _d(prob.omega)
     src = np.ascontiguousarray(prob.src_idx, np.int32)
     st = _d(prob.src_t)
@@ -94,7 +99,7 @@ def forward(prob, mode="gs", one_point_only=False, tol=0.0, max_sweeps=100000, T
     sw = ctypes.c_int(0)
     Ti = None if T_init is None else _d(T_init)
     status = lib().ora_forward(prob.nx, prob.ny, prob.h, _dp(M), _dp(om), src.size, _ip(src), _dp(st),
-                               None if Ti is None else _dp(Ti), 1 if mode == "jacobi" else 0,
+                               None if Ti is None else _dp(Ti), modes[mode],
                                int(one_point_only), int(max_sweeps), float(tol), _dp(T), ctypes.byref(sw))
     return T, sw.value, status
 

@@ -170,6 +170,12 @@ static int counts_as_change(double a, double b, double tol)
  * mode 1: Jacobi iteration (every node from the previous iterate; App.
  *         comparisons, the Jacobi baseline); converged after one iteration
  *         with no change.
+ * mode 2: the Gauss-Seidel sweeps of mode 0 with every stored value rounded
+ *         to the nearest single-precision number (each update is still
+ *         evaluated exactly in double precision): the fixed point a solve
+ *         that stores T in single precision can reach at best. Used only to
+ *         measure that storage's effect on the adjoint, never as a parity
+ *         reference.
  * T_init (optional) replaces the +inf initialisation; the update overwrites.
  * Returns 0 when converged, 1 when max_sweeps was reached. */
 int ora_forward(int nx, int ny, double h, const double *M, const double *om, int n_src,
@@ -211,6 +217,7 @@ int ora_forward(int nx, int ny, double h, const double *M, const double *om, int
                 size_t c = (size_t)j * nx + i;
                 if (is_src[c]) continue;
                 double t = local_update(&f, T, i, j, one_point_only, NULL);
+                if (mode == 2) t = (double)(float)t;
                 changed |= counts_as_change(T[c], t, tol);
                 T[c] = t;
             }
