@@ -14,12 +14,16 @@ under "compare".
 Workload (default): 2048 x 2048 stress case -- eigenvalue ratio 10, drift norm
 up to 0.9, 4 sharp-edged regions with rotated principal directions, 16 random
 sources, parameters rounded to FP32; the loss target is a smooth random field
-in [0, 3] that no solver produced. Inputs are seeded synthetic fields resident
-in HBM before timing starts.
+in [0, 3] that no solver produced (the target must not come from the HIP path,
+since the oracle's gradient uses it too). Inputs are seeded synthetic fields
+resident in HBM before timing starts.
 
 Prints one JSON line: value = cell-updates per second over the timed steps
 (all local-update evaluations of both forward phases divided by the whole step
-time, adjoint included); ms_per_step = forward + adjoint ms; roofline =
+time, adjoint included); ms_per_step = wall-clock time of the timed steps over
+their count; per_step = each step's forward and adjoint HIP-event times and the
+rounds of each phase, with the median, min and max of the step times beside
+it (fwd_ms and adj_ms are the medians); roofline =
 achieved algorithmic bandwidth of the dominant kernel, the FP32
 concurrent-direction cold-start sweep (28 bytes per FP32 cell-update), against
 the 8 TB/s HBM peak, its launches timed with HIP events on the stream they run
@@ -93,22 +97,54 @@ def traffic_bytes():
     return d.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    """CPU model name of this host (from /proc/cpuinfo) and its logical CPU count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def pinned(fn):
+    """Run fn() with this process pinned to one core it may use (the oracle is
+    single-threaded); the previous affinity is restored afterwards."""
+    prev = os.sched_getaffinity(0)
+    core = min(prev)
+    os.sched_setaffinity(0, {core})
+    try:
+        return fn(), core
+    finally:
+        os.sched_setaffinity(0, prev)
+
+
 def cpu_baseline(prob, tol):
     import numpy as np
 
     import oracle
     q = prob.rounded(np.float32)
-    t0 = time.perf_counter()
-    T, sweeps, _ = oracle.forward(q, tol=tol)
-    par, _ = oracle.parents_levels(q, T)
-    g = np.zeros_like(T)
-    m = np.isfinite(T)
-    g[m] = 1.0 / m.sum()
-    oracle.vjp(q, T, par, g)
-    dt = time.perf_counter() - t0
+
+    def run():
+        t0 = time.perf_counter()
+        T, sweeps, _ = oracle.forward(q, tol=tol)
+        par, _ = oracle.parents_levels(q, T)
+        g = np.zeros_like(T)
+        m = np.isfinite(T)
+        g[m] = 1.0 / m.sum()
+        oracle.vjp(q, T, par, g)
+        return T, sweeps, time.perf_counter() - t0
+
+    (T, sweeps, dt), core = pinned(run)
+    model, ncpu = host_cpu()
     return {"value": prob.n * sweeps / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_cpu_count": ncpu, "pinned_core": core,
             "sample": f"one full {prob.nx}x{prob.ny} solve to {tol:g} ({sweeps} Gauss-Seidel sweeps, FP64) "
-                      f"+ stencil/level pass + VJP, single thread, {dt:.1f} s"}, T
+                      f"+ stencil/level pass + VJP, single thread pinned to core {core}, {dt:.1f} s"}, T
 
 
 def bench_warm(args):
@@ -549,7 +585,7 @@ def main():
         loss = torch.zeros(1, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
 
-        def step(sink, t_ev):
+        def step(sink, adj_sink, t_ev):
             # one pass of the hot path, every stage a library call: projection,
             # forward, data term, adjoint, projection VJP
             t_ev[0].record()
@@ -564,22 +600,22 @@ def main():
             dLdT = V.obs_loss(T, target, mask_u8, scratch, loss)
             t_ev[1].record()
             if mixed:
-                gMp, gomp, _ = E.adjoint_mixed(Mp, omp, T, par, src, prob.h, dLdT, ws=ws)
+                gMp, gomp, _ = E.adjoint_mixed(Mp, omp, T, par, src, prob.h, dLdT, ws=ws, stats_out=adj_sink)
             else:
-                gMp, gomp, _ = E.adjoint(Mp, omp, T, par, None, src, prob.h, dLdT, ws=ws)
+                gMp, gomp, _ = E.adjoint(Mp, omp, T, par, None, src, prob.h, dLdT, ws=ws, stats_out=adj_sink)
             gM, gom = E.project_backward(M0, om0, gMp, gomp)
             t_ev[2].record()
             return T, gM, gom
 
         for _ in range(args.warmup):
-            step([], [torch.cuda.Event(enable_timing=True) for _ in range(3)])
+            step([], [], [torch.cuda.Event(enable_timing=True) for _ in range(3)])
         torch.cuda.synchronize()
-        sink = []
+        sink, adj_sink = [], []
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            T, gM, gom = step(sink, evs[k])
+            T, gM, gom = step(sink, adj_sink, evs[k])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         assert all(s.converged for s in sink[(1 if precision == "mixed" else 0)::(2 if precision == "mixed" else 1)]), \
@@ -589,9 +625,16 @@ def main():
         # phase of each mixed solve
         s32 = sink[0::2] if precision == "mixed" else sink
         s64 = sink[1::2] if precision == "mixed" else []
-        return dict(wall=wall, sink=sink, s32=s32, s64=s64,
-                    fwd_ms=float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
-                    adj_ms=float(np.mean([e[1].elapsed_time(e[2]) for e in evs])),
+        fwd = [e[0].elapsed_time(e[1]) for e in evs]
+        adj = [e[1].elapsed_time(e[2]) for e in evs]
+        # one record per timed step: event times and the round counts of each
+        # phase (FP32 rounds, FP64 rounds for the mixed path, adjoint rounds)
+        per = len(sink) // args.steps
+        steps = [{"fwd_ms": round(fwd[k], 3), "adj_ms": round(adj[k], 3), "step_ms": round(fwd[k] + adj[k], 3),
+                  "fwd_rounds": [s.rounds for s in sink[per * k:per * (k + 1)]],
+                  "adj_rounds": adj_sink[k].rounds} for k in range(args.steps)]
+        return dict(wall=wall, sink=sink, s32=s32, s64=s64, steps=steps,
+                    fwd_ms=float(np.median(fwd)), adj_ms=float(np.median(adj)),
                     T=T.detach().double().cpu().numpy(), gM=gM.double().cpu().numpy(), gom=gom.double().cpu().numpy())
 
     head = run(args.precision)
@@ -599,9 +642,12 @@ def main():
 
     def figures(r):
         updates = sum(s.cell_updates for s in r["sink"])
+        ev = [st["step_ms"] for st in r["steps"]]
         return dict(value=updates / r["wall"], ms_per_step=1e3 * r["wall"] / args.steps, fwd_ms=round(r["fwd_ms"], 3),
                     adj_ms=round(r["adj_ms"], 3), sweeps_per_cell=round(updates / args.steps / prob.n, 2),
-                    rounds=[s.rounds for s in r["sink"][-(2 if r["s64"] else 1):]])
+                    rounds=[s.rounds for s in r["sink"][-(2 if r["s64"] else 1):]],
+                    step_ms_median=round(float(np.median(ev)), 3), step_ms_max=round(float(np.max(ev)), 3),
+                    step_ms_min=round(float(np.min(ev)), 3))
 
     fh = figures(head)
     # dominant kernel: the FP32 concurrent-direction cold-start sweep (the
@@ -654,6 +700,8 @@ def main():
         "adj_ms": fh["adj_ms"],
         "sweeps_per_cell": fh["sweeps_per_cell"],
         "rounds": fh["rounds"],
+        "step_ms_median": fh["step_ms_median"], "step_ms_min": fh["step_ms_min"], "step_ms_max": fh["step_ms_max"],
+        "per_step": head["steps"],
         "roofline": roof,
         "cpu_baseline": None,
     }

@@ -252,8 +252,11 @@ struct LaunchTimer {
 // Without a host check (sync = false) exactly `budget` rounds are enqueued;
 // rounds after convergence find no flagged tile and exit at once. With host
 // checks, the first check comes after `first_batch` rounds (a phase that
-// starts near its fixed point settles in one or two), the others every
-// `per_check` rounds. round_fn(act_in, act_out, count_next) enqueues one round.
+// starts near its fixed point settles in one or two), else after `per_check`
+// rounds (the tuned estimate of a whole phase); later checks come every
+// per_check / 8 rounds (at least 2), so a phase that needs a few rounds more
+// than the estimate enqueues a few more launches, not another full batch.
+// round_fn(act_in, act_out, count_next) enqueues one round.
 template <typename F>
 int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int budget, int per_check, bool sync,
                hipStream_t st, F round_fn, int *rounds_done, bool *converged, LaunchTimer *timer = nullptr,
@@ -261,9 +264,10 @@ int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int bud
 {
     int r = first;
     const int end = std::min(first + budget, kMaxRounds);
+    const int later = std::max(2, per_check / 8);
     *converged = false;
     while (r < end) {
-        const int want = (r == first && first_batch > 0) ? std::min(first_batch, per_check) : per_check;
+        const int want = r == first ? (first_batch > 0 ? std::min(first_batch, per_check) : per_check) : later;
         const int batch = sync ? std::min(want, end - r) : end - r;
         if (timer && timer->on) timer->before(st);
         for (int b = 0; b < batch; ++b, ++r)
@@ -548,7 +552,7 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
     if (rc) return rc;
     const bool sync = single || stats != nullptr;
 
-    (void)level; // the adjoint orders each tile by its own dependency levels
+    (void)level; // the relaxation needs no levels: each tile sweeps until its equations hold exactly
     launch_fill_u64(w.ctr + kCtrAdjPending, 1, st);
     launch_adj_prep<R>(a, M, om, T, parent, w.w1, w.lam, st);
     int rounds = 0;
