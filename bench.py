@@ -70,8 +70,8 @@ WORKLOADS = {
 
 
 PRECISIONS = {
-    "mixed": "FP32 restricted-candidate sweeps until no change exceeds tol, FP64 full-update sweeps from that field to tol, adjoint with FP64 weights and parameter "
-             "derivatives and an FP32 relaxation",
+    "mixed": "FP32 restricted-candidate sweeps until no change exceeds tol, FP64 full-update sweeps from that field until "
+             "no change exceeds min(tol, 3e-7), adjoint with FP64 weights and parameter derivatives and an FP32 relaxation",
     "f32": "FP32 throughout",
 }
 
@@ -591,8 +591,8 @@ def main():
             t_ev[0].record()
             Mp, omp = E.project(M0, om0)
             if mixed:
-                T, par, _, st = E.solve_mixed(Mp, omp, src, prob.h, tol=args.tol, levels=False, ws=ws,
-                                              time_kernels=True)
+                T, par, _, st = E.solve_mixed(Mp, omp, src, prob.h, tol=min(args.tol, E.MIXED_FP64_TOL),
+                                              tol32=args.tol, levels=False, ws=ws, time_kernels=True)
                 sink.extend(st)
             else:
                 T, par, _, st = E.solve(Mp, omp, src, prob.h, tol=args.tol, levels=False, ws=ws, time_kernels=True)

@@ -127,7 +127,16 @@ typedef struct eik_tuning {
     int32_t full_waves;       /* waves per tile in the round scheduler's full-update visits when no levels are
                                  asked for: 1 (the four directions in turn, node_lanes lanes per node) or 4
                                  (one direction per wave, one lane per node, all at once); default 4 */
+    int32_t adjoint_mode;     /* EIK_ADJ_RELAX: tiles relax the adjoint equations by directional sweeps
+                                 (default); EIK_ADJ_LEVELS: the nodes are counting-sorted by dependency level
+                                 and solved level by level from the largest (needs the forward's levels) */
+    int32_t level_mode;       /* with levels asked for: EIK_LEVELS_CARRIED: the sweeps carry them (one wave per
+                                 tile; default); EIK_LEVELS_AFTER: the sweeps run as without levels and level
+                                 rounds compute them afterwards from the active stencils */
 } eik_tuning;
+
+enum { EIK_ADJ_RELAX = 1, EIK_ADJ_LEVELS = 2 };
+enum { EIK_LEVELS_CARRIED = 1, EIK_LEVELS_AFTER = 2 };
 
 enum { EIK_SCHED_ROUNDS = 1, EIK_SCHED_QUEUE = 2 };
 
@@ -186,13 +195,22 @@ int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega
 /* Adjoint (Sec. 3.3, Alg. backward): given dL/dT and the saved state
  * (M, omega, T, parent) of eik_forward, writes dL/dM [3][ny][nx]
  * (derivatives with respect to the stored m11, m12, m22), dL/domega
- * [2][ny][nx] and dL/dt_src [n_src]. Each tile relaxes the triangular
- * adjoint equations with directional line sweeps until they hold exactly;
- * each node gathers from the nodes it feeds (no atomics). Unreached nodes and the
- * parameters of source nodes get zero gradient. Tiles exchange their border
- * adjoints between rounds (the call synchronises the stream to test that no
- * border changed); stats, when given, receives the round count. `level` is
- * not read and may be NULL. */
+ * [2][ny][nx] and dL/dt_src [n_src]. The adjoint equations
+ * lambda_i = dL/dT_i + sum over the nodes j that i feeds of (dT_j/dT_i) lambda_j
+ * are triangular in the causal order; each node gathers from the nodes it
+ * feeds (no atomics in the arithmetic). Two schedules (tuning->adjoint_mode):
+ *   EIK_ADJ_RELAX (default): each tile relaxes its equations with directional
+ *     line sweeps until they hold exactly, and tiles exchange their border
+ *     adjoints between rounds (the call synchronises the stream to test that
+ *     no border changed; stats, when given, receives the round count);
+ *     `level` is not read and may be NULL;
+ *   EIK_ADJ_LEVELS: Alg. backward's back-substitution in level order: the
+ *     reached nodes of each grid are counting-sorted by `level` (the
+ *     forward's dependency levels, required: EIK_EINVAL when NULL) and solved
+ *     level by level from the largest, one workgroup per grid; no host
+ *     synchronisation.
+ * Both give the same lambda (the same sums in the same order). Unreached
+ * nodes and the parameters of source nodes get zero gradient. */
 int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
                  const uint8_t *parent, const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega,
                  void *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats,
@@ -204,10 +222,12 @@ int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void 
  * sum of weight-times-lambda terms, which FP32 carries to about 1e-6
  * relative; the sensitivity of the gradient to T sits in the weights, which
  * stay FP64-derived). All real arrays double, laid out as in eik_backward;
- * the workspace comes from eik_mixed_workspace_bytes. Errors as eik_backward. */
+ * `level` as in eik_backward (read only by EIK_ADJ_LEVELS); the workspace
+ * comes from eik_mixed_workspace_bytes. Errors as eik_backward. */
 int eik_backward_mixed(const eik_grid *grid, const double *M, const double *omega, const double *T,
-                       const uint8_t *parent, const double *dLdT, double *dLdM, double *dLdomega, double *dLdsrc,
-                       void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
+                       const uint8_t *parent, const int32_t *level, const double *dLdT, double *dLdM,
+                       double *dLdomega, double *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning,
+                       eik_stats *stats, hipStream_t stream);
 
 /* Batched solving (n_grids independent grids, packed as described above).
  * eik_batch_workspace_bytes sizes the workspace; eik_batch_plan writes the

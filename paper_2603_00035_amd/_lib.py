@@ -50,7 +50,7 @@ class EikTuning(ctypes.Structure):
                 ("adjoint_rounds", ctypes.c_int32), ("level_rounds", ctypes.c_int32),
                 ("scheduler", ctypes.c_int32), ("node_lanes", ctypes.c_int32),
                 ("adjoint_cycles", ctypes.c_int32), ("adjoint_waves", ctypes.c_int32),
-                ("full_waves", ctypes.c_int32)]
+                ("full_waves", ctypes.c_int32), ("adjoint_mode", ctypes.c_int32), ("level_mode", ctypes.c_int32)]
 
 
 class EikProjectParams(ctypes.Structure):
@@ -105,7 +105,7 @@ def lib():
         L.eik_mixed_workspace_bytes.restype = ctypes.c_size_t
         L.eik_forward_mixed.argtypes = [gp, vp, vp, d, d, i32, i32, vp, vp, vp, vp, ctypes.c_size_t, tp, tp, sp, vp]
         L.eik_forward_mixed.restype = ctypes.c_int
-        L.eik_backward_mixed.argtypes = [gp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, tp, sp, vp]
+        L.eik_backward_mixed.argtypes = [gp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, tp, sp, vp]
         L.eik_backward_mixed.restype = ctypes.c_int
         L.eik_inv_scratch_bytes.argtypes = []
         L.eik_inv_scratch_bytes.restype = ctypes.c_size_t

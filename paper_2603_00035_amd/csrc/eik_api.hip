@@ -194,6 +194,8 @@ eik_tuning tuning_or_default(const eik_tuning *t)
     d.adjoint_cycles = 1;
     d.adjoint_waves = 4;
     d.full_waves = 4;
+    d.adjoint_mode = EIK_ADJ_RELAX;
+    d.level_mode = EIK_LEVELS_CARRIED;
     if (t) {
         if (t->tile_height == 32 || t->tile_height == 64) d.tile_height = t->tile_height;
         if (t->max_local_cycles >= 1) d.max_local_cycles = t->max_local_cycles;
@@ -206,6 +208,8 @@ eik_tuning tuning_or_default(const eik_tuning *t)
         if (t->adjoint_cycles >= 1) d.adjoint_cycles = t->adjoint_cycles;
         if (t->adjoint_waves == 1 || t->adjoint_waves == 4) d.adjoint_waves = t->adjoint_waves;
         if (t->full_waves == 1 || t->full_waves == 4) d.full_waves = t->full_waves;
+        if (t->adjoint_mode == EIK_ADJ_RELAX || t->adjoint_mode == EIK_ADJ_LEVELS) d.adjoint_mode = t->adjoint_mode;
+        if (t->level_mode == EIK_LEVELS_CARRIED || t->level_mode == EIK_LEVELS_AFTER) d.level_mode = t->level_mode;
     }
     return d;
 }
@@ -254,8 +258,9 @@ struct LaunchTimer {
 // checks, the first check comes after `first_batch` rounds (a phase that
 // starts near its fixed point settles in one or two), else after `per_check`
 // rounds (the tuned estimate of a whole phase); later checks come every
-// per_check / 8 rounds (at least 2), so a phase that needs a few rounds more
-// than the estimate enqueues a few more launches, not another full batch.
+// min(per_check, 8) rounds, so a phase that needs a few rounds more than the
+// estimate enqueues a few more launches, not another full batch (a host
+// check costs about as much as ten launches that find no flagged tile).
 // round_fn(act_in, act_out, count_next) enqueues one round.
 template <typename F>
 int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int budget, int per_check, bool sync,
@@ -264,7 +269,7 @@ int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int bud
 {
     int r = first;
     const int end = std::min(first + budget, kMaxRounds);
-    const int later = std::max(2, per_check / 8);
+    const int later = std::min(per_check, 8);
     *converged = false;
     while (r < end) {
         const int want = r == first ? (first_batch > 0 ? std::min(first_batch, per_check) : per_check) : later;
@@ -351,6 +356,9 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     int r0 = 0, rounds = 0;
     bool conv = false;
     const bool fast = T_init == nullptr && tn.fast_cold_start;
+    // levels carried by the sweeps (one-wave visits), or computed afterwards
+    // by the level rounds alone while the sweeps run as without levels
+    int32_t *sweep_level = tn.level_mode == EIK_LEVELS_AFTER ? nullptr : level;
     // exact stationarity before certification here; without it (the mixed
     // path's FP32 phase) the caller's tolerance, its FP64 phase converging
     // from any start
@@ -364,7 +372,8 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
             w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
                 launch_sweep_round<R>(a, tn.fast_cold_start == 2 ? kModeFastCD : kModeFast, M, om, w.Pt, T,
-                                      parent, level, ain, aout, cnt, w.ctr, fast_tol, tn.max_local_cycles, 1, st);
+                                      parent, sweep_level, ain, aout, cnt, w.ctr, fast_tol, tn.max_local_cycles, 1,
+                                      st);
             },
             &rounds, &conv, &timer);
         if (rc) return rc;
@@ -382,12 +391,14 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         // the full update's fixed point from any start
     } else if (tn.scheduler == EIK_SCHED_QUEUE) {
         // one persistent launch over a device queue of flagged tiles
-        const int waves = std::min({sweep_queue_waves(a.th, dtype, level != nullptr), kMaxQueueWaves, a.n_tiles});
+        const int waves =
+            std::min({sweep_queue_waves(a.th, dtype, sweep_level != nullptr), kMaxQueueWaves, a.n_tiles});
         if (waves < 1) return fail(EIK_EDEVICE, "no occupancy for the work-queue sweep kernel");
         const uint32_t budget = (uint32_t)std::min<int64_t>((int64_t)max_rounds * a.n_tiles, INT32_MAX);
         launch_queue_setup(a, w.act + (r0 & 1) * a.n_tiles, w.q, budget, st);
         if (timer.on) timer.before(st);
-        launch_sweep_queue<R>(a, waves, M, om, w.Pt, T, parent, level, w.q, w.ctr, tol, tn.max_local_cycles, st);
+        launch_sweep_queue<R>(a, waves, M, om, w.Pt, T, parent, sweep_level, w.q, w.ctr, tol, tn.max_local_cycles,
+                              st);
         if (timer.on) timer.after(st);
         launch_note_queue(w.q, w.ctr + kCtrSweepPending, st);
         HIP_OK(hipGetLastError());
@@ -405,8 +416,9 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         rc = run_rounds(
             w.act, w.act_count, a.n_tiles, r0, max_rounds, tn.rounds_per_check, sync, st,
             [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
-                launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
-                                      tn.max_local_cycles, tn.full_waves == 4 ? kFullWavesCD : tn.node_lanes, st);
+                launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, sweep_level, ain, aout, cnt, w.ctr,
+                                      tol, tn.max_local_cycles, tn.full_waves == 4 ? kFullWavesCD : tn.node_lanes,
+                                      st);
             },
             &rounds, &conv, &timer, (fast || T_init) ? 2 : 0);
         if (rc) return rc;
@@ -552,25 +564,43 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
     if (rc) return rc;
     const bool sync = single || stats != nullptr;
 
-    (void)level; // the relaxation needs no levels: each tile sweeps until its equations hold exactly
+    // The relaxation needs no levels (each tile sweeps until its equations
+    // hold exactly); the level-scheduled gather sorts the nodes by the
+    // forward's levels. Its node list, bins and per-grid largest level take
+    // the place of the staged parameters, which only the forward sweeps use
+    // (5 reals per node >= 2 ints per node + one int per grid).
+    const bool by_levels = tn.adjoint_mode == EIK_ADJ_LEVELS;
+    if (by_levels && !level) return fail(EIK_EINVAL, "the level-scheduled adjoint needs the forward's levels");
+    int32_t *lv_order = (int32_t *)w.Pt, *lv_bins = lv_order + e.nodes, *lv_gmax = lv_bins + e.nodes;
     launch_fill_u64(w.ctr + kCtrAdjPending, 1, st);
     launch_adj_prep<R>(a, M, om, T, parent, w.w1, w.lam, st);
     int rounds = 0;
     bool conv = false;
+    if (by_levels) launch_level_buckets(a, level, lv_gmax, lv_bins, lv_order, st);
     if (r32) { // weights from the state in R, lambda relaxed in FP32, then widened
         launch_cast_f64_f32(e.nodes, (const double *)w.w1, r32->w1, st);
         launch_cast_f64_f32(e.nodes, (const double *)dLdT, r32->g, st);
         launch_fill_i32((int32_t *)r32->lam, e.nodes, 0, st); // +0.0f
         launch_adj_stage<float>(a, parent, r32->g, w.adjD, w.adjDT, w.adjGT, st);
-        const AdjNodes nd = {w.adjD, w.adjDT, r32->g, w.adjGT};
-        rc = relax<float>(a, w, tn, sync, nd, r32->w1, r32->lam, st, rounds, conv);
-        if (rc) return rc;
+        if (by_levels) {
+            launch_level_gather<float>(a, lv_gmax, lv_bins, lv_order, w.adjD, r32->g, r32->w1, r32->lam, st);
+            conv = true;
+        } else {
+            const AdjNodes nd = {w.adjD, w.adjDT, r32->g, w.adjGT};
+            rc = relax<float>(a, w, tn, sync, nd, r32->w1, r32->lam, st, rounds, conv);
+            if (rc) return rc;
+        }
         launch_cast_f32_f64(e.nodes, r32->lam, (double *)w.lam, st);
     } else {
         launch_adj_stage<R>(a, parent, dLdT, w.adjD, w.adjDT, w.adjGT, st);
-        const AdjNodes nd = {w.adjD, w.adjDT, dLdT, w.adjGT};
-        rc = relax<R>(a, w, tn, sync, nd, w.w1, w.lam, st, rounds, conv);
-        if (rc) return rc;
+        if (by_levels) {
+            launch_level_gather<R>(a, lv_gmax, lv_bins, lv_order, w.adjD, dLdT, w.w1, w.lam, st);
+            conv = true;
+        } else {
+            const AdjNodes nd = {w.adjD, w.adjDT, dLdT, w.adjGT};
+            rc = relax<R>(a, w, tn, sync, nd, w.w1, w.lam, st, rounds, conv);
+            if (rc) return rc;
+        }
     }
     launch_adj_params<R>(a, M, parent, w.w1, w.lam, dLdM, dLdom, st);
     launch_dsrc<R>(a, src_idx, w.lam, dLdsrc, st);
@@ -737,8 +767,9 @@ int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void 
 }
 
 int eik_backward_mixed(const eik_grid *grid, const double *M, const double *omega, const double *T,
-                       const uint8_t *parent, const double *dLdT, double *dLdM, double *dLdomega, double *dLdsrc,
-                       void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream)
+                       const uint8_t *parent, const int32_t *level, const double *dLdT, double *dLdM,
+                       double *dLdomega, double *dLdsrc, void *ws, size_t ws_bytes, const eik_tuning *tuning,
+                       eik_stats *stats, hipStream_t stream)
 {
     if (!grid) return fail(EIK_EINVAL, "grid is NULL");
     int rc = check_one(grid, 0);
@@ -754,7 +785,7 @@ int eik_backward_mixed(const eik_grid *grid, const double *M, const double *omeg
         return fail(EIK_EWORKSPACE, "workspace %zu bytes, %zu needed", ws_bytes, L.total);
     char *b = (char *)ws;
     const Relax32 r32 = {(float *)(b + L.M32), (float *)(b + L.om32), (float *)(b + L.T32)};
-    return backward_impl<double>(1, grid, grid->src_idx, M, omega, T, parent, nullptr, dLdT, dLdM, dLdomega, dLdsrc,
+    return backward_impl<double>(1, grid, grid->src_idx, M, omega, T, parent, level, dLdT, dLdM, dLdomega, dLdsrc,
                                  b + L.base, ws_bytes - L.base, tuning, true, stats, stream, &r32);
 }
 

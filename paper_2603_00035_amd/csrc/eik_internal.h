@@ -158,6 +158,14 @@ void launch_adj_params(const LaunchArgs &a, const void *M, const uint8_t *parent
                        void *dM, void *dom, hipStream_t st);
 template <typename R>
 void launch_dsrc(const LaunchArgs &a, const int32_t *src_idx, const void *lam, void *dsrc, hipStream_t st);
+// level-scheduled adjoint (eik_levels.hip): counting sort of each grid's
+// reached nodes by level into order (bins[off + l] ends as the end of bin l,
+// gmax[g] is the largest level of grid g), then the gather by decreasing level
+void launch_level_buckets(const LaunchArgs &a, const int32_t *level, int32_t *gmax, int32_t *bins, int32_t *order,
+                          hipStream_t st);
+template <typename R>
+void launch_level_gather(const LaunchArgs &a, const int32_t *gmax, const int32_t *bins, const int32_t *order,
+                         const uint16_t *D, const void *g, const void *w1, void *lam, hipStream_t st);
 
 // projection
 template <typename R>

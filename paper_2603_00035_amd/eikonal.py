@@ -59,14 +59,23 @@ def workspace(grid: L.EikGrid, dtype_code: int, device) -> torch.Tensor:
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
+ADJ_RELAX, ADJ_LEVELS = 1, 2
+LEVELS_CARRIED, LEVELS_AFTER = 1, 2
+
+
 def tuning(tile_height=0, max_local_cycles=0, rounds_per_check=0, fast_cold_start=-1, adjoint_rounds=0,
-           level_rounds=0, scheduler=0, node_lanes=0, adjoint_cycles=0, adjoint_waves=0, full_waves=0):
+           level_rounds=0, scheduler=0, node_lanes=0, adjoint_cycles=0, adjoint_waves=0, full_waves=0,
+           adjoint_mode=0, level_mode=0):
     """Scheduling knobs (0 / -1 keep the library default). scheduler: 1 rounds,
     2 device work queue; node_lanes: 1, 2 or 4 lanes per node update;
     fast_cold_start: 0, 1 or 2 (four directions at once); adjoint_waves and
-    full_waves: 1 or 4 (four directions at once)."""
+    full_waves: 1 or 4 (four directions at once); adjoint_mode: ADJ_RELAX
+    (tile relaxation) or ADJ_LEVELS (level-ordered gather, needs levels);
+    level_mode: LEVELS_CARRIED (the sweeps carry the levels) or LEVELS_AFTER
+    (level rounds after sweeps that run as without levels)."""
     return L.EikTuning(tile_height, max_local_cycles, rounds_per_check, fast_cold_start, adjoint_rounds,
-                       level_rounds, scheduler, node_lanes, adjoint_cycles, adjoint_waves, full_waves)
+                       level_rounds, scheduler, node_lanes, adjoint_cycles, adjoint_waves, full_waves,
+                       adjoint_mode, level_mode)
 
 
 def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=4096, check_feasible=False,
@@ -172,10 +181,12 @@ def adjoint(M, omega, T, parent, level, src_idx, h, dLdT, src_t=None, tune=None,
     return dM, dom, ds
 
 
-def adjoint_mixed(M, omega, T, parent, src_idx, h, dLdT, src_t=None, tune=None, ws=None, stats_out=None):
+def adjoint_mixed(M, omega, T, parent, src_idx, h, dLdT, src_t=None, tune=None, ws=None, stats_out=None,
+                  level=None):
     """Backward pass of the mixed-precision state (eik_backward_mixed): FP64
-    weights and parameter derivatives, FP32 adjoint relaxation. Returns FP64
-    (dL/dM, dL/domega, dL/dt_src)."""
+    weights and parameter derivatives, FP32 adjoint relaxation (or the
+    level-ordered gather with ``tune.adjoint_mode = ADJ_LEVELS`` and the
+    forward's ``level``). Returns FP64 (dL/dM, dL/domega, dL/dt_src)."""
     _check_fields(M, omega)
     if M.dtype != torch.float64 or T.dtype != torch.float64:
         raise TypeError("the mixed-precision adjoint takes the FP64 fields and field T")
@@ -192,7 +203,7 @@ def adjoint_mixed(M, omega, T, parent, src_idx, h, dLdT, src_t=None, tune=None, 
     ds = torch.empty(src_idx.numel(), dtype=torch.float64, device=dev)
     st = L.EikStats()
     rc = L.lib().eik_backward_mixed(ctypes.byref(grid), L.ptr(M), L.ptr(omega), L.ptr(T), L.ptr(parent),
-                                    L.ptr(dLdT), L.ptr(dM), L.ptr(dom), L.ptr(ds), L.ptr(ws), ws.numel(),
+                                    L.ptr(level), L.ptr(dLdT), L.ptr(dM), L.ptr(dom), L.ptr(ds), L.ptr(ws), ws.numel(),
                                     None if tune is None else ctypes.byref(tune), ctypes.byref(st),
                                     L.stream_handle(dev))
     L.check("eik_backward_mixed", rc)
@@ -240,17 +251,27 @@ class EikonalFn(torch.autograd.Function):
         return dM, dom, (ds if ctx.has_src_t else None), None, None, None, None, None, None, None, None, None
 
 
+# Tolerance of the FP64 phase of the mixed-precision solve when the caller
+# asks for a looser one. The adjoint's donor weights are difference quotients
+# of T at the grid scale, so the FP32 rounding the FP32 sweeps leave along the
+# characteristics must be propagated out, not only recomputed locally: on the
+# 2048^2 stress workload an FP64 phase stopped at 1e-5 leaves the gradient
+# 8.0e-5 from the exact one (1.2e-4 in one run), at 3e-7 4.2e-5, at 1e-7
+# 4.5e-6; the forward error falls from 6.7e-6 to 5.2e-7 at 3e-7.
+MIXED_FP64_TOL = 3e-7
+
+
 def eikonal(M, omega, src_idx, h, src_t=None, tol=1e-5, max_rounds=4096, stats_sink=None, time_kernels=False,
-            levels=False, precision=None, tol32=None):
+            levels=False, precision=None, tol32=None, tol64=None):
     """Differentiable solve; returns (T, parent, level) with level None unless
     ``levels`` is set. ``stats_sink`` (a list) receives the forward's Stats.
 
     precision None solves and differentiates in the dtype of M; "mixed" runs
-    the mixed-precision forward (FP32 sweeps to ``tol32``, then FP64 sweeps to
-    ``tol``) and the mixed adjoint (FP64 weights, FP32 relaxation): M, omega
-    and src_t enter in FP64 (their
-    gradients return in their own dtype), T is FP64, and ``stats_sink``
-    receives the Stats of both phases."""
+    the mixed-precision forward (FP32 sweeps to ``tol32``, default ``tol``,
+    then FP64 sweeps to ``tol64``, default min(tol, MIXED_FP64_TOL)) and the
+    mixed adjoint (FP64 weights, FP32 relaxation): M, omega and src_t enter
+    in FP64 (their gradients return in their own dtype), T is FP64, and
+    ``stats_sink`` receives the Stats of both phases."""
     if precision not in (None, "mixed"):
         raise ValueError(f"precision {precision!r}: None or 'mixed'")
     mixed = precision == "mixed"
@@ -258,6 +279,8 @@ def eikonal(M, omega, src_idx, h, src_t=None, tol=1e-5, max_rounds=4096, stats_s
         M, omega = M.to(torch.float64), omega.to(torch.float64)
         if src_t is not None:
             src_t = src_t.to(torch.float64)
+        tol32 = tol if tol32 is None else tol32
+        tol = min(tol, MIXED_FP64_TOL) if tol64 is None else tol64
     return EikonalFn.apply(M, omega, src_t, src_idx, h, tol, max_rounds, stats_sink, time_kernels, levels, mixed,
                            tol32)
 

@@ -102,14 +102,32 @@ def check_parent_choices(q, To, po, pg, rtol, Tg=None):
 
 FP32_EPS = 2.0 ** -24
 
-# Gradient rel-L2 bar of the plain FP32 path against the oracle. The 1e-4 bar
-# sits at the floor that FP32 storage of T allows on these anisotropic fields:
-# the oracle's own sweeps with every stored value rounded to FP32 land 1.0e-4
-# from the exact gradient of the 512^2 loss (1.4e-4 on the 2048^2 stress
-# field), because the donor weights of nearly degenerate two-point updates
-# amplify errors in T. FP32 runs are held to three times that; the
-# mixed-precision path is held to 1e-4.
+# Gradient rel-L2 bar of the plain FP32 path against the oracle. The donor
+# weights are difference quotients of T at the grid scale, so FP32 storage of T
+# alone puts the 512^2 loss gradient 1.0e-4 from the exact one: the oracle's
+# own sweeps with every stored value rounded to FP32 (exact updates otherwise)
+# land there (tests/test_fp32_storage_floor.py). The kernels' FP32 arithmetic
+# adds rounding of its own (2.5e-4 on that loss, in every visit mode, and the
+# oracle's exact VJP on the kernels' FP32 field is already 1.3e-4 off), so
+# FP32 runs are held to three times the storage floor; the mixed-precision
+# path, which stores T in FP64, is held to 1e-4. Where a test measures the
+# floor of its own loss it allows FP32_FLOOR_FACTOR times that floor (1.2 to
+# 3.2 times observed over the batched workload's grids), or 1e-4 where that
+# is looser.
 FP32_GRAD_RTOL = 3e-4
+FP32_FLOOR_FACTOR = 4.0
+
+
+def fp32_storage_floor(q, To, po, g_of_T):
+    """Parameter-gradient rel-L2 distance between the oracle's exact fixed
+    point and its fixed point with every stored value rounded to FP32, for the
+    loss gradient g_of_T(T): the best an FP32 field can do on this loss."""
+    T32, _, st = oracle.forward(q, mode="gs_f32")
+    assert st == 0
+    p32, _ = oracle.parents_levels(q, T32)
+    dMo, domo, _ = oracle.vjp(q, To, po, g_of_T(To))
+    dM3, dom3, _ = oracle.vjp(q, T32, p32, g_of_T(T32))
+    return rel_l2([dM3, dom3], [dMo, domo])
 
 
 def causality_margin(q, T, c, code):

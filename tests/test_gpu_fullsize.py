@@ -8,17 +8,10 @@ import pytest
 
 import oracle
 from synthetic.fields import fourier_field, make_problem
-from tests.gpu_common import check_parent_choices, near_tie_analysis, rel_l2, say
+from tests.gpu_common import check_parent_choices, fp32_storage_floor, near_tie_analysis, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
-
-# Gradient rel-L2 floor of any solve that stores T in FP32, on this workload:
-# the oracle's own Gauss-Seidel sweeps with every stored value rounded to FP32
-# (exact FP64 updates otherwise) reach 1.43e-4 against the exact FP64 state,
-# and random relative perturbations s of the exact field move the gradient by
-# about 1000 s. The plain FP32 path is held to twice that floor.
-FP32_STORAGE_GRAD_FLOOR = 1.43e-4
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +30,14 @@ def case():
     g = np.zeros_like(To)
     g[mask] = 2.0 * (To[mask] - target[mask]) / n_obs
     dMo, domo, _ = oracle.vjp(q, To, po, g)
-    return dict(p=p, q=q, To=To, sweeps=sweeps, po=po, target=target, mask=mask, n_obs=n_obs, dMo=dMo, domo=domo)
+
+    def g_of(T):
+        gg = np.zeros_like(T)
+        gg[mask] = 2.0 * (T[mask] - target[mask]) / n_obs
+        return gg
+
+    return dict(p=p, q=q, To=To, sweeps=sweeps, po=po, target=target, mask=mask, n_obs=n_obs, dMo=dMo, domo=domo,
+                g_of=g_of)
 
 
 def gpu_run(c, precision):
@@ -60,7 +60,9 @@ def gpu_run(c, precision):
 @pytest.mark.timeout(600)
 def test_stress_2048_mixed_precision(case):
     """The configuration the benchmark times: FP32 sweeps to 1e-5, FP64 sweeps
-    from there to 1e-5, mixed adjoint. Both bars hold at every node."""
+    from there until no change exceeds 3e-7, mixed adjoint. The forward bar
+    holds at every node and the gradient meets 1e-4 with a margin (4.2e-5
+    measured)."""
     c = case
     p = c["p"]
     say("[full] 2048x2048 stress, mixed precision: GPU solve to 1e-5 and adjoint")
@@ -76,6 +78,7 @@ def test_stress_2048_mixed_precision(case):
     assert err <= 1e-5
     check_parent_choices(c["q"], To, c["po"], pg, 1e-5, Tg=Tg)
     assert r <= 1e-4
+    assert err <= 1e-6
 
 
 @pytest.mark.timeout(600)
@@ -83,7 +86,9 @@ def test_stress_2048_fp32(case):
     """The plain FP32 path: 1e-5 everywhere except downstream of causality
     decisions that sit within FP32 rounding of a tie (where FP32 and FP64 may
     both be right); the GPU field must satisfy the oracle's local equations to
-    the solve tolerance. The gradient is held to twice the FP32-storage floor."""
+    the solve tolerance. The gradient is held to twice the floor of FP32
+    storage on this loss, measured here with the oracle (every stored value
+    rounded to FP32, exact updates otherwise)."""
     c = case
     p, q, To, po = c["p"], c["q"], c["To"], c["po"]
     say("[full] 2048x2048 stress, FP32: GPU solve to 1e-5 and adjoint")
@@ -92,13 +97,15 @@ def test_stress_2048_fp32(case):
     say(f"[full] fp32: forward max rel err {info['max_rel']:.3e}; {info['nodes_over_tol']} nodes over 1e-5, "
         f"all downstream of {info['decision_nodes']} near-tie decisions")
     assert info["nodes_over_tol"] <= p.n // 10000
+    floor = fp32_storage_floor(q, To, po, c["g_of"])
     mism = int(np.sum(pg != po))
     say(f"[full] fp32: parent differences {mism}, gradient rel L2 {r:.3e} "
-        f"(FP32-storage floor {FP32_STORAGE_GRAD_FLOOR:.2e})")
+        f"(FP32-storage floor {floor:.2e})")
     sample = np.array([x for x in np.flatnonzero((pg != po).ravel()) if x not in info["excluded"]], dtype=np.int64)
     if sample.size > 2000:  # the oracle checks a sample of the differing nodes one by one
         sample = np.random.default_rng(0).choice(sample, 2000, replace=False)
     pg_s = po.copy()
     pg_s.flat[sample] = pg.flat[sample]
     check_parent_choices(q, To, po, pg_s, 1e-5, Tg=Tg)
-    assert r <= 2 * FP32_STORAGE_GRAD_FLOOR
+    assert floor > 1e-4  # no FP32 field meets the 1e-4 bar on this workload
+    assert r <= 2 * floor
