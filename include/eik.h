@@ -167,6 +167,22 @@ int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *
                 double tol, int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level,
                 void *ws, size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
 
+/* eik_forward without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it): the same solve, arguments and results as eik_forward, with the
+ * workspace taken from a fixed array the library holds on each GPU for the
+ * life of the process (eik_noalloc_max_workspace_bytes(), 64 MiB: grids whose
+ * eik_workspace_bytes fit, about 1.8 million nodes in FP32 and 1 million in
+ * FP64). Larger grids are rejected with EIK_EWORKSPACE before anything runs;
+ * EIK_TIME_KERNELS is rejected with EIK_EINVAL. The call allocates nothing.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams or host threads) race, and must be serialised by the
+ * caller. The first call on each GPU looks up the array's device address. */
+size_t eik_noalloc_max_workspace_bytes(void);
+int eik_forward_noalloc(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T_init,
+                        double tol, int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level,
+                        const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
+
 /* Mixed-precision forward: the solve of eik_forward on FP64 parameters in two
  * phases. FP32 sweeps from the cold start, on FP32-rounded copies of M, omega
  * and the source times: with the restricted-candidate cold start on

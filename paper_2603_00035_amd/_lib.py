@@ -29,7 +29,8 @@ EXPORTS = ["eik_workspace_bytes", "eik_forward", "eik_backward", "eik_project", 
            "eik_backward_batched", "eik_batch_pending", "eik_mixed_workspace_bytes", "eik_forward_mixed",
            "eik_backward_mixed", "eik_inv_scratch_bytes", "eik_tv", "eik_obs_loss", "eik_sum_sq", "eik_param_step",
            "eik_tie_isotropic", "eik_enc_dense", "eik_enc_dense_backward", "eik_enc_combine",
-           "eik_enc_scratch_bytes", "eik_enc_combine_backward"]
+           "eik_enc_scratch_bytes", "eik_enc_combine_backward", "eik_forward_noalloc",
+           "eik_noalloc_max_workspace_bytes"]
 
 
 class EikGrid(ctypes.Structure):
@@ -105,6 +106,10 @@ def lib():
         L.eik_mixed_workspace_bytes.restype = ctypes.c_size_t
         L.eik_forward_mixed.argtypes = [gp, vp, vp, d, d, i32, i32, vp, vp, vp, vp, ctypes.c_size_t, tp, tp, sp, vp]
         L.eik_forward_mixed.restype = ctypes.c_int
+        L.eik_forward_noalloc.argtypes = [gp, i32, vp, vp, vp, d, i32, i32, vp, vp, vp, tp, sp, vp]
+        L.eik_forward_noalloc.restype = ctypes.c_int
+        L.eik_noalloc_max_workspace_bytes.argtypes = []
+        L.eik_noalloc_max_workspace_bytes.restype = ctypes.c_size_t
         L.eik_backward_mixed.argtypes = [gp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, tp, sp, vp]
         L.eik_backward_mixed.restype = ctypes.c_int
         L.eik_inv_scratch_bytes.argtypes = []

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -306,10 +307,15 @@ int prepare(int n_grids, const eik_grid *grids, int dtype, void *ws, size_t ws_b
     a.n_tiles = (int32_t)(a.th == 64 ? e.tiles64 : e.tiles32);
     a.n_nodes = e.nodes;
     if (write_desc) { // single grid: descriptor written by a kernel, no host copy
-        std::vector<GridDesc> d;
-        std::vector<int32_t> tg;
-        host_descs(1, grids, a.th, d, tg);
-        launch_write_single_desc(d[0], w.descs, w.tile_grid, a.n_tiles, st);
+        GridDesc d;
+        memset(&d, 0, sizeof d);
+        d.h = grids[0].h;
+        d.nx = grids[0].nx;
+        d.ny = grids[0].ny;
+        d.ntx = (d.nx + TW - 1) / TW;
+        d.nty = (d.ny + a.th - 1) / a.th;
+        d.n_src = grids[0].n_src;
+        launch_write_single_desc(d, w.descs, w.tile_grid, a.n_tiles, st);
     }
     return EIK_OK;
 }
@@ -620,6 +626,41 @@ int check_ptrs(const void *M, const void *om, const void *T, const void *parent)
     return EIK_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of eik_forward_noalloc: a fixed device array of this file instead
+// of the caller's buffer. Each GPU holds its own copy for the life of the
+// process; its device address is looked up once per device, on the first call
+// made with that device current, and kept. Every call on a device uses the
+// same array: the solve clears what must start at zero (counters, tile flags)
+// with fill kernels and writes every other region before reading it, so the
+// previous call's contents do not matter, but calls that overlap on one GPU
+// (other streams or host threads) race.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void **out)
+{
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(EIK_EDEVICE, "device %d is beyond the %d devices the static workspace tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(EIK_EDEVICE, "no device address for the static workspace on device %d", dev);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return EIK_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -676,6 +717,39 @@ int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *
                                     parent, level, ws, ws_bytes, tuning, stats, true, stream);
     return forward_impl<float>(1, grid, grid->src_idx, grid->src_t, M, omega, T_init, tol, max_rounds, flags, T,
                                parent, level, ws, ws_bytes, tuning, stats, true, stream);
+}
+
+size_t eik_noalloc_max_workspace_bytes(void) { return kStaticScratchBytes; }
+
+int eik_forward_noalloc(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T_init,
+                        double tol, int32_t max_rounds, int32_t flags, void *T, uint8_t *parent, int32_t *level,
+                        const eik_tuning *tuning, eik_stats *stats, hipStream_t stream)
+{
+    if (!grid) return fail(EIK_EINVAL, "grid is NULL");
+    if (dtype != EIK_F32 && dtype != EIK_F64) return fail(EIK_EINVAL, "dtype %d", dtype);
+    int rc = check_one(grid, 0);
+    if (rc) return rc;
+    if (!grid->src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
+    rc = check_ptrs(M, omega, T, parent);
+    if (rc) return rc;
+    if (!(tol >= 0.0)) return fail(EIK_EINVAL, "tol must be >= 0");
+    if (max_rounds < 1) return fail(EIK_EINVAL, "max_rounds must be >= 1");
+    if (flags & EIK_TIME_KERNELS) return fail(EIK_EINVAL, "EIK_TIME_KERNELS creates events; not available here");
+    Extent e;
+    rc = extent_of(1, grid, dtype, e);
+    if (rc) return rc;
+    const size_t need = layout(e, dtype).total;
+    if (need > kStaticScratchBytes)
+        return fail(EIK_EWORKSPACE, "a %d x %d grid needs %zu bytes of workspace; the static workspace holds %zu",
+                    grid->nx, grid->ny, need, kStaticScratchBytes);
+    void *ws = nullptr;
+    rc = static_scratch(&ws);
+    if (rc) return rc;
+    if (dtype == EIK_F64)
+        return forward_impl<double>(1, grid, grid->src_idx, grid->src_t, M, omega, T_init, tol, max_rounds, flags, T,
+                                    parent, level, ws, kStaticScratchBytes, tuning, stats, true, stream);
+    return forward_impl<float>(1, grid, grid->src_idx, grid->src_t, M, omega, T_init, tol, max_rounds, flags, T,
+                               parent, level, ws, kStaticScratchBytes, tuning, stats, true, stream);
 }
 
 size_t eik_mixed_workspace_bytes(const eik_grid *grid)

@@ -83,3 +83,22 @@ def test_project_rejects_bad_parameters():
     p = L.EikProjectParams(1e-3, 1e3, 1e3, 1.5)  # rho_max must be < 1
     assert lib.eik_project(10, L.EIK_F32, fake, fake, fake, fake, ctypes.byref(p), None) == -1
     assert lib.eik_project(0, L.EIK_F32, None, None, None, None, None, None) == 0
+
+
+@pytest.mark.parametrize("case", ["too_large", "timing", "null_fields"])
+def test_noalloc_forward_rejects_on_host(case):
+    """The allocation-free forward refuses grids whose workspace exceeds its
+    static array, and the timing flag, before touching the device."""
+    from paper_2603_00035_amd import _lib as L
+    lib = L.lib()
+    cap = lib.eik_noalloc_max_workspace_bytes()
+    assert cap == 64 << 20
+    g = grid(2048, 2048) if case == "too_large" else grid()
+    assert case != "too_large" or lib.eik_workspace_bytes(ctypes.byref(g), L.EIK_F32) > cap
+    fake = ctypes.c_void_p(0x1000)
+    flags = L.EIK_TIME_KERNELS if case == "timing" else 0
+    rc = lib.eik_forward_noalloc(ctypes.byref(g), L.EIK_F32, None if case == "null_fields" else fake, fake, None,
+                                 1e-5, 10, flags, fake, fake, None, None, None, None)
+    assert rc == (L.EIK_EWORKSPACE if case == "too_large" else L.EIK_EINVAL)
+    msg = lib.eik_last_error().decode()
+    assert msg and (case != "too_large" or "static workspace" in msg)
