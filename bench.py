@@ -55,7 +55,7 @@ WORKLOADS = {
     "c4": "256 grids with sides U{64..512} FP32, eigenvalue ratio 4, drift 0.5, 1-4 sources each, "
           "fwd to 1e-5 + adjoint, one HIP graph replay per step",
     "c5": "256x256 FP32 forward to 1e-5 on held-out seeds, batches of 250: cold start vs the learned BF16 "
-          "U-Net warm start (inference included) with and without the fixed-budget fallback",
+          "U-Net warm start (inference included) with and without the residual-monitor fallback",
     "gradcheck": "64x64 FP64 gradient checks of the validation section: pointwise central differences at 20 "
                  "interior nodes per configuration (isotropic, anisotropic, drift), 100 random directions, "
                  "1 % and 0.1 % metric noise, plain and averaged over 16 jittered copies",
@@ -171,6 +171,8 @@ def bench_warm(args):
         "warm_with_fallback_ms_per_grid": 1e3 * r["warm_fb_s"] / n, "inference_ms_per_grid": 1e3 * r["infer_s"] / n,
         "cold_sweeps_per_node": r["cold_sweeps_per_node"], "warm_sweeps_per_node": r["warm_sweeps_per_node"],
         "warm_speedup": r["speedup_warm"], "warm_with_fallback_speedup": r["speedup_warm_with_fallback"],
+        "fallback_batches": r["fallback_batches"], "batches": r["batches"],
+        "rounds": {"cold": r["cold_rounds"], "warm": r["warm_rounds"], "warm_with_fallback": r["fb_rounds"]},
         "prediction_rel_err_mean": sum(r["pred_rel_err_mean"]) / len(r["pred_rel_err_mean"]),
         "max_rel_warm_vs_cold": r["max_rel_warm_vs_cold"], "roofline": None, "cpu_baseline": None,
     }
@@ -416,31 +418,76 @@ def bench_encoder(args):
     }
 
 
+def _oracle_grid(args):
+    """One grid of the batched workload through the oracle (forward to tol,
+    stencils, VJP of a dense functional); returns (cell-updates, seconds)."""
+    import numpy as np
+
+    import oracle
+    from synthetic.fields import make_problem
+    seed, nx, ny, tol = args
+    q = make_problem("c4", seed, nx=nx, ny=ny).rounded(np.float32)
+    t0 = time.perf_counter()
+    T, sweeps, _ = oracle.forward(q, tol=tol)
+    par, _ = oracle.parents_levels(q, T)
+    g = np.where(np.isfinite(T), 1.0 / T.size, 0.0)
+    oracle.vjp(q, T, par, g)
+    return q.n * sweeps, time.perf_counter() - t0
+
+
+def cpu_baseline_batched(probs, tol):
+    """The oracle over all grids of the batched workload on a process pool
+    of every host core this process may use (started before the GPU is
+    touched, so the workers fork from a process without GPU state)."""
+    import multiprocessing as mp
+    cores = len(os.sched_getaffinity(0))
+    jobs = [(p.seed, p.nx, p.ny, tol) for p in probs]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        out = pool.map(_oracle_grid, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    model, ncpu = host_cpu()
+    updates = sum(u for u, _ in out)
+    return {"value": updates / wall, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_cpu_count": ncpu,
+            "sample": f"all {len(probs)} grids of the workload, each solved to {tol:g} (FP64 Gauss-Seidel) + "
+                      f"stencils + VJP by the single-threaded oracle, on a pool of {cores} processes, "
+                      f"{wall:.1f} s wall ({sum(t for _, t in out):.1f} s of CPU)"}
+
+
 def bench_batched(args):
     """The batched workload: all grids solved and differentiated by one replay
-    of a captured HIP graph (fixed round budgets, no host synchronisation),
-    with the tuning table's knobs and, for comparison, the library defaults."""
+    of a captured HIP graph (fixed round budgets, no host synchronisation):
+    FP32 with the tuning table's knobs and with the library defaults, and the
+    mixed-precision batch (FP32 sweeps, FP64 sweeps, mixed adjoint)."""
     import numpy as np
-    import torch
 
-    from paper_2603_00035_amd import _lib as L
-    from paper_2603_00035_amd import eikonal as E
-    from paper_2603_00035_amd.batched import Batch
     from synthetic.fields import batched_set, make_problem
 
-    dev = torch.device("cuda:0")
     probs = batched_set(256, 1000 + args.seed)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_batched(probs, args.tol)
+
+    import torch
+
+    from paper_2603_00035_amd import eikonal as E
+    from paper_2603_00035_amd.batched import Batch
+
+    dev = torch.device("cuda:0")
     tgts = [make_problem("c4", p.seed + 10000, nx=p.nx, ny=p.ny) for p in probs]
     shapes = [(p.nx, p.ny, p.h, p.src_idx.size) for p in probs]
     cat = lambda xs: torch.tensor(np.concatenate([x.reshape(-1) for x in xs]), dtype=torch.float32, device=dev)
-    M, om = cat([p.M for p in probs]), cat([p.omega for p in probs])
+    M32, om32 = cat([p.M for p in probs]), cat([p.omega for p in probs])
     Mt, omt = cat([p.M for p in tgts]), cat([p.omega for p in tgts])
     src = torch.tensor(np.concatenate([p.src_idx for p in probs]), dtype=torch.int32, device=dev)
     n_cells = sum(p.n for p in probs)
     results = {}
-    for label, tune in (("default", E.tuning()), ("autotuned", None)):
-        B = Batch(shapes, dtype=torch.float32, device=dev, tune=tune, max_rounds=4096)
-        target, _, _, _ = B.forward(Mt, omt, src, tol=args.tol)
+    B32 = Batch(shapes, dtype=torch.float32, device=dev, max_rounds=4096)
+    target32, _, _, _ = B32.forward(Mt, omt, src, tol=args.tol)
+    del B32
+    for label, tune, mixed in (("default", E.tuning(), False), ("autotuned", None, False), ("mixed", None, True)):
+        B = Batch(shapes, dtype=torch.float32, device=dev, tune=tune, max_rounds=4096, mixed=mixed)
+        M, om = (M32.double(), om32.double()) if mixed else (M32, om32)
+        target = target32.to(B.dtype)
         mask = torch.isfinite(target)
         gid = torch.repeat_interleave(torch.arange(len(probs), device=dev),
                                       torch.tensor([p.n for p in probs], device=dev))
@@ -451,11 +498,13 @@ def bench_batched(args):
         # eager run: round counts, update count, timed sweep launches
         T, par, lev, st = B.forward(M, om, src, tol=args.tol, time_kernels=True)
         assert st.converged, "batched solve did not reach the tolerance"
-        eager_rounds = st.rounds
+        st32 = st.fp32 if mixed else st  # the phase with the cold-start sweeps
+        eager_rounds = max(st.rounds, st32.rounds)
         # fixed budgets for the captured schedule, checked after the replays
         B.max_rounds = int(eager_rounds * 1.25) + 8
         fo, bo = B.alloc_forward(), B.alloc_backward()
-        gT = torch.zeros(B.n_nodes, device=dev)
+        gT = torch.zeros(B.n_nodes, dtype=B.dtype, device=dev)
+        scale = scale.to(B.dtype)
 
         def step():
             B.forward(M, om, src, tol=args.tol, out=fo, sync=False)
@@ -482,10 +531,12 @@ def bench_batched(args):
         pend = B.pending()
         assert pend == (0, 0, 0), f"fixed round budgets too small: {pend}"
         assert torch.isfinite(bo[0]).all()
-        results[label] = {"ms_per_step": 1e3 * wall, "updates": st.cell_updates, "rounds": eager_rounds,
-                          "budget_rounds": B.max_rounds, "sweep_ms": st.sweep_ms, "launches": st.sweep_launches,
-                          "fast_updates": st.fast_cell_updates, "fast_ms": st.fast_ms,
-                          "fast_launches": st.fast_launches,
+        updates = st.cell_updates + (st32.cell_updates if mixed else 0)
+        results[label] = {"ms_per_step": 1e3 * wall, "updates": updates,
+                          "rounds": [st32.rounds, st.rounds] if mixed else eager_rounds,
+                          "budget_rounds": B.max_rounds, "sweep_ms": st32.sweep_ms, "launches": st32.sweep_launches,
+                          "fast_updates": st32.fast_cell_updates, "fast_ms": st32.fast_ms,
+                          "fast_launches": st32.fast_launches,
                           "tuning": None if B.tune is None else {k: getattr(B.tune, k) for k, _ in B.tune._fields_}}
         del graph
     r = results["autotuned"]
@@ -513,7 +564,7 @@ def bench_batched(args):
                      "algorithmic_bytes_per_update": bpu, "timed": "eager synchronised run"},
         "autotuned_vs_default": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                                  for k, v in results.items()},
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
 
 
@@ -537,6 +588,10 @@ def main():
               "and the library has no multi-GPU path (the sharding plan is a design note); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c4":  # its CPU baseline forks a process pool before anything touches the GPU
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
+
     import numpy as np
     import torch
 
@@ -544,9 +599,6 @@ def main():
     from paper_2603_00035_amd import eikonal as E
     from synthetic.fields import fourier_field, make_problem
 
-    if args.workload == "c4":
-        print(json.dumps(bench_batched(args)), flush=True)
-        return
     if args.workload == "c5":
         print(json.dumps(bench_warm(args)), flush=True)
         return

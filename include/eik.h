@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-typedef enum { EIK_F32 = 0, EIK_F64 = 1 } eik_dtype;
+typedef enum { EIK_F32 = 0, EIK_F64 = 1, EIK_MIXED = 2 /* batched mixed-precision workspace only */ } eik_dtype;
 
 enum {
     EIK_OK = 0,
@@ -71,7 +71,12 @@ enum {
 /* Flags for the forward calls. */
 enum {
     EIK_CHECK_FEASIBLE = 1, /* verify m11 > 0, det M > 0, |omega|_{M^-1} < 1 first */
-    EIK_TIME_KERNELS = 2    /* time each sweep-kernel launch with HIP events (stats) */
+    EIK_TIME_KERNELS = 2,   /* time each sweep-kernel launch with HIP events (stats) */
+    EIK_WARM_FALLBACK = 4   /* warm starts only, in calls that synchronise (single grid, or batched with
+                               stats): after two full-update rounds from T_init, if more than a quarter of
+                               the tiles are still changing by more than tol, T_init is dropped and the
+                               solve restarts from the cold start (stats->fell_back = 1); the two rounds
+                               are counted in the stats */
 };
 
 /* One grid. src_idx: device array of n_src distinct flat node indices.
@@ -100,6 +105,7 @@ typedef struct eik_stats {
     double fast_ms;         /* the part of sweep_ms spent in the cold start's restricted-candidate rounds */
     int64_t fast_cell_updates; /* the part of cell_updates made in those rounds */
     int32_t fast_launches;  /* the part of sweep_launches made in those rounds */
+    int32_t fell_back;      /* 1 when EIK_WARM_FALLBACK dropped the warm start, else 0 */
 } eik_stats;
 
 /* Scheduling knobs; NULL or a field <= 0 keeps the library default. */
@@ -264,6 +270,27 @@ int eik_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, 
                          const void *M, const void *omega, const void *T, const uint8_t *parent,
                          const int32_t *level, const void *dLdT, void *dLdM, void *dLdomega, void *dLdsrc, void *ws,
                          size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
+
+/* Batched mixed precision: eik_forward_mixed / eik_backward_mixed over a
+ * batch (FP64 parameters, FP32 sweeps to tol32 from the cold start, FP64
+ * sweeps from that field to tol, FP64 donor weights and parameter
+ * derivatives around an FP32 adjoint relaxation). The workspace, the plan and
+ * eik_batch_pending take dtype EIK_MIXED (FP32 copies of the parameters and of
+ * T in front of the FP64 batched workspace, which holds the plan of both
+ * phases). tuning32 and tuning must share the plan's tile height. Without
+ * stats both run their fixed schedules (max_rounds rounds per sweep phase,
+ * adjoint_rounds adjoint rounds) and never synchronise (graph-capturable);
+ * stats is NULL or an array of two (FP32 phase, FP64 phase) for the forward,
+ * one for the backward. Real arrays double; errors as the batched calls. */
+int eik_forward_batched_mixed(int32_t n_grids, const eik_grid *grids, const int32_t *src_idx, const double *src_t,
+                              const double *M, const double *omega, double tol32, double tol, int32_t max_rounds,
+                              int32_t flags, double *T, uint8_t *parent, int32_t *level, void *ws, size_t ws_bytes,
+                              const eik_tuning *tuning32, const eik_tuning *tuning, eik_stats *stats,
+                              hipStream_t stream);
+int eik_backward_batched_mixed(int32_t n_grids, const eik_grid *grids, const int32_t *src_idx, const double *M,
+                               const double *omega, const double *T, const uint8_t *parent, const int32_t *level,
+                               const double *dLdT, double *dLdM, double *dLdomega, double *dLdsrc, void *ws,
+                               size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream);
 
 /* After an unsynchronised batched forward and/or backward (e.g. a graph
  * replay), reads how many tiles were still flagged when the fixed budgets ran

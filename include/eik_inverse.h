@@ -42,6 +42,21 @@ size_t eik_inv_scratch_bytes(void);
 int eik_tv(int32_t nx, int32_t ny, int32_t n_planes, int32_t dtype, const void *F, const double *weights,
            double scale, void *grad, double *value, void *scratch, hipStream_t stream);
 
+/* Log-Euclidean TV of a metric field (App. learning details, Total
+ * Variation Regularization): R = sum_ij |grad log G_ij|_F, with log G the
+ * matrix logarithm of each SPD 2x2 metric in closed form through its
+ * eigen-decomposition, and the norm that of eik_tv on the planes
+ * (p11, p12, p22) of log G with weights (1, 2, 1). Unlike the Frobenius
+ * variant it is invariant under a rotation of all metrics and under a common
+ * scale. M [3][ny][nx] must be SPD everywhere (m11 > 0, det > 0; not checked).
+ * Writes scale * R to *value (device double) and adds scale * dR/dM (with
+ * respect to the stored m11, m12, m22) to grad [3][ny][nx]. work: device
+ * memory of eik_tv_log_euclid_work_bytes bytes (log G and its gradient);
+ * scratch as for eik_tv. */
+size_t eik_tv_log_euclid_work_bytes(int32_t nx, int32_t ny, int32_t dtype);
+int eik_tv_log_euclid(int32_t nx, int32_t ny, int32_t dtype, const void *M, double scale, void *grad,
+                      double *value, void *work, void *scratch, hipStream_t stream);
+
 /* Data term of Eq. inverse_problem over the observed nodes: with mask w_i in
  * {0, 1} (uint8, nonzero = observed), r_i = T_i - That_i,
  *   L = 1/2 sum_i w_i r_i^2,  dL/dT_i = w_i r_i (0 where T or That is not finite).

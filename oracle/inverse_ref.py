@@ -82,3 +82,40 @@ def tie_isotropic(M):
     M = np.asarray(M, dtype=np.float64)
     g = 0.5 * (M[0] + M[2])
     return np.stack([g, np.zeros_like(g), g])
+
+
+def log_spd2(M):
+    """Matrix logarithm of 2x2 SPD metrics given as stored planes (m11, m12,
+    m22) [3, ...], as torch float64 planes (p11, p12, p22) of log G.
+
+    For a 2x2 matrix with eigenvalues t +- d (t half the trace, d half the
+    eigenvalue gap) any function f satisfies f(G) = a I + b (G - t I) with
+    a = (f(t + d) + f(t - d)) / 2 and b = (f(t + d) - f(t - d)) / (2 d); for
+    f = log, a = log(det G) / 2 and b = atanh(d / t) / d, which tends to
+    1 / t as d -> 0 (the series 1 / t (1 + x^2 / 3 + x^4 / 5), x = d / t,
+    is used below d / t = 1e-3, written in d^2 so that its derivative stays
+    finite where the eigenvalues coincide). Differentiable with autograd."""
+    import torch
+    m11, m12, m22 = M[0], M[1], M[2]
+    t = 0.5 * (m11 + m22)
+    q = (0.5 * (m11 - m22)) ** 2 + m12 * m12  # d^2, free of the square root's kink at 0
+    a = 0.5 * torch.log(m11 * m22 - m12 * m12)
+    x2 = q / (t * t)
+    small = x2 < 1e-6
+    xs = torch.sqrt(torch.where(small, torch.full_like(x2, 0.25), x2))  # finite gradients where unused
+    b = torch.where(small, (1.0 + x2 / 3.0 + x2 * x2 / 5.0) / t, torch.atanh(xs) / (xs * t))
+    return torch.stack([a + b * (m11 - t), b * m12, a + b * (m22 - t)])
+
+
+def tv_log_euclid(M):
+    """Log-Euclidean TV of a metric field (App. learning details, Total
+    Variation Regularization): R = sum_ij |grad log G_ij|_F, the Frobenius
+    norm of the forward differences of log G (off-diagonal weighted by 2 in
+    the squared norm, as for the Frobenius variant), and dR/d(m11, m12, m22)
+    with respect to the stored scalars (m12 enters both off-diagonal entries)."""
+    import torch
+    Mt = torch.tensor(np.asarray(M, dtype=np.float64), requires_grad=True)
+    P = log_spd2(Mt)
+    value, gP = tv(P.detach().numpy(), [1.0, 2.0, 1.0])
+    P.backward(torch.from_numpy(gP))
+    return value, Mt.grad.numpy()

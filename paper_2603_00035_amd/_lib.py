@@ -20,6 +20,8 @@ EIK_EINVAL, EIK_EINFEASIBLE, EIK_EDEVICE, EIK_EWORKSPACE = -1, -2, -3, -4
 EIK_SCHED_ROUNDS, EIK_SCHED_QUEUE = 1, 2
 EIK_CHECK_FEASIBLE = 1
 EIK_TIME_KERNELS = 2
+EIK_WARM_FALLBACK = 4
+EIK_MIXED = 2  # dtype code of the batched mixed-precision workspace, plan and pending calls
 STATUS_NAMES = {0: "EIK_OK", 1: "EIK_NOT_CONVERGED", -1: "EIK_EINVAL", -2: "EIK_EINFEASIBLE",
                 -3: "EIK_EDEVICE", -4: "EIK_EWORKSPACE"}
 SOURCE, UNREACHED = 0xFE, 0xFF
@@ -30,7 +32,8 @@ EXPORTS = ["eik_workspace_bytes", "eik_forward", "eik_backward", "eik_project", 
            "eik_backward_mixed", "eik_inv_scratch_bytes", "eik_tv", "eik_obs_loss", "eik_sum_sq", "eik_param_step",
            "eik_tie_isotropic", "eik_enc_dense", "eik_enc_dense_backward", "eik_enc_combine",
            "eik_enc_scratch_bytes", "eik_enc_combine_backward", "eik_forward_noalloc",
-           "eik_noalloc_max_workspace_bytes"]
+           "eik_noalloc_max_workspace_bytes", "eik_tv_log_euclid", "eik_tv_log_euclid_work_bytes",
+           "eik_forward_batched_mixed", "eik_backward_batched_mixed"]
 
 
 class EikGrid(ctypes.Structure):
@@ -42,7 +45,7 @@ class EikStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("converged", ctypes.c_int32), ("cell_updates", ctypes.c_int64),
                 ("n_levels", ctypes.c_int32), ("status", ctypes.c_int32), ("sweep_launches", ctypes.c_int32),
                 ("aux_rounds", ctypes.c_int32), ("sweep_ms", ctypes.c_double), ("fast_ms", ctypes.c_double),
-                ("fast_cell_updates", ctypes.c_int64), ("fast_launches", ctypes.c_int32)]
+                ("fast_cell_updates", ctypes.c_int64), ("fast_launches", ctypes.c_int32), ("fell_back", ctypes.c_int32)]
 
 
 class EikTuning(ctypes.Structure):
@@ -100,6 +103,12 @@ def lib():
         L.eik_backward_batched.argtypes = [i32, gp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                            ctypes.c_size_t, tp, sp, vp]
         L.eik_backward_batched.restype = ctypes.c_int
+        L.eik_forward_batched_mixed.argtypes = [i32, gp, vp, vp, vp, vp, d, d, i32, i32, vp, vp, vp, vp,
+                                                ctypes.c_size_t, tp, tp, sp, vp]
+        L.eik_forward_batched_mixed.restype = ctypes.c_int
+        L.eik_backward_batched_mixed.argtypes = [i32, gp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                                 ctypes.c_size_t, tp, sp, vp]
+        L.eik_backward_batched_mixed.restype = ctypes.c_int
         L.eik_batch_pending.argtypes = [i32, gp, i32, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64), vp]
         L.eik_batch_pending.restype = ctypes.c_int
         L.eik_mixed_workspace_bytes.argtypes = [gp]
@@ -116,6 +125,10 @@ def lib():
         L.eik_inv_scratch_bytes.restype = ctypes.c_size_t
         L.eik_tv.argtypes = [i32, i32, i32, i32, vp, ctypes.POINTER(ctypes.c_double), d, vp, vp, vp, vp]
         L.eik_tv.restype = ctypes.c_int
+        L.eik_tv_log_euclid_work_bytes.argtypes = [i32, i32, i32]
+        L.eik_tv_log_euclid_work_bytes.restype = ctypes.c_size_t
+        L.eik_tv_log_euclid.argtypes = [i32, i32, i32, vp, d, vp, vp, vp, vp, vp]
+        L.eik_tv_log_euclid.restype = ctypes.c_int
         L.eik_obs_loss.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, vp]
         L.eik_obs_loss.restype = ctypes.c_int
         L.eik_sum_sq.argtypes = [i64, i32, vp, vp, vp, vp]

@@ -20,21 +20,29 @@ import torch
 
 from . import _lib as L
 from . import autotune
-from .eikonal import stats_of
+from .eikonal import MIXED_FP64_TOL, stats_of
 
 
 class Batch:
-    def __init__(self, shapes, dtype=torch.float32, device="cuda", tune=None, max_rounds=64):
-        """shapes: list of (nx, ny, h, n_src)."""
+    def __init__(self, shapes, dtype=torch.float32, device="cuda", tune=None, max_rounds=64, mixed=False):
+        """shapes: list of (nx, ny, h, n_src). ``mixed``: the mixed-precision
+        calls (FP64 fields; FP32 sweeps with ``tune`` (default: the FP32 batch
+        entry of the tuning table), then FP64 sweeps and the mixed adjoint
+        with the library defaults at the same tile height)."""
         self.shapes = [(int(a), int(b), float(c), int(d)) for a, b, c, d in shapes]
         self.n_grids = len(self.shapes)
-        self.dtype = dtype
+        self.mixed = bool(mixed)
+        self.dtype = torch.float64 if self.mixed else dtype
         self.device = torch.device(device)
-        self.dc = L.dtype_code(torch.empty(0, dtype=dtype))
+        self.dc = L.EIK_MIXED if self.mixed else L.dtype_code(torch.empty(0, dtype=dtype))
         if tune is None:
-            tune = autotune.lookup(sum(nx * ny for nx, ny, _, _ in self.shapes), autotune.dtype_name(dtype),
-                                   kind="batch")
+            tune = autotune.lookup(sum(nx * ny for nx, ny, _, _ in self.shapes),
+                                   "f32" if self.mixed else autotune.dtype_name(dtype), kind="batch")
         self.tune = tune
+        self.tune64 = None
+        if self.mixed:
+            self.tune64 = L.EikTuning()
+            self.tune64.tile_height = tune.tile_height if tune is not None else 0
         self.max_rounds = max_rounds
         G = L.EikGrid * self.n_grids
         self.grids = G(*[L.EikGrid(nx, ny, h, ns, None, None) for nx, ny, h, ns in self.shapes])
@@ -76,12 +84,31 @@ class Batch:
         return T, parent, level
 
     def forward(self, M, om, src_idx, src_t=None, T_init=None, tol=1e-5, out=None, sync=True,
-                time_kernels=False, levels=False):
+                time_kernels=False, levels=False, warm_fallback=False, tol32=None, tol64=None):
         """Returns (T, parent, level, Stats); level is None unless ``levels``
-        (or an ``out`` triple with a level tensor) asks for it."""
+        (or an ``out`` triple with a level tensor) asks for it.
+        ``warm_fallback`` (with T_init and sync) drops a warm start that does
+        not settle in two rounds and solves from the cold start."""
         T, parent, level = out if out is not None else self.alloc_forward(levels)
-        st = L.EikStats() if sync else None
         flags = L.EIK_TIME_KERNELS if (time_kernels and sync) else 0
+        if self.mixed:
+            if T_init is not None:
+                raise ValueError("the mixed-precision batch solves from the cold start")
+            st2 = (L.EikStats * 2)() if sync else None
+            rc = L.lib().eik_forward_batched_mixed(
+                self.n_grids, self.grids, L.ptr(src_idx), L.ptr(src_t), L.ptr(M), L.ptr(om),
+                float(tol if tol32 is None else tol32), float(min(tol, MIXED_FP64_TOL) if tol64 is None else tol64),
+                int(self.max_rounds), flags, L.ptr(T), L.ptr(parent), L.ptr(level), L.ptr(self.ws), self.ws.numel(),
+                self._tp, ctypes.byref(self.tune64), st2, L.stream_handle(self.device))
+            L.check("eik_forward_batched_mixed", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
+            stats = None
+            if st2 is not None:
+                stats = stats_of(st2[1])
+                stats.fp32 = stats_of(st2[0])
+            return T, parent, level, stats
+        st = L.EikStats() if sync else None
+        if warm_fallback and sync:
+            flags |= L.EIK_WARM_FALLBACK
         rc = L.lib().eik_forward_batched(self.n_grids, self.grids, self.dc, L.ptr(src_idx), L.ptr(src_t),
                                          L.ptr(M), L.ptr(om), L.ptr(T_init), float(tol), int(self.max_rounds),
                                          flags, L.ptr(T), L.ptr(parent), L.ptr(level), L.ptr(self.ws),
@@ -102,6 +129,13 @@ class Batch:
     def backward(self, M, om, T, parent, level, src_idx, dLdT, out=None, sync=True):
         dM, dom, ds = out if out is not None else self.alloc_backward()
         st = L.EikStats() if sync else None
+        if self.mixed:
+            rc = L.lib().eik_backward_batched_mixed(
+                self.n_grids, self.grids, L.ptr(src_idx), L.ptr(M), L.ptr(om), L.ptr(T), L.ptr(parent), L.ptr(level),
+                L.ptr(dLdT), L.ptr(dM), L.ptr(dom), L.ptr(ds), L.ptr(self.ws), self.ws.numel(), ctypes.byref(self.tune64),
+                None if st is None else ctypes.byref(st), L.stream_handle(self.device))
+            L.check("eik_backward_batched_mixed", rc)
+            return dM, dom, ds, (None if st is None else st.rounds)
         rc = L.lib().eik_backward_batched(self.n_grids, self.grids, self.dc, L.ptr(src_idx), L.ptr(M), L.ptr(om),
                                           L.ptr(T), L.ptr(parent), L.ptr(level), L.ptr(dLdT), L.ptr(dM),
                                           L.ptr(dom), L.ptr(ds), L.ptr(self.ws), self.ws.numel(), self._tp,

@@ -266,7 +266,7 @@ struct LaunchTimer {
 template <typename F>
 int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int budget, int per_check, bool sync,
                hipStream_t st, F round_fn, int *rounds_done, bool *converged, LaunchTimer *timer = nullptr,
-               int first_batch = 0)
+               int first_batch = 0, int32_t *last_count = nullptr)
 {
     int r = first;
     const int end = std::min(first + budget, kMaxRounds);
@@ -284,6 +284,7 @@ int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int bud
         HIP_OK(hipMemcpyAsync(&cnt, act_count + r, sizeof cnt, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
         if (timer && timer->on) timer->collect();
+        if (last_count) *last_count = cnt;
         if (cnt == 0) {
             *converged = true;
             break;
@@ -361,7 +362,33 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     if (rc) return rc;
     int r0 = 0, rounds = 0;
     bool conv = false;
-    const bool fast = T_init == nullptr && tn.fast_cold_start;
+    // Warm start with a fallback: two full-update rounds from T_init probe it;
+    // a field that leaves more than a quarter of the tiles changing is dropped
+    // and the solve restarts from the cold start.
+    bool fell_back = false, probe_done = false;
+    int probe_rounds = 0;
+    if (T_init && (flags & EIK_WARM_FALLBACK) && sync && tn.scheduler == EIK_SCHED_ROUNDS) {
+        int32_t left = 0;
+        rc = run_rounds(
+            w.act, w.act_count, a.n_tiles, 0, 2, 2, sync, st,
+            [&](int32_t *ain, int32_t *aout, int32_t *cnt) {
+                launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
+                                      tn.max_local_cycles, tn.full_waves == 4 ? kFullWavesCD : tn.node_lanes, st);
+            },
+            &probe_rounds, &conv, &timer, 0, &left);
+        if (rc) return rc;
+        probe_done = true;
+        if (!conv && 4 * (int64_t)left > a.n_tiles) {
+            fell_back = true;
+            launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
+            launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
+            launch_init<R>(a, nullptr, T, parent, level, src_idx, src_t, w.act, w.act_count, w.ctr, false, st);
+            HIP_OK(hipGetLastError());
+        } else {
+            r0 = probe_rounds;
+        }
+    }
+    const bool fast = (T_init == nullptr || fell_back) && tn.fast_cold_start;
     // levels carried by the sweeps (one-wave visits), or computed afterwards
     // by the level rounds alone while the sweeps run as without levels
     int32_t *sweep_level = tn.level_mode == EIK_LEVELS_AFTER ? nullptr : level;
@@ -395,6 +422,8 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         // no full rounds: the caller continues from this field with full
         // updates of its own (the mixed path's FP64 phase), which converge to
         // the full update's fixed point from any start
+    } else if (probe_done && !fell_back && conv) {
+        launches = r0; // the warm start's two probe rounds reached the fixed point
     } else if (tn.scheduler == EIK_SCHED_QUEUE) {
         // one persistent launch over a device queue of flagged tiles
         const int waves =
@@ -466,12 +495,13 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     if (ctr[kCtrBadSource]) status = fail(EIK_EINVAL, "%llu source indices out of range", ctr[kCtrBadSource]);
     else if (!conv) fail(EIK_NOT_CONVERGED, "tolerance not reached in %d rounds", r0);
     if (stats) {
-        stats->rounds = r0;
+        stats->rounds = r0 + (fell_back ? probe_rounds : 0);
         stats->converged = conv ? 1 : 0;
         stats->cell_updates = (int64_t)ctr[kCtrCellUpdates];
         stats->n_levels = level ? (int32_t)ctr[kCtrMaxLevel] + 1 : 0;
         stats->status = status;
-        stats->sweep_launches = launches;
+        stats->sweep_launches = launches + (fell_back ? probe_rounds : 0);
+        stats->fell_back = fell_back ? 1 : 0;
         stats->sweep_ms = timer.ms;
         stats->aux_rounds = lrounds;
         stats->fast_ms = fast_ms;
@@ -676,6 +706,10 @@ size_t eik_workspace_bytes(const eik_grid *grid, int32_t dtype)
 size_t eik_batch_workspace_bytes(int32_t n_grids, const eik_grid *grids, int32_t dtype)
 {
     Extent e;
+    if (dtype == EIK_MIXED) {
+        if (extent_of(n_grids, grids, EIK_F64, e)) return 0;
+        return mixed_layout(e).total;
+    }
     if (extent_of(n_grids, grids, dtype, e)) return 0;
     return layout(e, dtype).total;
 }
@@ -683,6 +717,14 @@ size_t eik_batch_workspace_bytes(int32_t n_grids, const eik_grid *grids, int32_t
 int eik_batch_plan(int32_t n_grids, const eik_grid *grids, int32_t dtype, const eik_tuning *tuning, void *ws,
                    size_t ws_bytes, hipStream_t stream)
 {
+    if (dtype == EIK_MIXED) { // the FP64 workspace behind the FP32 copies holds the plan of both phases
+        Extent e;
+        int rc = extent_of(n_grids, grids, EIK_F64, e);
+        if (rc) return rc;
+        const MixedLayout L = mixed_layout(e);
+        if (!ws || ws_bytes < L.total) return fail(EIK_EWORKSPACE, "workspace %zu bytes, %zu needed", ws_bytes, L.total);
+        return eik_batch_plan(n_grids, grids, EIK_F64, tuning, (char *)ws + L.base, ws_bytes - L.base, stream);
+    }
     const eik_tuning tn = tuning_or_default(tuning);
     Extent e;
     int rc = extent_of(n_grids, grids, dtype, e);
@@ -798,7 +840,8 @@ int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega
     launch_cast_f32_f64(e.nodes, T32, T, stream);
     HIP_OK(hipGetLastError());
     return forward_impl<double>(1, grid, grid->src_idx, grid->src_t, M, omega, T, tol, max_rounds,
-                                flags & ~EIK_CHECK_FEASIBLE, T, parent, level, b + L.base, ws_bytes - L.base,
+                                flags & ~(EIK_CHECK_FEASIBLE | EIK_WARM_FALLBACK), T, parent, level, b + L.base,
+                                ws_bytes - L.base,
                                 tuning, stats ? stats + 1 : nullptr, true, stream);
 }
 
@@ -819,6 +862,62 @@ int eik_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, c
         return forward_impl<float>(n_grids, grids, src_idx, src_t, M, omega, T_init, tol, max_rounds, flags, T,
                                    parent, level, ws, ws_bytes, tuning, stats, false, stream);
     return fail(EIK_EINVAL, "dtype %d", dtype);
+}
+
+int eik_forward_batched_mixed(int32_t n_grids, const eik_grid *grids, const int32_t *src_idx, const double *src_t,
+                              const double *M, const double *omega, double tol32, double tol, int32_t max_rounds,
+                              int32_t flags, double *T, uint8_t *parent, int32_t *level, void *ws, size_t ws_bytes,
+                              const eik_tuning *tuning32, const eik_tuning *tuning, eik_stats *stats,
+                              hipStream_t stream)
+{
+    if (!src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
+    int rc = check_ptrs(M, omega, T, parent);
+    if (rc) return rc;
+    if (!(tol >= 0.0) || !(tol32 >= 0.0)) return fail(EIK_EINVAL, "tolerances must be >= 0");
+    if (max_rounds < 1) return fail(EIK_EINVAL, "max_rounds must be >= 1");
+    if (tuning_or_default(tuning32).tile_height != tuning_or_default(tuning).tile_height)
+        return fail(EIK_EINVAL, "both phases must use the tile height of the plan");
+    Extent e;
+    rc = extent_of(n_grids, grids, EIK_F64, e);
+    if (rc) return rc;
+    const MixedLayout L = mixed_layout(e);
+    if (!ws || ws_bytes < L.total) return fail(EIK_EWORKSPACE, "workspace %zu bytes, %zu needed", ws_bytes, L.total);
+    char *b = (char *)ws;
+    float *M32 = (float *)(b + L.M32), *om32 = (float *)(b + L.om32), *T32 = (float *)(b + L.T32);
+    float *src32 = src_t ? (float *)(b + L.src32) : nullptr;
+    launch_cast_f64_f32(3 * e.nodes, M, M32, stream);
+    launch_cast_f64_f32(2 * e.nodes, omega, om32, stream);
+    if (src_t) launch_cast_f64_f32(e.n_src, src_t, src32, stream);
+    HIP_OK(hipGetLastError());
+    // FP32 sweeps from the cold start (not reaching tol32 is no error here),
+    // then FP64 sweeps from that field in place in T
+    rc = forward_impl<float>(n_grids, grids, src_idx, src32, M32, om32, nullptr, tol32, max_rounds, flags, T32,
+                             parent, nullptr, b + L.base, ws_bytes - L.base, tuning32, stats, false, stream,
+                             /*certify=*/false);
+    if (rc < 0) return rc;
+    launch_cast_f32_f64(e.nodes, T32, T, stream);
+    HIP_OK(hipGetLastError());
+    return forward_impl<double>(n_grids, grids, src_idx, src_t, M, omega, T, tol, max_rounds,
+                                flags & ~(EIK_CHECK_FEASIBLE | EIK_WARM_FALLBACK), T, parent, level, b + L.base,
+                                ws_bytes - L.base, tuning, stats ? stats + 1 : nullptr, false, stream);
+}
+
+int eik_backward_batched_mixed(int32_t n_grids, const eik_grid *grids, const int32_t *src_idx, const double *M,
+                               const double *omega, const double *T, const uint8_t *parent, const int32_t *level,
+                               const double *dLdT, double *dLdM, double *dLdomega, double *dLdsrc, void *ws,
+                               size_t ws_bytes, const eik_tuning *tuning, eik_stats *stats, hipStream_t stream)
+{
+    if (!src_idx || !M || !omega || !T || !parent || !dLdT || !dLdM || !dLdomega || !dLdsrc)
+        return fail(EIK_EINVAL, "NULL pointer argument");
+    Extent e;
+    int rc = extent_of(n_grids, grids, EIK_F64, e);
+    if (rc) return rc;
+    const MixedLayout L = mixed_layout(e);
+    if (!ws || ws_bytes < L.total) return fail(EIK_EWORKSPACE, "workspace %zu bytes, %zu needed", ws_bytes, L.total);
+    char *b = (char *)ws;
+    const Relax32 r32 = {(float *)(b + L.M32), (float *)(b + L.om32), (float *)(b + L.T32)};
+    return backward_impl<double>(n_grids, grids, src_idx, M, omega, T, parent, level, dLdT, dLdM, dLdomega, dLdsrc,
+                                 b + L.base, ws_bytes - L.base, tuning, false, stats, stream, &r32);
 }
 
 int eik_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
@@ -929,6 +1028,15 @@ int eik_batch_pending(int32_t n_grids, const eik_grid *grids, int32_t dtype, con
                       int64_t pending[3], hipStream_t stream)
 {
     if (!pending) return fail(EIK_EINVAL, "pending is NULL");
+    if (dtype == EIK_MIXED) {
+        Extent e;
+        int rc = extent_of(n_grids, grids, EIK_F64, e);
+        if (rc) return rc;
+        const MixedLayout L = mixed_layout(e);
+        if (!ws || ws_bytes < L.total) return fail(EIK_EWORKSPACE, "workspace %zu bytes, %zu needed", ws_bytes, L.total);
+        return eik_batch_pending(n_grids, grids, EIK_F64, (const char *)ws + L.base, ws_bytes - L.base, pending,
+                                 stream);
+    }
     Extent e;
     int rc = extent_of(n_grids, grids, dtype, e);
     if (rc) return rc;
@@ -956,6 +1064,28 @@ int eik_tv(int32_t nx, int32_t ny, int32_t n_planes, int32_t dtype, const void *
         launch_tv<double>(nx, ny, n_planes, F, weights, scale, grad, value, (double *)scratch, stream);
     else if (dtype == EIK_F32)
         launch_tv<float>(nx, ny, n_planes, F, weights, scale, grad, value, (double *)scratch, stream);
+    else
+        return fail(EIK_EINVAL, "dtype %d", dtype);
+    HIP_OK(hipGetLastError());
+    return EIK_OK;
+}
+
+size_t eik_tv_log_euclid_work_bytes(int32_t nx, int32_t ny, int32_t dtype)
+{
+    if (nx < 1 || ny < 1 || (dtype != EIK_F32 && dtype != EIK_F64)) return 0;
+    return 6 * (size_t)nx * (size_t)ny * (dtype == EIK_F64 ? 8 : 4);
+}
+
+int eik_tv_log_euclid(int32_t nx, int32_t ny, int32_t dtype, const void *M, double scale, void *grad,
+                      double *value, void *work, void *scratch, hipStream_t stream)
+{
+    if (nx < 1 || ny < 1) return fail(EIK_EINVAL, "sizes %d x %d", nx, ny);
+    if ((int64_t)nx * ny >= ((int64_t)1 << 40)) return fail(EIK_EINVAL, "field too large");
+    if (!M || !grad || !value || !work || !scratch) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        launch_tv_log_euclid<double>(nx, ny, M, scale, grad, value, work, (double *)scratch, stream);
+    else if (dtype == EIK_F32)
+        launch_tv_log_euclid<float>(nx, ny, M, scale, grad, value, work, (double *)scratch, stream);
     else
         return fail(EIK_EINVAL, "dtype %d", dtype);
     HIP_OK(hipGetLastError());

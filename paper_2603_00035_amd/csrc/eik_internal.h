@@ -110,6 +110,10 @@ template <typename R>
 void launch_sum_sq(int64_t n, const void *x, double *acc, double *partial, hipStream_t st);
 template <typename R>
 void launch_tie_isotropic(int64_t n, void *M, hipStream_t st);
+// Log-Euclidean TV of the metric: work holds log G and its gradient (6 n reals)
+template <typename R>
+void launch_tv_log_euclid(int nx, int ny, const void *M, double scale, void *grad, double *value, void *work,
+                          double *partial, hipStream_t st);
 template <typename R>
 void launch_param_step(int64_t n, int method, void *p, const void *g, void *m, void *v, double lr, double b1,
                        double b2, double eps, int t, double max_norm, const double *grad_sq, hipStream_t st);

@@ -165,6 +165,90 @@ __global__ void k_tie_isotropic(int64_t n, R *__restrict__ M)
 }
 
 // ---------------------------------------------------------------------------
+// Log-Euclidean TV (App. learning details, Total Variation Regularization):
+// the TV of the planes of log G, with log G in closed form through the
+// eigen-decomposition of each 2x2 metric, G = Q diag(l1, l2) Q^T with Q the
+// rotation by theta = atan2(2 m12, m11 - m22) / 2:
+//   log G = Q diag(log l1, log l2) Q^T.
+// Its derivative in direction E (a symmetric matrix) is
+//   Q (F o (Q^T E Q)) Q^T,  F11 = 1/l1, F22 = 1/l2,
+//   F12 = F21 = (log l1 - log l2) / (l1 - l2),
+// a self-adjoint map under the Frobenius product, so the gradient with
+// respect to G is the same map applied to the gradient with respect to log G.
+// With t = (l1 + l2)/2 and d = (l1 - l2)/2 the divided difference is
+// atanh(d/t)/d, which tends to 1/t where the eigenvalues meet (series below
+// d/t = 1e-3).
+template <typename R>
+struct Eig2 {
+    R c, s, l1, l2, L1, L2, f12;
+};
+
+template <typename R>
+__device__ __forceinline__ Eig2<R> eig2(R m11, R m12, R m22)
+{
+    Eig2<R> e;
+    const R t = R(0.5) * (m11 + m22), hd = R(0.5) * (m11 - m22);
+    const R d = sqrt(hd * hd + m12 * m12);
+    e.l1 = t + d;
+    e.l2 = (m11 * m22 - m12 * m12) / e.l1; // the smaller eigenvalue, free of cancellation
+    const R th = R(0.5) * atan2(m12, hd);
+    e.c = cos(th);
+    e.s = sin(th);
+    e.L1 = log(e.l1);
+    e.L2 = log(e.l2);
+    const R x = d / t;
+    e.f12 = x < R(1e-3) ? (R(1) + x * x * (R(1) / R(3) + x * x * R(0.2))) / t : atanh(x) / d;
+    return e;
+}
+
+// P[3][n] = planes (p11, p12, p22) of log G.
+template <typename R>
+__global__ void k_logm(int64_t n, const R *__restrict__ M, R *__restrict__ P)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const Eig2<R> e = eig2<R>(M[k], M[n + k], M[2 * n + k]);
+        const R cc = e.c * e.c, ss = e.s * e.s, cs = e.c * e.s;
+        P[k] = cc * e.L1 + ss * e.L2;
+        P[n + k] = cs * (e.L1 - e.L2);
+        P[2 * n + k] = ss * e.L1 + cc * e.L2;
+    }
+}
+
+// grad[3][n] += d(R)/d(m11, m12, m22) given gP = dR/d(p11, p12, p22); the
+// stored m12 and p12 stand for both off-diagonal entries.
+template <typename R>
+__global__ void k_logm_vjp(int64_t n, const R *__restrict__ M, const R *__restrict__ gP, R *__restrict__ grad)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const Eig2<R> e = eig2<R>(M[k], M[n + k], M[2 * n + k]);
+        const R cc = e.c * e.c, ss = e.s * e.s, cs = e.c * e.s, dcs = cc - ss;
+        // the symmetric gradient with respect to log G
+        const R a11 = gP[k], a12 = R(0.5) * gP[n + k], a22 = gP[2 * n + k];
+        // rotated into the eigenbasis, scaled by F, rotated back
+        const R A11 = cc * a11 + R(2) * cs * a12 + ss * a22;
+        const R A22 = ss * a11 - R(2) * cs * a12 + cc * a22;
+        const R A12 = cs * (a22 - a11) + dcs * a12;
+        const R B11 = A11 / e.l1, B22 = A22 / e.l2, B12 = e.f12 * A12;
+        grad[k] += cc * B11 - R(2) * cs * B12 + ss * B22;
+        grad[n + k] += R(2) * (cs * (B11 - B22) + dcs * B12);
+        grad[2 * n + k] += ss * B11 + R(2) * cs * B12 + cc * B22;
+    }
+}
+
+template <typename R>
+void launch_tv_log_euclid(int nx, int ny, const void *M, double scale, void *grad, double *value, void *work,
+                          double *partial, hipStream_t st)
+{
+    const int64_t n = (int64_t)nx * ny;
+    R *P = (R *)work, *gP = P + 3 * n;
+    hipLaunchKernelGGL(k_logm<R>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, (const R *)M, P);
+    launch_fill_i32((int32_t *)gP, 3 * n * (int64_t)(sizeof(R) / 4), 0, st); // +0.0
+    const double w[3] = {1.0, 2.0, 1.0};
+    launch_tv<R>(nx, ny, 3, P, w, scale, gP, value, partial, st);
+    hipLaunchKernelGGL(k_logm_vjp<R>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, (const R *)M, gP, (R *)grad);
+}
+
+// ---------------------------------------------------------------------------
 template <typename R>
 void launch_tie_isotropic(int64_t n, void *M, hipStream_t st)
 {
@@ -215,7 +299,9 @@ void launch_param_step(int64_t n, int method, void *p, const void *g, void *m, v
     template void launch_sum_sq<R>(int64_t, const void *, double *, double *, hipStream_t);                      \
     template void launch_param_step<R>(int64_t, int, void *, const void *, void *, void *, double, double,       \
                                        double, double, int, double, const double *, hipStream_t);               \
-    template void launch_tie_isotropic<R>(int64_t, void *, hipStream_t);
+    template void launch_tie_isotropic<R>(int64_t, void *, hipStream_t);                                     \
+    template void launch_tv_log_euclid<R>(int, int, const void *, double, void *, double *, void *, double *,   \
+                                          hipStream_t);
 EIK_INV_INSTANTIATE(float)
 EIK_INV_INSTANTIATE(double)
 

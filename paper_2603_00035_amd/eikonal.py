@@ -30,6 +30,7 @@ class Stats:
     fast_ms: float = 0.0
     fast_cell_updates: int = 0
     fast_launches: int = 0
+    fell_back: bool = False
 
 
 def _check_fields(M, omega):
@@ -79,9 +80,11 @@ def tuning(tile_height=0, max_local_cycles=0, rounds_per_check=0, fast_cold_star
 
 
 def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=4096, check_feasible=False,
-          tune=None, ws=None, time_kernels=False, levels=True):
+          tune=None, ws=None, time_kernels=False, levels=True, warm_fallback=False):
     """Forward solve. Returns (T, parent, level, Stats); level is None when
-    ``levels`` is False (the adjoint does not need it)."""
+    ``levels`` is False (the adjoint does not need it). ``warm_fallback``
+    (with T_init) drops a warm start that does not settle in two rounds and
+    solves from the cold start instead (Stats.fell_back)."""
     _check_fields(M, omega)
     ny, nx = M.shape[1:]
     dev = M.device
@@ -101,7 +104,8 @@ def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=40
     st = L.EikStats()
     rc = L.lib().eik_forward(ctypes.byref(grid), dc, L.ptr(M), L.ptr(omega), L.ptr(T_init), float(tol),
                              int(max_rounds),
-                             (L.EIK_CHECK_FEASIBLE if check_feasible else 0) | (L.EIK_TIME_KERNELS if time_kernels else 0),
+                             (L.EIK_CHECK_FEASIBLE if check_feasible else 0) | (L.EIK_TIME_KERNELS if time_kernels else 0)
+                             | (L.EIK_WARM_FALLBACK if warm_fallback else 0),
                              L.ptr(T),
                              L.ptr(parent), L.ptr(level), L.ptr(ws), ws.numel(),
                              None if tune is None else ctypes.byref(tune), ctypes.byref(st), L.stream_handle(dev))
@@ -112,7 +116,7 @@ def solve(M, omega, src_idx, h, src_t=None, T_init=None, tol=1e-5, max_rounds=40
 def stats_of(st):
     """Stats from an eik_stats filled by a forward call."""
     return Stats(st.rounds, bool(st.converged), st.cell_updates, st.n_levels, st.status, st.sweep_launches,
-                 st.sweep_ms, st.aux_rounds, st.fast_ms, st.fast_cell_updates, st.fast_launches)
+                 st.sweep_ms, st.aux_rounds, st.fast_ms, st.fast_cell_updates, st.fast_launches, bool(st.fell_back))
 
 
 def mixed_workspace(grid: L.EikGrid, device) -> torch.Tensor:

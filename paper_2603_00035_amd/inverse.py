@@ -4,8 +4,9 @@ Eq. inverse_problem): minimise
     1/2 sum_{i observed} (T_i(theta) - That_i)^2 + lam_G R(G) + lam_b R(b)
 
 with total-variation regularisers (App. learning details: Frobenius norm of
-the metric's gradient with the off-diagonal weighted by 2, Euclidean norm of
-the drift's) by projected gradient steps or Adam with global-norm clipping and
+the metric's gradient with the off-diagonal weighted by 2, or of the gradient
+of its matrix logarithm (Log-Euclidean variant), Euclidean norm of the
+drift's) by projected gradient steps or Adam with global-norm clipping and
 a learning-rate schedule (App. inverse problem experiments), then projection
 onto the feasible set (SPD metric, |b|_{G^-1} < 1).
 
@@ -47,6 +48,7 @@ class InverseConfig:
     free_metric: bool = True
     free_drift: bool = True
     isotropic: bool = False       # constrain the metric to G = g I (projection after each step)
+    tv_metric: str = "frobenius"  # metric TV: "frobenius" (|grad G|_F) or "log_euclid" (|grad log G|_F)
     tol: float = 0.0              # forward solve tolerance of every iteration
     eig_min: float = 1e-3         # projection (eik_project)
     eig_max: float = 1e3
@@ -97,6 +99,12 @@ class Recovery:
         self.vo = torch.zeros_like(self.om)
         self.t = 0
         self._stream = L.stream_handle(dev)
+        if self.cfg.tv_metric not in ("frobenius", "log_euclid"):
+            raise ValueError(f"tv_metric {self.cfg.tv_metric!r}: 'frobenius' or 'log_euclid'")
+        self.tv_work = None
+        if self.cfg.tv_metric == "log_euclid":
+            nb = L.lib().eik_tv_log_euclid_work_bytes(self.nx, self.ny, self.dc)
+            self.tv_work = torch.empty(nb, dtype=torch.uint8, device=dev)
 
     def _sp(self, k):
         return self.scalars.data_ptr() + 8 * k
@@ -122,7 +130,11 @@ class Recovery:
         n = self.nx * self.ny
         gM, gom = self._data_gradient()
         self.scalars[1:].zero_()
-        if c.free_metric and c.lam_G > 0:
+        if c.free_metric and c.lam_G > 0 and c.tv_metric == "log_euclid":
+            L.check("eik_tv_log_euclid",
+                    lib.eik_tv_log_euclid(self.nx, self.ny, self.dc, L.ptr(self.M), c.lam_G, L.ptr(gM), self._sp(1),
+                                          L.ptr(self.tv_work), L.ptr(self.scratch), st))
+        elif c.free_metric and c.lam_G > 0:
             w = (ctypes.c_double * 3)(*G_WEIGHTS)
             L.check("eik_tv", lib.eik_tv(self.nx, self.ny, 3, self.dc, L.ptr(self.M), w, c.lam_G, L.ptr(gM),
                                          self._sp(1), L.ptr(self.scratch), st))

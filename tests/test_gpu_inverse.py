@@ -55,6 +55,42 @@ def test_tv_matches_oracle(dt, rtol, C, ny, nx):
     assert np.max(np.abs(got - want)) <= rtol * (1 + np.max(np.abs(want))) * (1 if dt == torch.float64 else 10)
 
 
+@pytest.mark.parametrize("dt,rtol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+@pytest.mark.parametrize("ny,nx,iso", [(37, 53, 0.0), (64, 70, 0.3), (1, 90, 0.5), (480, 600, 0.1)])
+def test_tv_log_euclid_matches_oracle(dt, rtol, ny, nx, iso):
+    """Random SPD metrics, a share of them isotropic (coinciding eigenvalues,
+    where the logarithm's divided difference takes its limit), and a block of
+    constant metric (zero norms, subgradient 0)."""
+    L, lb = lib()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(nx + ny)
+    A = rng.normal(size=(ny, nx, 2, 2))
+    G = A @ np.swapaxes(A, -1, -2) + 0.3 * np.eye(2)
+    sel = rng.uniform(size=(ny, nx)) < iso
+    G[sel] = rng.uniform(0.5, 2.0, size=(ny, nx))[sel][:, None, None] * np.eye(2)
+    G[: ny // 4, : nx // 4] = np.array([[1.3, 0.2], [0.2, 0.7]])
+    M = np.stack([G[..., 0, 0], G[..., 0, 1], G[..., 1, 1]])
+    say(f"[tv log-euclid] {nx}x{ny} {dt}, isotropic share {iso}")
+    Md = torch.tensor(M, dtype=dt, device=dev)
+    if dt == torch.float32:
+        M = Md.double().cpu().numpy()
+    g0 = rng.normal(size=M.shape)
+    gd = torch.tensor(g0, dtype=dt, device=dev)
+    val = torch.zeros(1, dtype=torch.float64, device=dev)
+    work = torch.empty(lb.eik_tv_log_euclid_work_bytes(nx, ny, L.dtype_code(Md)), dtype=torch.uint8, device=dev)
+    rc = lb.eik_tv_log_euclid(nx, ny, L.dtype_code(Md), L.ptr(Md), 0.3, L.ptr(gd), val.data_ptr(), L.ptr(work),
+                              L.ptr(scratch(dev)), L.stream_handle(dev))
+    assert rc == 0
+    vo, go = I.tv_log_euclid(M)
+    torch.cuda.synchronize()
+    assert float(val) == pytest.approx(0.3 * vo, rel=rtol * (1 if dt == torch.float64 else 10))
+    want = torch.tensor(g0, dtype=dt).double().numpy() + 0.3 * go
+    got = gd.double().cpu().numpy()
+    err = np.max(np.abs(got - want)) / (1 + np.max(np.abs(want)))
+    say(f"  value {float(val):.6e} vs {0.3 * vo:.6e}, gradient max rel {err:.2e}")
+    assert err <= rtol * (1 if dt == torch.float64 else 10)
+
+
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 def test_obs_loss_and_sum_sq_match_oracle(dt):
     L, lb = lib()
@@ -134,7 +170,10 @@ def _oracle_iterations(truth, T_obs, mask, M0, om0, cfg, iters):
         par, _ = oracle.parents_levels(prob, T)
         _, g = I.obs_loss(T, T_obs, mask)
         gM, gom, _ = oracle.vjp(prob, T, par, g)
-        gM = gM + cfg.lam_G * I.tv(M, V.G_WEIGHTS)[1]
+        if cfg.tv_metric == "log_euclid":
+            gM = gM + cfg.lam_G * I.tv_log_euclid(M)[1]
+        else:
+            gM = gM + cfg.lam_G * I.tv(M, V.G_WEIGHTS)[1]
         gom = gom + cfg.lam_b * I.tv(om, V.B_WEIGHTS)[1]
         gsq = float(np.sum(gM * gM) + np.sum(gom * gom))
         method = 1 if cfg.method == "adam" else 0
@@ -153,19 +192,23 @@ def _oracle_iterations(truth, T_obs, mask, M0, om0, cfg, iters):
 # the arithmetic: the TV subgradient of a nearly flat field points wherever
 # rounding puts it, and Adam turns any such direction into a full step, so TV
 # enters only from a rough initial field (its kernel is checked exactly above).
-@pytest.mark.parametrize("method,max_norm,lam_G,rough,iso", [("adam", 0.5, 0.0, False, False),
-                                                              ("gd", 0.0, 0.0, False, False),
-                                                              ("gd", 0.0, 1e-2, True, False),
-                                                              ("adam", 0.0, 1e-2, True, False),
-                                                              ("adam", 0.5, 0.0, False, True)])
-def test_recovery_iterations_match_the_oracle(method, max_norm, lam_G, rough, iso):
+@pytest.mark.parametrize("method,max_norm,lam_G,rough,iso,tvm", [("adam", 0.5, 0.0, False, False, "frobenius"),
+                                                                  ("gd", 0.0, 0.0, False, False, "frobenius"),
+                                                                  ("gd", 0.0, 1e-2, True, False, "frobenius"),
+                                                                  ("adam", 0.0, 1e-2, True, False, "frobenius"),
+                                                                  ("adam", 0.5, 0.0, False, True, "frobenius"),
+                                                                  ("gd", 0.0, 1e-2, True, False, "log_euclid"),
+                                                                  ("adam", 0.0, 1e-2, True, False, "log_euclid")])
+def test_recovery_iterations_match_the_oracle(method, max_norm, lam_G, rough, iso, tvm):
     from paper_2603_00035_amd import inverse as V
     truth, T_obs, mask, M0, om0 = _isotropic_case(41, 37, 0.4, 1)
     if rough:
         M0 = M0 * np.random.default_rng(2).uniform(0.8, 1.2, M0.shape)
         M0[1] = 0.0
+        if tvm == "log_euclid":  # a rotated, anisotropic start so that log G is not diagonal
+            M0[1] = np.random.default_rng(3).uniform(-0.3, 0.3, M0[1].shape)
     cfg = V.InverseConfig(method=method, max_norm=max_norm, lam_G=lam_G, lam_b=0.0, lr_G=0.05, lr_b=0.02,
-                          isotropic=iso)
+                          isotropic=iso, tv_metric=tvm)
     iters = 4
     say(f"[recovery] {method} clip={max_norm} lam_G={lam_G} rough={rough} 41x37, {iters} iterations vs the oracle")
     dev = torch.device("cuda:0")
@@ -243,7 +286,10 @@ def _oracle_multi_iterations(fires, T_obs, masks, M0, om0, cfg, iters):
             _, g = I.obs_loss(T, To, mk)
             a, b, _ = oracle.vjp(prob, T, par, g)
             gM, gom = gM + a, gom + b
-        gM = gM + cfg.lam_G * I.tv(M, V.G_WEIGHTS)[1]
+        if cfg.tv_metric == "log_euclid":
+            gM = gM + cfg.lam_G * I.tv_log_euclid(M)[1]
+        else:
+            gM = gM + cfg.lam_G * I.tv(M, V.G_WEIGHTS)[1]
         gom = gom + cfg.lam_b * I.tv(om, V.B_WEIGHTS)[1]
         gsq = float(np.sum(gM * gM) + np.sum(gom * gom))
         method = 1 if cfg.method == "adam" else 0

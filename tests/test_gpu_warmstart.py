@@ -1,8 +1,16 @@
 """The learned warm start with the committed weights (trained by the project's
-own BF16 MFMA kernels on 20k cold solves of the 256^2 recipe): on held-out
-seeds the warm-started solve must reach the cold-start fixed point within 1e-5
-(the fixed point does not depend on the initial field), and the comparison of
-sweeps and time against the cold start is reported."""
+own BF16 MFMA kernels on 20k cold solves of the 256^2 recipe), on held-out
+seeds:
+  * the warm-started solve reaches the cold-start fixed point within 1e-5 (the
+    fixed point does not depend on the initial field);
+  * the residual monitor (EIK_WARM_FALLBACK) drops the network's field, whose
+    4 % error leaves every tile changing after the two probe rounds, and the
+    solve from the cold start then matches the cold solve; the loss is bounded
+    by the inference plus the two probe rounds;
+  * a warm field within rounding of the fixed point is kept and settles in the
+    probe rounds, so the monitor does not throw away good starts.
+The network cannot win on this workload: its inference alone costs several
+cold solves (reported, not asserted)."""
 import os
 
 import numpy as np
@@ -14,17 +22,56 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def test_warm_start_reaches_cold_fixed_point_and_reports_gain():
+@pytest.fixture(scope="module")
+def net():
     from paper_2603_00035_amd import warmstart as W
     from paper_2603_00035_amd.unet import UNet
     assert os.path.exists(W.WEIGHTS), "trained weights missing"
-    net = UNet()
-    net.load_state_dict(torch.load(W.WEIGHTS, weights_only=True))
-    seeds = list(range(1_000_000, 1_000_032))
+    n = UNet()
+    n.load_state_dict(torch.load(W.WEIGHTS, weights_only=True))
+    return n
+
+
+def test_warm_start_reaches_cold_fixed_point_and_falls_back(net):
+    from paper_2603_00035_amd import warmstart as W
+    seeds = list(range(1_000_000, 1_000_064))
+    W.evaluate(net, seeds[:32], chunk=32, log=lambda s: None)  # warm-up
     res = W.evaluate(net, seeds, chunk=32, log=say)
     say(f"[warm] cold {res['cold_s'] * 1e3:.1f} ms, {res['cold_sweeps_per_node']:.1f} sweeps/node; warm "
         f"{res['warm_s'] * 1e3:.1f} ms (incl. inference {res['infer_s'] * 1e3:.1f} ms), "
-        f"{res['warm_sweeps_per_node']:.1f} sweeps/node; with fallback {res['warm_fb_s'] * 1e3:.1f} ms; "
-        f"prediction mean rel err {np.mean(res['pred_rel_err_mean']):.2e}")
+        f"{res['warm_sweeps_per_node']:.1f} sweeps/node; with the monitor {res['warm_fb_s'] * 1e3:.1f} ms, "
+        f"{res['fallback_batches']}/{res['batches']} batches fell back; prediction mean rel err "
+        f"{np.mean(res['pred_rel_err_mean']):.2e}")
     assert res["max_rel_warm_vs_cold"] <= 1e-5
     assert np.mean(res["pred_rel_err_mean"]) < 0.2  # the network predicts T, not noise
+    # the monitor drops the network's field in every batch and the restarted
+    # solve matches the cold one: the two probe rounds on top of the cold
+    # solve's (host checks may add one interval of rounds that find nothing)
+    assert res["fallback_batches"] == res["batches"]
+    assert res["max_rel_fb_vs_cold"] <= 1e-5
+    assert all(c + 2 <= f <= c + 10 for f, c in zip(res["fb_rounds"], res["cold_rounds"]))
+    # bounded loss: inference + probe + cold solve, against inference + cold
+    # solve (generous for timing noise on a shared box)
+    assert res["warm_fb_s"] <= 1.5 * (res["cold_s"] + res["infer_s"])
+
+
+def test_monitor_keeps_a_good_warm_start():
+    from paper_2603_00035_amd import warmstart as W
+    from synthetic.fields import make_problem
+    dev = torch.device("cuda")
+    ps = [make_problem("c5", 1_000_100 + k) for k in range(8)]
+    M = torch.tensor(np.stack([p.M for p in ps]), dtype=torch.float32, device=dev)
+    om = torch.tensor(np.stack([p.omega for p in ps]), dtype=torch.float32, device=dev)
+    src = torch.full((len(ps), 4), -1, dtype=torch.int32)
+    for b, p in enumerate(ps):
+        src[b, :p.src_idx.size] = torch.tensor(p.src_idx)
+    src = src.to(dev)
+    Tc, _, stc, _ = W.solve_batch(M, om, src, ps[0].h, tol=1e-5)
+    g = torch.Generator(device=dev).manual_seed(0)
+    Tn = Tc * (1 + 1e-7 * torch.randn(Tc.shape, generator=g, device=dev))
+    Tw, _, stw, _ = W.solve_batch(M, om, src, ps[0].h, tol=1e-5, T_init=Tn, fallback=True)
+    say(f"[warm] near-exact start: {stw.rounds} rounds (cold {stc.rounds}), fell back {stw.fell_back}")
+    assert not stw.fell_back
+    assert stw.converged and stw.rounds <= 4
+    m = torch.isfinite(Tc) & (Tc > 0)
+    assert ((Tw - Tc).abs()[m] / Tc[m]).max().item() <= 1e-5

@@ -111,3 +111,72 @@ def test_isotropic_tie_is_the_frobenius_nearest_isotropic_metric():
         d = (m11 - gs) ** 2 + 2 * m12 ** 2 + (m22 - gs) ** 2
         assert P[0, j, i] == pytest.approx(gs[np.argmin(d)], abs=1e-4)
         assert P[1, j, i] == 0.0 and P[0, j, i] == P[2, j, i]
+
+
+# --- Log-Euclidean TV (App. learning details, Total Variation Regularization) --
+
+def _spd_field(rng, ny, nx, iso_frac=0.0):
+    A = rng.normal(size=(ny, nx, 2, 2))
+    G = A @ np.swapaxes(A, -1, -2) + 0.2 * np.eye(2)
+    iso = rng.uniform(size=(ny, nx)) < iso_frac
+    g = rng.uniform(0.5, 2.0, size=(ny, nx))
+    G[iso] = g[iso][:, None, None] * np.eye(2)
+    return np.stack([G[..., 0, 0], G[..., 0, 1], G[..., 1, 1]]), G
+
+
+def test_log_spd2_matches_scipy_logm():
+    import scipy.linalg
+    import torch
+    rng = np.random.default_rng(1)
+    M, G = _spd_field(rng, 6, 7, iso_frac=0.2)
+    P = I.log_spd2(torch.tensor(M)).numpy()
+    for j in range(6):
+        for i in range(7):
+            L = scipy.linalg.logm(G[j, i]).real
+            assert np.allclose([P[0, j, i], P[1, j, i], P[2, j, i]], [L[0, 0], L[0, 1], L[1, 1]], atol=1e-13)
+
+
+def test_log_euclid_tv_of_isotropic_fields_is_tv_of_log_g():
+    """G = g I: log G = log(g) I, so |grad log G|_F = sqrt(2) |grad log g|."""
+    rng = np.random.default_rng(2)
+    g = rng.uniform(0.5, 3.0, size=(5, 8))
+    M = np.stack([g, 0 * g, g])
+    val, _ = I.tv_log_euclid(M)
+    vlog, _ = I.tv(np.log(g)[None], [1.0])
+    assert val == pytest.approx(np.sqrt(2.0) * vlog, rel=1e-12)
+
+
+def test_log_euclid_tv_invariances():
+    """Invariant under one rotation applied at every node (G -> Q G Q^T) and
+    under one scale (log(a G) = log G + log(a) I, constant over the grid),
+    neither of which holds for the Frobenius variant."""
+    rng = np.random.default_rng(3)
+    M, G = _spd_field(rng, 5, 6)
+    v0, _ = I.tv_log_euclid(M)
+    c, s = np.cos(0.7), np.sin(0.7)
+    Q = np.array([[c, -s], [s, c]])
+    GR = Q @ G @ Q.T
+    v1, _ = I.tv_log_euclid(np.stack([GR[..., 0, 0], GR[..., 0, 1], GR[..., 1, 1]]))
+    v2, _ = I.tv_log_euclid(3.7 * M)
+    assert v1 == pytest.approx(v0, rel=1e-12)
+    assert v2 == pytest.approx(v0, rel=1e-12)
+    vf0, _ = I.tv(M, [1.0, 2.0, 1.0])
+    vf2, _ = I.tv(3.7 * M, [1.0, 2.0, 1.0])
+    assert vf2 == pytest.approx(3.7 * vf0, rel=1e-12)
+
+
+def test_log_euclid_tv_gradient_matches_central_differences():
+    """Every stored scalar (m12 enters both off-diagonal entries), including
+    isotropic nodes where the eigenvalues coincide."""
+    rng = np.random.default_rng(4)
+    M, _ = _spd_field(rng, 4, 5, iso_frac=0.3)
+    _, g = I.tv_log_euclid(M)
+    eps = 1e-6
+    for c in range(3):
+        for j in range(4):
+            for i in range(5):
+                Mp, Mm = M.copy(), M.copy()
+                Mp[c, j, i] += eps
+                Mm[c, j, i] -= eps
+                fd = (I.tv_log_euclid(Mp)[0] - I.tv_log_euclid(Mm)[0]) / (2 * eps)
+                assert g[c, j, i] == pytest.approx(fd, rel=1e-5, abs=1e-7), (c, j, i)
