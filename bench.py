@@ -34,6 +34,7 @@ exact fixed point and its gradient of the same loss.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -637,9 +638,10 @@ def main():
         loss = torch.zeros(1, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
 
-        def step(sink, adj_sink, t_ev):
+        def step(sink, adj_sink, t_ev, host=None):
             # one pass of the hot path, every stage a library call: projection,
             # forward, data term, adjoint, projection VJP
+            h0 = time.perf_counter()
             t_ev[0].record()
             Mp, omp = E.project(M0, om0)
             if mixed:
@@ -651,25 +653,34 @@ def main():
                 sink.append(st)
             dLdT = V.obs_loss(T, target, mask_u8, scratch, loss)
             t_ev[1].record()
+            h1 = time.perf_counter()
             if mixed:
                 gMp, gomp, _ = E.adjoint_mixed(Mp, omp, T, par, src, prob.h, dLdT, ws=ws, stats_out=adj_sink)
             else:
                 gMp, gomp, _ = E.adjoint(Mp, omp, T, par, None, src, prob.h, dLdT, ws=ws, stats_out=adj_sink)
             gM, gom = E.project_backward(M0, om0, gMp, gomp)
             t_ev[2].record()
+            if host is not None:
+                host.append((1e3 * (h1 - h0), 1e3 * (time.perf_counter() - h1)))
             return T, gM, gom
 
         for _ in range(args.warmup):
             step([], [], [torch.cuda.Event(enable_timing=True) for _ in range(3)])
         torch.cuda.synchronize()
-        sink, adj_sink = [], []
+        sink, adj_sink, host = [], [], []
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        # the interpreter's cyclic garbage collector is held off during the
+        # timed steps: a full collection stalls the submitting thread for tens
+        # of milliseconds, during which the GPU idles
+        gc.collect()
+        gc.disable()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            T, gM, gom = step(sink, adj_sink, evs[k])
+            T, gM, gom = step(sink, adj_sink, evs[k], host)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        gc.enable()
         assert all(s.converged for s in sink[(1 if precision == "mixed" else 0)::(2 if precision == "mixed" else 1)]), \
             "solve did not reach the tolerance"
         assert torch.isfinite(gM).all() and torch.isfinite(gom).all()
@@ -683,6 +694,7 @@ def main():
         # phase (FP32 rounds, FP64 rounds for the mixed path, adjoint rounds)
         per = len(sink) // args.steps
         steps = [{"fwd_ms": round(fwd[k], 3), "adj_ms": round(adj[k], 3), "step_ms": round(fwd[k] + adj[k], 3),
+                  "host_fwd_ms": round(host[k][0], 3), "host_adj_ms": round(host[k][1], 3),
                   "fwd_rounds": [s.rounds for s in sink[per * k:per * (k + 1)]],
                   "adj_rounds": adj_sink[k].rounds} for k in range(args.steps)]
         return dict(wall=wall, sink=sink, s32=s32, s64=s64, steps=steps,

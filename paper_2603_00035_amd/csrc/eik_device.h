@@ -178,9 +178,12 @@ __device__ __forceinline__ R local_update(const NodeConst<R> &k, const R Tn[8], 
 // Candidates of one sweep direction (the line sweep steps along +x, +y, -x,
 // -y for DIR = 0, 1, 2, 3). FULL: every candidate in the canonical order
 // (two-point 0..7, then one-point 0..7; first minimum wins). Otherwise only
-// the candidates whose donors sit on the line just updated or on the current
-// line: stencils 7+2 DIR .. 2+2 DIR and one-point donors 7+2 DIR .. 3+2 DIR
-// (mod 8); each stencil belongs to two of the four directions.
+// the candidates whose donors all sit on the line just updated: donors
+// 2 DIR, 2 DIR + 1, 2 DIR + 2 (mod 8) and the two stencils between them. Each
+// stencil then belongs to exactly one direction, the one that sweeps its
+// donors' line just before the node's, and each donor to one or two; the four
+// directions together cover every candidate, so a field no direction can
+// lower is a fixed point of the full update's minimum.
 template <typename R, int DIR, bool FULL>
 __device__ __forceinline__ R local_update_dir(const NodeConst<R> &k, const R Tn[8], int &code)
 {
@@ -224,8 +227,8 @@ __device__ __forceinline__ R local_update_dir(const NodeConst<R> &k, const R Tn[
         R b1 = inf;
         int c1 = kUnreached;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            const int s = (7 + 2 * DIR + q) & 7;
+        for (int q = 0; q < 3; ++q) {
+            const int s = (2 * DIR + q) & 7;
             const R t = Tn[s] + k.c1[s]; // +inf for an unreached donor
             if (t < b1) {
                 b1 = t;
@@ -233,8 +236,8 @@ __device__ __forceinline__ R local_update_dir(const NodeConst<R> &k, const R Tn[
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int s = (7 + 2 * DIR + q) & 7;
+        for (int q = 0; q < 2; ++q) {
+            const int s = (2 * DIR + q) & 7;
             const R Tp = Tn[s], Tq = Tn[(s + 1) & 7];
             if (Tp < b1 && Tq < b1) {
                 R t, m1, m2;
