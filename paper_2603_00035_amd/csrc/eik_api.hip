@@ -76,7 +76,8 @@ Layout layout(const Extent &e, int dtype)
     L.act = o;       o += align256(2 * NT * 4);
     L.act_count = o; o += align256((size_t)(kMaxRounds + 2) * 4);
     L.ctr = o;       o += align256(kCtrCount * 8);
-    L.Pt = o;        o += align256(5 * (size_t)e.nodes * rs);
+    // staged sweep inputs: parameters (and, in FP64, the metric roots in both orientations)
+    L.Pt = o;        o += align256((dtype == EIK_F64 ? 5 + 2 * 6 : 5) * (size_t)e.nodes * rs);
     L.lam = o;       o += align256((size_t)e.nodes * rs);
     L.w1 = o;        o += align256((size_t)e.nodes * rs);
     L.adjD = o;      o += align256((size_t)e.nodes * 2);

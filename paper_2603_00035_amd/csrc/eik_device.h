@@ -68,13 +68,33 @@ struct NodeConst {
     R det, h, inv_h, inv_m11, inv_m22;
 };
 
+// The square roots and reciprocals among a node's constants, which depend on
+// the metric alone: |(1,0)|_G, |(0,1)|_G, |(1,1)|_G, |(1,-1)|_G, 1/m11, 1/m22.
+// The sweeps read them from a copy staged once per solve.
+constexpr int kRoots = 6;
+
 template <typename R>
-__device__ __forceinline__ void node_const(R m11, R m12, R m22, R bx, R by, R h, R inv_h, NodeConst<R> &k)
+__device__ __forceinline__ void node_roots(R m11, R m12, R m22, R r[kRoots])
+{
+    const R dp = m11 + R(2) * m12 + m22; // |(1, 1)|_G^2
+    const R dm = m11 - R(2) * m12 + m22; // |(1,-1)|_G^2
+    r[0] = dsqrt(m11);
+    r[1] = dsqrt(m22);
+    r[2] = dsqrt(dp);
+    r[3] = dsqrt(dm);
+    r[4] = drcp(m11);
+    r[5] = drcp(m22);
+}
+
+// Constants from the metric, the drift and node_roots' values.
+template <typename R>
+__device__ __forceinline__ void node_const_pre(R m11, R m12, R m22, R bx, R by, const R r[kRoots], R h, R inv_h,
+                                               NodeConst<R> &k)
 {
     // displacements m_k = -offset_k: (1,-1) (1,0) (1,1) (0,1) (-1,1) (-1,0) (-1,-1) (0,-1)
     const R dp = m11 + R(2) * m12 + m22; // |(1, 1)|_G^2
     const R dm = m11 - R(2) * m12 + m22; // |(1,-1)|_G^2
-    const R sx = dsqrt(m11), sy = dsqrt(m22), sp = dsqrt(dp), sm = dsqrt(dm);
+    const R sx = r[0], sy = r[1], sp = r[2], sm = r[3];
     k.e[0] = dm; k.e[1] = m11; k.e[2] = dp; k.e[3] = m22;
     k.e[4] = dm; k.e[5] = m11; k.e[6] = dp; k.e[7] = m22;
     const R b0 = bx - by, b1 = bx, b2 = bx + by, b3 = by;
@@ -91,8 +111,16 @@ __device__ __forceinline__ void node_const(R m11, R m12, R m22, R bx, R by, R h,
     k.det = m11 * m22 - m12 * m12;
     k.h = h;
     k.inv_h = inv_h;
-    k.inv_m11 = drcp(m11);
-    k.inv_m22 = drcp(m22);
+    k.inv_m11 = r[4];
+    k.inv_m22 = r[5];
+}
+
+template <typename R>
+__device__ __forceinline__ void node_const(R m11, R m12, R m22, R bx, R by, R h, R inv_h, NodeConst<R> &k)
+{
+    R r[kRoots];
+    node_roots<R>(m11, m12, m22, r);
+    node_const_pre<R>(m11, m12, m22, bx, by, r, h, inv_h, k);
 }
 
 // Two-point candidate of stencil s (donors s and s+1 with times Tp, Tq).

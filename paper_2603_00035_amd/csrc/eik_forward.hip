@@ -61,17 +61,59 @@ __device__ __forceinline__ TileGeo tile_geo(const LaunchArgs &a, int t)
     return g;
 }
 
-// Transposed copy of the five parameter planes: Pt[5][nx][ny] per grid.
+// Staged per-node inputs of the sweeps, once per solve. The staging region
+// holds, for all grids, first the transposed planes Pt[cols][nx][ny] of each
+// grid at cols * off: the five parameters and, in FP64, node_roots' values;
+// then, in FP64, the row-major root planes Pc[kRoots][ny][nx] of each grid at
+// cols * n_nodes + kRoots * off. Column sweeps read Pt, row sweeps the
+// caller's M and omega (and Pc), so every load is coalesced. FP64 sweeps read
+// the roots instead of computing them in every line step (the correctly
+// rounded FP64 square root and reciprocal are instruction sequences); FP32
+// sweeps compute them (one instruction each), which costs less than the
+// six more loads per step.
+template <typename R>
+struct Staged {
+    static constexpr bool roots = sizeof(R) == 8;
+    static constexpr int cols = roots ? 5 + kRoots : 5;
+};
+
+template <typename R>
+__device__ __forceinline__ const R *staged_cols(const LaunchArgs &a, const R *Ptall, const GridDesc &gd)
+{
+    return Ptall + Staged<R>::cols * gd.off;
+}
+
+template <typename R>
+__device__ __forceinline__ const R *staged_roots_rows(const LaunchArgs &a, const R *Ptall, const GridDesc &gd)
+{
+    return Staged<R>::roots ? Ptall + Staged<R>::cols * a.n_nodes + kRoots * gd.off : nullptr;
+}
+
 template <typename R, int TH>
 __global__ __launch_bounds__(256) void k_stage(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
                                                R *__restrict__ Pt)
 {
+    constexpr int kCols = Staged<R>::cols;
     __shared__ R buf[TH][TW + 1];
     const TileGeo g = tile_geo<TH>(a, blockIdx.x);
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
-    for (int p = 0; p < 5; ++p) {
-        const R *src = p < 3 ? M + 3 * g.gd.off + p * n : om + 2 * g.gd.off + (p - 3) * n;
-        R *dst = Pt + 5 * g.gd.off + p * n;
+    const R *Mg = M + 3 * g.gd.off;
+    R *Pc = Pt + kCols * a.n_nodes + kRoots * g.gd.off;
+    if (Staged<R>::roots) { // row-major roots
+        for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+            const int r = idx / TW, c = idx - r * TW;
+            if (r >= g.h || c >= g.w) continue;
+            const size_t ad = (size_t)(g.j0 + r) * g.gd.nx + g.i0 + c;
+            R rt[kRoots];
+            node_roots<R>(Mg[ad], Mg[n + ad], Mg[2 * n + ad], rt);
+#pragma unroll
+            for (int q = 0; q < kRoots; ++q) Pc[q * n + ad] = rt[q];
+        }
+        __syncthreads(); // this block's root planes are read back below
+    }
+    for (int p = 0; p < kCols; ++p) {
+        const R *src = p < 3 ? Mg + p * n : (p < 5 ? om + 2 * g.gd.off + (p - 3) * n : Pc + (p - 5) * n);
+        R *dst = Pt + kCols * g.gd.off + p * n;
         for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
             const int r = idx / TW, c = idx - r * TW;
             if (r < g.h && c < g.w) buf[r][c] = src[(size_t)(g.j0 + r) * g.gd.nx + g.i0 + c];
@@ -204,7 +246,8 @@ __device__ __forceinline__ void wave_step_sync()
 // LEV: carry the active update's code and dependency level along with T.
 template <typename R, int TH, int DIR, bool FULL, bool LEV>
 __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict__ Mb, const R *__restrict__ Ob,
-                                          R *sT, int32_t *sL, uint8_t *sC, R tol, R h, R inv_h)
+                                          const R *__restrict__ Cb, R *sT, int32_t *sL, uint8_t *sC, R tol, R h,
+                                          R inv_h)
 {
     constexpr int LP = TW + 3;
     constexpr bool COL = (DIR & 1) == 0; // a column (fixed x) per step
@@ -221,6 +264,10 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
         const size_t ad =
             COL ? (size_t)(g.i0 + pos) * g.gd.ny + (g.j0 + lc) : (size_t)(g.j0 + pos) * g.gd.nx + (g.i0 + lc);
         p[0] = Mb[ad]; p[1] = Mb[n + ad]; p[2] = Mb[2 * n + ad]; p[3] = Ob[ad]; p[4] = Ob[n + ad];
+        if (Staged<R>::roots) {
+#pragma unroll
+            for (int q = 0; q < kRoots; ++q) p[5 + q] = Cb[q * n + ad];
+        }
     };
     bool changed = false;
     auto step = [&](int s, const R *q) {
@@ -230,7 +277,8 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
         const int cc = cj * kBytePitch + ci;
         if (lane < span && sC[cc] != kSource) {
             NodeConst<R> k;
-            node_const<R>(q[0], q[1], q[2], q[3], q[4], h, inv_h, k);
+            if (Staged<R>::roots) node_const_pre<R>(q[0], q[1], q[2], q[3], q[4], q + 5, h, inv_h, k);
+            else node_const<R>(q[0], q[1], q[2], q[3], q[4], h, inv_h, k);
             R Tn[8];
 #pragma unroll
             for (int d = 0; d < 8; ++d) Tn[d] = sT[(cj + 1 + nb_dy(d)) * LP + (ci + 1 + nb_dx(d))];
@@ -273,7 +321,7 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
     // line is updated. Two steps per iteration alternate the buffers, and each
     // buffer is refilled only after its last use, so no register copy (and no
     // wait for the loads in flight) sits between steps.
-    R X[5], Y[5];
+    R X[Staged<R>::cols], Y[Staged<R>::cols];
     load(0, X);
     for (int s = 0; s < len; s += 2) {
         load(s + 1, Y);
@@ -311,7 +359,8 @@ __device__ __forceinline__ Visit visit_tile(const LaunchArgs &a, int t, const R 
     int32_t *level = LEV ? levall + g.gd.off : nullptr;
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
     const R *Mg = M + 3 * g.gd.off, *Og = om + 2 * g.gd.off; // row-major planes
-    const R *Pt = Ptall + 5 * g.gd.off, *Pto = Pt + 3 * n;   // column-major copy
+    const R *Pt = staged_cols(a, Ptall, g.gd), *Pto = Pt + 3 * n, *Ptr = Pt + 5 * n; // column-major copy
+    const R *Pc = staged_roots_rows(a, Ptall, g.gd);
     const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
 
     load_tile_halo<R, TH, LP>(T, sT, g.gd.nx, g.gd.ny, g.i0, g.j0, inf_v<R>());
@@ -324,10 +373,10 @@ __device__ __forceinline__ Visit visit_tile(const LaunchArgs &a, int t, const R 
     while (quiet < 4 && sweeps < max_sweeps) {
         bool ch;
         switch (sweeps & 3) {
-        case 0: ch = sweep_dir<R, TH, 0, FULL, LEV>(g, Pt, Pto, sT, sL, sC, tol, h, inv_h); break;
-        case 1: ch = sweep_dir<R, TH, 1, FULL, LEV>(g, Mg, Og, sT, sL, sC, tol, h, inv_h); break;
-        case 2: ch = sweep_dir<R, TH, 2, FULL, LEV>(g, Pt, Pto, sT, sL, sC, tol, h, inv_h); break;
-        default: ch = sweep_dir<R, TH, 3, FULL, LEV>(g, Mg, Og, sT, sL, sC, tol, h, inv_h); break;
+        case 0: ch = sweep_dir<R, TH, 0, FULL, LEV>(g, Pt, Pto, Ptr, sT, sL, sC, tol, h, inv_h); break;
+        case 1: ch = sweep_dir<R, TH, 1, FULL, LEV>(g, Mg, Og, Pc, sT, sL, sC, tol, h, inv_h); break;
+        case 2: ch = sweep_dir<R, TH, 2, FULL, LEV>(g, Pt, Pto, Ptr, sT, sL, sC, tol, h, inv_h); break;
+        default: ch = sweep_dir<R, TH, 3, FULL, LEV>(g, Mg, Og, Pc, sT, sL, sC, tol, h, inv_h); break;
         }
         ++sweeps;
         quiet = __ballot(ch) ? 0 : quiet + 1;
@@ -420,7 +469,8 @@ __device__ __forceinline__ Visit visit_tile_cd(const LaunchArgs &a, int t, const
     R *T = Tall + g.gd.off;
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
     const R *Mg = M + 3 * g.gd.off, *Og = om + 2 * g.gd.off;
-    const R *Pt = Ptall + 5 * g.gd.off, *Pto = Pt + 3 * n;
+    const R *Pt = staged_cols(a, Ptall, g.gd), *Pto = Pt + 3 * n, *Ptr = Pt + 5 * n;
+    const R *Pc = staged_roots_rows(a, Ptall, g.gd);
     const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
 
     load_tile_halo<R, TH, LP>(T, sT, g.gd.nx, g.gd.ny, g.i0, g.j0, inf_v<R>());
@@ -432,10 +482,10 @@ __device__ __forceinline__ Visit visit_tile_cd(const LaunchArgs &a, int t, const
     while (!quiet && cycles < max_cycles) {
         bool ch;
         switch (wave) { // uniform per wave
-        case 0: ch = sweep_dir<R, TH, 0, FULL, false>(g, Pt, Pto, sT, nullptr, sC, tol, h, inv_h); break;
-        case 1: ch = sweep_dir<R, TH, 1, FULL, false>(g, Mg, Og, sT, nullptr, sC, tol, h, inv_h); break;
-        case 2: ch = sweep_dir<R, TH, 2, FULL, false>(g, Pt, Pto, sT, nullptr, sC, tol, h, inv_h); break;
-        default: ch = sweep_dir<R, TH, 3, FULL, false>(g, Mg, Og, sT, nullptr, sC, tol, h, inv_h); break;
+        case 0: ch = sweep_dir<R, TH, 0, FULL, false>(g, Pt, Pto, Ptr, sT, nullptr, sC, tol, h, inv_h); break;
+        case 1: ch = sweep_dir<R, TH, 1, FULL, false>(g, Mg, Og, Pc, sT, nullptr, sC, tol, h, inv_h); break;
+        case 2: ch = sweep_dir<R, TH, 2, FULL, false>(g, Pt, Pto, Ptr, sT, nullptr, sC, tol, h, inv_h); break;
+        default: ch = sweep_dir<R, TH, 3, FULL, false>(g, Mg, Og, Pc, sT, nullptr, sC, tol, h, inv_h); break;
         }
         ++cycles;
         quiet = !__syncthreads_or(ch ? 1 : 0);
@@ -775,7 +825,7 @@ __device__ __forceinline__ Visit visit_tile_split(const LaunchArgs &a, int t, co
     R *T = Tall + g.gd.off;
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
     const R *Mg = M + 3 * g.gd.off, *Og = om + 2 * g.gd.off;
-    const R *Pt = Ptall + 5 * g.gd.off, *Pto = Pt + 3 * n;
+    const R *Pt = staged_cols(a, Ptall, g.gd), *Pto = Pt + 3 * n;
     const R h = R(g.gd.h), inv_h = R(1) / R(g.gd.h);
 
     if (threadIdx.x == 0) *sbits = 0;
