@@ -178,8 +178,8 @@ int eik_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *
  * forbid it): the same solve, arguments and results as eik_forward, with the
  * workspace taken from a fixed array the library holds on each GPU for the
  * life of the process (eik_noalloc_max_workspace_bytes(), 64 MiB: grids whose
- * eik_workspace_bytes fit, about 790 000 nodes in FP32 and 400 000 in FP64,
- * 512 x 512 in either). Larger grids are rejected with EIK_EWORKSPACE before anything runs;
+ * eik_workspace_bytes fit, about 1 850 000 nodes (1360 x 1360) in FP32 and
+ * 407 000 (638 x 638) in FP64, 512 x 512 in either). Larger grids are rejected with EIK_EWORKSPACE before anything runs;
  * EIK_TIME_KERNELS is rejected with EIK_EINVAL. The call allocates nothing.
  * Every call on one GPU shares that GPU's array: calls that overlap on one
  * GPU (other streams or host threads) race, and must be serialised by the
