@@ -23,7 +23,11 @@
  *               grid B x 2H x 2W, y(2y+a, 2x+c) = sum_ci x(y, x) W[2a+c][co][ci];
  *   EIKU_DOWN2  the data-gradient of EIKU_UP2: input grid B x 2H x 2W, output grid
  *               B x H x W, y(p) = sum_{a, c, ci} x(2y+a, 2x+c) W[2a+c][co][ci].
- * Cin and Cout must be multiples of 16 (pad channels with zeros).
+ * Cin and Cout must be multiples of 16 (pad channels with zeros). The
+ * convolutions and the 3x3 weight gradient move 8 channels per 16-byte
+ * access: x (and dy) channel strides and offsets must be multiples of 8 and
+ * x, w (dy) 16-byte aligned; y strides and offsets multiples of 4 and y
+ * 8-byte aligned. Other layouts are rejected with -1.
  */
 #ifndef EIK_UNET_H
 #define EIK_UNET_H

@@ -1,13 +1,20 @@
 // unet.hip -- BF16 MFMA kernels of the learned warm start (gfx950).
 //
-// The convolutions are implicit GEMMs on v_mfma_f32_16x16x16bf16: the M
-// dimension runs over pixels (NHWC, batch folded in), N over output channels,
-// K over (tap, input channel). A 64-lane wave owns 16 pixels x 16*NT output
-// channels; each lane feeds 4 consecutive channels of one pixel (8-byte load)
-// and 4 consecutive input channels of one output channel's weights, and the
-// accumulators stay in FP32. The weight gradient is the GEMM with K running
-// over pixels: one wave per (pixel chunk, tap, 16x16 channel tile), partial
-// sums added into FP32 gradients with atomics.
+// The convolutions are implicit GEMMs over output channels x pixels (NHWC,
+// batch folded in) with K over (tap, input channel), accumulated in FP32.
+// k_conv_lds (3x3 convolution, 2x2 transposed convolution and its data
+// gradient, the 2x2 stride-2 convolution): a workgroup owns an 8 x 32 tile of
+// output pixels (of input pixels for the transposed convolution) and 16 NT
+// output channels. Per slice of KC input channels it stages the tile's input
+// patch and the slice of the weights in LDS, loads of the next slice in flight
+// while the current one is used; each wave runs 2 rows x 32 pixels through
+// v_mfma_f32_16x16x32_bf16 (v_mfma_f32_16x16x16_bf16 for 16-channel slices),
+// weights as the A operand and pixels as B, so a lane ends up with 4
+// consecutive channels of one pixel and stores them as one 8-byte word.
+// The weight gradients are GEMMs with K running over pixels: k_wgrad3_lds
+// stages pixel tiles of dy and x in LDS transposed to channel-major rows;
+// k_wgrad_up2 (transposed convolution) reads its operands from global memory.
+// Partial sums go to the FP32 gradients with atomics.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,17 +37,6 @@ __device__ __forceinline__ bf16 f2bf(float f)
     return (bf16)(u >> 16);
 }
 
-__device__ __forceinline__ s4 load4(const bf16 *p)
-{
-    const uint2 v = *reinterpret_cast<const uint2 *>(p);
-    s4 r;
-    r[0] = (short)(v.x & 0xffff);
-    r[1] = (short)(v.x >> 16);
-    r[2] = (short)(v.y & 0xffff);
-    r[3] = (short)(v.y >> 16);
-    return r;
-}
-
 struct ConvArgs {
     const bf16 *x;
     const bf16 *w;
@@ -50,69 +46,199 @@ struct ConvArgs {
     int B, H, W, Cin, Cout, relu;
 };
 
-template <int MODE, int NT>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs a)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t npix = (int64_t)a.B * a.H * a.W;
-    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-    if (p0 >= npix) return; // no workgroup barrier below
-    const int co0 = blockIdx.y * 16 * NT;
-    const int r = lane & 15, kq = lane >> 4;
-    int64_t pa = p0 + r;
-    const bool va = pa < npix;
-    if (!va) pa = npix - 1;
-    const int xx = (int)(pa % a.W);
-    const int64_t tt = pa / a.W;
-    const int yy = (int)(tt % a.H);
-    const int bb = (int)(tt / a.H);
-    f4 acc[NT];
+// ---------------------------------------------------------------------------
+// LDS-staged convolution (EIKU_CONV3, EIKU_UP2).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kTileY = 8, kTileX = 32; // pixels per workgroup: 4 waves x 2 rows x 32 columns
+
+// Patch geometry per mode: EIKU_CONV3 reads the output tile plus a one-pixel
+// halo, EIKU_UP2 the input tile itself (its pixel grid is the input's), and
+// EIKU_DOWN2 the 2x finer input region under the output tile.
+template <int MODE, int KC, int NT> struct LdsConv {
+    static constexpr int HALO = MODE == EIKU_CONV3 ? 1 : 0;
+    static constexpr int SCALE = MODE == EIKU_DOWN2 ? 2 : 1;
+    static constexpr int PY = SCALE * kTileY + 2 * HALO, PX = SCALE * kTileX + 2 * HALO;
+    static constexpr int NPATCH = PY * PX;
+    // staged row pitch in bf16: 16 lanes reading 16 consecutive rows then hit
+    // 16 disjoint groups of 4 banks (pitch 40 or 24 elements = 20 or 12 banks)
+    static constexpr int PITCH = KC + 8;
+    // taps staged per step (EIKU_UP2: the step's own tap)
+    static constexpr int TAPS = MODE == EIKU_CONV3 ? 9 : (MODE == EIKU_DOWN2 ? 4 : 1);
+    static constexpr int COT = 16 * NT;
+    static constexpr int U16 = KC / 8; // 16-byte units per staged row
+};
+
+template <int KC> struct Frag;
+template <> struct Frag<16> {
+    typedef s4 type;
+    static __device__ __forceinline__ type load(const uint16_t *p)
+    {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+        return __builtin_bit_cast(type, v);
+    }
+    static __device__ __forceinline__ f4 mma(type a, type b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Frag<32> {
+    typedef bf8 type;
+    static __device__ __forceinline__ type load(const uint16_t *p)
+    {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+        return __builtin_bit_cast(type, v);
+    }
+    static __device__ __forceinline__ f4 mma(type a, type b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16); }
+
+// The staging of one step: the patch's slice of KC input channels (skipped
+// when the slice is already resident) and the weights of the step's taps for
+// the workgroup's output channels, loaded into registers first so that every
+// load of the step is in flight at once, then written to LDS.
+template <int MODE, int KC, int NT> struct Staging {
+    using G = LdsConv<MODE, KC, NT>;
+    static constexpr int NP = (G::NPATCH * G::U16 + 255) / 256;
+    static constexpr int NW = (G::TAPS * G::COT * G::U16 + 255) / 256;
+    uint4 p[NP], w[NW];
+
+    __device__ __forceinline__ void load(const ConvArgs &a, int t, int b, int x0, int y0, int co0, int c0, int wtap,
+                                         bool patch)
+    {
+        if (patch) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
-    const s4 zero = s4{0, 0, 0, 0};
-    constexpr int NTAP = MODE == EIKU_CONV3 ? 9 : (MODE == EIKU_UP2 ? 1 : 4);
-    for (int ti = 0; ti < NTAP; ++ti) {
-        const int tap = MODE == EIKU_UP2 ? (int)blockIdx.z : ti;
-        int64_t pin = pa;
-        bool v = va;
-        if (MODE == EIKU_CONV3) {
-            const int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
-            v = v && sy >= 0 && sy < a.H && sx >= 0 && sx < a.W;
-            pin = ((int64_t)bb * a.H + sy) * a.W + sx;
-        } else if (MODE == EIKU_DOWN2) {
-            const int sy = 2 * yy + (tap >> 1), sx = 2 * xx + (tap & 1);
-            pin = ((int64_t)bb * 2 * a.H + sy) * (2 * a.W) + sx;
+            for (int i = 0; i < NP; ++i) {
+                const int u = t + 256 * i;
+                p[i] = uint4{0u, 0u, 0u, 0u};
+                if (u < G::NPATCH * G::U16) {
+                    const int pp = u / G::U16, q = u - pp * G::U16;
+                    const int py = pp / G::PX, px = pp - py * G::PX;
+                    const int gy = G::SCALE * y0 + py - G::HALO, gx = G::SCALE * x0 + px - G::HALO;
+                    const int hin = G::SCALE * a.H, win = G::SCALE * a.W;
+                    if (gy >= 0 && gy < hin && gx >= 0 && gx < win)
+                        p[i] = *reinterpret_cast<const uint4 *>(a.x + (((int64_t)b * hin + gy) * win + gx) * a.x_cs +
+                                                                a.x_co + c0 + 8 * q);
+                }
+            }
         }
-        const bf16 *xr = a.x + (v ? pin : 0) * a.x_cs + a.x_co + 4 * kq;
-        const bf16 *wr = a.w + ((int64_t)tap * a.Cout + co0 + r) * a.Cin + 4 * kq;
-        for (int cb = 0; cb < a.Cin; cb += 16) {
-            const s4 av = v ? load4(xr + cb) : zero;
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const s4 bv = load4(wr + (int64_t)nt * 16 * a.Cin + cb);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nt], 0, 0, 0);
+        for (int i = 0; i < NW; ++i) {
+            const int u = t + 256 * i;
+            if (u < G::TAPS * G::COT * G::U16) {
+                const int q = u % G::U16, r = u / G::U16;
+                const int col = r % G::COT, tp = r / G::COT;
+                const int tap = MODE == EIKU_UP2 ? wtap : tp;
+                w[i] = *reinterpret_cast<const uint4 *>(a.w + ((int64_t)tap * a.Cout + co0 + col) * a.Cin + c0 + 8 * q);
             }
         }
     }
+
+    __device__ __forceinline__ void store(uint16_t *s_patch, uint16_t *s_w, int t, bool patch) const
+    {
+        if (patch) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int col = co0 + nt * 16 + r;
-        const float bias = a.bias ? a.bias[col] : 0.f;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t po = p0 + 4 * kq + i;
-            if (po >= npix) continue;
-            float val = acc[nt][i] + bias;
-            if (a.relu) val = fmaxf(val, 0.f);
-            int64_t pout = po;
-            if (MODE == EIKU_UP2) {
-                const int ox = (int)(po % a.W);
-                const int64_t ot = po / a.W;
-                const int oy = (int)(ot % a.H), ob = (int)(ot / a.H);
-                const int tap = (int)blockIdx.z;
-                pout = ((int64_t)ob * 2 * a.H + 2 * oy + (tap >> 1)) * (2 * a.W) + 2 * ox + (tap & 1);
+            for (int i = 0; i < NP; ++i) {
+                const int u = t + 256 * i;
+                if (u < G::NPATCH * G::U16) {
+                    const int pp = u / G::U16, q = u - pp * G::U16;
+                    *reinterpret_cast<uint4 *>(s_patch + pp * G::PITCH + 8 * q) = p[i];
+                }
             }
-            a.y[pout * a.y_cs + a.y_co + col] = f2bf(val);
+        }
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const int u = t + 256 * i;
+            if (u < G::TAPS * G::COT * G::U16) {
+                const int q = u % G::U16, r = u / G::U16;
+                *reinterpret_cast<uint4 *>(s_w + r * G::PITCH + 8 * q) = w[i];
+            }
+        }
+    }
+};
+
+// grid: x = B * tiles_y * tiles_x, y = Cout / (16 NT). The steps run over the
+// slices of KC input channels; for EIKU_UP2 over (tap, slice) pairs, each tap's
+// outputs (one of the four interleaved sub-grids) stored after its last slice,
+// so the four sub-grids of a tile are written by one workgroup close in time.
+template <int MODE, int KC, int NT>
+__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
+{
+    using G = LdsConv<MODE, KC, NT>;
+    using F = Frag<KC>;
+    __shared__ __attribute__((aligned(16))) uint16_t s_patch[G::NPATCH * G::PITCH];
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[G::TAPS * G::COT * G::PITCH];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int tiles_x = (a.W + kTileX - 1) / kTileX, tiles_y = (a.H + kTileY - 1) / kTileY;
+    const int bx = (int)(blockIdx.x % tiles_x);
+    const int rest = (int)(blockIdx.x / tiles_x);
+    const int by = rest % tiles_y, b = rest / tiles_y;
+    const int x0 = bx * kTileX, y0 = by * kTileY;
+    const int co0 = blockIdx.y * G::COT;
+    const int n = lane & 15, kq = lane >> 4;
+    const int nch = a.Cin / KC;
+    const int nsteps = (MODE == EIKU_UP2 ? 4 : 1) * nch;
+    f4 acc[4][NT];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[f][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    Staging<MODE, KC, NT> stg;
+    stg.load(a, t, b, x0, y0, co0, 0, 0, true);
+    for (int s = 0; s < nsteps; ++s) {
+        const int ci = s % nch, utap = s / nch;
+        const bool patch = nch > 1 || s == 0; // one slice: the patch stays resident for every tap
+        __syncthreads(); // the previous step's readers are done
+        stg.store(s_patch, s_w, t, patch);
+        __syncthreads();
+        if (s + 1 < nsteps) {
+            const int cn = (s + 1) % nch;
+            stg.load(a, t, b, x0, y0, co0, cn * KC, (s + 1) / nch, nch > 1);
+        }
+#pragma unroll 1
+        for (int tp = 0; tp < G::TAPS; ++tp) {
+            const int dy = MODE == EIKU_CONV3 ? tp / 3 : (MODE == EIKU_DOWN2 ? tp >> 1 : 0);
+            const int dx = MODE == EIKU_CONV3 ? tp % 3 : (MODE == EIKU_DOWN2 ? tp & 1 : 0);
+            typename F::type wa[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) wa[nt] = F::load(s_w + (tp * G::COT + nt * 16 + n) * G::PITCH + kq * (KC / 4));
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int r = 2 * wave + (f >> 1), cx = 16 * (f & 1) + n;
+                const int prow = G::SCALE * r + dy, pcol = G::SCALE * cx + dx;
+                const typename F::type xb = F::load(s_patch + (prow * G::PX + pcol) * G::PITCH + kq * (KC / 4));
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[f][nt] = F::mma(wa[nt], xb, acc[f][nt]);
+            }
+        }
+        if (ci != nch - 1) continue;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int gy = y0 + 2 * wave + (f >> 1), gx = x0 + 16 * (f & 1) + n;
+            if (gy < a.H && gx < a.W) {
+                const int64_t pout =
+                    MODE == EIKU_UP2 ? ((int64_t)b * 2 * a.H + 2 * gy + (utap >> 1)) * (2 * a.W) + 2 * gx + (utap & 1)
+                                     : ((int64_t)b * a.H + gy) * a.W + gx;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int col = co0 + nt * 16 + 4 * kq;
+                    float v[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        v[i] = acc[f][nt][i] + (a.bias ? a.bias[col + i] : 0.f);
+                        if (a.relu) v[i] = fmaxf(v[i], 0.f);
+                    }
+                    *reinterpret_cast<uint2 *>(a.y + pout * a.y_cs + a.y_co + col) =
+                        uint2{pack2(v[0], v[1]), pack2(v[2], v[3])};
+                }
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[f][nt] = f4{0.f, 0.f, 0.f, 0.f};
         }
     }
 }
@@ -126,8 +252,10 @@ struct WgradArgs {
     int64_t chunk;
 };
 
-template <int MODE>
-__global__ __launch_bounds__(64) void k_wgrad(WgradArgs a)
+// Weight gradient of the transposed convolution, dW[tap][co][ci] = sum over
+// input pixels p of dy(2p + d_tap, co) x(p, ci): one wave per (pixel chunk,
+// tap, 16x16 channel tile), partial sums added with atomics.
+__global__ __launch_bounds__(64) void k_wgrad_up2(WgradArgs a)
 {
     const int lane = threadIdx.x;
     const int r = lane & 15, kq = lane >> 4;
@@ -150,23 +278,142 @@ __global__ __launch_bounds__(64) void k_wgrad(WgradArgs a)
             const int xx = (int)(pc % a.W);
             const int64_t tt = pc / a.W;
             const int yy = (int)(tt % a.H), bb = (int)(tt / a.H);
-            int64_t pdy = pc, pin = pc;
-            bool vin = v;
-            if (MODE == EIKU_CONV3) {
-                const int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
-                vin = vin && sy >= 0 && sy < a.H && sx >= 0 && sx < a.W;
-                pin = ((int64_t)bb * a.H + sy) * a.W + sx;
-            } else { // EIKU_UP2: x on this grid, dy on the doubled grid
-                pdy = ((int64_t)bb * 2 * a.H + 2 * yy + (tap >> 1)) * (2 * a.W) + 2 * xx + (tap & 1);
-            }
+            const int64_t pdy = ((int64_t)bb * 2 * a.H + 2 * yy + (tap >> 1)) * (2 * a.W) + 2 * xx + (tap & 1);
             av[j] = v ? (short)a.dy[pdy * a.dy_cs + a.dy_co + co0 + r] : (short)0;
-            bv[j] = vin ? (short)a.x[pin * a.x_cs + a.x_co + ci0 + r] : (short)0;
+            bv[j] = v ? (short)a.x[pc * a.x_cs + a.x_co + ci0 + r] : (short)0;
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         atomicAdd(&a.dw[((int64_t)tap * a.Cout + co0 + 4 * kq + i) * a.Cin + ci0 + r], acc[i]);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged weight gradient of the 3x3 convolution:
+//   dW[tap][co][ci] = sum_p dy(p, co) x(p + d_tap, ci)
+// a GEMM per tap with K over pixels. A workgroup owns a block of 16 CT output
+// x 16 IT input channels and a run of 8 x 32 pixel tiles; per tile it stages
+// dy (256 pixels) and the x patch (10 x 34 pixels) in LDS transposed to
+// channel-major rows, so a lane's MFMA operand (8 consecutive pixels of one
+// channel) is one 16-byte read; the tap's column shift of the x operand is
+// taken from two aligned reads in registers. Wave w takes the tile's rows
+// 2w, 2w+1 (one 32-pixel K step each) for all taps and channel tiles; the
+// partial sums go to dw with one atomic per element and wave at the end.
+// ---------------------------------------------------------------------------
+constexpr int kWdPitch = 264; // dy row per channel: 256 pixels + 8 (an odd number of 16-byte bank groups)
+constexpr int kWxCols = 40;   // x patch row: 34 columns + 6
+constexpr int kWxPlane = 408; // x patch per channel: 10 rows x 40 + 8 (an odd number of 16-byte bank groups)
+
+template <int CT, int IT>
+__global__ __launch_bounds__(256) void k_wgrad3_lds(WgradArgs a, int tiles_per_wg)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t s_dy[CT * 16 * kWdPitch];
+    __shared__ __attribute__((aligned(16))) uint16_t s_x[IT * 16 * kWxPlane];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int n = lane & 15, kq = lane >> 4;
+    const int cblocks = a.Cout / (16 * CT);
+    const int co0 = (int)(blockIdx.y % cblocks) * 16 * CT, ci0 = (int)(blockIdx.y / cblocks) * 16 * IT;
+    const int tiles_x = (a.W + kTileX - 1) / kTileX, tiles_y = (a.H + kTileY - 1) / kTileY;
+    const int64_t ntiles = (int64_t)a.B * tiles_y * tiles_x;
+    const int64_t t0 = (int64_t)blockIdx.x * tiles_per_wg;
+    const int64_t t1 = t0 + tiles_per_wg < ntiles ? t0 + tiles_per_wg : ntiles;
+    f4 acc[9][CT][IT];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int i = 0; i < IT; ++i) acc[k][c][i] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int bx = (int)(tile % tiles_x);
+        const int64_t rest = tile / tiles_x;
+        const int by = (int)(rest % tiles_y), b = (int)(rest / tiles_y);
+        const int x0 = bx * kTileX, y0 = by * kTileY;
+        __syncthreads(); // the previous tile's readers are done
+        // dy: pairs of horizontally adjacent pixels x 8-channel groups; each
+        // channel's two values go to LDS as one 32-bit word
+        for (int u = t; u < 128 * 2 * CT; u += 256) {
+            const int pr = u / (2 * CT), q = u - pr * (2 * CT);
+            const int px = 2 * pr, r = px / kTileX, c = px - r * kTileX;
+            const int gy = y0 + r, gx = x0 + c;
+            uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+            if (gy < a.H) {
+                const bf16 *row = a.dy + ((int64_t)b * a.H + gy) * a.W * a.dy_cs + a.dy_co + co0 + 8 * q;
+                if (gx < a.W) v0 = *reinterpret_cast<const uint4 *>(row + (int64_t)gx * a.dy_cs);
+                if (gx + 1 < a.W) v1 = *reinterpret_cast<const uint4 *>(row + (int64_t)(gx + 1) * a.dy_cs);
+            }
+            const uint32_t e0[4] = {v0.x, v0.y, v0.z, v0.w}, e1[4] = {v1.x, v1.y, v1.z, v1.w};
+            uint32_t *dst = reinterpret_cast<uint32_t *>(s_dy + (8 * q) * kWdPitch + px);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                dst[(2 * j) * (kWdPitch / 2)] = (e0[j] & 0xffffu) | (e1[j] << 16);
+                dst[(2 * j + 1) * (kWdPitch / 2)] = (e0[j] >> 16) | (e1[j] & 0xffff0000u);
+            }
+        }
+        // x patch rows y0-1 .. y0+8, columns x0-1 .. x0+32, zero outside the image
+        for (int u = t; u < 170 * 2 * IT; u += 256) {
+            const int pr = u / (2 * IT), q = u - pr * (2 * IT);
+            const int py = pr / 17, pc = 2 * (pr - py * 17);
+            const int gy = y0 + py - 1, gx = x0 + pc - 1;
+            uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+            if (gy >= 0 && gy < a.H) {
+                const bf16 *row = a.x + ((int64_t)b * a.H + gy) * a.W * a.x_cs + a.x_co + ci0 + 8 * q;
+                if (gx >= 0 && gx < a.W) v0 = *reinterpret_cast<const uint4 *>(row + (int64_t)gx * a.x_cs);
+                if (gx + 1 >= 0 && gx + 1 < a.W) v1 = *reinterpret_cast<const uint4 *>(row + (int64_t)(gx + 1) * a.x_cs);
+            }
+            const uint32_t e0[4] = {v0.x, v0.y, v0.z, v0.w}, e1[4] = {v1.x, v1.y, v1.z, v1.w};
+            uint32_t *dst = reinterpret_cast<uint32_t *>(s_x + (8 * q) * kWxPlane + py * kWxCols + pc);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                dst[(2 * j) * (kWxPlane / 2)] = (e0[j] & 0xffffu) | (e1[j] << 16);
+                dst[(2 * j + 1) * (kWxPlane / 2)] = (e0[j] >> 16) | (e1[j] & 0xffff0000u);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int r = 2 * wave + rr;
+            bf8 dv[CT];
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                dv[c] = Frag<32>::load(s_dy + (c * 16 + n) * kWdPitch + r * kTileX + 8 * kq);
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int ty = tap / 3, tx = tap % 3;
+#pragma unroll
+                for (int i = 0; i < IT; ++i) {
+                    const uint16_t *src = s_x + (i * 16 + n) * kWxPlane + (r + ty) * kWxCols + 8 * kq;
+                    const uint4 lo = *reinterpret_cast<const uint4 *>(src);
+                    uint4 w;
+                    if (tx == 0) {
+                        w = lo;
+                    } else {
+                        const uint4 hi = *reinterpret_cast<const uint4 *>(src + 8);
+                        if (tx == 2)
+                            w = uint4{lo.y, lo.z, lo.w, hi.x};
+                        else
+                            w = uint4{(lo.x >> 16) | (lo.y << 16), (lo.y >> 16) | (lo.z << 16),
+                                      (lo.z >> 16) | (lo.w << 16), (lo.w >> 16) | (hi.x << 16)};
+                    }
+                    const bf8 xv = __builtin_bit_cast(bf8, w);
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) acc[tap][c][i] = Frag<32>::mma(dv[c], xv, acc[tap][c][i]);
+                }
+            }
+        }
+    }
+    if (t0 >= t1) return;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int i = 0; i < IT; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    atomicAdd(&a.dw[((int64_t)tap * a.Cout + co0 + c * 16 + 4 * kq + e) * a.Cin + ci0 + i * 16 + n],
+                              acc[tap][c][i][e]);
 }
 
 // ---------------------------------------------------------------------------
@@ -418,22 +665,31 @@ int eiku_conv_fwd(int32_t mode, int32_t B, int32_t H, int32_t W, const uint16_t 
                   int32_t y_co, int32_t Cout, hipStream_t st)
 {
     if (B < 1 || H < 1 || W < 1 || Cin < 16 || Cin % 16 || Cout < 16 || Cout % 16 || !x || !w || !y) return -1;
-    if ((x_cs | x_co | y_co) % 4 || x_co + Cin > x_cs || y_co + Cout > y_cs) return -1;
+    if ((x_cs | x_co) % 8 || (y_cs | y_co) % 4 || x_co + Cin > x_cs || y_co + Cout > y_cs) return -1;
+    if (((uintptr_t)x | (uintptr_t)w) % 16 || (uintptr_t)y % 8) return -1;
     if (mode != EIKU_CONV3 && mode != EIKU_UP2 && mode != EIKU_DOWN2) return -1;
     ConvArgs a{x, w, bias, y, x_cs, x_co, y_cs, y_co, B, H, W, Cin, Cout, relu};
-    const int64_t npix = (int64_t)B * H * W;
     const int nt = Cout % 64 == 0 ? 4 : (Cout % 32 == 0 ? 2 : 1);
-    dim3 grid((unsigned)((npix + 63) / 64), (unsigned)(Cout / (16 * nt)), mode == EIKU_UP2 ? 4 : 1);
-#define EIKU_LAUNCH(MODE)                                                                                 \
-    do {                                                                                                  \
-        if (nt == 4) hipLaunchKernelGGL((k_conv<MODE, 4>), grid, dim3(256), 0, st, a);                    \
-        else if (nt == 2) hipLaunchKernelGGL((k_conv<MODE, 2>), grid, dim3(256), 0, st, a);               \
-        else hipLaunchKernelGGL((k_conv<MODE, 1>), grid, dim3(256), 0, st, a);                            \
+    const int64_t tiles = (int64_t)B * ((H + kTileY - 1) / kTileY) * ((W + kTileX - 1) / kTileX);
+    if (tiles > 0x7fffffff) return -1;
+    const dim3 g((unsigned)tiles, (unsigned)(Cout / (16 * nt)));
+    const bool k32 = Cin % 32 == 0;
+#define EIKU_LDS(MODE, KC)                                                                                    \
+    do {                                                                                                      \
+        if (nt == 4) hipLaunchKernelGGL((k_conv_lds<MODE, KC, 4>), g, dim3(256), 0, st, a);                   \
+        else if (nt == 2) hipLaunchKernelGGL((k_conv_lds<MODE, KC, 2>), g, dim3(256), 0, st, a);              \
+        else hipLaunchKernelGGL((k_conv_lds<MODE, KC, 1>), g, dim3(256), 0, st, a);                           \
     } while (0)
-    if (mode == EIKU_CONV3) EIKU_LAUNCH(EIKU_CONV3);
-    else if (mode == EIKU_UP2) EIKU_LAUNCH(EIKU_UP2);
-    else EIKU_LAUNCH(EIKU_DOWN2);
-#undef EIKU_LAUNCH
+    if (mode == EIKU_CONV3) {
+        if (k32) EIKU_LDS(EIKU_CONV3, 32);
+        else EIKU_LDS(EIKU_CONV3, 16);
+    } else if (mode == EIKU_UP2) {
+        if (k32) EIKU_LDS(EIKU_UP2, 32);
+        else EIKU_LDS(EIKU_UP2, 16);
+    } else {
+        EIKU_LDS(EIKU_DOWN2, 16); // 16-channel slices keep the 2x patch at 48 KiB of LDS
+    }
+#undef EIKU_LDS
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -445,14 +701,30 @@ int eiku_conv_wgrad(int32_t mode, int32_t B, int32_t H, int32_t W, const uint16_
     if (x_co + Cin > x_cs || dy_co + Cout > dy_cs) return -1;
     if (mode != EIKU_CONV3 && mode != EIKU_UP2) return -1;
     const int64_t npix = (int64_t)B * H * W;
+    if (mode == EIKU_CONV3) {
+        if ((x_cs | x_co | dy_cs | dy_co) % 8 || ((uintptr_t)x | (uintptr_t)dy) % 16) return -1;
+        WgradArgs a{x, dy, dw, x_cs, x_co, dy_cs, dy_co, B, H, W, Cin, Cout, 0};
+        const int ct = Cout % 32 == 0 ? 2 : 1, it = Cin % 32 == 0 ? 2 : 1;
+        const int blocks = (Cout / (16 * ct)) * (Cin / (16 * it));
+        const int64_t ntiles = (int64_t)B * ((H + kTileY - 1) / kTileY) * ((W + kTileX - 1) / kTileX);
+        // about 2048 workgroups over the channel blocks and pixel runs
+        int64_t per = (ntiles * blocks + 2047) / 2048;
+        per = per < 1 ? 1 : per;
+        const int64_t runs = (ntiles + per - 1) / per;
+        if (runs > 0x7fffffff) return -1;
+        const dim3 g((unsigned)runs, (unsigned)blocks);
+        if (ct == 2 && it == 2) hipLaunchKernelGGL((k_wgrad3_lds<2, 2>), g, dim3(256), 0, st, a, (int)per);
+        else if (ct == 2) hipLaunchKernelGGL((k_wgrad3_lds<2, 1>), g, dim3(256), 0, st, a, (int)per);
+        else if (it == 2) hipLaunchKernelGGL((k_wgrad3_lds<1, 2>), g, dim3(256), 0, st, a, (int)per);
+        else hipLaunchKernelGGL((k_wgrad3_lds<1, 1>), g, dim3(256), 0, st, a, (int)per);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
     int64_t chunk = npix / 128;
     chunk = chunk < 256 ? 256 : (chunk > 8192 ? 8192 : chunk);
     chunk = (chunk + 15) / 16 * 16;
     WgradArgs a{x, dy, dw, x_cs, x_co, dy_cs, dy_co, B, H, W, Cin, Cout, chunk};
-    const int taps = mode == EIKU_CONV3 ? 9 : 4;
-    dim3 grid((unsigned)((npix + chunk - 1) / chunk), (unsigned)(taps * (Cout / 16) * (Cin / 16)));
-    if (mode == EIKU_CONV3) hipLaunchKernelGGL(k_wgrad<EIKU_CONV3>, grid, dim3(64), 0, st, a);
-    else hipLaunchKernelGGL(k_wgrad<EIKU_UP2>, grid, dim3(64), 0, st, a);
+    dim3 grid((unsigned)((npix + chunk - 1) / chunk), (unsigned)(4 * (Cout / 16) * (Cin / 16)));
+    hipLaunchKernelGGL(k_wgrad_up2, grid, dim3(64), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -102,3 +102,27 @@ def test_noalloc_forward_rejects_on_host(case):
     assert rc == (L.EIK_EWORKSPACE if case == "too_large" else L.EIK_EINVAL)
     msg = lib.eik_last_error().decode()
     assert msg and (case != "too_large" or "static workspace" in msg)
+
+
+@pytest.mark.parametrize("case", ["x_stride", "x_offset", "y_offset", "x_pointer", "w_pointer", "y_pointer",
+                                  "wgrad_dy_offset", "wgrad_x_pointer"])
+def test_network_kernels_reject_unaligned_layouts_on_host(case):
+    """The staged convolutions move 8 channels per 16-byte access; layouts that
+    would misalign those accesses are refused before any launch."""
+    from paper_2603_00035_amd import unet
+    lib = unet._bind()
+    X, Wt, Y = 0x10000, 0x20000, 0x30000
+    if case.startswith("wgrad"):
+        args = dict(x=X, x_cs=32, x_co=0, dy=Y, dy_cs=32, dy_co=0)
+        if case == "wgrad_dy_offset":
+            args.update(dy_cs=48, dy_co=4)
+        else:
+            args.update(x=X + 8)
+        assert lib.eiku_conv_wgrad(0, 1, 8, 8, args["x"], args["x_cs"], args["x_co"], 16, args["dy"], args["dy_cs"],
+                                   args["dy_co"], 16, Wt, None) == -1
+        return
+    args = dict(x=X, x_cs=32, x_co=0, w=Wt, y=Y, y_cs=32, y_co=0)
+    args.update({"x_stride": dict(x_cs=36), "x_offset": dict(x_cs=48, x_co=4), "y_offset": dict(y_cs=48, y_co=2),
+                 "x_pointer": dict(x=X + 8), "w_pointer": dict(w=Wt + 4), "y_pointer": dict(y=Y + 2)}[case])
+    assert lib.eiku_conv_fwd(0, 1, 8, 8, args["x"], args["x_cs"], args["x_co"], 16, args["w"], None, 0, args["y"],
+                             args["y_cs"], args["y_co"], 16, None) == -1

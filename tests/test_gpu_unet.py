@@ -119,6 +119,52 @@ def test_channel_slices_up2_down2_and_gradients():
           out_bf16=False)
 
 
+@pytest.mark.parametrize("B,H,W,Cin,Cout", [(1, 5, 9, 128, 64), (2, 12, 40, 64, 32), (3, 16, 32, 32, 16)])
+def test_up2_and_down2_ragged_multi_slice(B, H, W, Cin, Cout):
+    """The transposed convolution over several 32-channel slices and all four
+    taps in one workgroup, and its data gradient over 16-channel slices, on
+    grids that are not multiples of the 8 x 32 tile."""
+    rng = np.random.default_rng(H * W + Cin)
+    x = U.bf16_round(rng.standard_normal((B, H, W, Cin)))
+    w = U.bf16_round(rng.standard_normal((4, Cout, Cin)) * 0.2)
+    bias = rng.standard_normal(Cout).astype(np.float32)
+    say(f"[unet] up2/down2 {B}x{H}x{W} {Cin}<->{Cout}")
+    yd = torch.zeros(B * 4 * H * W * Cout, dtype=torch.int16, device="cuda")
+    assert lib().eiku_conv_fwd(1, B, H, W, P(to_dev_bf16(x)), Cin, 0, Cin, P(to_dev_bf16(w)), P(to_dev(bias)), 1,
+                               P(yd), Cout, 0, Cout, st()) == 0
+    ref = np.maximum(U.up2(x, w) + bias, 0.0)
+    check(from_dev_bf16(yd, (B, 2 * H, 2 * W, Cout)), ref, U.up2(np.abs(x), np.abs(w)) + np.abs(bias), Cin + 1)
+    g = U.bf16_round(rng.standard_normal((B, 2 * H, 2 * W, Cout)))
+    wt = U.bf16_round(w.transpose(0, 2, 1).copy())
+    dd = torch.zeros(B * H * W * Cin, dtype=torch.int16, device="cuda")
+    assert lib().eiku_conv_fwd(2, B, H, W, P(to_dev_bf16(g)), Cout, 0, Cout, P(to_dev_bf16(wt)), None, 0, P(dd),
+                               Cin, 0, Cin, st()) == 0
+    check(from_dev_bf16(dd, (B, H, W, Cin)), U.down2(g, wt), U.down2(np.abs(g), np.abs(wt)), 4 * Cout)
+
+
+@pytest.mark.parametrize("B,H,W,Cin,Cout,xs,dys", [(1, 5, 7, 16, 16, (16, 0), (16, 0)),
+                                                   (2, 24, 40, 64, 128, (64, 0), (128, 0)),
+                                                   (3, 20, 36, 32, 16, (64, 32), (32, 16)),
+                                                   (16, 256, 256, 16, 16, (16, 0), (16, 0))])
+def test_conv3_weight_gradient(B, H, W, Cin, Cout, xs, dys):
+    """The 3x3 weight gradient: ragged tiles, 32 x 32 channel blocks, channel
+    slices of wider buffers, and (at 16 x 256^2) workgroups that run over
+    several pixel tiles before their atomics."""
+    rng = np.random.default_rng(B + H + Cin)
+    x = U.bf16_round(rng.standard_normal((B, H, W, Cin)))
+    g = U.bf16_round(rng.standard_normal((B, H, W, Cout)))
+    xb = np.zeros((B, H, W, xs[0]))
+    xb[..., xs[1]:xs[1] + Cin] = x
+    gb = np.zeros((B, H, W, dys[0]))
+    gb[..., dys[1]:dys[1] + Cout] = g
+    say(f"[unet] conv3 wgrad {B}x{H}x{W} {Cin}->{Cout}, x slice {xs}, dy slice {dys}")
+    dw = torch.zeros(9 * Cout * Cin, dtype=torch.float32, device="cuda")
+    assert lib().eiku_conv_wgrad(0, B, H, W, P(to_dev_bf16(xb)), xs[0], xs[1], Cin, P(to_dev_bf16(gb)), dys[0],
+                                 dys[1], Cout, P(dw), st()) == 0
+    check(dw.cpu().numpy().reshape(9, Cout, Cin), U.conv3_wgrad(x, g), U.conv3_wgrad(np.abs(x), np.abs(g)),
+          B * H * W, out_bf16=False)
+
+
 def test_weight_prep_mirrors_taps_for_the_data_gradient():
     """conv3 with the prepared backward weights is the adjoint of conv3."""
     rng = np.random.default_rng(6)
