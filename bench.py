@@ -148,9 +148,38 @@ def cpu_baseline(prob, tol):
                       f"+ stencil/level pass + VJP, single thread pinned to core {core}, {dt:.1f} s"}, T
 
 
+MFMA_BF16_PEAK_TFS = 2500.0
+
+
+def unet_cost(H, W):
+    """Algorithmic FLOPs and HBM bytes of one network forward on an H x W grid:
+    every convolution's multiply-adds, every layer reading its input and
+    writing its output once in bf16 (the pools; the head writing FP32)."""
+    from paper_2603_00035_amd import unet as U
+    npix = [H * W >> (2 * k) for k in range(4)]
+    level = {"e0": 0, "d0": 0, "e1": 1, "d1": 1, "e2": 2, "d2": 2, "ba": 3, "bb": 3}
+    flops = byts = 0
+    for name, mode, cin, cout, _ in U.LAYERS:
+        if mode == U.CONV3:
+            p = npix[level[name[:2]]]
+            flops += 2 * p * 9 * cin * cout
+            byts += 2 * p * (cin + cout)
+        else:  # uK: input on level K+1, output on level K
+            p = npix[int(name[1]) + 1]
+            flops += 2 * p * 4 * cin * cout
+            byts += 2 * p * cin + 2 * 4 * p * cout
+    for k, c in ((0, 16), (1, 32), (2, 64)):
+        byts += 2 * npix[k] * c + 2 * npix[k + 1] * c
+    byts += npix[0] * (2 * 16 + 4)
+    return flops, byts
+
+
 def bench_warm(args):
     """The learned warm start against the cold start on held-out seeds (the
-    committed weights), each side timed over whole batched solves."""
+    committed weights), each side timed over whole batched solves; the
+    network's inference timed alone with HIP events against its rooflines; the
+    oracle's cold solve timed on the host for a few of the same grids."""
+    import numpy as np
     import torch
 
     from paper_2603_00035_amd import warmstart as W
@@ -162,6 +191,47 @@ def bench_warm(args):
     W.evaluate(net, seeds[:250], chunk=250, tol=args.tol, log=lambda s: None)  # warm-up
     r = W.evaluate(net, seeds, chunk=250, tol=args.tol, log=lambda s: None)
     n = r["grids"]
+    # the network alone: 250 grids per launch sequence, inputs resident
+    B = 250
+    times = []
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        net.forward(B, 256, 256)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    t_net = float(np.median(times[1:]))
+    flops, byts = unet_cost(256, 256)
+    gbs, tfs = B * byts / t_net / 1e9, B * flops / t_net / 1e12
+    roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "U-Net forward: 17 k_conv_lds launches, 3 max pools, the head",
+            "grids_per_launch_sequence": B, "ms": round(t_net * 1e3, 4),
+            "algorithmic_flops_per_grid": flops, "algorithmic_bytes_per_grid": byts,
+            "flops_per_byte": round(flops / byts, 1),
+            "mfma": {"achieved": round(tfs, 2), "peak": MFMA_BF16_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": round(tfs / MFMA_BF16_PEAK_TFS, 5)}}
+    cb = None
+    if not args.no_cpu_baseline:
+        from synthetic.fields import make_problem
+
+        import oracle
+
+        def run():
+            t0, sweeps = time.perf_counter(), 0
+            for s in seeds[:80]:
+                q = make_problem("c5", int(s)).rounded(np.float32)
+                _, sw, _ = oracle.forward(q, tol=args.tol)
+                sweeps += sw * q.n
+            return sweeps, time.perf_counter() - t0
+
+        (upd, dt), core = pinned(run)
+        model, ncpu = host_cpu()
+        cb = {"value": upd / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle", "cpu_model": model,
+              "host_cpu_count": ncpu, "pinned_core": core, "ms_per_grid": round(1e3 * dt / 80, 2),
+              "sample": f"cold-start solves of 80 of the same 256x256 grids to {args.tol:g} (FP64 Gauss-Seidel), "
+                        f"single thread pinned to core {core}, {dt:.1f} s"}
     return {
         "metric": "cell-updates/s; fwd+adjoint ms to 1e-5 at 2048^2; learned warm vs cold",
         "value": r["cold_updates"] / r["cold_s"], "unit": "cell-updates/s",
@@ -175,7 +245,7 @@ def bench_warm(args):
         "fallback_batches": r["fallback_batches"], "batches": r["batches"],
         "rounds": {"cold": r["cold_rounds"], "warm": r["warm_rounds"], "warm_with_fallback": r["fb_rounds"]},
         "prediction_rel_err_mean": sum(r["pred_rel_err_mean"]) / len(r["pred_rel_err_mean"]),
-        "max_rel_warm_vs_cold": r["max_rel_warm_vs_cold"], "roofline": None, "cpu_baseline": None,
+        "max_rel_warm_vs_cold": r["max_rel_warm_vs_cold"], "roofline": roof, "cpu_baseline": cb,
     }
 
 

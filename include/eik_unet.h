@@ -83,7 +83,7 @@ int eiku_head_bwd(int64_t npix, const uint16_t *x, int32_t cs, int32_t co, int32
 /* Network inputs for B grids of H x W nodes (spacing h[b]): channels m11, m12,
  * m22, bx, by, Euclidean distance to the nearest source, zeros up to cs = 16.
  * M [B][3][H][W] and omega [B][2][H][W] are FP32; src [B][max_src] holds flat
- * node indices, negative entries unused. */
+ * node indices, negative entries unused; x is 16-byte aligned. */
 int eiku_features(int32_t B, int32_t H, int32_t W, const float *M, const float *omega, const int32_t *src,
                   int32_t max_src, const float *h, uint16_t *x, float *dist, hipStream_t stream);
 

@@ -485,6 +485,38 @@ __global__ void k_maxpool_fwd(int B, int H, int W, const bf16 *__restrict__ x, i
     }
 }
 
+// The same pooling 8 channels (one 16-byte word) per thread, for layouts whose
+// channel strides and offsets are multiples of 8.
+__global__ void k_maxpool_fwd8(int B, int H, int W, const bf16 *__restrict__ x, int xcs, int xco,
+                               bf16 *__restrict__ y, int ycs, int yco, int C)
+{
+    const int G = C / 8;
+    const int64_t n = (int64_t)B * H * W * G;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(e % G);
+        const int64_t p = e / G;
+        const int xo = (int)(p % W);
+        const int64_t t = p / W;
+        const int yo = (int)(t % H), b = (int)(t / H);
+        float m[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) m[j] = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t pi = ((int64_t)b * 2 * H + 2 * yo + (q >> 1)) * (2 * W) + 2 * xo + (q & 1);
+            const uint4 v = *reinterpret_cast<const uint4 *>(x + pi * xcs + xco + 8 * g);
+            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                m[2 * j] = fmaxf(m[2 * j], bf2f((bf16)(w4[j] & 0xffffu)));
+                m[2 * j + 1] = fmaxf(m[2 * j + 1], bf2f((bf16)(w4[j] >> 16)));
+            }
+        }
+        *reinterpret_cast<uint4 *>(y + p * ycs + yco + 8 * g) =
+            uint4{pack2(m[0], m[1]), pack2(m[2], m[3]), pack2(m[4], m[5]), pack2(m[6], m[7])};
+    }
+}
+
 __global__ void k_maxpool_bwd(int B, int H, int W, const bf16 *__restrict__ x, int xcs, int xco,
                               const bf16 *__restrict__ dy, int dycs, int dyco, bf16 *__restrict__ dx, int dxcs,
                               int dxco, int C)
@@ -520,6 +552,28 @@ __global__ void k_head_fwd(int64_t n, const bf16 *__restrict__ x, int cs, int co
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         float s = b[0];
         for (int c = 0; c < C; ++c) s += w[c] * bf2f(x[p * cs + co + c]);
+        out[p] = s;
+    }
+}
+
+// 16 channels per pixel read as two 16-byte words (the same sum in the same order).
+__global__ void k_head_fwd16(int64_t n, const bf16 *__restrict__ x, int cs, int co, const float *__restrict__ w,
+                             const float *__restrict__ b, float *__restrict__ out)
+{
+    float wr[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) wr[c] = w[c];
+    const float b0 = b[0];
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 v0 = *reinterpret_cast<const uint4 *>(x + p * cs + co);
+        const uint4 v1 = *reinterpret_cast<const uint4 *>(x + p * cs + co + 8);
+        const uint32_t u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        float s = b0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            s += wr[2 * j] * bf2f((bf16)(u[j] & 0xffffu));
+            s += wr[2 * j + 1] * bf2f((bf16)(u[j] >> 16));
+        }
         out[p] = s;
     }
 }
@@ -581,14 +635,9 @@ __global__ void k_features(int B, int H, int W, const float *__restrict__ M, con
         const float d = sqrtf(d2) * h[b];
         const float *Mb = M + (int64_t)b * 3 * plane;
         const float *ob = om + (int64_t)b * 2 * plane;
-        bf16 *xp = x + p * 16;
-        xp[0] = f2bf(Mb[q]);
-        xp[1] = f2bf(Mb[plane + q]);
-        xp[2] = f2bf(Mb[2 * plane + q]);
-        xp[3] = f2bf(ob[q]);
-        xp[4] = f2bf(ob[plane + q]);
-        xp[5] = f2bf(d);
-        for (int c = 6; c < 16; ++c) xp[c] = 0;
+        uint4 *xp = reinterpret_cast<uint4 *>(x + p * 16);
+        xp[0] = uint4{pack2(Mb[q], Mb[plane + q]), pack2(Mb[2 * plane + q], ob[q]), pack2(ob[plane + q], d), 0u};
+        xp[1] = uint4{0u, 0u, 0u, 0u};
         if (dist) dist[p] = d;
     }
 }
@@ -757,8 +806,12 @@ int eiku_maxpool_fwd(int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t
                      int32_t y_cs, int32_t y_co, int32_t C, hipStream_t st)
 {
     if (B < 1 || H < 1 || W < 1 || C < 1 || !x || !y || x_co + C > x_cs || y_co + C > y_cs) return -1;
-    hipLaunchKernelGGL(k_maxpool_fwd, dim3(gblocks((int64_t)B * H * W * C, 256)), dim3(256), 0, st, B, H, W, x, x_cs,
-                       x_co, y, y_cs, y_co, C);
+    if (C % 8 == 0 && (x_cs | x_co | y_cs | y_co) % 8 == 0 && ((uintptr_t)x | (uintptr_t)y) % 16 == 0)
+        hipLaunchKernelGGL(k_maxpool_fwd8, dim3(gblocks((int64_t)B * H * W * (C / 8), 256)), dim3(256), 0, st, B, H, W,
+                           x, x_cs, x_co, y, y_cs, y_co, C);
+    else
+        hipLaunchKernelGGL(k_maxpool_fwd, dim3(gblocks((int64_t)B * H * W * C, 256)), dim3(256), 0, st, B, H, W, x,
+                           x_cs, x_co, y, y_cs, y_co, C);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -778,7 +831,10 @@ int eiku_head_fwd(int64_t npix, const uint16_t *x, int32_t cs, int32_t co, int32
                   float *out, hipStream_t st)
 {
     if (npix < 1 || C < 1 || C > 16 || !x || !w || !b || !out || co + C > cs) return -1;
-    hipLaunchKernelGGL(k_head_fwd, dim3(gblocks(npix, 256)), dim3(256), 0, st, npix, x, cs, co, C, w, b, out);
+    if (C == 16 && (cs | co) % 8 == 0 && (uintptr_t)x % 16 == 0)
+        hipLaunchKernelGGL(k_head_fwd16, dim3(gblocks(npix, 256)), dim3(256), 0, st, npix, x, cs, co, w, b, out);
+    else
+        hipLaunchKernelGGL(k_head_fwd, dim3(gblocks(npix, 256)), dim3(256), 0, st, npix, x, cs, co, C, w, b, out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -795,7 +851,7 @@ int eiku_head_bwd(int64_t npix, const uint16_t *x, int32_t cs, int32_t co, int32
 int eiku_features(int32_t B, int32_t H, int32_t W, const float *M, const float *omega, const int32_t *src,
                   int32_t max_src, const float *h, uint16_t *x, float *dist, hipStream_t st)
 {
-    if (B < 1 || H < 1 || W < 1 || max_src < 1 || !M || !omega || !src || !h || !x) return -1;
+    if (B < 1 || H < 1 || W < 1 || max_src < 1 || !M || !omega || !src || !h || !x || (uintptr_t)x % 16) return -1;
     hipLaunchKernelGGL(k_features, dim3(gblocks((int64_t)B * H * W, 256)), dim3(256), 0, st, B, H, W, M, omega, src,
                        max_src, h, x, dist);
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -209,6 +209,56 @@ def test_pool_head_features_and_adam():
     assert torch.allclose(p, exp, atol=1e-6) and torch.all(g == 0)
 
 
+@pytest.mark.parametrize("C,cs,co", [(32, 64, 32), (12, 12, 0), (16, 48, 8)])
+def test_pool_and_head_on_slices_and_odd_channel_counts(C, cs, co):
+    """Max pooling and the head on channel slices of wider buffers and on
+    channel counts that are not multiples of 8 (the 16-byte and the per-channel
+    kernels), against their definitions."""
+    rng = np.random.default_rng(C + cs)
+    B, H, W = 2, 6, 10
+    x = U.bf16_round(rng.standard_normal((B, 2 * H, 2 * W, C)))
+    xb = np.zeros((B, 2 * H, 2 * W, cs))
+    xb[..., co:co + C] = x
+    yd = torch.zeros(B * H * W * cs, dtype=torch.int16, device="cuda")
+    assert lib().eiku_maxpool_fwd(B, H, W, P(to_dev_bf16(xb)), cs, co, P(yd), cs, co, C, st()) == 0
+    got = from_dev_bf16(yd, (B, H, W, cs))
+    assert np.array_equal(got[..., co:co + C], U.maxpool(x))
+    assert np.all(got[..., :co] == 0) and np.all(got[..., co + C:] == 0)
+    if C <= 16:
+        hw = rng.standard_normal(C).astype(np.float32)
+        xh = U.bf16_round(rng.standard_normal((B * H * W, C)))
+        xhb = np.zeros((B * H * W, cs))
+        xhb[:, co:co + C] = xh
+        out = torch.zeros(B * H * W, device="cuda")
+        assert lib().eiku_head_fwd(B * H * W, P(to_dev_bf16(xhb)), cs, co, C, P(to_dev(hw)),
+                                   P(to_dev(np.array([0.25], np.float32))), P(out), st()) == 0
+        ref = U.head(xh, hw.astype(np.float64), 0.25)
+        assert np.allclose(out.cpu().numpy(), ref, rtol=1e-5, atol=1e-5)
+
+
+def test_features_are_the_rounded_inputs_and_the_source_distance():
+    rng = np.random.default_rng(11)
+    B, H, W = 3, 16, 24
+    M = rng.uniform(0.5, 2, (B, 3, H, W)).astype(np.float32)
+    om = rng.uniform(-0.3, 0.3, (B, 2, H, W)).astype(np.float32)
+    src = np.array([[5, 100, -1], [0, -1, -1], [H * W - 1, 37, 200]], np.int32)
+    h = np.array([0.1, 0.05, 0.2], np.float32)
+    x = torch.zeros(B * H * W * 16, dtype=torch.int16, device="cuda")
+    dist = torch.zeros(B * H * W, device="cuda")
+    assert lib().eiku_features(B, H, W, P(to_dev(M)), P(to_dev(om)), P(to_dev(src)), 3, P(to_dev(h)), P(x),
+                               P(dist), st()) == 0
+    got = from_dev_bf16(x, (B, H, W, 16))
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    for b in range(B):
+        s = [c for c in src[b] if c >= 0]
+        d2 = np.min([(ii - c % W) ** 2 + (jj - c // W) ** 2 for c in s], axis=0).astype(np.float32)
+        d = np.sqrt(d2) * h[b]  # FP32 throughout, as the kernel computes it
+        assert np.array_equal(dist.cpu().numpy().reshape(B, H, W)[b], d)
+        want = np.stack([M[b, 0], M[b, 1], M[b, 2], om[b, 0], om[b, 1], d], -1)
+        assert np.array_equal(got[b, ..., :6], U.bf16_round(want))
+        assert np.all(got[b, ..., 6:] == 0)
+
+
 def test_network_gradient_matches_finite_differences_of_its_loss():
     """End to end: the backward pass of the whole network (all kernels) agrees
     with central differences of its own forward loss on a few parameters."""
