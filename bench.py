@@ -393,6 +393,7 @@ def bench_gradcheck(args):
     f10, f1, med = chk.random_directions(count=100)
     stab = chk.stability(trials=10)
     stab_small = chk.stability(trials=10, noise=0.001)
+    stab_corr = {str(c): chk.stability(trials=10, corr=c) for c in (2, 8)}
     smooth = {"K": 16, "sigma": 0.01}
     smooth.update(chk.stability(trials=10, grad=chk.smoothed(K=16, sigma=0.01)))
     wall = time.perf_counter() - t0
@@ -406,6 +407,7 @@ def bench_gradcheck(args):
         "noise_1pct_gradient_change": stab,
         "noise_1pct_gradient_change_jitter_averaged": smooth,
         "noise_0.1pct_gradient_change": stab_small,
+        "noise_1pct_correlated_gradient_change": stab_corr,
         "paper": {"pointwise_max_rel_err": "< 1e-6", "random_directions_within_10pct": 0.20,
                   "noise_1pct_mean_gradient_change_interior": 0.0048, "note": "the paper's own figures"},
         "roofline": None, "cpu_baseline": None,

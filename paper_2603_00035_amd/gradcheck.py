@@ -8,7 +8,8 @@ validation; App. gradient verification), run on the library's FP64 path:
 * random directions: directional derivatives along random unit directions in
   the metric's parameter space, by finite differences and by the gradient;
 * stability: change of the gradient when 1 % Gaussian noise is added to the
-  metric, over the whole field and entry by entry at interior nodes.
+  metric, over the whole field and entry by entry at interior nodes; the
+  noise independent per node or spatially correlated.
 
 Configurations follow the paper: isotropic (G = I, b = 0), anisotropic
 (eigenvalues 2 and 0.5 at 30 degrees), drift (G = I, b = (0.15, 0.08)); one
@@ -134,9 +135,23 @@ class Check:
             return gM, gom
         return grad
 
-    def stability(self, trials=10, noise=0.01, rel_floor=1e-2, grad=None):
+    def noise_field(self, corr=None):
+        """Standard Gaussian noise on the three metric planes: independent per
+        node (corr None), or spatially correlated, white noise filtered by a
+        Gaussian of standard deviation ``corr`` nodes and rescaled to unit
+        variance per plane."""
+        Z = self.rng.normal(size=self.M.shape)
+        if corr:
+            k = np.fft.fftfreq(self.n)
+            g = np.exp(-0.5 * (2 * np.pi * corr) ** 2 * (k[:, None] ** 2 + k[None, :] ** 2))
+            Z = np.real(np.fft.ifft2(np.fft.fft2(Z, axes=(1, 2)) * g, axes=(1, 2)))
+            Z /= Z.std(axis=(1, 2), keepdims=True)
+        return torch.tensor(Z, device=self.dev)
+
+    def stability(self, trials=10, noise=0.01, rel_floor=1e-2, grad=None, corr=None):
         """Change of the metric gradient under relative Gaussian noise of the
         given size on the metric (kept SPD by the feasibility projection),
+        independent per node or correlated over ``corr`` nodes (noise_field),
         averaged over trials: the relative L2 change of the whole gradient
         field, and the mean and median of the per-entry relative change at
         interior nodes whose unperturbed entry is at least rel_floor of the
@@ -151,7 +166,7 @@ class Check:
         sel = inner & (dM0.abs() >= rel_floor * float(dM0.abs().max()))
         field, mean_pt, med_pt = [], [], []
         for _ in range(trials):
-            Z = torch.tensor(self.rng.normal(size=self.M.shape), device=self.dev)
+            Z = self.noise_field(corr)
             Mn, omn = E.project(self.M * (1.0 + noise * Z), self.om)
             dM, _ = grad(Mn, omn)
             field.append(float((dM - dM0).norm() / dM0.norm()))
