@@ -108,11 +108,14 @@ __device__ __forceinline__ bool adj_sweep_dir(const TileGeoB &g, R *sLam, const 
     // descriptor and dL/dT of the node this lane updates at step s (steps past
     // the last line are clamped to it): Dsrc / Gsrc are the transposed arrays
     // of the grid in column sweeps, the row-major ones in row sweeps
+    // 32-bit node offsets (grids hold fewer than 2^32 nodes), advanced by one
+    // line per step
+    const uint32_t stride = COL ? (uint32_t)g.gd.ny : (uint32_t)g.gd.nx;
+    const uint32_t base = COL ? (uint32_t)g.i0 * stride + (uint32_t)(g.j0 + lc) : (uint32_t)g.j0 * stride + (uint32_t)(g.i0 + lc);
     auto load = [&](int s, uint32_t &d, R &gv) {
         s = s < len ? s : len - 1;
         const int pos = DIR < 2 ? s : len - 1 - s;
-        const size_t ad =
-            COL ? (size_t)(g.i0 + pos) * g.gd.ny + (g.j0 + lc) : (size_t)(g.j0 + pos) * g.gd.nx + (g.i0 + lc);
+        const uint32_t ad = base + (uint32_t)pos * stride;
         d = Dsrc[ad];
         gv = Gsrc[ad];
     };
@@ -182,7 +185,7 @@ __device__ __forceinline__ AdjVisit adj_visit_sweep(const LaunchArgs &a, int t, 
 {
     constexpr int LP = TW + 3;
     constexpr int NW = CD ? 4 : 1;
-    const int lane = threadIdx.x % TW, wave = threadIdx.x / TW;
+    const int lane = threadIdx.x % TW, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / TW); // uniform per wave
     const TileGeoB g = tile_geo_b<TH>(a, t);
     const int nx = g.gd.nx, ny = g.gd.ny;
     R *lam = lamall + g.gd.off;

@@ -256,17 +256,22 @@ __device__ __forceinline__ bool sweep_dir(const TileGeo &g, const R *__restrict_
     const int span = COL ? g.h : g.w;
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
     const int lc = lane < span ? lane : span - 1; // clamped lane for loads
-    // parameters of the node this lane updates at step s (steps past the last
-    // line are clamped to it)
+    // Parameters of the node this lane updates at step s (steps past the last
+    // line are clamped to it). The planes' bases are uniform across the wave
+    // and the node's index is a 32-bit offset (grids hold fewer than 2^32
+    // nodes), so each load takes a scalar base and one vector offset.
+    const R *__restrict__ P0 = Mb, *__restrict__ P1 = Mb + n, *__restrict__ P2 = Mb + 2 * n;
+    const R *__restrict__ P3 = Ob, *__restrict__ P4 = Ob + n;
+    const uint32_t stride = COL ? (uint32_t)g.gd.ny : (uint32_t)g.gd.nx;
+    const uint32_t base = COL ? (uint32_t)g.i0 * stride + (uint32_t)(g.j0 + lc) : (uint32_t)g.j0 * stride + (uint32_t)(g.i0 + lc);
     auto load = [&](int s, R *p) {
         s = s < len ? s : len - 1;
         const int pos = DIR < 2 ? s : len - 1 - s;
-        const size_t ad =
-            COL ? (size_t)(g.i0 + pos) * g.gd.ny + (g.j0 + lc) : (size_t)(g.j0 + pos) * g.gd.nx + (g.i0 + lc);
-        p[0] = Mb[ad]; p[1] = Mb[n + ad]; p[2] = Mb[2 * n + ad]; p[3] = Ob[ad]; p[4] = Ob[n + ad];
+        const uint32_t ad = base + (uint32_t)pos * stride;
+        p[0] = P0[ad]; p[1] = P1[ad]; p[2] = P2[ad]; p[3] = P3[ad]; p[4] = P4[ad];
         if (Staged<R>::roots) {
 #pragma unroll
-            for (int q = 0; q < kRoots; ++q) p[5 + q] = Cb[q * n + ad];
+            for (int q = 0; q < kRoots; ++q) p[5 + q] = Cb[(size_t)q * n + ad];
         }
     };
     bool changed = false;
@@ -464,7 +469,9 @@ __device__ __forceinline__ Visit visit_tile_cd(const LaunchArgs &a, int t, const
                                                R tol, int max_cycles, R *sT, uint8_t *sC, int *sBits)
 {
     constexpr int LP = TW + 3;
-    const int lane = threadIdx.x % TW, wave = threadIdx.x / TW;
+    // the wave index is uniform across each wave: taken from the first lane, the
+    // direction switch below is a scalar branch and its plane pointers stay scalar
+    const int lane = threadIdx.x % TW, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / TW);
     const TileGeo g = tile_geo<TH>(a, t);
     R *T = Tall + g.gd.off;
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;

@@ -138,3 +138,32 @@ def test_graph_capture_replays_match_eager():
         assert torch.isfinite(x)
         assert torch.equal(Tr, Te), rep
         assert torch.equal(dMr, dMe), rep
+
+
+def test_batched_mixed_degenerate_grids_match_oracle():
+    """The mixed-precision batch (FP32 sweeps, FP64 sweeps to exact
+    stationarity, mixed adjoint) on degenerate grids packed beside ordinary
+    ones: a single node, single rows and columns, a 2 x 2 grid, grids one node
+    wider or taller than a tile."""
+    from synthetic.fields import constant_problem
+    sizes = [(1, 70), (70, 1), (2, 2), (65, 1), (1, 65), (64, 64), (65, 33), (3, 129)]
+    probs = [constant_problem(1, 1, 0.1, 1.3, 0.2, 0.7, 0.1, -0.05, [(0, 0)])] + uneven_set(len(sizes), 1300, sizes)
+    say(f"[batched mixed] {len(probs)} degenerate and ordinary grids")
+    B = make_batch(probs, torch.float64, mixed=True)
+    M, om, src = packed_inputs(B, probs, torch.float64)
+    T, par, _, st = B.forward(M, om, src, tol=0.0, tol32=1e-5, tol64=0.0)
+    assert st.converged
+    Ts, ps = B.unpack_nodes(T), B.unpack_nodes(par)
+    gs = [np.random.default_rng(g).uniform(0, 1, (p.ny, p.nx)) for g, p in enumerate(probs)]
+    gT = torch.tensor(np.concatenate([x.ravel() for x in gs]), dtype=torch.float64, device=B.device)
+    dM, dom, ds, _ = B.backward(M, om, T, par, None, src, gT)
+    dMs, doms = B.unpack_planes(dM, 3), B.unpack_planes(dom, 2)
+    for g, p in enumerate(probs):
+        To, _, _ = oracle.forward(p)
+        po, _ = oracle.parents_levels(p, To)
+        assert rel_err_cells(Ts[g].cpu().numpy(), To, p.src_idx) <= 1e-12, g
+        assert np.array_equal(ps[g].cpu().numpy(), po), g
+        dMo, domo, dso = oracle.vjp(p, To, po, gs[g])
+        dsg = ds[B.src_offsets[g]:B.src_offsets[g + 1]].cpu().numpy()
+        # FP64 weights, FP32 relaxation of lambda
+        assert rel_l2([dMs[g].cpu().numpy(), doms[g].cpu().numpy(), dsg], [dMo, domo, dso]) <= 1e-5, g
