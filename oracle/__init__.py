@@ -63,6 +63,10 @@ def lib():
         L.ora_parents_levels.argtypes = [i, i, d, dp, dp, i, ip, dp, up, ip]
         L.ora_vjp.argtypes = [i, i, d, dp, dp, i, ip, dp, up, dp, dp, dp, dp]
         L.ora_jvp.argtypes = [i, i, d, dp, dp, i, ip, dp, up, dp, dp, dp, dp]
+        L.ora_soft_forward.argtypes = [i, i, d, dp, dp, i, ip, dp, d, i, d, dp, ip]
+        L.ora_soft_forward.restype = i
+        L.ora_soft_local.argtypes = [i, i, d, dp, dp, dp, d, i, dp, dp]
+        L.ora_soft_local.restype = d
         _lib = L
     return _lib
 
@@ -306,3 +310,75 @@ def project_vjp(M, om, gM, gom, **kw):
     Mo, oo = project_torch(Mt, ot, **kw)
     (Mo * torch.from_numpy(_d(gM))).sum().add((oo * torch.from_numpy(_d(gom))).sum()).backward()
     return Mt.grad.numpy(), ot.grad.numpy()
+
+
+# -- soft-min mode -------------------------------------------------------------
+# The smooth alternative to stencil selection the paper names (Sec. 3.3): each
+# stencil contributes the minimum of the Hopf-Lax objective over its segment
+# (its two-point value when both barycentric coordinates are >= 0, else the
+# smaller one-point value of its endpoints), and a node takes the soft minimum
+# -tau log sum exp(-H_k / tau) over its eight stencils.
+
+def soft_forward(prob, tau, tol=1e-14, max_sweeps=100000):
+    """Gauss-Seidel sweeps of the soft update from +inf until a full cycle
+    changes no node by more than tol (relative). Returns (T, sweeps, status)."""
+    M, om = _d(prob.M), _d(prob.omega)
+    src = np.ascontiguousarray(prob.src_idx, np.int32)
+    st = _d(prob.src_t)
+    T = np.empty((prob.ny, prob.nx))
+    sw = ctypes.c_int(0)
+    status = lib().ora_soft_forward(prob.nx, prob.ny, prob.h, _dp(M), _dp(om), src.size, _ip(src), _dp(st),
+                                    float(tau), int(max_sweeps), float(tol), _dp(T), ctypes.byref(sw))
+    return T, sw.value, status
+
+
+def soft_local(prob, T, tau, c):
+    """(value, coef[8], dth[5]) of the soft update at node c: its derivatives
+    with respect to the eight neighbour times and the stored parameters."""
+    M, om, T = _d(prob.M), _d(prob.omega), _d(T)
+    coef = np.zeros(8)
+    dth = np.zeros(5)
+    v = lib().ora_soft_local(prob.nx, prob.ny, prob.h, _dp(M), _dp(om), _dp(T), float(tau), int(c), _dp(coef),
+                             _dp(dth))
+    return v, coef, dth
+
+
+def soft_vjp(prob, T, tau, g):
+    """Vector-Jacobian product of the soft fixed point T = F(T, theta): the
+    adjoint lambda solves (I - J^T) lambda = g, J_ij = dF_i/dT_j (sources and
+    unreached nodes have empty rows), with a sparse direct solve (scipy); then
+    dL/dtheta_i = lambda_i dF_i/dtheta_i and dL/dt_s = lambda_s. Returns
+    (dL/dM (3,ny,nx) w.r.t. the stored scalars, dL/domega (2,ny,nx), dL/dt_src)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    nx, ny = prob.nx, prob.ny
+    n = nx * ny
+    NBX = (-1, -1, -1, 0, 1, 1, 1, 0)
+    NBY = (1, 0, -1, -1, -1, 0, 1, 1)
+    T = _d(T)
+    src = set(int(c) for c in np.asarray(prob.src_idx).ravel())
+    reach = np.isfinite(T.ravel())
+    rows, cols, vals = [], [], []
+    dth = np.zeros((5, n))
+    for c in range(n):
+        if c in src or not reach[c]:
+            continue
+        _, coef, d5 = soft_local(prob, T, tau, c)
+        dth[:, c] = d5
+        i, j = c % nx, c // nx
+        for k in range(8):
+            if coef[k] != 0.0:
+                rows.append(c)
+                cols.append((j + NBY[k]) * nx + (i + NBX[k]))
+                vals.append(coef[k])
+    J = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    A = (sp.identity(n, format="csr") - J.T).tocsc()
+    gg = np.where(reach, _d(g).ravel(), 0.0)
+    keep = np.nonzero(reach)[0]
+    lam = np.zeros(n)
+    lam[keep] = spla.spsolve(A[keep][:, keep], gg[keep])
+    grad = lam * dth
+    dM = grad[:3].reshape(3, ny, nx)
+    dom = grad[3:].reshape(2, ny, nx)
+    ds = np.array([lam[int(c)] for c in np.asarray(prob.src_idx).ravel()])
+    return dM, dom, ds

@@ -505,3 +505,159 @@ double ora_candidate(int nx, int ny, double h, const double *M, const double *om
     *valid = two_point(g, b, h, code, kq, Tn[code], Tn[kq], &t, NULL, NULL);
     return t;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Soft-min mode: the smooth alternative to stencil selection that the paper  */
+/* names (Sec. 3.3, closing remarks on stencil boundaries).                   */
+/* ------------------------------------------------------------------------- */
+/* Each stencil k (neighbours k, k+1) contributes the minimum over its segment
+ * of the Hopf-Lax objective: the two-point value when its barycentric
+ * coordinates are both >= 0 (Eq. two_point; no causality test), else the
+ * smaller one-point value of its finite endpoints (Eq. one_point). The node
+ * takes the soft minimum T = -tau log sum_k exp(-H_k / tau) over the eight
+ * stencils. Each H_k is continuously differentiable in its donor times and the
+ * node's parameters (at the barycentric boundary the interior solution meets
+ * the endpoint with the same derivatives), so T is too, and tau -> 0 gives the
+ * minimum over all two-point and one-point values. */
+
+/* H_k with its partial derivatives: dT[0], dT[1] with respect to the two donor
+ * times, dth[5] with respect to the stored m11, m12, m22, bx, by. Returns
+ * +inf (and zero partials) when neither donor is finite. */
+static double stencil_hl(const double g[3], const double b[2], double h, int k, const double Tn[8], double dT[2],
+                         double dth[5])
+{
+    int kq = (k + 1) & 7;
+    dT[0] = dT[1] = 0.0;
+    for (int a = 0; a < 5; ++a) dth[a] = 0.0;
+    double best = INFINITY;
+    int which = -1; /* 0: endpoint k, 1: endpoint kq, 2: interior */
+    double lam[2] = {0.0, 0.0};
+    if (isfinite(Tn[k]) && isfinite(Tn[kq])) {
+        /* two_point leaves its outputs unwritten when the quadratic has no root */
+        double t = INFINITY, l[2] = {-1.0, -1.0}, Qu[2];
+        two_point(g, b, h, k, kq, Tn[k], Tn[kq], &t, l, Qu);
+        if (isfinite(t) && l[0] >= 0.0 && l[1] >= 0.0) {
+            best = t;
+            which = 2;
+            lam[0] = l[0];
+            lam[1] = l[1];
+        }
+    }
+    for (int e = 0; e < 2; ++e) {
+        int kk = e == 0 ? k : kq;
+        if (!isfinite(Tn[kk])) continue;
+        double t = one_point(g, b, h, kk, Tn[kk]);
+        if (t < best) {
+            best = t;
+            which = e;
+        }
+    }
+    if (which < 0) return INFINITY;
+    if (which < 2) {
+        /* one-point from neighbour kk: T0 = T_kk + m.b + sqrt(m^T G m) */
+        int kk = which == 0 ? k : kq;
+        double mx = -h * NBX[kk], my = -h * NBY[kk];
+        double e = sqrt(gform(g, mx, my, mx, my));
+        dT[which] = 1.0;
+        dth[0] = mx * mx / (2.0 * e);
+        dth[1] = mx * my / e; /* the stored m12 enters G12 and G21 */
+        dth[2] = my * my / (2.0 * e);
+        dth[3] = mx;
+        dth[4] = my;
+        return best;
+    }
+    /* interior: residual R = u^T Q u - 1 with u = S - T0 1 and Q u = -lambda,
+     * so dR/dT0 = 2 (l1 + l2), dR/dT_a = -2 l_a, dR/db = -2 Mst lambda,
+     * dR/dG = -(Mst lambda)(Mst lambda)^T, and dT0/dx = -(dR/dx) / (dR/dT0) */
+    double m1x = -h * NBX[k], m1y = -h * NBY[k], m2x = -h * NBX[kq], m2y = -h * NBY[kq];
+    double dR0 = 2.0 * (lam[0] + lam[1]);
+    double px = m1x * lam[0] + m2x * lam[1], py = m1y * lam[0] + m2y * lam[1];
+    dT[0] = 2.0 * lam[0] / dR0;
+    dT[1] = 2.0 * lam[1] / dR0;
+    dth[0] = px * px / dR0;
+    dth[1] = 2.0 * px * py / dR0;
+    dth[2] = py * py / dR0;
+    dth[3] = 2.0 * px / dR0;
+    dth[4] = 2.0 * py / dR0;
+    return best;
+}
+
+/* Soft update of node c: value, the derivatives coef[d] of that value with
+ * respect to neighbour d's time (they sum to 1 over the finite neighbours),
+ * and dth[5] with respect to the node's stored parameters. */
+static double soft_local(const ora_field *f, const double *T, int c, double tau, double coef[8], double dth[5])
+{
+    double g[3], b[2], Tn[8], H[8], dTk[8][2], dthk[8][5];
+    params_at(f, c, g, b);
+    neighbour_times(f, T, c % f->nx, c / f->nx, Tn);
+    double m = INFINITY;
+    for (int k = 0; k < 8; ++k) {
+        H[k] = stencil_hl(g, b, f->h, k, Tn, dTk[k], dthk[k]);
+        if (H[k] < m) m = H[k];
+    }
+    for (int d = 0; d < 8; ++d) coef[d] = 0.0;
+    for (int a = 0; a < 5; ++a) dth[a] = 0.0;
+    if (!isfinite(m)) return INFINITY;
+    double s = 0.0;
+    for (int k = 0; k < 8; ++k)
+        if (isfinite(H[k])) s += exp(-(H[k] - m) / tau);
+    double v = m - tau * log(s);
+    for (int k = 0; k < 8; ++k) {
+        if (!isfinite(H[k])) continue;
+        double p = exp(-(H[k] - v) / tau); /* softmax weight, sum 1 */
+        coef[k] += p * dTk[k][0];
+        coef[(k + 1) & 7] += p * dTk[k][1];
+        for (int a = 0; a < 5; ++a) dth[a] += p * dthk[k][a];
+    }
+    return v;
+}
+
+/* Gauss-Seidel sweeps of the soft update in the four raster orderings, from
+ * +inf (sources fixed at their times), until a full cycle changes no node by
+ * more than tol relative. Returns 0 when converged, 1 at max_sweeps. */
+int ora_soft_forward(int nx, int ny, double h, const double *M, const double *om, int n_src,
+                     const int *src_idx, const double *src_t, double tau, int max_sweeps, double tol, double *T,
+                     int *sweeps_out)
+{
+    ora_field f = {nx, ny, h, M, om};
+    size_t n = (size_t)nx * ny;
+    unsigned char *is_src = (unsigned char *)calloc(n, 1);
+    for (size_t c = 0; c < n; ++c) T[c] = INFINITY;
+    for (int s = 0; s < n_src; ++s) {
+        is_src[src_idx[s]] = 1;
+        T[src_idx[s]] = src_t ? src_t[s] : 0.0;
+    }
+    double coef[8], dth[5];
+    int sweeps = 0, quiet = 0, status = 1;
+    while (sweeps < max_sweeps) {
+        int changed = 0, o = sweeps & 3;
+        for (int jj = 0; jj < ny; ++jj) {
+            int j = (o >= 2) ? ny - 1 - jj : jj;
+            for (int ii = 0; ii < nx; ++ii) {
+                int i = (o == 1 || o == 2) ? nx - 1 - ii : ii;
+                int c = j * nx + i;
+                if (is_src[c]) continue;
+                double v = soft_local(&f, T, c, tau, coef, dth);
+                if (counts_as_change(T[c], v, tol)) changed = 1;
+                T[c] = v;
+            }
+        }
+        ++sweeps;
+        quiet = changed ? 0 : quiet + 1;
+        if (quiet >= 4) {
+            status = 0;
+            break;
+        }
+    }
+    if (sweeps_out) *sweeps_out = sweeps;
+    free(is_src);
+    return status;
+}
+
+/* The soft update's value and partial derivatives at node c of the field T. */
+double ora_soft_local(int nx, int ny, double h, const double *M, const double *om, const double *T, double tau,
+                      int c, double *coef, double *dth)
+{
+    ora_field f = {nx, ny, h, M, om};
+    return soft_local(&f, T, c, tau, coef, dth);
+}
