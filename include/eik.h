@@ -320,6 +320,53 @@ int eik_project_backward(int64_t n, int32_t dtype, const void *M_in, const void 
                          const void *gomega_out, void *gM_in, void *gomega_in, const eik_project_params *params,
                          hipStream_t stream);
 
+/* Soft-min mode (Sec. 3.3, the smooth alternative to selecting one stencil
+ * named where the paper discusses stencil switches). Each of the eight
+ * stencils contributes the minimum of the Hopf-Lax objective over its segment:
+ * the two-point value of Eq. two_point when both barycentric weights are >= 0
+ * (no causality test), else the smaller one-point value (Eq. one_point) of its
+ * finite endpoints; the node takes T = -tau log sum_k exp(-H_k / tau) over the
+ * stencils with a finite donor, sources stay at their times. The result is a
+ * continuously differentiable function of the parameters; tau -> 0 recovers
+ * the minimum over all candidates (within tau ln 8 per update), and the
+ * derivative no longer jumps where the active stencil changes.
+ *
+ * tau must be small against the cost of one step: the soft minimum lies up to
+ * tau ln 8 below the smallest H_k, and where that bonus outweighs the step the
+ * values fall without limit (no fixed point; EIK_NOT_CONVERGED). A fixed point
+ * exists when tau ln 8 < h (1 - |omega|_{M^-1}) sqrt(lambda_min(M)) at every
+ * node (each H_k exceeds its smaller donor time by at least that much); it can
+ * exist beyond.
+ *
+ * Workspace: eik_soft_workspace_bytes(grid, dtype) bytes (about 14 reals and
+ * one byte per node), caller-owned; 0 for an invalid grid or dtype. One grid
+ * per call, sides up to 4096 nodes (EIK_EINVAL beyond). The arrays, dtype and
+ * source conventions are those of eik_forward / eik_backward.
+ *
+ * eik_soft_forward: from +inf (sources at src_t, or 0), repeated cycles of
+ * four sweeps of the soft update (rows up, rows down, columns up, columns
+ * down; the nodes of one line at once from the current values) until a cycle
+ * changes no value by more than tol max(|T|, largest |T| of the previous
+ * cycle), or max_cycles cycles (EIK_NOT_CONVERGED, T valid). *cycles (may be
+ * NULL) receives the cycles run. Synchronises the stream once per 4 cycles.
+ *
+ * eik_soft_backward: vector-Jacobian product of the converged field T of
+ * eik_soft_forward (same tau, grid and parameters): solves (I - J^T) lambda =
+ * dL/dT over the reached nodes, J the partial derivatives of each node's soft
+ * update with respect to its neighbours' times, by cycles of the same four
+ * sweeps (stopping as above, on lambda); then dL/dM, dL/domega (planes as M,
+ * omega; zero at sources and unreached nodes) = lambda times the update's
+ * partial derivatives with respect to the node's stored parameters, and
+ * dL/dt_src[s] = lambda at source s. The system is not triangular (every node
+ * depends on all its neighbours), hence the iteration. Errors as
+ * eik_soft_forward. */
+size_t eik_soft_workspace_bytes(const eik_grid *grid, int32_t dtype);
+int eik_soft_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, double tau, double tol,
+                     int32_t max_cycles, void *T, void *ws, size_t ws_bytes, int32_t *cycles, hipStream_t stream);
+int eik_soft_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
+                      double tau, const void *dLdT, double tol, int32_t max_cycles, void *dLdM, void *dLdomega,
+                      void *dLdsrc, void *ws, size_t ws_bytes, int32_t *cycles, hipStream_t stream);
+
 /* Thread-local description of the last non-OK status. */
 const char *eik_last_error(void);
 

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeik.so")
-SOURCES = ["eik_api.hip", "eik_forward.hip", "eik_backward.hip", "eik_levels.hip", "eik_project.hip", "eik_inverse.hip", "eik_encoder.hip", "unet.hip"]
+SOURCES = ["eik_api.hip", "eik_forward.hip", "eik_backward.hip", "eik_levels.hip", "eik_project.hip", "eik_inverse.hip", "eik_encoder.hip", "eik_soft.hip", "unet.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -692,6 +693,119 @@ int static_scratch(void **out)
     return EIK_OK;
 }
 
+// Workspace of the soft-min mode: source marks, convergence flags of one
+// batch of cycles, the bad-source count, the scale of the convergence test,
+// and for the adjoint the update's partials and lambda.
+constexpr int kSoftCheck = 4; // cycles between host checks
+struct SoftLayout {
+    size_t mark, flags, scale, coef, dth, lam, total;
+};
+
+SoftLayout soft_layout(int64_t n, int dtype)
+{
+    const size_t rs = dtype == EIK_F64 ? 8 : 4;
+    SoftLayout L;
+    size_t o = 0;
+    L.mark = o;  o += align256((size_t)n);
+    L.flags = o; o += align256((kSoftCheck + 1) * 4); // kSoftCheck cycle flags, then the bad-source count
+    L.scale = o; o += align256(rs);
+    L.coef = o;  o += align256(8 * (size_t)n * rs);
+    L.dth = o;   o += align256(5 * (size_t)n * rs);
+    L.lam = o;   o += align256((size_t)n * rs);
+    L.total = o;
+    return L;
+}
+
+int soft_check(const eik_grid *grid, int dtype, double tau, double tol, int max_cycles, const void *ws,
+               size_t ws_bytes)
+{
+    if (!grid) return fail(EIK_EINVAL, "grid is NULL");
+    if (dtype != EIK_F32 && dtype != EIK_F64) return fail(EIK_EINVAL, "dtype %d", dtype);
+    int rc = check_one(grid, 0);
+    if (rc) return rc;
+    if (!grid->src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
+    if (grid->nx > kSoftMaxLine || grid->ny > kSoftMaxLine)
+        return fail(EIK_EINVAL, "soft-min mode: grid sides up to %d nodes, got %d x %d", kSoftMaxLine, grid->nx,
+                    grid->ny);
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(EIK_EINVAL, "tau must be positive and finite");
+    if (!(tol >= 0.0)) return fail(EIK_EINVAL, "tol must be >= 0");
+    if (max_cycles < 1) return fail(EIK_EINVAL, "max_cycles must be >= 1");
+    const size_t need = soft_layout((int64_t)grid->nx * grid->ny, dtype).total;
+    if (!ws || ws_bytes < need) return fail(EIK_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    return EIK_OK;
+}
+
+// Runs cycles in batches of kSoftCheck until one comes back quiet or
+// max_cycles have run; the bad-source count is read with the first batch.
+template <typename F>
+int soft_cycles(int max_cycles, int32_t *flags, hipStream_t st, F &&cycle, int &cycles, bool &conv, bool &bad_src)
+{
+    cycles = 0;
+    conv = false;
+    bad_src = false;
+    while (cycles < max_cycles && !conv) {
+        const int k = std::min(kSoftCheck, max_cycles - cycles);
+        for (int c = 0; c < k; ++c) cycle(flags + c);
+        HIP_OK(hipGetLastError());
+        int32_t h[kSoftCheck + 1];
+        HIP_OK(hipMemcpyAsync(h, flags, sizeof h, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (h[kSoftCheck] != 0) bad_src = true;
+        cycles += k;
+        for (int c = 0; c < k; ++c) conv = conv || h[c] == 0;
+        if (bad_src) break;
+    }
+    return EIK_OK;
+}
+
+template <typename R>
+int soft_forward_impl(const eik_grid *g, const void *M, const void *om, double tau, double tol, int max_cycles,
+                      void *T, void *ws, int32_t *cycles_out, hipStream_t st)
+{
+    const SoftLayout L = soft_layout((int64_t)g->nx * g->ny, sizeof(R) == 8 ? EIK_F64 : EIK_F32);
+    char *b = (char *)ws;
+    uint8_t *mark = (uint8_t *)(b + L.mark);
+    int32_t *flags = (int32_t *)(b + L.flags);
+    void *scale = b + L.scale;
+    launch_soft_init<R>(g->nx, g->ny, g->n_src, g->src_idx, g->src_t, T, mark, flags + kSoftCheck, scale, st);
+    int cycles;
+    bool conv, bad;
+    int rc = soft_cycles(
+        max_cycles, flags, st,
+        [&](int32_t *f) { launch_soft_cycle<R>(g->nx, g->ny, g->h, M, om, T, mark, tau, tol, f, scale, st); },
+        cycles, conv, bad);
+    if (rc) return rc;
+    if (cycles_out) *cycles_out = cycles;
+    if (bad) return fail(EIK_EINVAL, "a source index is outside the grid");
+    return conv ? EIK_OK : fail(EIK_NOT_CONVERGED, "no quiet cycle within %d cycles", max_cycles);
+}
+
+template <typename R>
+int soft_backward_impl(const eik_grid *g, const void *M, const void *om, const void *T, double tau, const void *gT,
+                       double tol, int max_cycles, void *dM, void *dom, void *dsrc, void *ws, int32_t *cycles_out,
+                       hipStream_t st)
+{
+    const SoftLayout L = soft_layout((int64_t)g->nx * g->ny, sizeof(R) == 8 ? EIK_F64 : EIK_F32);
+    char *b = (char *)ws;
+    uint8_t *mark = (uint8_t *)(b + L.mark);
+    int32_t *flags = (int32_t *)(b + L.flags);
+    void *scale = b + L.scale, *coef = b + L.coef, *dth = b + L.dth, *lam = b + L.lam;
+    launch_soft_init<R>(g->nx, g->ny, g->n_src, g->src_idx, nullptr, nullptr, mark, flags + kSoftCheck, scale, st);
+    launch_soft_coef<R>(g->nx, g->ny, g->h, M, om, T, mark, tau, coef, dth, lam, scale, st);
+    int cycles;
+    bool conv, bad;
+    int rc = soft_cycles(
+        max_cycles, flags, st,
+        [&](int32_t *f) { launch_soft_adj_cycle<R>(g->nx, g->ny, coef, gT, T, lam, tol, f, scale, st); }, cycles,
+        conv, bad);
+    if (rc) return rc;
+    if (cycles_out) *cycles_out = cycles;
+    if (bad) return fail(EIK_EINVAL, "a source index is outside the grid");
+    launch_soft_params<R>(g->nx, g->ny, g->n_src, g->src_idx, lam, dth, dM, dom, dsrc, st);
+    HIP_OK(hipGetLastError());
+    return conv ? EIK_OK : fail(EIK_NOT_CONVERGED, "no quiet adjoint cycle within %d cycles", max_cycles);
+}
+
 } // namespace
 
 extern "C" {
@@ -1217,5 +1331,35 @@ int eik_enc_combine_backward(int32_t B, int64_t n, int32_t dtype, double alpha, 
 }
 
 const char *eik_last_error(void) { return g_last_error.c_str(); }
+
+size_t eik_soft_workspace_bytes(const eik_grid *grid, int32_t dtype)
+{
+    if (!grid || grid->nx < 1 || grid->ny < 1 || (dtype != EIK_F32 && dtype != EIK_F64)) return 0;
+    return soft_layout((int64_t)grid->nx * grid->ny, dtype).total;
+}
+
+int eik_soft_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, double tau, double tol,
+                     int32_t max_cycles, void *T, void *ws, size_t ws_bytes, int32_t *cycles, hipStream_t stream)
+{
+    int rc = soft_check(grid, dtype, tau, tol, max_cycles, ws, ws_bytes);
+    if (rc) return rc;
+    if (!M || !omega || !T) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64) return soft_forward_impl<double>(grid, M, omega, tau, tol, max_cycles, T, ws, cycles, stream);
+    return soft_forward_impl<float>(grid, M, omega, tau, tol, max_cycles, T, ws, cycles, stream);
+}
+
+int eik_soft_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
+                      double tau, const void *dLdT, double tol, int32_t max_cycles, void *dLdM, void *dLdomega,
+                      void *dLdsrc, void *ws, size_t ws_bytes, int32_t *cycles, hipStream_t stream)
+{
+    int rc = soft_check(grid, dtype, tau, tol, max_cycles, ws, ws_bytes);
+    if (rc) return rc;
+    if (!M || !omega || !T || !dLdT || !dLdM || !dLdomega || !dLdsrc) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        return soft_backward_impl<double>(grid, M, omega, T, tau, dLdT, tol, max_cycles, dLdM, dLdomega, dLdsrc, ws,
+                                          cycles, stream);
+    return soft_backward_impl<float>(grid, M, omega, T, tau, dLdT, tol, max_cycles, dLdM, dLdomega, dLdsrc, ws,
+                                     cycles, stream);
+}
 
 } // extern "C"

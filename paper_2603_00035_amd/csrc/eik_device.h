@@ -148,6 +148,32 @@ __device__ __forceinline__ bool two_point(const NodeConst<R> &k, int s, R Tp, R 
     return mu1 >= R(0) && mu2 >= R(0) && t > Tp && t > Tq;
 }
 
+// The larger root of stencil s's quadratic and its unnormalised barycentric
+// weights, as in two_point but without its validity tests (the soft-min mode
+// takes the segment minimum itself). Returns false, leaving the outputs
+// unwritten, when the quadratic has no real root.
+template <typename R>
+__device__ __forceinline__ bool two_point_root(const NodeConst<R> &k, int s, R Tp, R Tq, R &t, R &mu1, R &mu2)
+{
+    const int q = (s + 1) & 7;
+    const R Ep = k.e[s], Eq = k.e[q], Epq = k.E12[s];
+    const R delta = (Tq - Tp) * k.inv_h + k.db[s];
+    const bool base_q = delta < R(0);
+    const R s1 = base_q ? -delta : R(0);
+    const R s2 = base_q ? R(0) : delta;
+    const R S0 = base_q ? Tq + k.hbm[q] : Tp + k.hbm[s];
+    const R beta = s1 * (Eq - Epq) + s2 * (Ep - Epq);
+    const R c = Eq * s1 * s1 + Ep * s2 * s2 - k.det;
+    const R inv_a = (s == 2 || s == 3 || s == 6 || s == 7) ? k.inv_m11 : k.inv_m22;
+    const R D = beta * beta - k.a[s] * c;
+    if (!(D >= R(0))) return false;
+    const R tau = (beta + dsqrt(D)) * inv_a;
+    mu1 = Eq * (tau - s1) - Epq * (tau - s2);
+    mu2 = Ep * (tau - s2) - Epq * (tau - s1);
+    t = S0 + k.h * tau;
+    return true;
+}
+
 // two_point for a stencil index known only at run time: one constant-index
 // call per case, so the per-node constants stay in registers (an indexed
 // access into them would go through scratch memory).

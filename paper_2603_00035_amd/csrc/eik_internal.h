@@ -180,6 +180,26 @@ void launch_project_backward(int64_t n, const void *M, const void *om, const voi
                              void *go, double eig_min, double eig_max, double eucl_clip, double rho_max,
                              hipStream_t st);
 
+// soft-min mode (eik_soft.hip): one workgroup per grid; lines (rows and
+// columns) of at most kSoftMaxLine nodes; *scale is one real of the caller's
+// workspace that carries the convergence test's scale between cycles
+constexpr int kSoftMaxLine = 4096;
+template <typename R>
+void launch_soft_init(int32_t nx, int32_t ny, int n_src, const int32_t *src, const void *src_t, void *T,
+                      uint8_t *mark, int32_t *bad, void *scale, hipStream_t st);
+template <typename R>
+void launch_soft_cycle(int32_t nx, int32_t ny, double h, const void *M, const void *om, void *T, const uint8_t *mark,
+                       double tau, double tol, int32_t *changed, void *scale, hipStream_t st);
+template <typename R>
+void launch_soft_coef(int32_t nx, int32_t ny, double h, const void *M, const void *om, const void *T,
+                      const uint8_t *mark, double tau, void *coef, void *dth, void *lam, void *scale, hipStream_t st);
+template <typename R>
+void launch_soft_adj_cycle(int32_t nx, int32_t ny, const void *coef, const void *gT, const void *T, void *lam,
+                           double tol, int32_t *changed, void *scale, hipStream_t st);
+template <typename R>
+void launch_soft_params(int32_t nx, int32_t ny, int n_src, const int32_t *src, const void *lam, const void *dth,
+                        void *dM, void *dom, void *dsrc, hipStream_t st);
+
 static inline int blocks_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 8192); }
 
 } // namespace eik

@@ -289,6 +289,92 @@ def eikonal(M, omega, src_idx, h, src_t=None, tol=1e-5, max_rounds=4096, stats_s
                            tol32)
 
 
+def soft_workspace(grid: L.EikGrid, dtype_code: int, device) -> torch.Tensor:
+    nbytes = L.lib().eik_soft_workspace_bytes(ctypes.byref(grid), dtype_code)
+    if nbytes == 0:
+        L.check("eik_soft_workspace_bytes", L.EIK_EINVAL)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def soft_solve(M, omega, src_idx, h, tau, src_t=None, tol=None, max_cycles=4096, ws=None):
+    """Soft-min forward (eik_soft_forward): every stencil's segment minimum
+    enters T = -tau log sum exp(-H_k / tau). Returns (T, cycles, converged).
+    tol defaults to 1e-13 in FP64 and 1e-6 in FP32."""
+    _check_fields(M, omega)
+    ny, nx = M.shape[1:]
+    dev = M.device
+    if src_t is not None:
+        src_t = src_t.to(device=dev, dtype=M.dtype).contiguous()
+    grid = make_grid(nx, ny, h, src_idx, src_t)
+    dc = L.dtype_code(M)
+    if ws is None:
+        ws = soft_workspace(grid, dc, dev)
+    if tol is None:
+        tol = 1e-13 if M.dtype == torch.float64 else 1e-6
+    T = torch.empty((ny, nx), dtype=M.dtype, device=dev)
+    cyc = ctypes.c_int32(0)
+    rc = L.lib().eik_soft_forward(ctypes.byref(grid), dc, L.ptr(M), L.ptr(omega), float(tau), float(tol),
+                                  int(max_cycles), L.ptr(T), L.ptr(ws), ws.numel(), ctypes.byref(cyc),
+                                  L.stream_handle(dev))
+    L.check("eik_soft_forward", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
+    return T, cyc.value, rc == L.EIK_OK
+
+
+def soft_adjoint(M, omega, T, src_idx, h, tau, dLdT, tol=None, max_cycles=4096, ws=None, cycles_out=None):
+    """VJP of soft_solve's converged field (eik_soft_backward). Returns
+    (dL/dM, dL/domega, dL/dt_src); ``cycles_out`` (a list) receives the
+    relaxation cycles."""
+    _check_fields(M, omega)
+    ny, nx = M.shape[1:]
+    dev = M.device
+    grid = make_grid(nx, ny, h, src_idx)
+    dc = L.dtype_code(M)
+    if ws is None:
+        ws = soft_workspace(grid, dc, dev)
+    if tol is None:
+        tol = 1e-13 if M.dtype == torch.float64 else 1e-6
+    dLdT = dLdT.to(dtype=M.dtype).contiguous()
+    T = T.contiguous()
+    dM = torch.empty_like(M)
+    dom = torch.empty_like(omega)
+    ds = torch.empty(src_idx.numel(), dtype=M.dtype, device=dev)
+    cyc = ctypes.c_int32(0)
+    rc = L.lib().eik_soft_backward(ctypes.byref(grid), dc, L.ptr(M), L.ptr(omega), L.ptr(T), float(tau),
+                                   L.ptr(dLdT), float(tol), int(max_cycles), L.ptr(dM), L.ptr(dom), L.ptr(ds),
+                                   L.ptr(ws), ws.numel(), ctypes.byref(cyc), L.stream_handle(dev))
+    L.check("eik_soft_backward", rc)
+    if cycles_out is not None:
+        cycles_out.append(cyc.value)
+    return dM, dom, ds
+
+
+class SoftEikonalFn(torch.autograd.Function):
+    """T = soft-min eikonal(M, omega, src_t); the VJP solves the adjoint of the
+    smooth fixed point."""
+
+    @staticmethod
+    def forward(ctx, M, omega, src_t, src_idx, h, tau, tol, max_cycles):
+        M, omega = M.contiguous(), omega.contiguous()
+        T, _, conv = soft_solve(M, omega, src_idx, h, tau, src_t=src_t, tol=tol, max_cycles=max_cycles)
+        if not conv:
+            raise RuntimeError("soft-min solve did not settle within max_cycles")
+        ctx.save_for_backward(M, omega, T, src_idx)
+        ctx.h, ctx.tau, ctx.tol, ctx.max_cycles = h, tau, tol, max_cycles
+        ctx.has_src_t = src_t is not None
+        return T
+
+    @staticmethod
+    def backward(ctx, gT):
+        M, omega, T, src_idx = ctx.saved_tensors
+        dM, dom, ds = soft_adjoint(M, omega, T, src_idx, ctx.h, ctx.tau, gT, tol=ctx.tol, max_cycles=ctx.max_cycles)
+        return dM, dom, (ds if ctx.has_src_t else None), None, None, None, None, None
+
+
+def soft_eikonal(M, omega, src_idx, h, tau, src_t=None, tol=None, max_cycles=4096):
+    """Differentiable soft-min solve (Sec. 3.3's smooth stencil selection)."""
+    return SoftEikonalFn.apply(M, omega, src_t, src_idx, h, tau, tol, max_cycles)
+
+
 def _proj_params(eig_min, eig_max, eucl_clip, rho_max):
     return L.EikProjectParams(eig_min, eig_max, eucl_clip, rho_max)
 

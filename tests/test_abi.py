@@ -126,3 +126,26 @@ def test_network_kernels_reject_unaligned_layouts_on_host(case):
                  "x_pointer": dict(x=X + 8), "w_pointer": dict(w=Wt + 4), "y_pointer": dict(y=Y + 2)}[case])
     assert lib.eiku_conv_fwd(0, 1, 8, 8, args["x"], args["x_cs"], args["x_co"], 16, args["w"], None, 0, args["y"],
                              args["y_cs"], args["y_co"], 16, None) == -1
+
+
+@pytest.mark.parametrize("case", ["tau_zero", "tau_inf", "side", "tol", "cycles", "workspace"])
+def test_soft_mode_rejects_bad_arguments_on_host(case):
+    """The soft-min entry points check tau, the side limit of one line per
+    workgroup, tol, the cycle budget and the workspace before any launch."""
+    import ctypes
+    from paper_2603_00035_amd import _lib as L
+    lib = L.lib()
+    nx, ny = (4097, 2) if case == "side" else (16, 16)
+    g = L.EikGrid(nx, ny, 0.1, 1, 0x1000, None)
+    need = lib.eik_soft_workspace_bytes(ctypes.byref(g), L.EIK_F64)
+    assert need >= nx * ny * (14 * 8 + 1)
+    tau = {"tau_zero": 0.0, "tau_inf": float("inf")}.get(case, 0.01)
+    tol = -1.0 if case == "tol" else 1e-12
+    cycles = 0 if case == "cycles" else 8
+    ws_bytes = need - 1 if case == "workspace" else need
+    M, om, T, ws = 0x10000, 0x20000, 0x30000, 0x40000
+    rc = lib.eik_soft_forward(ctypes.byref(g), L.EIK_F64, M, om, tau, tol, cycles, T, ws, ws_bytes, None, None)
+    assert rc == (L.EIK_EWORKSPACE if case == "workspace" else L.EIK_EINVAL)
+    rc = lib.eik_soft_backward(ctypes.byref(g), L.EIK_F64, M, om, T, tau, 0x50000, tol, cycles, 0x60000, 0x70000,
+                               0x80000, ws, ws_bytes, None, None)
+    assert rc == (L.EIK_EWORKSPACE if case == "workspace" else L.EIK_EINVAL)
