@@ -59,7 +59,8 @@ WORKLOADS = {
           "U-Net warm start (inference included) with and without the residual-monitor fallback",
     "gradcheck": "64x64 FP64 gradient checks of the validation section: pointwise central differences at 20 "
                  "interior nodes per configuration (isotropic, anisotropic, drift), 100 random directions, "
-                 "1 % and 0.1 % metric noise, plain and averaged over 16 jittered copies",
+                 "1 % and 0.1 % metric noise, plain and averaged over 16 jittered copies; the same checks "
+                 "of the soft-min mode at tau = 0.1 h and 0.3 h",
     "encoder": "covariate encoder (5-layer BF16 CNN, 64 channels, + global dense pathway) trained end to end "
                "through FP32 solves and implicit adjoints on 16 synthetic 64x64 scenes (one ignition, 70 % of "
                "the nodes observed), evaluated on 4 held-out scenes",
@@ -396,6 +397,25 @@ def bench_gradcheck(args):
     stab_corr = {str(c): chk.stability(trials=10, corr=c) for c in (2, 8)}
     smooth = {"K": 16, "sigma": 0.01}
     smooth.update(chk.stability(trials=10, grad=chk.smoothed(K=16, sigma=0.01)))
+    dM_hard, _ = chk.grad(chk.M, chk.om)
+    soft = {}
+    for tau in (0.1, 0.3):
+        ts = time.perf_counter()
+        entry = {"tau_h": tau, "pointwise": {}}
+        for name in C.CONFIGS:
+            sc = C.Check(name, n=64, seed=args.seed + 1, tau=tau)
+            err, tested, skipped = sc.pointwise(points=20, planes=C.PLANES[name])
+            entry["pointwise"][name] = {"max_rel_err": err, "points": tested, "skipped": skipped}
+        sc = C.Check("anisotropic", n=64, seed=args.seed + 2, tau=tau)
+        f10s, f1s, meds = sc.random_directions(count=100)
+        entry["random_directions"] = {"within_10pct": f10s, "within_1pct": f1s, "median_rel_err": meds,
+                                      "count": 100}
+        entry["noise_1pct_gradient_change"] = sc.stability(trials=10)
+        entry["noise_1pct_correlated_8_gradient_change"] = sc.stability(trials=10, corr=8)
+        dM_soft, _ = sc.grad(sc.M, sc.om)
+        entry["rel_l2_to_hard_gradient"] = float((dM_soft - dM_hard).norm() / dM_hard.norm())
+        entry["wall_s"] = time.perf_counter() - ts
+        soft[str(tau)] = entry
     wall = time.perf_counter() - t0
     return {
         "metric": "cell-updates/s; fwd+adjoint ms to 1e-5 at 2048^2; learned warm vs cold",
@@ -408,6 +428,7 @@ def bench_gradcheck(args):
         "noise_1pct_gradient_change_jitter_averaged": smooth,
         "noise_0.1pct_gradient_change": stab_small,
         "noise_1pct_correlated_gradient_change": stab_corr,
+        "soft_min": soft,
         "paper": {"pointwise_max_rel_err": "< 1e-6", "random_directions_within_10pct": 0.20,
                   "noise_1pct_mean_gradient_change_interior": 0.0048, "note": "the paper's own figures"},
         "roofline": None, "cpu_baseline": None,
