@@ -339,16 +339,21 @@ int eik_project_backward(int64_t n, int32_t dtype, const void *M_in, const void 
  * exist beyond.
  *
  * Workspace: eik_soft_workspace_bytes(grid, dtype) bytes (about 14 reals and
- * one byte per node), caller-owned; 0 for an invalid grid or dtype. One grid
- * per call, sides up to 4096 nodes (EIK_EINVAL beyond). The arrays, dtype and
- * source conventions are those of eik_forward / eik_backward.
+ * one byte per node), caller-owned; 0 for an invalid grid or dtype. Grid sides
+ * up to 4096 nodes (EIK_EINVAL beyond). The arrays, dtype and source
+ * conventions are those of eik_forward / eik_backward. The batched calls take
+ * n_grids grids packed as in eik_forward_batched (src_idx / src_t / dL/dt_src
+ * per grid in order), one workgroup per grid, and
+ * eik_soft_batch_workspace_bytes; each grid stops at its own first quiet
+ * cycle, so its result equals that of a call on it alone.
  *
  * eik_soft_forward: from +inf (sources at src_t, or 0), repeated cycles of
  * four sweeps of the soft update (rows up, rows down, columns up, columns
  * down; the nodes of one line at once from the current values) until a cycle
  * changes no value by more than tol max(|T|, largest |T| of the previous
- * cycle), or max_cycles cycles (EIK_NOT_CONVERGED, T valid). *cycles (may be
- * NULL) receives the cycles run. Synchronises the stream once per 4 cycles.
+ * cycle), or max_cycles cycles (EIK_NOT_CONVERGED, T valid). cycles (NULL or
+ * one int32 per grid, host memory) receives the cycles each grid ran.
+ * Synchronises the stream once per 4 cycles.
  *
  * eik_soft_backward: vector-Jacobian product of the converged field T of
  * eik_soft_forward (same tau, grid and parameters): solves (I - J^T) lambda =
@@ -366,6 +371,15 @@ int eik_soft_forward(const eik_grid *grid, int32_t dtype, const void *M, const v
 int eik_soft_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
                       double tau, const void *dLdT, double tol, int32_t max_cycles, void *dLdM, void *dLdomega,
                       void *dLdsrc, void *ws, size_t ws_bytes, int32_t *cycles, hipStream_t stream);
+size_t eik_soft_batch_workspace_bytes(int32_t n_grids, const eik_grid *grids, int32_t dtype);
+int eik_soft_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
+                             const void *src_t, const void *M, const void *omega, double tau, double tol,
+                             int32_t max_cycles, void *T, void *ws, size_t ws_bytes, int32_t *cycles,
+                             hipStream_t stream);
+int eik_soft_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
+                              const void *M, const void *omega, const void *T, double tau, const void *dLdT,
+                              double tol, int32_t max_cycles, void *dLdM, void *dLdomega, void *dLdsrc, void *ws,
+                              size_t ws_bytes, int32_t *cycles, hipStream_t stream);
 
 /* Thread-local description of the last non-OK status. */
 const char *eik_last_error(void);

@@ -34,7 +34,8 @@ EXPORTS = ["eik_workspace_bytes", "eik_forward", "eik_backward", "eik_project", 
            "eik_enc_scratch_bytes", "eik_enc_combine_backward", "eik_forward_noalloc",
            "eik_noalloc_max_workspace_bytes", "eik_tv_log_euclid", "eik_tv_log_euclid_work_bytes",
            "eik_forward_batched_mixed", "eik_backward_batched_mixed", "eik_soft_workspace_bytes",
-           "eik_soft_forward", "eik_soft_backward"]
+           "eik_soft_forward", "eik_soft_backward", "eik_soft_batch_workspace_bytes", "eik_soft_forward_batched",
+           "eik_soft_backward_batched"]
 
 
 class EikGrid(ctypes.Structure):
@@ -155,6 +156,14 @@ def lib():
         L.eik_soft_forward.restype = ctypes.c_int
         L.eik_soft_backward.argtypes = [gp, i32, vp, vp, vp, d, vp, d, i32, vp, vp, vp, vp, ctypes.c_size_t, ip, vp]
         L.eik_soft_backward.restype = ctypes.c_int
+        L.eik_soft_batch_workspace_bytes.argtypes = [i32, gp, i32]
+        L.eik_soft_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.eik_soft_forward_batched.argtypes = [i32, gp, i32, vp, vp, vp, vp, d, d, i32, vp, vp, ctypes.c_size_t, ip,
+                                               vp]
+        L.eik_soft_forward_batched.restype = ctypes.c_int
+        L.eik_soft_backward_batched.argtypes = [i32, gp, i32, vp, vp, vp, vp, d, vp, d, i32, vp, vp, vp, vp,
+                                                ctypes.c_size_t, ip, vp]
+        L.eik_soft_backward_batched.restype = ctypes.c_int
         L.eik_last_error.argtypes = []
         L.eik_last_error.restype = ctypes.c_char_p
         _lib = L

@@ -23,27 +23,14 @@ from . import autotune
 from .eikonal import MIXED_FP64_TOL, stats_of
 
 
-class Batch:
-    def __init__(self, shapes, dtype=torch.float32, device="cuda", tune=None, max_rounds=64, mixed=False):
-        """shapes: list of (nx, ny, h, n_src). ``mixed``: the mixed-precision
-        calls (FP64 fields; FP32 sweeps with ``tune`` (default: the FP32 batch
-        entry of the tuning table), then FP64 sweeps and the mixed adjoint
-        with the library defaults at the same tile height)."""
+class _Packed:
+    """Shapes of a batch and the packing of its arrays (include/eik.h)."""
+
+    def __init__(self, shapes, dtype, device):
         self.shapes = [(int(a), int(b), float(c), int(d)) for a, b, c, d in shapes]
         self.n_grids = len(self.shapes)
-        self.mixed = bool(mixed)
-        self.dtype = torch.float64 if self.mixed else dtype
+        self.dtype = dtype
         self.device = torch.device(device)
-        self.dc = L.EIK_MIXED if self.mixed else L.dtype_code(torch.empty(0, dtype=dtype))
-        if tune is None:
-            tune = autotune.lookup(sum(nx * ny for nx, ny, _, _ in self.shapes),
-                                   "f32" if self.mixed else autotune.dtype_name(dtype), kind="batch")
-        self.tune = tune
-        self.tune64 = None
-        if self.mixed:
-            self.tune64 = L.EikTuning()
-            self.tune64.tile_height = tune.tile_height if tune is not None else 0
-        self.max_rounds = max_rounds
         G = L.EikGrid * self.n_grids
         self.grids = G(*[L.EikGrid(nx, ny, h, ns, None, None) for nx, ny, h, ns in self.shapes])
         sizes = [nx * ny for nx, ny, _, _ in self.shapes]
@@ -51,14 +38,6 @@ class Batch:
         self.n_nodes = int(self.offsets[-1])
         self.src_offsets = np.concatenate([[0], np.cumsum([s[3] for s in self.shapes])]).astype(np.int64)
         self.n_src = int(self.src_offsets[-1])
-        nbytes = L.lib().eik_batch_workspace_bytes(self.n_grids, self.grids, self.dc)
-        if nbytes == 0:
-            L.check("eik_batch_workspace_bytes", L.EIK_EINVAL)
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self._tp = None if tune is None else ctypes.byref(tune)
-        L.check("eik_batch_plan", L.lib().eik_batch_plan(self.n_grids, self.grids, self.dc, self._tp,
-                                                           L.ptr(self.ws), self.ws.numel(),
-                                                           L.stream_handle(self.device)))
 
     # -- packing helpers --------------------------------------------------
     def pack(self, Ms, oms):
@@ -75,6 +54,34 @@ class Batch:
     def unpack_planes(self, x, k):
         return [x[k * self.offsets[g]:k * self.offsets[g + 1]].reshape(k, self.shapes[g][1], self.shapes[g][0])
                 for g in range(self.n_grids)]
+
+
+class Batch(_Packed):
+    def __init__(self, shapes, dtype=torch.float32, device="cuda", tune=None, max_rounds=64, mixed=False):
+        """shapes: list of (nx, ny, h, n_src). ``mixed``: the mixed-precision
+        calls (FP64 fields; FP32 sweeps with ``tune`` (default: the FP32 batch
+        entry of the tuning table), then FP64 sweeps and the mixed adjoint
+        with the library defaults at the same tile height)."""
+        super().__init__(shapes, torch.float64 if mixed else dtype, device)
+        self.mixed = bool(mixed)
+        self.dc = L.EIK_MIXED if self.mixed else L.dtype_code(torch.empty(0, dtype=dtype))
+        if tune is None:
+            tune = autotune.lookup(sum(nx * ny for nx, ny, _, _ in self.shapes),
+                                   "f32" if self.mixed else autotune.dtype_name(dtype), kind="batch")
+        self.tune = tune
+        self.tune64 = None
+        if self.mixed:
+            self.tune64 = L.EikTuning()
+            self.tune64.tile_height = tune.tile_height if tune is not None else 0
+        self.max_rounds = max_rounds
+        nbytes = L.lib().eik_batch_workspace_bytes(self.n_grids, self.grids, self.dc)
+        if nbytes == 0:
+            L.check("eik_batch_workspace_bytes", L.EIK_EINVAL)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._tp = None if tune is None else ctypes.byref(tune)
+        L.check("eik_batch_plan", L.lib().eik_batch_plan(self.n_grids, self.grids, self.dc, self._tp,
+                                                           L.ptr(self.ws), self.ws.numel(),
+                                                           L.stream_handle(self.device)))
 
     # -- calls ------------------------------------------------------------
     def alloc_forward(self, levels=False):
@@ -150,3 +157,47 @@ class Batch:
                                                                  self.ws.numel(), out,
                                                                  L.stream_handle(self.device)))
         return tuple(int(v) for v in out)
+
+
+class SoftBatch(_Packed):
+    """Batched soft-min solves (eik_soft_forward_batched / _backward_batched):
+    one workgroup per grid, each grid stopping at its own first quiet cycle."""
+
+    def __init__(self, shapes, dtype=torch.float64, device="cuda"):
+        super().__init__(shapes, dtype, device)
+        self.dc = L.dtype_code(torch.empty(0, dtype=dtype))
+        nbytes = L.lib().eik_soft_batch_workspace_bytes(self.n_grids, self.grids, self.dc)
+        if nbytes == 0:
+            L.check("eik_soft_batch_workspace_bytes", L.EIK_EINVAL)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def _tol(self, tol):
+        return (1e-13 if self.dtype == torch.float64 else 1e-6) if tol is None else float(tol)
+
+    def forward(self, M, om, src_idx, tau, src_t=None, tol=None, max_cycles=4096, out=None):
+        """Packed fields -> (T packed, per-grid cycles, converged)."""
+        T = out if out is not None else torch.empty(self.n_nodes, dtype=self.dtype, device=self.device)
+        if src_t is not None:
+            src_t = src_t.to(self.device, self.dtype).contiguous()
+        cyc = (ctypes.c_int32 * self.n_grids)()
+        rc = L.lib().eik_soft_forward_batched(self.n_grids, self.grids, self.dc, L.ptr(src_idx), L.ptr(src_t),
+                                              L.ptr(M), L.ptr(om), float(tau), self._tol(tol), int(max_cycles),
+                                              L.ptr(T), L.ptr(self.ws), self.ws.numel(), cyc,
+                                              L.stream_handle(self.device))
+        L.check("eik_soft_forward_batched", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
+        return T, np.array(cyc[:], dtype=np.int32), rc == L.EIK_OK
+
+    def backward(self, M, om, T, src_idx, tau, dLdT, tol=None, max_cycles=4096, out=None):
+        """-> (dL/dM, dL/domega, dL/dt_src packed, per-grid cycles)."""
+        if out is None:
+            out = (torch.empty_like(M), torch.empty_like(om),
+                   torch.empty(self.n_src, dtype=self.dtype, device=self.device))
+        dM, dom, ds = out
+        dLdT = dLdT.to(self.dtype).contiguous()
+        cyc = (ctypes.c_int32 * self.n_grids)()
+        rc = L.lib().eik_soft_backward_batched(self.n_grids, self.grids, self.dc, L.ptr(src_idx), L.ptr(M),
+                                               L.ptr(om), L.ptr(T), float(tau), L.ptr(dLdT), self._tol(tol),
+                                               int(max_cycles), L.ptr(dM), L.ptr(dom), L.ptr(ds), L.ptr(self.ws),
+                                               self.ws.numel(), cyc, L.stream_handle(self.device))
+        L.check("eik_soft_backward_batched", rc)
+        return dM, dom, ds, np.array(cyc[:], dtype=np.int32)

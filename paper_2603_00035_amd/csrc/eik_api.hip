@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <string>
@@ -693,117 +694,168 @@ int static_scratch(void **out)
     return EIK_OK;
 }
 
-// Workspace of the soft-min mode: source marks, convergence flags of one
-// batch of cycles, the bad-source count, the scale of the convergence test,
-// and for the adjoint the update's partials and lambda.
+// Workspace of the soft-min mode: grid descriptors, per-grid iteration state
+// (scale, done flag, cycle count), the bad-source count, source marks, and for
+// the adjoint the update's partials and lambda.
 constexpr int kSoftCheck = 4; // cycles between host checks
 struct SoftLayout {
-    size_t mark, flags, scale, coef, dth, lam, total;
+    size_t descs, scale, done, cycles, bad, mark, coef, dth, lam, total;
 };
 
-SoftLayout soft_layout(int64_t n, int dtype)
+SoftLayout soft_layout(int n_grids, int64_t n, int dtype)
 {
     const size_t rs = dtype == EIK_F64 ? 8 : 4;
     SoftLayout L;
     size_t o = 0;
-    L.mark = o;  o += align256((size_t)n);
-    L.flags = o; o += align256((kSoftCheck + 1) * 4); // kSoftCheck cycle flags, then the bad-source count
-    L.scale = o; o += align256(rs);
-    L.coef = o;  o += align256(8 * (size_t)n * rs);
-    L.dth = o;   o += align256(5 * (size_t)n * rs);
-    L.lam = o;   o += align256((size_t)n * rs);
+    L.descs = o;  o += align256((size_t)n_grids * kSoftDescBytes);
+    L.scale = o;  o += align256((size_t)n_grids * rs);
+    L.done = o;   o += align256((size_t)n_grids * 4);
+    L.cycles = o; o += align256((size_t)n_grids * 4);
+    L.bad = o;    o += align256(4);
+    L.mark = o;   o += align256((size_t)n);
+    L.coef = o;   o += align256(8 * (size_t)n * rs);
+    L.dth = o;    o += align256(5 * (size_t)n * rs);
+    L.lam = o;    o += align256((size_t)n * rs);
     L.total = o;
     return L;
 }
 
-int soft_check(const eik_grid *grid, int dtype, double tau, double tol, int max_cycles, const void *ws,
-               size_t ws_bytes)
+int soft_extent(int n_grids, const eik_grid *grids, int dtype, int64_t &n, int64_t &max_n, int64_t &n_src)
 {
-    if (!grid) return fail(EIK_EINVAL, "grid is NULL");
+    if (!grids || n_grids < 1) return fail(EIK_EINVAL, "no grids");
     if (dtype != EIK_F32 && dtype != EIK_F64) return fail(EIK_EINVAL, "dtype %d", dtype);
-    int rc = check_one(grid, 0);
+    n = max_n = n_src = 0;
+    for (int g = 0; g < n_grids; ++g) {
+        int rc = check_one(&grids[g], g);
+        if (rc) return rc;
+        if (grids[g].nx > kSoftMaxLine || grids[g].ny > kSoftMaxLine)
+            return fail(EIK_EINVAL, "grid %d: soft-min mode takes sides up to %d nodes, got %d x %d", g, kSoftMaxLine,
+                        grids[g].nx, grids[g].ny);
+        const int64_t m = (int64_t)grids[g].nx * grids[g].ny;
+        n += m;
+        max_n = std::max(max_n, m);
+        n_src += grids[g].n_src;
+    }
+    if (n_src >= ((int64_t)1 << 31)) return fail(EIK_EINVAL, "too many sources");
+    return EIK_OK;
+}
+
+int soft_check(int n_grids, const eik_grid *grids, int dtype, const int32_t *src, double tau, double tol,
+               int max_cycles, const void *ws, size_t ws_bytes, int64_t &n, int64_t &max_n)
+{
+    int64_t n_src;
+    int rc = soft_extent(n_grids, grids, dtype, n, max_n, n_src);
     if (rc) return rc;
-    if (!grid->src_idx) return fail(EIK_EINVAL, "src_idx is NULL");
-    if (grid->nx > kSoftMaxLine || grid->ny > kSoftMaxLine)
-        return fail(EIK_EINVAL, "soft-min mode: grid sides up to %d nodes, got %d x %d", kSoftMaxLine, grid->nx,
-                    grid->ny);
+    if (!src) return fail(EIK_EINVAL, "src_idx is NULL");
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(EIK_EINVAL, "tau must be positive and finite");
     if (!(tol >= 0.0)) return fail(EIK_EINVAL, "tol must be >= 0");
     if (max_cycles < 1) return fail(EIK_EINVAL, "max_cycles must be >= 1");
-    const size_t need = soft_layout((int64_t)grid->nx * grid->ny, dtype).total;
+    const size_t need = soft_layout(n_grids, n, dtype).total;
     if (!ws || ws_bytes < need) return fail(EIK_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     return EIK_OK;
 }
 
-// Runs cycles in batches of kSoftCheck until one comes back quiet or
-// max_cycles have run; the bad-source count is read with the first batch.
-template <typename F>
-int soft_cycles(int max_cycles, int32_t *flags, hipStream_t st, F &&cycle, int &cycles, bool &conv, bool &bad_src)
+// Carves the workspace and uploads the grid descriptors.
+int soft_batch(int n_grids, const eik_grid *grids, int dtype, int64_t n, int64_t max_n, void *ws, SoftBatch &b,
+               hipStream_t st)
 {
-    cycles = 0;
+    const SoftLayout L = soft_layout(n_grids, n, dtype);
+    char *w = (char *)ws;
+    b.n_grids = n_grids;
+    b.n_nodes = n;
+    b.max_nodes = max_n;
+    b.descs = w + L.descs;
+    b.scale = w + L.scale;
+    b.done = (int32_t *)(w + L.done);
+    b.cycles = (int32_t *)(w + L.cycles);
+    b.bad = (int32_t *)(w + L.bad);
+    b.mark = (uint8_t *)(w + L.mark);
+    b.coef = w + L.coef;
+    b.dth = w + L.dth;
+    b.lam = w + L.lam;
+    std::vector<unsigned char> d((size_t)n_grids * kSoftDescBytes);
+    int64_t off = 0;
+    int32_t sb = 0;
+    b.max_line = 1;
+    for (int g = 0; g < n_grids; ++g) {
+        b.max_line = std::max({b.max_line, grids[g].nx, grids[g].ny});
+        write_soft_desc(off, grids[g].h, grids[g].nx, grids[g].ny, grids[g].n_src, sb, d.data() + g * kSoftDescBytes);
+        off += (int64_t)grids[g].nx * grids[g].ny;
+        sb += grids[g].n_src;
+    }
+    HIP_OK(hipMemcpyAsync(b.descs, d.data(), d.size(), hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return EIK_OK;
+}
+
+// Runs cycles in batches of kSoftCheck until every grid is done or
+// max_cycles have run; the bad-source count is read with the first batch.
+// cycles_out (n_grids, may be NULL) receives each grid's cycles.
+template <typename F>
+int soft_cycles(const SoftBatch &b, int max_cycles, hipStream_t st, F &&cycle, int32_t *cycles_out, bool &conv,
+                bool &bad_src)
+{
     conv = false;
     bad_src = false;
-    while (cycles < max_cycles && !conv) {
-        const int k = std::min(kSoftCheck, max_cycles - cycles);
-        for (int c = 0; c < k; ++c) cycle(flags + c);
+    std::vector<int32_t> done(b.n_grids);
+    int run = 0;
+    while (run < max_cycles && !conv) {
+        const int k = std::min(kSoftCheck, max_cycles - run);
+        for (int c = 0; c < k; ++c) cycle();
         HIP_OK(hipGetLastError());
-        int32_t h[kSoftCheck + 1];
-        HIP_OK(hipMemcpyAsync(h, flags, sizeof h, hipMemcpyDeviceToHost, st));
+        run += k;
+        int32_t bad = 0;
+        HIP_OK(hipMemcpyAsync(done.data(), b.done, done.size() * 4, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipMemcpyAsync(&bad, b.bad, 4, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
-        if (h[kSoftCheck] != 0) bad_src = true;
-        cycles += k;
-        for (int c = 0; c < k; ++c) conv = conv || h[c] == 0;
-        if (bad_src) break;
+        if (bad) {
+            bad_src = true;
+            break;
+        }
+        conv = std::all_of(done.begin(), done.end(), [](int32_t x) { return x != 0; });
+    }
+    if (cycles_out) {
+        HIP_OK(hipMemcpyAsync(cycles_out, b.cycles, (size_t)b.n_grids * 4, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
     }
     return EIK_OK;
 }
 
 template <typename R>
-int soft_forward_impl(const eik_grid *g, const void *M, const void *om, double tau, double tol, int max_cycles,
-                      void *T, void *ws, int32_t *cycles_out, hipStream_t st)
+int soft_forward_impl(int n_grids, const eik_grid *grids, const int32_t *src, const void *src_t, const void *M,
+                      const void *om, double tau, double tol, int max_cycles, void *T, void *ws, int64_t n,
+                      int64_t max_n, int32_t *cycles_out, hipStream_t st)
 {
-    const SoftLayout L = soft_layout((int64_t)g->nx * g->ny, sizeof(R) == 8 ? EIK_F64 : EIK_F32);
-    char *b = (char *)ws;
-    uint8_t *mark = (uint8_t *)(b + L.mark);
-    int32_t *flags = (int32_t *)(b + L.flags);
-    void *scale = b + L.scale;
-    launch_soft_init<R>(g->nx, g->ny, g->n_src, g->src_idx, g->src_t, T, mark, flags + kSoftCheck, scale, st);
-    int cycles;
-    bool conv, bad;
-    int rc = soft_cycles(
-        max_cycles, flags, st,
-        [&](int32_t *f) { launch_soft_cycle<R>(g->nx, g->ny, g->h, M, om, T, mark, tau, tol, f, scale, st); },
-        cycles, conv, bad);
+    SoftBatch b;
+    int rc = soft_batch(n_grids, grids, sizeof(R) == 8 ? EIK_F64 : EIK_F32, n, max_n, ws, b, st);
     if (rc) return rc;
-    if (cycles_out) *cycles_out = cycles;
-    if (bad) return fail(EIK_EINVAL, "a source index is outside the grid");
-    return conv ? EIK_OK : fail(EIK_NOT_CONVERGED, "no quiet cycle within %d cycles", max_cycles);
+    launch_soft_init<R>(b, src, src_t, T, st);
+    bool conv, bad;
+    rc = soft_cycles(
+        b, max_cycles, st, [&]() { launch_soft_cycle<R>(b, M, om, T, tau, tol, st); }, cycles_out, conv, bad);
+    if (rc) return rc;
+    if (bad) return fail(EIK_EINVAL, "a source index is outside its grid");
+    return conv ? EIK_OK : fail(EIK_NOT_CONVERGED, "a grid had no quiet cycle within %d cycles", max_cycles);
 }
 
 template <typename R>
-int soft_backward_impl(const eik_grid *g, const void *M, const void *om, const void *T, double tau, const void *gT,
-                       double tol, int max_cycles, void *dM, void *dom, void *dsrc, void *ws, int32_t *cycles_out,
-                       hipStream_t st)
+int soft_backward_impl(int n_grids, const eik_grid *grids, const int32_t *src, const void *M, const void *om,
+                       const void *T, double tau, const void *gT, double tol, int max_cycles, void *dM, void *dom,
+                       void *dsrc, void *ws, int64_t n, int64_t max_n, int32_t *cycles_out, hipStream_t st)
 {
-    const SoftLayout L = soft_layout((int64_t)g->nx * g->ny, sizeof(R) == 8 ? EIK_F64 : EIK_F32);
-    char *b = (char *)ws;
-    uint8_t *mark = (uint8_t *)(b + L.mark);
-    int32_t *flags = (int32_t *)(b + L.flags);
-    void *scale = b + L.scale, *coef = b + L.coef, *dth = b + L.dth, *lam = b + L.lam;
-    launch_soft_init<R>(g->nx, g->ny, g->n_src, g->src_idx, nullptr, nullptr, mark, flags + kSoftCheck, scale, st);
-    launch_soft_coef<R>(g->nx, g->ny, g->h, M, om, T, mark, tau, coef, dth, lam, scale, st);
-    int cycles;
-    bool conv, bad;
-    int rc = soft_cycles(
-        max_cycles, flags, st,
-        [&](int32_t *f) { launch_soft_adj_cycle<R>(g->nx, g->ny, coef, gT, T, lam, tol, f, scale, st); }, cycles,
-        conv, bad);
+    SoftBatch b;
+    int rc = soft_batch(n_grids, grids, sizeof(R) == 8 ? EIK_F64 : EIK_F32, n, max_n, ws, b, st);
     if (rc) return rc;
-    if (cycles_out) *cycles_out = cycles;
-    if (bad) return fail(EIK_EINVAL, "a source index is outside the grid");
-    launch_soft_params<R>(g->nx, g->ny, g->n_src, g->src_idx, lam, dth, dM, dom, dsrc, st);
+    launch_soft_init<R>(b, src, nullptr, nullptr, st);
+    launch_soft_coef<R>(b, M, om, T, tau, st);
+    bool conv, bad;
+    rc = soft_cycles(
+        b, max_cycles, st, [&]() { launch_soft_adj_cycle<R>(b, gT, T, tol, st); }, cycles_out, conv, bad);
+    if (rc) return rc;
+    if (bad) return fail(EIK_EINVAL, "a source index is outside its grid");
+    launch_soft_params<R>(b, src, dM, dom, dsrc, st);
     HIP_OK(hipGetLastError());
-    return conv ? EIK_OK : fail(EIK_NOT_CONVERGED, "no quiet adjoint cycle within %d cycles", max_cycles);
+    return conv ? EIK_OK : fail(EIK_NOT_CONVERGED, "a grid had no quiet adjoint cycle within %d cycles", max_cycles);
 }
 
 } // namespace
@@ -1334,32 +1386,67 @@ const char *eik_last_error(void) { return g_last_error.c_str(); }
 
 size_t eik_soft_workspace_bytes(const eik_grid *grid, int32_t dtype)
 {
-    if (!grid || grid->nx < 1 || grid->ny < 1 || (dtype != EIK_F32 && dtype != EIK_F64)) return 0;
-    return soft_layout((int64_t)grid->nx * grid->ny, dtype).total;
+    return eik_soft_batch_workspace_bytes(1, grid, dtype);
+}
+
+size_t eik_soft_batch_workspace_bytes(int32_t n_grids, const eik_grid *grids, int32_t dtype)
+{
+    if (!grids || n_grids < 1 || (dtype != EIK_F32 && dtype != EIK_F64)) return 0;
+    int64_t n = 0;
+    for (int g = 0; g < n_grids; ++g) {
+        if (grids[g].nx < 1 || grids[g].ny < 1) return 0;
+        n += (int64_t)grids[g].nx * grids[g].ny;
+    }
+    return soft_layout(n_grids, n, dtype).total;
+}
+
+int eik_soft_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
+                             const void *src_t, const void *M, const void *omega, double tau, double tol,
+                             int32_t max_cycles, void *T, void *ws, size_t ws_bytes, int32_t *cycles,
+                             hipStream_t stream)
+{
+    int64_t n, max_n;
+    int rc = soft_check(n_grids, grids, dtype, src_idx, tau, tol, max_cycles, ws, ws_bytes, n, max_n);
+    if (rc) return rc;
+    if (!M || !omega || !T) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        return soft_forward_impl<double>(n_grids, grids, src_idx, src_t, M, omega, tau, tol, max_cycles, T, ws, n,
+                                         max_n, cycles, stream);
+    return soft_forward_impl<float>(n_grids, grids, src_idx, src_t, M, omega, tau, tol, max_cycles, T, ws, n, max_n,
+                                    cycles, stream);
+}
+
+int eik_soft_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
+                              const void *M, const void *omega, const void *T, double tau, const void *dLdT,
+                              double tol, int32_t max_cycles, void *dLdM, void *dLdomega, void *dLdsrc, void *ws,
+                              size_t ws_bytes, int32_t *cycles, hipStream_t stream)
+{
+    int64_t n, max_n;
+    int rc = soft_check(n_grids, grids, dtype, src_idx, tau, tol, max_cycles, ws, ws_bytes, n, max_n);
+    if (rc) return rc;
+    if (!M || !omega || !T || !dLdT || !dLdM || !dLdomega || !dLdsrc) return fail(EIK_EINVAL, "NULL pointer argument");
+    if (dtype == EIK_F64)
+        return soft_backward_impl<double>(n_grids, grids, src_idx, M, omega, T, tau, dLdT, tol, max_cycles, dLdM,
+                                          dLdomega, dLdsrc, ws, n, max_n, cycles, stream);
+    return soft_backward_impl<float>(n_grids, grids, src_idx, M, omega, T, tau, dLdT, tol, max_cycles, dLdM, dLdomega,
+                                     dLdsrc, ws, n, max_n, cycles, stream);
 }
 
 int eik_soft_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, double tau, double tol,
                      int32_t max_cycles, void *T, void *ws, size_t ws_bytes, int32_t *cycles, hipStream_t stream)
 {
-    int rc = soft_check(grid, dtype, tau, tol, max_cycles, ws, ws_bytes);
-    if (rc) return rc;
-    if (!M || !omega || !T) return fail(EIK_EINVAL, "NULL pointer argument");
-    if (dtype == EIK_F64) return soft_forward_impl<double>(grid, M, omega, tau, tol, max_cycles, T, ws, cycles, stream);
-    return soft_forward_impl<float>(grid, M, omega, tau, tol, max_cycles, T, ws, cycles, stream);
+    if (!grid) return fail(EIK_EINVAL, "grid is NULL");
+    return eik_soft_forward_batched(1, grid, dtype, grid->src_idx, grid->src_t, M, omega, tau, tol, max_cycles, T, ws,
+                                    ws_bytes, cycles, stream);
 }
 
 int eik_soft_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
                       double tau, const void *dLdT, double tol, int32_t max_cycles, void *dLdM, void *dLdomega,
                       void *dLdsrc, void *ws, size_t ws_bytes, int32_t *cycles, hipStream_t stream)
 {
-    int rc = soft_check(grid, dtype, tau, tol, max_cycles, ws, ws_bytes);
-    if (rc) return rc;
-    if (!M || !omega || !T || !dLdT || !dLdM || !dLdomega || !dLdsrc) return fail(EIK_EINVAL, "NULL pointer argument");
-    if (dtype == EIK_F64)
-        return soft_backward_impl<double>(grid, M, omega, T, tau, dLdT, tol, max_cycles, dLdM, dLdomega, dLdsrc, ws,
-                                          cycles, stream);
-    return soft_backward_impl<float>(grid, M, omega, T, tau, dLdT, tol, max_cycles, dLdM, dLdomega, dLdsrc, ws,
-                                     cycles, stream);
+    if (!grid) return fail(EIK_EINVAL, "grid is NULL");
+    return eik_soft_backward_batched(1, grid, dtype, grid->src_idx, M, omega, T, tau, dLdT, tol, max_cycles, dLdM,
+                                     dLdomega, dLdsrc, ws, ws_bytes, cycles, stream);
 }
 
 } // extern "C"

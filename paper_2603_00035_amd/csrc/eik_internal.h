@@ -180,25 +180,36 @@ void launch_project_backward(int64_t n, const void *M, const void *om, const voi
                              void *go, double eig_min, double eig_max, double eucl_clip, double rho_max,
                              hipStream_t st);
 
-// soft-min mode (eik_soft.hip): one workgroup per grid; lines (rows and
-// columns) of at most kSoftMaxLine nodes; *scale is one real of the caller's
-// workspace that carries the convergence test's scale between cycles
+// soft-min mode (eik_soft.hip): one workgroup per grid of a batch; lines
+// (rows and columns) of at most kSoftMaxLine nodes. SoftBatch points into the
+// caller's workspace: descs (kSoftDescBytes per grid, written with
+// write_soft_desc), per-grid iteration state (scale: one real, done and cycle
+// count), source marks, the bad-source count, and for the adjoint the
+// update's partials (coef 8, dth 5 reals per node) and lambda.
 constexpr int kSoftMaxLine = 4096;
+constexpr size_t kSoftDescBytes = 32;
+struct SoftBatch {
+    int32_t n_grids;
+    int32_t max_line; // longest row or column of the batch
+    int64_t n_nodes, max_nodes;
+    void *descs;
+    void *scale;
+    int32_t *done, *cycles, *bad;
+    uint8_t *mark;
+    void *coef, *dth, *lam;
+};
+void write_soft_desc(int64_t off, double h, int32_t nx, int32_t ny, int32_t n_src, int32_t src_base, void *dst);
 template <typename R>
-void launch_soft_init(int32_t nx, int32_t ny, int n_src, const int32_t *src, const void *src_t, void *T,
-                      uint8_t *mark, int32_t *bad, void *scale, hipStream_t st);
+void launch_soft_init(const SoftBatch &b, const int32_t *src, const void *src_t, void *T, hipStream_t st);
 template <typename R>
-void launch_soft_cycle(int32_t nx, int32_t ny, double h, const void *M, const void *om, void *T, const uint8_t *mark,
-                       double tau, double tol, int32_t *changed, void *scale, hipStream_t st);
+void launch_soft_cycle(const SoftBatch &b, const void *M, const void *om, void *T, double tau, double tol,
+                       hipStream_t st);
 template <typename R>
-void launch_soft_coef(int32_t nx, int32_t ny, double h, const void *M, const void *om, const void *T,
-                      const uint8_t *mark, double tau, void *coef, void *dth, void *lam, void *scale, hipStream_t st);
+void launch_soft_coef(const SoftBatch &b, const void *M, const void *om, const void *T, double tau, hipStream_t st);
 template <typename R>
-void launch_soft_adj_cycle(int32_t nx, int32_t ny, const void *coef, const void *gT, const void *T, void *lam,
-                           double tol, int32_t *changed, void *scale, hipStream_t st);
+void launch_soft_adj_cycle(const SoftBatch &b, const void *gT, const void *T, double tol, hipStream_t st);
 template <typename R>
-void launch_soft_params(int32_t nx, int32_t ny, int n_src, const int32_t *src, const void *lam, const void *dth,
-                        void *dM, void *dom, void *dsrc, hipStream_t st);
+void launch_soft_params(const SoftBatch &b, const int32_t *src, void *dM, void *dom, void *dsrc, hipStream_t st);
 
 static inline int blocks_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 8192); }
 

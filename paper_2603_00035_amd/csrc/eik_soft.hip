@@ -8,22 +8,29 @@
 // every neighbour (later ones too), so the adjoint system is not triangular:
 // it is relaxed until it settles.
 //
-// Layout of the work: one workgroup per grid sweeps the grid line by line,
-// rows up, rows down, columns up, columns down (the paper's column/row
-// sweeps): the nodes of a line are updated in parallel from the current
-// values (all reads of a line before its writes), the lines one after the
-// other. A cycle of four directions that changes no value beyond the
-// tolerance ends the solve. Lines are at most kSoftMaxLine nodes long.
+// Layout of the work: one workgroup per grid of a batch sweeps its grid line
+// by line, rows up, rows down, columns up, columns down (the paper's
+// column/row sweeps): the nodes of a line are updated in parallel from the
+// current values (all reads of a line before its writes), the lines one after
+// the other. A grid whose cycle of four directions changes no value beyond the
+// tolerance is done: later cycle launches skip it, so its result does not
+// depend on the rest of the batch. Lines are at most kSoftMaxLine nodes long.
+// Arrays are packed grid after grid as in the batched hard solve.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "eik_device.h"
 #include "eik_internal.h"
 
 namespace eik {
 
-constexpr int kSoftThreads = 512; // 2 waves per SIMD: room for the FP64 update's registers
-constexpr int kSoftPer = kSoftMaxLine / kSoftThreads; // nodes of a line per thread
+// Workgroup shapes of the line sweeps: NT threads, PER nodes of a line per
+// thread. The host takes the smallest that covers the batch's longest line:
+// one wave per grid for grids up to 64 nodes wide (many grids per CU), up to
+// 512 threads with 8 nodes each for lines up to kSoftMaxLine.
+constexpr int kSoftWideThreads = 512;
+constexpr int kSoftWidePer = kSoftMaxLine / kSoftWideThreads;
 
 // Segment minimum of stencil S: value, the code of the piece that attains it
 // (S for the interior two-point value, 8 + k for the one-point value of
@@ -90,13 +97,17 @@ __device__ __forceinline__ R soft_min(const R H[8], R tau)
     return m - tau * log(sum);
 }
 
-struct SoftGrid {
-    int32_t nx, ny;
+// One grid of a batch, as the device sees it.
+struct SoftDesc {
+    int64_t off; // first node in the packed node arrays
     double h;
+    int32_t nx, ny;
+    int32_t n_src, src_base;
 };
+static_assert(sizeof(SoftDesc) == kSoftDescBytes, "descriptor size shared with the host layout");
 
 template <typename R>
-__device__ __forceinline__ void node_inputs(const SoftGrid &g, const R *__restrict__ M, const R *__restrict__ om,
+__device__ __forceinline__ void node_inputs(const SoftDesc &g, const R *__restrict__ M, const R *__restrict__ om,
                                             const R *T, int i, int j, NodeConst<R> &k, R Tn[8])
 {
     const int64_t n = (int64_t)g.nx * g.ny, c = (int64_t)j * g.nx + i;
@@ -111,7 +122,7 @@ __device__ __forceinline__ void node_inputs(const SoftGrid &g, const R *__restri
 
 // Node e of line `line` in direction dir: 0 rows up, 1 rows down, 2 columns
 // up, 3 columns down.
-__device__ __forceinline__ void line_node(const SoftGrid &g, int dir, int line, int e, int &i, int &j)
+__device__ __forceinline__ void line_node(const SoftDesc &g, int dir, int line, int e, int &i, int &j)
 {
     if (dir < 2) {
         i = e;
@@ -136,32 +147,46 @@ __device__ __forceinline__ bool soft_change(R a, R b, R tol, R scale)
     return d > tol * (m > scale ? m : scale);
 }
 
-// Largest value over the workgroup; every thread must call it.
-template <typename R>
+// Largest value over the workgroup of NT threads; every thread must call it.
+template <typename R, int NT>
 __device__ R block_max(R v, R *red)
 {
     red[threadIdx.x] = v;
     __syncthreads();
-    for (int w = kSoftThreads / 2; w > 0; w >>= 1) {
+    for (int w = NT / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
     return red[0];
 }
 
-// One cycle of the four directional sweeps of the soft update. changed
-// receives 1 when some value moved (soft_change); ctl_scale carries the scale
-// of soft_change from cycle to cycle (0 before the first).
+// Per-grid state of an iteration (caller's workspace): the scale of
+// soft_change carried from cycle to cycle, whether the grid is done, and its
+// cycle count.
 template <typename R>
-__global__ __launch_bounds__(kSoftThreads) void k_soft_cycle(SoftGrid g, const R *__restrict__ M,
-                                                            const R *__restrict__ om, R *T,
-                                                            const uint8_t *__restrict__ mark, R tau, R tol,
-                                                            int32_t *__restrict__ changed, R *ctl_scale)
+struct SoftState {
+    R *scale;
+    int32_t *done, *cycles;
+};
+
+// One cycle of the four directional sweeps of the soft update over grid
+// blockIdx.x (skipped once the grid is done).
+template <typename R, int NT, int PER>
+__global__ __launch_bounds__(NT) void k_soft_cycle(const SoftDesc *__restrict__ descs,
+                                                            const R *__restrict__ Mall, const R *__restrict__ omall,
+                                                            R *Tall, const uint8_t *__restrict__ markall, R tau,
+                                                            R tol, SoftState<R> st)
 {
+    const int gi = blockIdx.x;
+    if (st.done[gi]) return; // uniform over the workgroup
+    const SoftDesc g = descs[gi];
+    const R *M = Mall + 3 * g.off, *om = omall + 2 * g.off;
+    R *T = Tall + g.off;
+    const uint8_t *mark = markall + g.off;
     __shared__ int s_changed;
-    __shared__ R s_red[kSoftThreads];
+    __shared__ R s_red[NT];
     if (threadIdx.x == 0) s_changed = 0;
-    const R scale = *ctl_scale;
+    const R scale = st.scale[gi];
     __syncthreads();
     bool ch = false;
     R vmax = R(0);
@@ -169,10 +194,10 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_cycle(SoftGrid g, const R
         const int len = dir < 2 ? g.ny : g.nx, span = dir < 2 ? g.nx : g.ny;
         for (int s = 0; s < len; ++s) {
             const int line = (dir & 1) ? len - 1 - s : s;
-            R v[kSoftPer];
+            R v[PER];
 #pragma unroll
-            for (int q = 0; q < kSoftPer; ++q) {
-                const int e = threadIdx.x + q * kSoftThreads;
+            for (int q = 0; q < PER; ++q) {
+                const int e = threadIdx.x + q * NT;
                 if (e >= span) continue;
                 int i, j;
                 line_node(g, dir, line, e, i, j);
@@ -190,8 +215,8 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_cycle(SoftGrid g, const R
             }
             __syncthreads(); // every read of the line before its writes
 #pragma unroll
-            for (int q = 0; q < kSoftPer; ++q) {
-                const int e = threadIdx.x + q * kSoftThreads;
+            for (int q = 0; q < PER; ++q) {
+                const int e = threadIdx.x + q * NT;
                 if (e >= span) continue;
                 int i, j;
                 line_node(g, dir, line, e, i, j);
@@ -204,57 +229,73 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_cycle(SoftGrid g, const R
         }
     }
     if (ch) atomicOr(&s_changed, 1);
-    vmax = block_max<R>(vmax, s_red); // its barriers also order s_changed
+    vmax = block_max<R, NT>(vmax, s_red); // its barriers also order s_changed
     if (threadIdx.x == 0) {
-        *changed = s_changed;
-        *ctl_scale = vmax;
+        if (!s_changed) st.done[gi] = 1;
+        st.scale[gi] = vmax;
+        st.cycles[gi] += 1;
     }
 }
 
 template <typename R>
-__global__ void k_soft_init(int64_t n, R *__restrict__ T, uint8_t *__restrict__ mark)
+__global__ void k_soft_init(int64_t n, R *__restrict__ T, uint8_t *__restrict__ mark, int32_t *__restrict__ bad)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *bad = 0;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         if (T) T[c] = inf_v<R>();
         mark[c] = 0;
     }
 }
 
-// Sources: T = t_s (0 without times), marked; out-of-range indices are
-// counted in *bad. One workgroup: it also clears *bad and the scale.
+// Sources of grid blockIdx.x: T = t_s (0 without times), marked; indices
+// outside the grid are counted in *bad. Also resets the grid's iteration state.
 template <typename R>
-__global__ void k_soft_sources(int64_t n, int n_src, const int32_t *__restrict__ src, const R *__restrict__ src_t,
-                               R *__restrict__ T, uint8_t *__restrict__ mark, int32_t *__restrict__ bad,
-                               R *__restrict__ ctl_scale)
+__global__ void k_soft_sources(const SoftDesc *__restrict__ descs, const int32_t *__restrict__ src,
+                               const R *__restrict__ src_t, R *__restrict__ T, uint8_t *__restrict__ mark,
+                               int32_t *__restrict__ bad, SoftState<R> st)
 {
+    const int gi = blockIdx.x;
+    const SoftDesc g = descs[gi];
     if (threadIdx.x == 0) {
-        *bad = 0;
-        *ctl_scale = R(0);
+        st.scale[gi] = R(0);
+        st.done[gi] = 0;
+        st.cycles[gi] = 0;
     }
-    __syncthreads();
-    for (int s = threadIdx.x; s < n_src; s += blockDim.x) {
-        const int32_t c = src[s];
+    const int64_t n = (int64_t)g.nx * g.ny;
+    for (int s = threadIdx.x; s < g.n_src; s += blockDim.x) {
+        const int32_t c = src[g.src_base + s];
         if (c < 0 || (int64_t)c >= n) {
             atomicAdd(bad, 1);
             continue;
         }
-        mark[c] = kSource;
-        if (T) T[c] = src_t ? src_t[s] : R(0);
+        mark[g.off + c] = kSource;
+        if (T) T[g.off + c] = src_t ? src_t[g.src_base + s] : R(0);
     }
 }
 
-// Partial derivatives of each node's soft update at the field T: coef[d][c]
-// with respect to neighbour d's time (summing to 1), dth[a][c] with respect
-// to the node's stored m11, m12, m22, bx, by; zero at sources and unreached
-// nodes (their values do not follow the update). Also clears the adjoint
-// (lam and the scale of its convergence test).
+// Partial derivatives of each node's soft update at the field T: coef[d]
+// with respect to neighbour d's time (summing to 1), dth[a] with respect to
+// the node's stored m11, m12, m22, bx, by (planes per grid at 8 off and 5 off);
+// zero at sources and unreached nodes (their values do not follow the
+// update). Grid blockIdx.y. Also clears the adjoint (lam and the iteration
+// state).
 template <typename R>
-__global__ __launch_bounds__(256) void k_soft_coef(SoftGrid g, const R *__restrict__ M, const R *__restrict__ om, const R *__restrict__ T,
-                            const uint8_t *__restrict__ mark, R tau, R *__restrict__ coef, R *__restrict__ dth,
-                            R *__restrict__ lam, R *__restrict__ ctl_scale)
+__global__ __launch_bounds__(256) void k_soft_coef(const SoftDesc *__restrict__ descs, const R *__restrict__ Mall,
+                                                   const R *__restrict__ omall, const R *__restrict__ Tall,
+                                                   const uint8_t *__restrict__ markall, R tau, R *__restrict__ coefall,
+                                                   R *__restrict__ dthall, R *__restrict__ lamall, SoftState<R> st)
 {
+    const int gi = blockIdx.y;
+    const SoftDesc g = descs[gi];
     const int64_t n = (int64_t)g.nx * g.ny;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *ctl_scale = R(0);
+    const R *M = Mall + 3 * g.off, *om = omall + 2 * g.off, *T = Tall + g.off;
+    const uint8_t *mark = markall + g.off;
+    R *coef = coefall + 8 * g.off, *dth = dthall + 5 * g.off, *lam = lamall + g.off;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st.scale[gi] = R(0);
+        st.done[gi] = 0;
+        st.cycles[gi] = 0;
+    }
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         lam[c] = R(0);
         R cf[8], dt[5];
@@ -295,30 +336,36 @@ __global__ __launch_bounds__(256) void k_soft_coef(SoftGrid g, const R *__restri
 }
 
 // One cycle of the adjoint relaxation lambda_i = g_i + sum_d coef[opp d][nb_d]
-// lambda_{nb_d}, with the same line order as the forward (unreached nodes keep
-// lambda = 0).
-template <typename R>
-__global__ __launch_bounds__(kSoftThreads) void k_soft_adj_cycle(SoftGrid g, const R *__restrict__ coef,
-                                                                const R *__restrict__ gT, const R *__restrict__ T,
-                                                                R *lam, R tol, int32_t *__restrict__ changed,
-                                                                R *ctl_scale)
+// lambda_{nb_d} over grid blockIdx.x, with the same line order as the forward
+// (unreached nodes keep lambda = 0).
+template <typename R, int NT, int PER>
+__global__ __launch_bounds__(NT) void k_soft_adj_cycle(const SoftDesc *__restrict__ descs,
+                                                                const R *__restrict__ coefall,
+                                                                const R *__restrict__ gall,
+                                                                const R *__restrict__ Tall, R *lamall, R tol,
+                                                                SoftState<R> st)
 {
-    __shared__ int s_changed;
-    __shared__ R s_red[kSoftThreads];
-    if (threadIdx.x == 0) s_changed = 0;
-    const R scale = *ctl_scale;
-    __syncthreads();
+    const int gi = blockIdx.x;
+    if (st.done[gi]) return;
+    const SoftDesc g = descs[gi];
     const int64_t n = (int64_t)g.nx * g.ny;
+    const R *coef = coefall + 8 * g.off, *gT = gall + g.off, *T = Tall + g.off;
+    R *lam = lamall + g.off;
+    __shared__ int s_changed;
+    __shared__ R s_red[NT];
+    if (threadIdx.x == 0) s_changed = 0;
+    const R scale = st.scale[gi];
+    __syncthreads();
     bool ch = false;
     R vmax = R(0);
     for (int dir = 0; dir < 4; ++dir) {
         const int len = dir < 2 ? g.ny : g.nx, span = dir < 2 ? g.nx : g.ny;
         for (int s = 0; s < len; ++s) {
             const int line = (dir & 1) ? len - 1 - s : s;
-            R v[kSoftPer];
+            R v[PER];
 #pragma unroll
-            for (int q = 0; q < kSoftPer; ++q) {
-                const int e = threadIdx.x + q * kSoftThreads;
+            for (int q = 0; q < PER; ++q) {
+                const int e = threadIdx.x + q * NT;
                 if (e >= span) continue;
                 int i, j;
                 line_node(g, dir, line, e, i, j);
@@ -339,8 +386,8 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_adj_cycle(SoftGrid g, con
             }
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < kSoftPer; ++q) {
-                const int e = threadIdx.x + q * kSoftThreads;
+            for (int q = 0; q < PER; ++q) {
+                const int e = threadIdx.x + q * NT;
                 if (e >= span) continue;
                 int i, j;
                 line_node(g, dir, line, e, i, j);
@@ -353,19 +400,24 @@ __global__ __launch_bounds__(kSoftThreads) void k_soft_adj_cycle(SoftGrid g, con
         }
     }
     if (ch) atomicOr(&s_changed, 1);
-    vmax = block_max<R>(vmax, s_red);
+    vmax = block_max<R, NT>(vmax, s_red);
     if (threadIdx.x == 0) {
-        *changed = s_changed;
-        *ctl_scale = vmax;
+        if (!s_changed) st.done[gi] = 1;
+        st.scale[gi] = vmax;
+        st.cycles[gi] += 1;
     }
 }
 
-// dL/dtheta_i = lambda_i dth_i (zero at sources and unreached nodes: their dth is
-// zero), dL/dt_s = lambda_s.
+// dL/dtheta_i = lambda_i dth_i (zero at sources and unreached nodes: their dth
+// is zero), grid blockIdx.y.
 template <typename R>
-__global__ void k_soft_params(int64_t n, const R *__restrict__ lam, const R *__restrict__ dth, R *__restrict__ dM,
-                              R *__restrict__ dom)
+__global__ void k_soft_params(const SoftDesc *__restrict__ descs, const R *__restrict__ lamall,
+                              const R *__restrict__ dthall, R *__restrict__ dMall, R *__restrict__ domall)
 {
+    const SoftDesc g = descs[blockIdx.y];
+    const int64_t n = (int64_t)g.nx * g.ny;
+    const R *lam = lamall + g.off, *dth = dthall + 5 * g.off;
+    R *dM = dMall + 3 * g.off, *dom = domall + 2 * g.off;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         const R l = lam[c];
         dM[c] = l * dth[c];
@@ -376,76 +428,112 @@ __global__ void k_soft_params(int64_t n, const R *__restrict__ lam, const R *__r
     }
 }
 
+// dL/dt_s = lambda_s, grid blockIdx.x.
 template <typename R>
-__global__ void k_soft_dsrc(int n_src, const int32_t *__restrict__ src, const R *__restrict__ lam,
-                            R *__restrict__ dsrc, int64_t n)
+__global__ void k_soft_dsrc(const SoftDesc *__restrict__ descs, const int32_t *__restrict__ src,
+                            const R *__restrict__ lamall, R *__restrict__ dsrc)
 {
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n_src; s += gridDim.x * blockDim.x) {
-        const int32_t c = src[s];
-        dsrc[s] = (c >= 0 && (int64_t)c < n) ? lam[c] : R(0);
+    const SoftDesc g = descs[blockIdx.x];
+    const int64_t n = (int64_t)g.nx * g.ny;
+    for (int s = threadIdx.x; s < g.n_src; s += blockDim.x) {
+        const int32_t c = src[g.src_base + s];
+        dsrc[g.src_base + s] = (c >= 0 && (int64_t)c < n) ? lamall[g.off + c] : R(0);
     }
 }
 
-static inline unsigned soft_blocks(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 4096); }
-
-template <typename R>
-void launch_soft_init(int32_t nx, int32_t ny, int n_src, const int32_t *src, const void *src_t, void *T,
-                      uint8_t *mark, int32_t *bad, void *scale, hipStream_t st)
+// 2-D launch over the nodes of every grid: y = grid, x = enough blocks of 256
+// for the largest grid (at most 1024).
+static inline dim3 soft_node_grid(int n_grids, int64_t max_nodes)
 {
-    const int64_t n = (int64_t)nx * ny;
-    hipLaunchKernelGGL(k_soft_init<R>, dim3(soft_blocks(n)), dim3(256), 0, st, n, (R *)T, mark);
-    hipLaunchKernelGGL(k_soft_sources<R>, dim3(1), dim3(256), 0, st, n, n_src, src, (const R *)src_t, (R *)T, mark,
-                       bad, (R *)scale);
+    return dim3((unsigned)std::min<int64_t>((max_nodes + 255) / 256, 1024), (unsigned)n_grids);
 }
 
 template <typename R>
-void launch_soft_cycle(int32_t nx, int32_t ny, double h, const void *M, const void *om, void *T, const uint8_t *mark,
-                       double tau, double tol, int32_t *changed, void *scale, hipStream_t st)
+static SoftState<R> soft_state(const SoftBatch &b)
 {
-    const SoftGrid g{nx, ny, h};
-    hipLaunchKernelGGL(k_soft_cycle<R>, dim3(1), dim3(kSoftThreads), 0, st, g, (const R *)M, (const R *)om, (R *)T,
-                       mark, R(tau), R(tol), changed, (R *)scale);
+    return SoftState<R>{(R *)b.scale, b.done, b.cycles};
 }
 
 template <typename R>
-void launch_soft_coef(int32_t nx, int32_t ny, double h, const void *M, const void *om, const void *T,
-                      const uint8_t *mark, double tau, void *coef, void *dth, void *lam, void *scale, hipStream_t st)
+void launch_soft_init(const SoftBatch &b, const int32_t *src, const void *src_t, void *T, hipStream_t st)
 {
-    const SoftGrid g{nx, ny, h};
-    hipLaunchKernelGGL(k_soft_coef<R>, dim3(soft_blocks((int64_t)nx * ny)), dim3(256), 0, st, g, (const R *)M,
-                       (const R *)om, (const R *)T, mark, R(tau), (R *)coef, (R *)dth, (R *)lam, (R *)scale);
+    hipLaunchKernelGGL(k_soft_init<R>, dim3((unsigned)std::min<int64_t>((b.n_nodes + 255) / 256, 4096)), dim3(256), 0,
+                       st, b.n_nodes, (R *)T, b.mark, b.bad);
+    hipLaunchKernelGGL(k_soft_sources<R>, dim3(b.n_grids), dim3(256), 0, st, (const SoftDesc *)b.descs, src,
+                       (const R *)src_t, (R *)T, b.mark, b.bad, soft_state<R>(b));
+}
+
+template <typename R, int NT, int PER>
+static void soft_cycle_nt(const SoftBatch &b, const void *M, const void *om, void *T, double tau, double tol,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL((k_soft_cycle<R, NT, PER>), dim3(b.n_grids), dim3(NT), 0, st, (const SoftDesc *)b.descs,
+                       (const R *)M, (const R *)om, (R *)T, b.mark, R(tau), R(tol), soft_state<R>(b));
 }
 
 template <typename R>
-void launch_soft_adj_cycle(int32_t nx, int32_t ny, const void *coef, const void *gT, const void *T, void *lam,
-                           double tol, int32_t *changed, void *scale, hipStream_t st)
+void launch_soft_cycle(const SoftBatch &b, const void *M, const void *om, void *T, double tau, double tol,
+                       hipStream_t st)
 {
-    const SoftGrid g{nx, ny, 0.0};
-    hipLaunchKernelGGL(k_soft_adj_cycle<R>, dim3(1), dim3(kSoftThreads), 0, st, g, (const R *)coef, (const R *)gT,
-                       (const R *)T, (R *)lam, R(tol), changed, (R *)scale);
+    if (b.max_line <= 64) soft_cycle_nt<R, 64, 1>(b, M, om, T, tau, tol, st);
+    else if (b.max_line <= 128) soft_cycle_nt<R, 128, 1>(b, M, om, T, tau, tol, st);
+    else if (b.max_line <= 256) soft_cycle_nt<R, 256, 1>(b, M, om, T, tau, tol, st);
+    else soft_cycle_nt<R, kSoftWideThreads, kSoftWidePer>(b, M, om, T, tau, tol, st);
 }
 
 template <typename R>
-void launch_soft_params(int32_t nx, int32_t ny, int n_src, const int32_t *src, const void *lam, const void *dth,
-                        void *dM, void *dom, void *dsrc, hipStream_t st)
+void launch_soft_coef(const SoftBatch &b, const void *M, const void *om, const void *T, double tau, hipStream_t st)
 {
-    const int64_t n = (int64_t)nx * ny;
-    hipLaunchKernelGGL(k_soft_params<R>, dim3(soft_blocks(n)), dim3(256), 0, st, n, (const R *)lam, (const R *)dth,
-                       (R *)dM, (R *)dom);
-    hipLaunchKernelGGL(k_soft_dsrc<R>, dim3(1), dim3(256), 0, st, n_src, src, (const R *)lam, (R *)dsrc, n);
+    hipLaunchKernelGGL(k_soft_coef<R>, soft_node_grid(b.n_grids, b.max_nodes), dim3(256), 0, st,
+                       (const SoftDesc *)b.descs, (const R *)M, (const R *)om, (const R *)T, b.mark, R(tau),
+                       (R *)b.coef, (R *)b.dth, (R *)b.lam, soft_state<R>(b));
+}
+
+template <typename R, int NT, int PER>
+static void soft_adj_cycle_nt(const SoftBatch &b, const void *gT, const void *T, double tol, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_soft_adj_cycle<R, NT, PER>), dim3(b.n_grids), dim3(NT), 0, st, (const SoftDesc *)b.descs,
+                       (const R *)b.coef, (const R *)gT, (const R *)T, (R *)b.lam, R(tol), soft_state<R>(b));
+}
+
+template <typename R>
+void launch_soft_adj_cycle(const SoftBatch &b, const void *gT, const void *T, double tol, hipStream_t st)
+{
+    if (b.max_line <= 64) soft_adj_cycle_nt<R, 64, 1>(b, gT, T, tol, st);
+    else if (b.max_line <= 128) soft_adj_cycle_nt<R, 128, 1>(b, gT, T, tol, st);
+    else if (b.max_line <= 256) soft_adj_cycle_nt<R, 256, 1>(b, gT, T, tol, st);
+    else soft_adj_cycle_nt<R, kSoftWideThreads, kSoftWidePer>(b, gT, T, tol, st);
+}
+
+template <typename R>
+void launch_soft_params(const SoftBatch &b, const int32_t *src, void *dM, void *dom, void *dsrc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_soft_params<R>, soft_node_grid(b.n_grids, b.max_nodes), dim3(256), 0, st,
+                       (const SoftDesc *)b.descs, (const R *)b.lam, (const R *)b.dth, (R *)dM, (R *)dom);
+    hipLaunchKernelGGL(k_soft_dsrc<R>, dim3(b.n_grids), dim3(256), 0, st, (const SoftDesc *)b.descs, src,
+                       (const R *)b.lam, (R *)dsrc);
+}
+
+void write_soft_desc(int64_t off, double h, int32_t nx, int32_t ny, int32_t n_src, int32_t src_base, void *dst)
+{
+    SoftDesc d;
+    d.off = off;
+    d.h = h;
+    d.nx = nx;
+    d.ny = ny;
+    d.n_src = n_src;
+    d.src_base = src_base;
+    memcpy(dst, &d, sizeof d);
 }
 
 #define EIK_SOFT_INST(R)                                                                                           \
-    template void launch_soft_init<R>(int32_t, int32_t, int, const int32_t *, const void *, void *, uint8_t *,       \
-                                      int32_t *, void *, hipStream_t);                                             \
-    template void launch_soft_cycle<R>(int32_t, int32_t, double, const void *, const void *, void *,                \
-                                       const uint8_t *, double, double, int32_t *, void *, hipStream_t);           \
-    template void launch_soft_coef<R>(int32_t, int32_t, double, const void *, const void *, const void *,            \
-                                      const uint8_t *, double, void *, void *, void *, void *, hipStream_t);        \
-    template void launch_soft_adj_cycle<R>(int32_t, int32_t, const void *, const void *, const void *, void *,      \
-                                           double, int32_t *, void *, hipStream_t);                                \
-    template void launch_soft_params<R>(int32_t, int32_t, int, const int32_t *, const void *, const void *, void *, \
-                                        void *, void *, hipStream_t);
+    template void launch_soft_init<R>(const SoftBatch &, const int32_t *, const void *, void *, hipStream_t);       \
+    template void launch_soft_cycle<R>(const SoftBatch &, const void *, const void *, void *, double, double,       \
+                                       hipStream_t);                                                               \
+    template void launch_soft_coef<R>(const SoftBatch &, const void *, const void *, const void *, double,          \
+                                      hipStream_t);                                                                \
+    template void launch_soft_adj_cycle<R>(const SoftBatch &, const void *, const void *, double, hipStream_t);    \
+    template void launch_soft_params<R>(const SoftBatch &, const int32_t *, void *, void *, void *, hipStream_t);
 EIK_SOFT_INST(float)
 EIK_SOFT_INST(double)
 #undef EIK_SOFT_INST

@@ -181,3 +181,52 @@ def test_soft_rejects_bad_sources_and_arguments():
     M, om, src, t = to_dev(q, torch.float64)
     T, cycles, conv = E.soft_solve(M, om, src, q.h, 0.5 * q.h, max_cycles=64)
     assert not conv and cycles == 64
+
+
+def test_soft_batched_equals_single_grid_calls_and_oracle():
+    """A batch of uneven grids (a one-node grid, rows longer than a
+    workgroup, ragged shapes) gives every grid exactly the field and the VJP of
+    a call on it alone (each grid stops at its own first quiet cycle), and the
+    oracle's to the FP64 bars."""
+    from paper_2603_00035_amd import eikonal as E
+    from paper_2603_00035_amd.batched import SoftBatch
+    probs = [make_problem("c2", 11, nx=30, ny=20), constant_problem(1, 1, 0.5, 1.0, 0.0, 1.0, 0.0, 0.0, [(0, 0)]),
+             make_problem("c4", 12, nx=300, ny=7), make_problem("c1", 13, nx=17, ny=45),
+             make_problem("c3", 14, nx=64, ny=64)]
+    tau = [0.05, 0.1, 0.05, 0.1, 0.02]
+    say("soft batched: 5 uneven grids")
+    # one tau per call: grids of one batch share it, so group by value
+    for tv in sorted(set(tau)):
+        sel = [g for g in range(len(probs)) if tau[g] == tv]
+        ps = [probs[g] for g in sel]
+        B = SoftBatch([(p.nx, p.ny, p.h, p.src_idx.size) for p in ps], dtype=torch.float64)
+        M, om = B.pack([torch.tensor(p.M) for p in ps], [torch.tensor(p.omega) for p in ps])
+        src = torch.tensor(np.concatenate([p.src_idx for p in ps]), dtype=torch.int32, device=M.device)
+        st = torch.tensor(np.concatenate([p.src_t for p in ps]), device=M.device)
+        # tau is absolute: in units of the group's smallest spacing, which keeps
+        # every grid of the group below its existence bound
+        ta = tv * min(p.h for p in ps)
+        T, cyc, conv = B.forward(M, om, src, ta, src_t=st)
+        assert conv
+        rng = np.random.default_rng(int(1000 * tv))
+        gs = [rng.standard_normal((p.ny, p.nx)) for p in ps]
+        g = torch.tensor(np.concatenate([x.ravel() for x in gs]), device=M.device)
+        dM, dom, ds, acyc = B.backward(M, om, T, src, ta, g)
+        Ts, dMs, doms = B.unpack_nodes(T), B.unpack_planes(dM, 3), B.unpack_planes(dom, 2)
+        for k, p in enumerate(ps):
+            Mi, omi, srci, sti = to_dev(p, torch.float64)
+            T1, c1, ok = E.soft_solve(Mi, omi, srci, p.h, ta, src_t=sti)
+            assert ok and c1 == cyc[k]
+            assert torch.equal(T1, Ts[k])
+            cy = []
+            dM1, dom1, ds1 = E.soft_adjoint(Mi, omi, T1, srci, p.h, ta, torch.tensor(gs[k], device=M.device),
+                                            cycles_out=cy)
+            assert cy[0] == acyc[k]
+            assert torch.equal(dM1, dMs[k]) and torch.equal(dom1, doms[k])
+            s0, s1 = int(B.src_offsets[k]), int(B.src_offsets[k + 1])
+            assert torch.equal(ds1, ds[s0:s1])
+            To, _, _ = oracle.soft_forward(p, ta)
+            assert _rel_max(Ts[k].cpu().numpy(), To) <= F64_FWD_RTOL
+            dMo, domo, dso = oracle.soft_vjp(p, To, ta, gs[k])
+            assert _rel_l2(dMs[k].cpu().numpy(), dMo) <= F64_VJP_RTOL
+            assert _rel_l2(ds[s0:s1].cpu().numpy(), dso) <= F64_VJP_RTOL
