@@ -61,6 +61,9 @@ WORKLOADS = {
                  "interior nodes per configuration (isotropic, anisotropic, drift), 100 random directions, "
                  "1 % and 0.1 % metric noise, plain and averaged over 16 jittered copies; the same checks "
                  "of the soft-min mode at tau = 0.1 h and 0.3 h",
+    "softmin": "batches of 64x64 FP64 grids (anisotropic metric, eigenvalues 2 and 0.5 at 30 degrees, 1 % "
+               "independent per-node noise, central source): soft-min solve at tau = 0.3 h to 1e-13 + adjoint of a "
+               "dense linear functional, one batched call each",
     "encoder": "covariate encoder (5-layer BF16 CNN, 64 channels, + global dense pathway) trained end to end "
                "through FP32 solves and implicit adjoints on 16 synthetic 64x64 scenes (one ignition, 70 % of "
                "the nodes observed), evaluated on 4 held-out scenes",
@@ -435,6 +438,120 @@ def bench_gradcheck(args):
     }
 
 
+# FP64 operations of one soft-min node update, counted from its definition
+# (Sec. 3.3 soft minimum over the eight segment minima): the node's constants
+# 33 (adds and multiplies; a fused multiply-add counts 2), eight segment minima
+# of 35 each (the two-point quadratic, its weights, both endpoints), the soft
+# minimum 18, and 39 square roots, reciprocals, divisions, exponentials and
+# logarithms counted as one operation each.
+SOFT_OPS_PER_UPDATE = 33 + 8 * 35 + 18 + 39
+FP64_VECTOR_PEAK_TFS = 78.6
+
+
+def bench_softmin(args):
+    """The soft-min mode on the gradient checks' noise-trial setting at batch
+    scale: 64x64 FP64 grids with the anisotropic metric (eigenvalues 2 and 0.5
+    at 30 degrees) under 1 % independent per-node noise, one central source,
+    tau = 0.3 h; each step solves every grid to 1e-13 and runs the adjoint of a
+    dense linear functional, one batched call each. The cycle kernels are
+    timed with events against the FP64 vector roofline; the oracle's soft
+    solve and sparse direct adjoint run on the host for a sample of the grids."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2603_00035_amd import gradcheck as C
+    from paper_2603_00035_amd.batched import SoftBatch
+    from synthetic.fields import Problem
+
+    n, B = 64, args.soft_grids
+    h, tol = 1.0 / (n - 1), 1e-13
+    tau = 0.3 * h
+    dev = torch.device("cuda:0")
+    M0, om0 = C.config_fields("anisotropic", n, "cpu")
+    rng = np.random.default_rng(args.seed)
+    Mnp = M0.numpy()[None] * (1.0 + 0.01 * rng.normal(size=(B, 3, n, n)))  # stays SPD: eigenvalues 2 and 0.5
+    omnp = np.zeros((B, 2, n, n))
+    cnp = rng.uniform(0.0, 1.0, (B, n, n))
+    centre = (n // 2) * n + n // 2
+    SB = SoftBatch([(n, n, h, 1)] * B, dtype=torch.float64)
+    M = torch.tensor(Mnp, device=dev).reshape(-1).contiguous()
+    om = torch.tensor(omnp, device=dev).reshape(-1).contiguous()
+    c = torch.tensor(cnp, device=dev).reshape(-1).contiguous()
+    src = torch.full((B,), centre, dtype=torch.int32, device=dev)
+
+    def step():
+        T, fc, ok = SB.forward(M, om, src, tau, tol=tol)
+        dM, dom, ds, ac = SB.backward(M, om, T, src, tau, c, tol=tol)
+        return T, dM, ds, fc, ac, ok, SB.last_cycle_ms, SB.last_adj_cycle_ms
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    walls, fcyc, acyc, fms, ams = [], [], [], [], []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        T, dM, ds, fc, ac, ok, f_ms, a_ms = step()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        assert ok
+        fcyc.append(int(fc.sum()))
+        acyc.append(int(ac.sum()))
+        fms.append(f_ms)
+        ams.append(a_ms)
+    wall = float(np.sum(walls))
+    upd = 4 * n * n * (np.sum(fcyc) + np.sum(acyc))
+    fwd_upd = 4 * n * n * np.sum(fcyc)
+    t_cyc = 1e-3 * float(np.sum(fms))
+    tfs = SOFT_OPS_PER_UPDATE * fwd_upd / t_cyc / 1e12
+    roof = {"bound": "alu", "achieved": round(tfs, 3), "peak": FP64_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": round(tfs / FP64_VECTOR_PEAK_TFS, 5), "traffic": None,
+            "kernel": "k_soft_cycle<double, 64, 1>", "ops_per_update": SOFT_OPS_PER_UPDATE,
+            "kernel_ms_per_step": round(float(np.mean(fms)), 4), "updates_per_step": int(fwd_upd / args.steps),
+            "adjoint_kernel": "k_soft_adj_cycle<double, 64, 1>", "adjoint_kernel_ms_per_step": round(float(np.mean(ams)), 4)}
+    Tn = T.reshape(B, n, n).cpu().numpy()
+    dMn = dM.reshape(B, 3, n, n).cpu().numpy()
+    dsn = ds.cpu().numpy()
+    cb, parity = None, {}
+    if not args.no_cpu_baseline:
+        S = min(B, args.soft_cpu_grids)
+
+        def run():
+            t0, sweeps = time.perf_counter(), 0
+            worst_T, worst_g = 0.0, 0.0
+            for g in range(S):
+                p = Problem(n, n, h, Mnp[g], omnp[g], np.array([centre], np.int32), np.zeros(1))
+                To, sw, st = oracle.soft_forward(p, tau, tol=tol)
+                dMo, _, dso = oracle.soft_vjp(p, To, tau, cnp[g])
+                sweeps += sw
+                worst_T = max(worst_T, float(np.max(np.abs(Tn[g] - To) / np.maximum(np.abs(To), 1e-300))))
+                worst_g = max(worst_g, float(np.linalg.norm(dMn[g] - dMo) / np.linalg.norm(dMo)))
+            return sweeps, worst_T, worst_g, time.perf_counter() - t0
+
+        (sweeps, worst_T, worst_g, dt), core = pinned(run)
+        model, ncpu = host_cpu()
+        cb = {"value": n * n * sweeps / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+              "cpu_model": model, "host_cpu_count": ncpu, "pinned_core": core,
+              "grids_per_s": S / dt, "ms_per_grid": round(1e3 * dt / S, 2),
+              "sample": f"{S} of the same grids: soft-min Gauss-Seidel solve to {tol:g} (FP64) + sparse direct "
+                        f"adjoint, single thread pinned to core {core}, {dt:.1f} s"}
+        parity = {"parity_fwd_max_rel_vs_oracle": worst_T, "parity_grad_rel_l2_vs_oracle": worst_g,
+                  "parity_grids": S}
+    out = {
+        "metric": "cell-updates/s; fwd+adjoint ms to 1e-5 at 2048^2; learned warm vs cold",
+        "value": upd / wall, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"softmin: {WORKLOADS['softmin']}", "grids": B, "n": n, "tau_h": 0.3, "tol": tol},
+        "grids_per_s": B * args.steps / wall,
+        "fwd_cycles_per_grid": float(np.mean(fcyc)) / B, "adj_cycles_per_grid": float(np.mean(acyc)) / B,
+        "fwd_cycle_ms_per_step": float(np.mean(fms)), "adj_cycle_ms_per_step": float(np.mean(ams)),
+        "roofline": roof, "cpu_baseline": cb,
+    }
+    out.update(parity)
+    return out
+
+
 def bench_encoder(args):
     """Hybrid training of the covariate encoder on synthetic scenes; reports
     the time of one training step (encoder forward, projection, FP32 solve,
@@ -679,6 +796,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=sorted(PRECISIONS))
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precision beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--soft-grids", type=int, default=1024, help="softmin workload: grids per batch")
+    ap.add_argument("--soft-cpu-grids", type=int, default=48, help="softmin workload: grids the oracle solves")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after the steps, copy a 1 GiB buffer once (a plain copy kernel of known size that "
                          "calibrates the HBM byte counters of a profiler run)")
@@ -710,6 +829,9 @@ def main():
         return
     if args.workload == "gradcheck":
         print(json.dumps(bench_gradcheck(args)), flush=True)
+        return
+    if args.workload == "softmin":
+        print(json.dumps(bench_softmin(args)), flush=True)
         return
 
     dev = torch.device("cuda:0")

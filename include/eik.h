@@ -345,7 +345,9 @@ int eik_project_backward(int64_t n, int32_t dtype, const void *M_in, const void 
  * n_grids grids packed as in eik_forward_batched (src_idx / src_t / dL/dt_src
  * per grid in order), one workgroup per grid, and
  * eik_soft_batch_workspace_bytes; each grid stops at its own first quiet
- * cycle, so its result equals that of a call on it alone.
+ * cycle, so its result equals that of a call on it alone. cycle_ms (host, may
+ * be NULL) receives the GPU time of the cycle launches, timed with events
+ * around each batch of launches between host checks.
  *
  * eik_soft_forward: from +inf (sources at src_t, or 0), repeated cycles of
  * four sweeps of the soft update (rows up, rows down, columns up, columns
@@ -375,11 +377,11 @@ size_t eik_soft_batch_workspace_bytes(int32_t n_grids, const eik_grid *grids, in
 int eik_soft_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
                              const void *src_t, const void *M, const void *omega, double tau, double tol,
                              int32_t max_cycles, void *T, void *ws, size_t ws_bytes, int32_t *cycles,
-                             hipStream_t stream);
+                             double *cycle_ms, hipStream_t stream);
 int eik_soft_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
                               const void *M, const void *omega, const void *T, double tau, const void *dLdT,
                               double tol, int32_t max_cycles, void *dLdM, void *dLdomega, void *dLdsrc, void *ws,
-                              size_t ws_bytes, int32_t *cycles, hipStream_t stream);
+                              size_t ws_bytes, int32_t *cycles, double *cycle_ms, hipStream_t stream);
 
 /* Thread-local description of the last non-OK status. */
 const char *eik_last_error(void);

@@ -158,11 +158,12 @@ def lib():
         L.eik_soft_backward.restype = ctypes.c_int
         L.eik_soft_batch_workspace_bytes.argtypes = [i32, gp, i32]
         L.eik_soft_batch_workspace_bytes.restype = ctypes.c_size_t
+        dpp = ctypes.POINTER(ctypes.c_double)
         L.eik_soft_forward_batched.argtypes = [i32, gp, i32, vp, vp, vp, vp, d, d, i32, vp, vp, ctypes.c_size_t, ip,
-                                               vp]
+                                               dpp, vp]
         L.eik_soft_forward_batched.restype = ctypes.c_int
         L.eik_soft_backward_batched.argtypes = [i32, gp, i32, vp, vp, vp, vp, d, vp, d, i32, vp, vp, vp, vp,
-                                                ctypes.c_size_t, ip, vp]
+                                                ctypes.c_size_t, ip, dpp, vp]
         L.eik_soft_backward_batched.restype = ctypes.c_int
         L.eik_last_error.argtypes = []
         L.eik_last_error.restype = ctypes.c_char_p

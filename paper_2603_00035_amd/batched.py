@@ -175,29 +175,35 @@ class SoftBatch(_Packed):
         return (1e-13 if self.dtype == torch.float64 else 1e-6) if tol is None else float(tol)
 
     def forward(self, M, om, src_idx, tau, src_t=None, tol=None, max_cycles=4096, out=None):
-        """Packed fields -> (T packed, per-grid cycles, converged)."""
+        """Packed fields -> (T packed, per-grid cycles, converged);
+        ``self.last_cycle_ms`` receives the GPU time of the cycle launches."""
         T = out if out is not None else torch.empty(self.n_nodes, dtype=self.dtype, device=self.device)
         if src_t is not None:
             src_t = src_t.to(self.device, self.dtype).contiguous()
         cyc = (ctypes.c_int32 * self.n_grids)()
+        ms = ctypes.c_double(0.0)
         rc = L.lib().eik_soft_forward_batched(self.n_grids, self.grids, self.dc, L.ptr(src_idx), L.ptr(src_t),
                                               L.ptr(M), L.ptr(om), float(tau), self._tol(tol), int(max_cycles),
-                                              L.ptr(T), L.ptr(self.ws), self.ws.numel(), cyc,
+                                              L.ptr(T), L.ptr(self.ws), self.ws.numel(), cyc, ctypes.byref(ms),
                                               L.stream_handle(self.device))
         L.check("eik_soft_forward_batched", rc, ok=(L.EIK_OK, L.EIK_NOT_CONVERGED))
+        self.last_cycle_ms = ms.value
         return T, np.array(cyc[:], dtype=np.int32), rc == L.EIK_OK
 
     def backward(self, M, om, T, src_idx, tau, dLdT, tol=None, max_cycles=4096, out=None):
-        """-> (dL/dM, dL/domega, dL/dt_src packed, per-grid cycles)."""
+        """-> (dL/dM, dL/domega, dL/dt_src packed, per-grid cycles);
+        ``self.last_adj_cycle_ms`` receives the GPU time of the cycle launches."""
         if out is None:
             out = (torch.empty_like(M), torch.empty_like(om),
                    torch.empty(self.n_src, dtype=self.dtype, device=self.device))
         dM, dom, ds = out
         dLdT = dLdT.to(self.dtype).contiguous()
         cyc = (ctypes.c_int32 * self.n_grids)()
+        ms = ctypes.c_double(0.0)
         rc = L.lib().eik_soft_backward_batched(self.n_grids, self.grids, self.dc, L.ptr(src_idx), L.ptr(M),
                                                L.ptr(om), L.ptr(T), float(tau), L.ptr(dLdT), self._tol(tol),
                                                int(max_cycles), L.ptr(dM), L.ptr(dom), L.ptr(ds), L.ptr(self.ws),
-                                               self.ws.numel(), cyc, L.stream_handle(self.device))
+                                               self.ws.numel(), cyc, ctypes.byref(ms), L.stream_handle(self.device))
         L.check("eik_soft_backward_batched", rc)
+        self.last_adj_cycle_ms = ms.value
         return dM, dom, ds, np.array(cyc[:], dtype=np.int32)

@@ -695,11 +695,12 @@ int static_scratch(void **out)
 }
 
 // Workspace of the soft-min mode: grid descriptors, per-grid iteration state
-// (scale, done flag, cycle count), the bad-source count, source marks, and for
-// the adjoint the update's partials and lambda.
-constexpr int kSoftCheck = 4; // cycles between host checks
+// (scale, done flag, cycle count), the bad-source count, source marks, the
+// transposed parameters, and for the adjoint the incoming weights in both
+// layouts, the parameter partials, the transposed dL/dT and lambda.
+constexpr int kSoftCheck = 4; // cycles between host checks, one launch
 struct SoftLayout {
-    size_t descs, scale, done, cycles, bad, mark, coef, dth, lam, total;
+    size_t descs, scale, done, cycles, bad, mark, Pt, win, wint, dth, gt, lam, total;
 };
 
 SoftLayout soft_layout(int n_grids, int64_t n, int dtype)
@@ -713,8 +714,11 @@ SoftLayout soft_layout(int n_grids, int64_t n, int dtype)
     L.cycles = o; o += align256((size_t)n_grids * 4);
     L.bad = o;    o += align256(4);
     L.mark = o;   o += align256((size_t)n);
-    L.coef = o;   o += align256(8 * (size_t)n * rs);
+    L.Pt = o;     o += align256(5 * (size_t)n * rs);
+    L.win = o;    o += align256(8 * (size_t)n * rs);
+    L.wint = o;   o += align256(8 * (size_t)n * rs);
     L.dth = o;    o += align256(5 * (size_t)n * rs);
+    L.gt = o;     o += align256((size_t)n * rs);
     L.lam = o;    o += align256((size_t)n * rs);
     L.total = o;
     return L;
@@ -770,15 +774,20 @@ int soft_batch(int n_grids, const eik_grid *grids, int dtype, int64_t n, int64_t
     b.cycles = (int32_t *)(w + L.cycles);
     b.bad = (int32_t *)(w + L.bad);
     b.mark = (uint8_t *)(w + L.mark);
-    b.coef = w + L.coef;
+    b.Pt = w + L.Pt;
+    b.win = w + L.win;
+    b.wint = w + L.wint;
     b.dth = w + L.dth;
+    b.gt = w + L.gt;
     b.lam = w + L.lam;
     std::vector<unsigned char> d((size_t)n_grids * kSoftDescBytes);
     int64_t off = 0;
     int32_t sb = 0;
-    b.max_line = 1;
+    b.max_line = b.max_rows = b.max_cols = 1;
     for (int g = 0; g < n_grids; ++g) {
         b.max_line = std::max({b.max_line, grids[g].nx, grids[g].ny});
+        b.max_rows = std::max(b.max_rows, grids[g].ny);
+        b.max_cols = std::max(b.max_cols, grids[g].nx);
         write_soft_desc(off, grids[g].h, grids[g].nx, grids[g].ny, grids[g].n_src, sb, d.data() + g * kSoftDescBytes);
         off += (int64_t)grids[g].nx * grids[g].ny;
         sb += grids[g].n_src;
@@ -788,26 +797,33 @@ int soft_batch(int n_grids, const eik_grid *grids, int dtype, int64_t n, int64_t
     return EIK_OK;
 }
 
-// Runs cycles in batches of kSoftCheck until every grid is done or
-// max_cycles have run; the bad-source count is read with the first batch.
+// Runs cycles in launches of up to kSoftCheck (cycle(k) enqueues one) until
+// every grid is done or max_cycles have run; the bad-source count is read with
+// the first launch.
 // cycles_out (n_grids, may be NULL) receives each grid's cycles.
 template <typename F>
-int soft_cycles(const SoftBatch &b, int max_cycles, hipStream_t st, F &&cycle, int32_t *cycles_out, bool &conv,
-                bool &bad_src)
+int soft_cycles(const SoftBatch &b, int max_cycles, hipStream_t st, F &&cycle, int32_t *cycles_out,
+                double *cycle_ms, bool &conv, bool &bad_src)
 {
     conv = false;
     bad_src = false;
     std::vector<int32_t> done(b.n_grids);
+    LaunchTimer timer;
+    int rc = timer.init(cycle_ms != nullptr);
+    if (rc) return rc;
     int run = 0;
     while (run < max_cycles && !conv) {
         const int k = std::min(kSoftCheck, max_cycles - run);
-        for (int c = 0; c < k; ++c) cycle();
+        timer.before(st);
+        cycle(k);
+        timer.after(st);
         HIP_OK(hipGetLastError());
         run += k;
         int32_t bad = 0;
         HIP_OK(hipMemcpyAsync(done.data(), b.done, done.size() * 4, hipMemcpyDeviceToHost, st));
         HIP_OK(hipMemcpyAsync(&bad, b.bad, 4, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
+        timer.collect();
         if (bad) {
             bad_src = true;
             break;
@@ -818,21 +834,23 @@ int soft_cycles(const SoftBatch &b, int max_cycles, hipStream_t st, F &&cycle, i
         HIP_OK(hipMemcpyAsync(cycles_out, b.cycles, (size_t)b.n_grids * 4, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
     }
+    if (cycle_ms) *cycle_ms = timer.ms;
     return EIK_OK;
 }
 
 template <typename R>
 int soft_forward_impl(int n_grids, const eik_grid *grids, const int32_t *src, const void *src_t, const void *M,
                       const void *om, double tau, double tol, int max_cycles, void *T, void *ws, int64_t n,
-                      int64_t max_n, int32_t *cycles_out, hipStream_t st)
+                      int64_t max_n, int32_t *cycles_out, double *cycle_ms, hipStream_t st)
 {
     SoftBatch b;
     int rc = soft_batch(n_grids, grids, sizeof(R) == 8 ? EIK_F64 : EIK_F32, n, max_n, ws, b, st);
     if (rc) return rc;
-    launch_soft_init<R>(b, src, src_t, T, st);
+    launch_soft_init<R>(b, src, src_t, T, M, om, st);
     bool conv, bad;
     rc = soft_cycles(
-        b, max_cycles, st, [&]() { launch_soft_cycle<R>(b, M, om, T, tau, tol, st); }, cycles_out, conv, bad);
+        b, max_cycles, st, [&](int k) { launch_soft_cycles<R>(b, M, om, T, tau, tol, k, st); }, cycles_out, cycle_ms,
+        conv, bad);
     if (rc) return rc;
     if (bad) return fail(EIK_EINVAL, "a source index is outside its grid");
     return conv ? EIK_OK : fail(EIK_NOT_CONVERGED, "a grid had no quiet cycle within %d cycles", max_cycles);
@@ -841,16 +859,18 @@ int soft_forward_impl(int n_grids, const eik_grid *grids, const int32_t *src, co
 template <typename R>
 int soft_backward_impl(int n_grids, const eik_grid *grids, const int32_t *src, const void *M, const void *om,
                        const void *T, double tau, const void *gT, double tol, int max_cycles, void *dM, void *dom,
-                       void *dsrc, void *ws, int64_t n, int64_t max_n, int32_t *cycles_out, hipStream_t st)
+                       void *dsrc, void *ws, int64_t n, int64_t max_n, int32_t *cycles_out, double *cycle_ms,
+                       hipStream_t st)
 {
     SoftBatch b;
     int rc = soft_batch(n_grids, grids, sizeof(R) == 8 ? EIK_F64 : EIK_F32, n, max_n, ws, b, st);
     if (rc) return rc;
-    launch_soft_init<R>(b, src, nullptr, nullptr, st);
-    launch_soft_coef<R>(b, M, om, T, tau, st);
+    launch_soft_init<R>(b, src, nullptr, nullptr, nullptr, nullptr, st);
+    launch_soft_coef<R>(b, M, om, T, gT, tau, st);
     bool conv, bad;
     rc = soft_cycles(
-        b, max_cycles, st, [&]() { launch_soft_adj_cycle<R>(b, gT, T, tol, st); }, cycles_out, conv, bad);
+        b, max_cycles, st, [&](int k) { launch_soft_adj_cycles<R>(b, gT, T, tol, k, st); }, cycles_out, cycle_ms,
+        conv, bad);
     if (rc) return rc;
     if (bad) return fail(EIK_EINVAL, "a source index is outside its grid");
     launch_soft_params<R>(b, src, dM, dom, dsrc, st);
@@ -1403,7 +1423,7 @@ size_t eik_soft_batch_workspace_bytes(int32_t n_grids, const eik_grid *grids, in
 int eik_soft_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
                              const void *src_t, const void *M, const void *omega, double tau, double tol,
                              int32_t max_cycles, void *T, void *ws, size_t ws_bytes, int32_t *cycles,
-                             hipStream_t stream)
+                             double *cycle_ms, hipStream_t stream)
 {
     int64_t n, max_n;
     int rc = soft_check(n_grids, grids, dtype, src_idx, tau, tol, max_cycles, ws, ws_bytes, n, max_n);
@@ -1411,15 +1431,15 @@ int eik_soft_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dty
     if (!M || !omega || !T) return fail(EIK_EINVAL, "NULL pointer argument");
     if (dtype == EIK_F64)
         return soft_forward_impl<double>(n_grids, grids, src_idx, src_t, M, omega, tau, tol, max_cycles, T, ws, n,
-                                         max_n, cycles, stream);
+                                         max_n, cycles, cycle_ms, stream);
     return soft_forward_impl<float>(n_grids, grids, src_idx, src_t, M, omega, tau, tol, max_cycles, T, ws, n, max_n,
-                                    cycles, stream);
+                                    cycles, cycle_ms, stream);
 }
 
 int eik_soft_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
                               const void *M, const void *omega, const void *T, double tau, const void *dLdT,
                               double tol, int32_t max_cycles, void *dLdM, void *dLdomega, void *dLdsrc, void *ws,
-                              size_t ws_bytes, int32_t *cycles, hipStream_t stream)
+                              size_t ws_bytes, int32_t *cycles, double *cycle_ms, hipStream_t stream)
 {
     int64_t n, max_n;
     int rc = soft_check(n_grids, grids, dtype, src_idx, tau, tol, max_cycles, ws, ws_bytes, n, max_n);
@@ -1427,9 +1447,9 @@ int eik_soft_backward_batched(int32_t n_grids, const eik_grid *grids, int32_t dt
     if (!M || !omega || !T || !dLdT || !dLdM || !dLdomega || !dLdsrc) return fail(EIK_EINVAL, "NULL pointer argument");
     if (dtype == EIK_F64)
         return soft_backward_impl<double>(n_grids, grids, src_idx, M, omega, T, tau, dLdT, tol, max_cycles, dLdM,
-                                          dLdomega, dLdsrc, ws, n, max_n, cycles, stream);
+                                          dLdomega, dLdsrc, ws, n, max_n, cycles, cycle_ms, stream);
     return soft_backward_impl<float>(n_grids, grids, src_idx, M, omega, T, tau, dLdT, tol, max_cycles, dLdM, dLdomega,
-                                     dLdsrc, ws, n, max_n, cycles, stream);
+                                     dLdsrc, ws, n, max_n, cycles, cycle_ms, stream);
 }
 
 int eik_soft_forward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, double tau, double tol,
@@ -1437,7 +1457,7 @@ int eik_soft_forward(const eik_grid *grid, int32_t dtype, const void *M, const v
 {
     if (!grid) return fail(EIK_EINVAL, "grid is NULL");
     return eik_soft_forward_batched(1, grid, dtype, grid->src_idx, grid->src_t, M, omega, tau, tol, max_cycles, T, ws,
-                                    ws_bytes, cycles, stream);
+                                    ws_bytes, cycles, nullptr, stream);
 }
 
 int eik_soft_backward(const eik_grid *grid, int32_t dtype, const void *M, const void *omega, const void *T,
@@ -1446,7 +1466,7 @@ int eik_soft_backward(const eik_grid *grid, int32_t dtype, const void *M, const 
 {
     if (!grid) return fail(EIK_EINVAL, "grid is NULL");
     return eik_soft_backward_batched(1, grid, dtype, grid->src_idx, M, omega, T, tau, dLdT, tol, max_cycles, dLdM,
-                                     dLdomega, dLdsrc, ws, ws_bytes, cycles, stream);
+                                     dLdomega, dLdsrc, ws, ws_bytes, cycles, nullptr, stream);
 }
 
 } // extern "C"

@@ -184,30 +184,39 @@ void launch_project_backward(int64_t n, const void *M, const void *om, const voi
 // (rows and columns) of at most kSoftMaxLine nodes. SoftBatch points into the
 // caller's workspace: descs (kSoftDescBytes per grid, written with
 // write_soft_desc), per-grid iteration state (scale: one real, done and cycle
-// count), source marks, the bad-source count, and for the adjoint the
-// update's partials (coef 8, dth 5 reals per node) and lambda.
+// count), source marks, the bad-source count, the transposed parameters
+// (Pt, 5 reals per node), and for the adjoint the incoming weights in both
+// layouts (win, wint: 8 reals per node each), the parameter partials (dth, 5),
+// the transposed dL/dT (gt) and lambda. Grids whose values fit kSoftLdsBudget
+// bytes of LDS are swept there.
 constexpr int kSoftMaxLine = 4096;
 constexpr size_t kSoftDescBytes = 32;
+constexpr size_t kSoftLdsBudget = 56 * 1024; // with the static arrays, within 64 KB per workgroup
 struct SoftBatch {
     int32_t n_grids;
-    int32_t max_line; // longest row or column of the batch
+    int32_t max_line;           // longest row or column of the batch
+    int32_t max_rows, max_cols; // largest ny and nx of the batch
     int64_t n_nodes, max_nodes;
     void *descs;
     void *scale;
     int32_t *done, *cycles, *bad;
     uint8_t *mark;
-    void *coef, *dth, *lam;
+    void *Pt, *win, *wint, *dth, *gt, *lam;
 };
 void write_soft_desc(int64_t off, double h, int32_t nx, int32_t ny, int32_t n_src, int32_t src_base, void *dst);
+// sources and marks (T may be NULL: marks only); with M non-NULL also the transposed parameters
 template <typename R>
-void launch_soft_init(const SoftBatch &b, const int32_t *src, const void *src_t, void *T, hipStream_t st);
+void launch_soft_init(const SoftBatch &b, const int32_t *src, const void *src_t, void *T, const void *M,
+                      const void *om, hipStream_t st);
+// one launch of up to ncyc cycles per grid
 template <typename R>
-void launch_soft_cycle(const SoftBatch &b, const void *M, const void *om, void *T, double tau, double tol,
-                       hipStream_t st);
+void launch_soft_cycles(const SoftBatch &b, const void *M, const void *om, void *T, double tau, double tol, int ncyc,
+                        hipStream_t st);
 template <typename R>
-void launch_soft_coef(const SoftBatch &b, const void *M, const void *om, const void *T, double tau, hipStream_t st);
+void launch_soft_coef(const SoftBatch &b, const void *M, const void *om, const void *T, const void *gT, double tau,
+                      hipStream_t st);
 template <typename R>
-void launch_soft_adj_cycle(const SoftBatch &b, const void *gT, const void *T, double tol, hipStream_t st);
+void launch_soft_adj_cycles(const SoftBatch &b, const void *gT, const void *T, double tol, int ncyc, hipStream_t st);
 template <typename R>
 void launch_soft_params(const SoftBatch &b, const int32_t *src, void *dM, void *dom, void *dsrc, hipStream_t st);
 

@@ -81,9 +81,10 @@ __device__ __forceinline__ void all_stencils(const NodeConst<R> &k, const R Tn[8
 }
 
 // -tau log sum exp(-H_k / tau), shifted by the smallest H for range; +inf when
-// no stencil has a finite donor.
+// no stencil has a finite donor. inv_tau = 1 / tau (a multiply per stencil in
+// place of a division).
 template <typename R>
-__device__ __forceinline__ R soft_min(const R H[8], R tau)
+__device__ __forceinline__ R soft_min(const R H[8], R tau, R inv_tau)
 {
     const R inf = inf_v<R>();
     R m = inf;
@@ -93,7 +94,7 @@ __device__ __forceinline__ R soft_min(const R H[8], R tau)
     R sum = R(0);
 #pragma unroll
     for (int s = 0; s < 8; ++s)
-        if (H[s] < inf) sum += exp((m - H[s]) / tau);
+        if (H[s] < inf) sum += exp((m - H[s]) * inv_tau);
     return m - tau * log(sum);
 }
 
@@ -106,23 +107,21 @@ struct SoftDesc {
 };
 static_assert(sizeof(SoftDesc) == kSoftDescBytes, "descriptor size shared with the host layout");
 
+// Neighbour times of node (i, j) from a row-major field of pitch tp (+inf
+// outside the grid).
 template <typename R>
-__device__ __forceinline__ void node_inputs(const SoftDesc &g, const R *__restrict__ M, const R *__restrict__ om,
-                                            const R *T, int i, int j, NodeConst<R> &k, R Tn[8])
+__device__ __forceinline__ void neighbour_times(const SoftDesc &g, const R *T, int tp, int i, int j, R Tn[8])
 {
-    const int64_t n = (int64_t)g.nx * g.ny, c = (int64_t)j * g.nx + i;
-    const R h = R(g.h);
-    node_const<R>(M[c], M[n + c], M[2 * n + c], om[c], om[n + c], h, R(1) / h, k);
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
         const int a = i + nb_dx(d), b = j + nb_dy(d);
-        Tn[d] = (a < 0 || a >= g.nx || b < 0 || b >= g.ny) ? inf_v<R>() : T[(int64_t)b * g.nx + a];
+        Tn[d] = (a < 0 || a >= g.nx || b < 0 || b >= g.ny) ? inf_v<R>() : T[b * tp + a];
     }
 }
 
 // Node e of line `line` in direction dir: 0 rows up, 1 rows down, 2 columns
 // up, 3 columns down.
-__device__ __forceinline__ void line_node(const SoftDesc &g, int dir, int line, int e, int &i, int &j)
+__device__ __forceinline__ void line_node(int dir, int line, int e, int &i, int &j)
 {
     if (dir < 2) {
         i = e;
@@ -132,6 +131,10 @@ __device__ __forceinline__ void line_node(const SoftDesc &g, int dir, int line, 
         j = e;
     }
 }
+
+// Pitch of a grid held in LDS: odd, so that a column of values falls in
+// distinct banks.
+__host__ __device__ inline int soft_pitch(int nx) { return nx | 1; }
 
 // Whether a value's move from a to b keeps the iteration going: any change
 // between finite and infinite, else |b - a| > tol max(|b|, scale), where scale
@@ -169,71 +172,139 @@ struct SoftState {
     int32_t *done, *cycles;
 };
 
-// One cycle of the four directional sweeps of the soft update over grid
-// blockIdx.x (skipped once the grid is done).
-template <typename R, int NT, int PER>
-__global__ __launch_bounds__(NT) void k_soft_cycle(const SoftDesc *__restrict__ descs,
-                                                            const R *__restrict__ Mall, const R *__restrict__ omall,
-                                                            R *Tall, const uint8_t *__restrict__ markall, R tau,
-                                                            R tol, SoftState<R> st)
+// The end of one cycle: flag and scale over the workgroup. Returns whether
+// the cycle changed anything; every thread must call it.
+template <typename R, int NT>
+__device__ __forceinline__ bool cycle_end(bool ch, R &vmax, int *s_changed, R *s_red)
 {
+    if (ch) atomicOr(s_changed, 1);
+    vmax = block_max<R, NT>(vmax, s_red); // its barriers also order s_changed
+    const bool changed = *s_changed != 0;
+    __syncthreads(); // every thread has read the flag and the maximum before the next cycle resets them
+    return changed;
+}
+
+// Up to ncyc cycles of the four directional sweeps of the soft update over
+// grid blockIdx.x, stopping after the first quiet one (skipped once the grid
+// is done). LDS: the grid's times and source marks live in LDS for the
+// launch (row-major, odd pitch), else the sweeps work on the global field.
+// Rows read the parameters row-major (M, om), columns from the transposed
+// copy Pt ([5][nx][ny]), so that the nodes of a line are contiguous either way.
+template <typename R, int NT, int PER, bool LDS>
+__global__ __launch_bounds__(NT) void k_soft_cycle(const SoftDesc *__restrict__ descs,
+                                                  const R *__restrict__ Mall, const R *__restrict__ omall,
+                                                  const R *__restrict__ Ptall, R *Tall,
+                                                  const uint8_t *__restrict__ markall, R tau, R tol, int ncyc,
+                                                  SoftState<R> st)
+{
+    extern __shared__ __align__(16) unsigned char soft_lds[];
     const int gi = blockIdx.x;
     if (st.done[gi]) return; // uniform over the workgroup
     const SoftDesc g = descs[gi];
-    const R *M = Mall + 3 * g.off, *om = omall + 2 * g.off;
-    R *T = Tall + g.off;
-    const uint8_t *mark = markall + g.off;
+    const int n = g.nx * g.ny;
+    const R *M = Mall + 3 * g.off, *om = omall + 2 * g.off, *Pt = Ptall + 5 * g.off;
+    R *Tg = Tall + g.off;
+    const uint8_t *markg = markall + g.off;
+    const int tp = LDS ? soft_pitch(g.nx) : g.nx;
+    R *T = LDS ? (R *)soft_lds : Tg;
+    uint8_t *mark = LDS ? soft_lds + (size_t)g.ny * tp * sizeof(R) : (uint8_t *)markg;
+    const R h = R(g.h), inv_h = R(1) / h, inv_tau = R(1) / tau;
     __shared__ int s_changed;
     __shared__ R s_red[NT];
-    if (threadIdx.x == 0) s_changed = 0;
-    const R scale = st.scale[gi];
-    __syncthreads();
-    bool ch = false;
-    R vmax = R(0);
-    for (int dir = 0; dir < 4; ++dir) {
-        const int len = dir < 2 ? g.ny : g.nx, span = dir < 2 ? g.nx : g.ny;
-        for (int s = 0; s < len; ++s) {
-            const int line = (dir & 1) ? len - 1 - s : s;
-            R v[PER];
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int e = threadIdx.x + q * NT;
-                if (e >= span) continue;
-                int i, j;
-                line_node(g, dir, line, e, i, j);
-                const int64_t c = (int64_t)j * g.nx + i;
-                if (mark[c] == kSource) {
-                    v[q] = T[c];
-                    continue;
-                }
-                NodeConst<R> k;
-                R Tn[8], H[8], w1[8];
-                int code[8];
-                node_inputs<R>(g, M, om, T, i, j, k, Tn);
-                all_stencils<R>(k, Tn, H, code, w1);
-                v[q] = soft_min<R>(H, tau);
-            }
-            __syncthreads(); // every read of the line before its writes
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int e = threadIdx.x + q * NT;
-                if (e >= span) continue;
-                int i, j;
-                line_node(g, dir, line, e, i, j);
-                const int64_t c = (int64_t)j * g.nx + i;
-                ch |= soft_change<R>(T[c], v[q], tol, scale);
-                if (v[q] < inf_v<R>()) vmax = fmax(vmax, fabs(v[q]));
-                T[c] = v[q];
-            }
-            __syncthreads(); // the line's values before the next line reads them
+    if (LDS) {
+        for (int c = threadIdx.x; c < n; c += NT) {
+            const int i = c % g.nx, j = c / g.nx;
+            T[j * tp + i] = Tg[c];
+            mark[j * tp + i] = markg[c];
         }
     }
-    if (ch) atomicOr(&s_changed, 1);
-    vmax = block_max<R, NT>(vmax, s_red); // its barriers also order s_changed
+    R scale = st.scale[gi];
+    int cyc = 0;
+    bool quiet = false;
+    while (cyc < ncyc && !quiet) {
+        if (threadIdx.x == 0) s_changed = 0;
+        __syncthreads();
+        bool ch = false;
+        R vmax = R(0);
+        for (int dir = 0; dir < 4; ++dir) {
+            const int len = dir < 2 ? g.ny : g.nx, span = dir < 2 ? g.nx : g.ny;
+            const R *P = dir < 2 ? M : Pt;
+            const R *O = dir < 2 ? om : Pt + 3 * n;
+            // the parameters of the next line load while a line is updated
+            // (c: the node in the layout P and O follow; lanes past the line
+            // read its last node)
+            auto fetch = [&](int s, R (*p)[5]) {
+                const int line = (dir & 1) ? len - 1 - s : s;
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = min(threadIdx.x + q * NT, span - 1);
+                    const int c = line * span + e;
+                    p[q][0] = P[c];
+                    p[q][1] = P[n + c];
+                    p[q][2] = P[2 * n + c];
+                    p[q][3] = O[c];
+                    p[q][4] = O[n + c];
+                }
+            };
+            // one line ahead with one node per thread; wide workgroups (8 nodes
+            // per thread) load each line as it comes, to stay within registers
+            constexpr bool AHEAD = PER == 1;
+            R pc[PER][5], pn[AHEAD ? PER : 1][5];
+            if (AHEAD) fetch(0, pc);
+            for (int s = 0; s < len; ++s) {
+                const int line = (dir & 1) ? len - 1 - s : s;
+                if (!AHEAD) fetch(s, pc);
+                else if (s + 1 < len) fetch(s + 1, pn); // uniform over the workgroup
+                R v[PER];
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = threadIdx.x + q * NT;
+                    if (e >= span) continue;
+                    int i, j;
+                    line_node(dir, line, e, i, j);
+                    const int at = j * tp + i;
+                    if (mark[at] == kSource) {
+                        v[q] = T[at];
+                        continue;
+                    }
+                    NodeConst<R> k;
+                    node_const<R>(pc[q][0], pc[q][1], pc[q][2], pc[q][3], pc[q][4], h, inv_h, k);
+                    R Tn[8], H[8], w1[8];
+                    int code[8];
+                    neighbour_times<R>(g, T, tp, i, j, Tn);
+                    all_stencils<R>(k, Tn, H, code, w1);
+                    v[q] = soft_min<R>(H, tau, inv_tau);
+                }
+                __syncthreads(); // every read of the line before its writes
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = threadIdx.x + q * NT;
+                    if (e >= span) continue;
+                    int i, j;
+                    line_node(dir, line, e, i, j);
+                    const int at = j * tp + i;
+                    ch |= soft_change<R>(T[at], v[q], tol, scale);
+                    if (v[q] < inf_v<R>()) vmax = fmax(vmax, fabs(v[q]));
+                    T[at] = v[q];
+                }
+                if (AHEAD) {
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) pc[0][a] = pn[0][a];
+                }
+                __syncthreads(); // the line's values before the next line reads them
+            }
+        }
+        quiet = !cycle_end<R, NT>(ch, vmax, &s_changed, s_red);
+        scale = vmax;
+        ++cyc;
+    }
+    if (LDS) {
+        for (int c = threadIdx.x; c < n; c += NT) Tg[c] = T[(c / g.nx) * tp + c % g.nx];
+    }
     if (threadIdx.x == 0) {
-        if (!s_changed) st.done[gi] = 1;
-        st.scale[gi] = vmax;
-        st.cycles[gi] += 1;
+        if (quiet) st.done[gi] = 1;
+        st.scale[gi] = scale;
+        st.cycles[gi] += cyc;
     }
 }
 
@@ -273,49 +344,80 @@ __global__ void k_soft_sources(const SoftDesc *__restrict__ descs, const int32_t
     }
 }
 
-// Partial derivatives of each node's soft update at the field T: coef[d]
-// with respect to neighbour d's time (summing to 1), dth[a] with respect to
-// the node's stored m11, m12, m22, bx, by (planes per grid at 8 off and 5 off);
-// zero at sources and unreached nodes (their values do not follow the
-// update). Grid blockIdx.y. Also clears the adjoint (lam and the iteration
-// state).
+// Transposed copy of a grid's five parameter planes ([5][nx][ny]) for the
+// column sweeps; grid blockIdx.y.
+template <typename R>
+__global__ void k_soft_transpose(const SoftDesc *__restrict__ descs, const R *__restrict__ Mall,
+                                 const R *__restrict__ omall, R *__restrict__ Ptall)
+{
+    const SoftDesc g = descs[blockIdx.y];
+    const int n = g.nx * g.ny;
+    const R *M = Mall + 3 * g.off, *om = omall + 2 * g.off;
+    R *Pt = Ptall + 5 * g.off;
+    for (int ct = blockIdx.x * blockDim.x + threadIdx.x; ct < n; ct += gridDim.x * blockDim.x) {
+        const int j = ct % g.ny, i = ct / g.ny, c = j * g.nx + i; // consecutive threads write consecutive ct
+        Pt[ct] = M[c];
+        Pt[n + ct] = M[n + c];
+        Pt[2 * n + ct] = M[2 * n + c];
+        Pt[3 * n + ct] = om[c];
+        Pt[4 * n + ct] = om[n + c];
+    }
+}
+
+// Partial derivatives of each node's soft update at the field T, stored for
+// the adjoint as incoming weights: win[d][x] (row-major) and winT[d][x]
+// (transposed) hold the derivative of neighbour nb_d(x)'s update with respect
+// to T_x, so that lambda_x = g_x + sum_d win[d][x] lambda_{nb_d(x)}; node c
+// writes its coefficient for neighbour d into entry (opp d, nb_d(c)), one
+// writer per entry, and entries towards nodes outside the grid are never read.
+// dth[a] (planes per grid at 5 off) holds the derivative with respect to the
+// node's stored m11, m12, m22, bx, by; coefficients and dth are zero at
+// sources and unreached nodes (their values do not follow the update). Also
+// writes the transposed dL/dT (gt), clears lambda and the iteration state.
+// Grid blockIdx.y.
 template <typename R>
 __global__ __launch_bounds__(256) void k_soft_coef(const SoftDesc *__restrict__ descs, const R *__restrict__ Mall,
                                                    const R *__restrict__ omall, const R *__restrict__ Tall,
-                                                   const uint8_t *__restrict__ markall, R tau, R *__restrict__ coefall,
-                                                   R *__restrict__ dthall, R *__restrict__ lamall, SoftState<R> st)
+                                                   const uint8_t *__restrict__ markall, const R *__restrict__ gall,
+                                                   R tau, R *__restrict__ winall, R *__restrict__ wintall,
+                                                   R *__restrict__ dthall, R *__restrict__ gtall,
+                                                   R *__restrict__ lamall, SoftState<R> st)
 {
     const int gi = blockIdx.y;
     const SoftDesc g = descs[gi];
-    const int64_t n = (int64_t)g.nx * g.ny;
-    const R *M = Mall + 3 * g.off, *om = omall + 2 * g.off, *T = Tall + g.off;
+    const int n = g.nx * g.ny;
+    const R *M = Mall + 3 * g.off, *om = omall + 2 * g.off, *T = Tall + g.off, *gT = gall + g.off;
     const uint8_t *mark = markall + g.off;
-    R *coef = coefall + 8 * g.off, *dth = dthall + 5 * g.off, *lam = lamall + g.off;
+    R *win = winall + 8 * g.off, *wint = wintall + 8 * g.off, *dth = dthall + 5 * g.off, *gt = gtall + g.off;
+    R *lam = lamall + g.off;
+    const R h = R(g.h), inv_tau = R(1) / tau;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st.scale[gi] = R(0);
         st.done[gi] = 0;
         st.cycles[gi] = 0;
     }
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        const int i = c % g.nx, j = c / g.nx;
         lam[c] = R(0);
+        gt[i * g.ny + j] = gT[c];
         R cf[8], dt[5];
 #pragma unroll
         for (int d = 0; d < 8; ++d) cf[d] = R(0);
 #pragma unroll
         for (int a = 0; a < 5; ++a) dt[a] = R(0);
         if (mark[c] != kSource && T[c] < inf_v<R>()) {
-            const int i = (int)(c % g.nx), j = (int)(c / g.nx);
             NodeConst<R> k;
+            node_const<R>(M[c], M[n + c], M[2 * n + c], om[c], om[n + c], h, R(1) / h, k);
             R Tn[8], H[8], w1[8];
             int code[8];
-            node_inputs<R>(g, M, om, T, i, j, k, Tn);
+            neighbour_times<R>(g, T, g.nx, i, j, Tn);
             all_stencils<R>(k, Tn, H, code, w1);
-            const R v = soft_min<R>(H, tau);
+            const R v = soft_min<R>(H, tau, inv_tau);
             const R m11 = M[c], m12 = M[n + c], m22 = M[2 * n + c];
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 if (!(H[s] < inf_v<R>())) continue;
-                const R p = exp((v - H[s]) / tau); // soft-min weight of stencil s
+                const R p = exp((v - H[s]) * inv_tau); // soft-min weight of stencil s
                 if (code[s] < 8) {
                     cf[s] += p * w1[s];
                     cf[(s + 1) & 7] += p * (R(1) - w1[s]);
@@ -323,88 +425,140 @@ __global__ __launch_bounds__(256) void k_soft_coef(const SoftDesc *__restrict__ 
                     cf[code[s] - 8] += p;
                 }
                 R f[5];
-                param_derivs<R>(code[s], w1[s], m11, m12, m22, R(g.h), f);
+                param_derivs<R>(code[s], w1[s], m11, m12, m22, h, f);
 #pragma unroll
                 for (int a = 0; a < 5; ++a) dt[a] += p * f[a];
             }
         }
 #pragma unroll
-        for (int d = 0; d < 8; ++d) coef[d * n + c] = cf[d];
+        for (int d = 0; d < 8; ++d) {
+            const int a = i + nb_dx(d), b = j + nb_dy(d);
+            if (a < 0 || a >= g.nx || b < 0 || b >= g.ny) continue;
+            const int o = (d + 4) & 7;
+            win[o * n + b * g.nx + a] = cf[d];
+            wint[o * n + a * g.ny + b] = cf[d];
+        }
 #pragma unroll
         for (int a = 0; a < 5; ++a) dth[a * n + c] = dt[a];
     }
 }
 
-// One cycle of the adjoint relaxation lambda_i = g_i + sum_d coef[opp d][nb_d]
-// lambda_{nb_d} over grid blockIdx.x, with the same line order as the forward
-// (unreached nodes keep lambda = 0).
-template <typename R, int NT, int PER>
+// Up to ncyc cycles of the adjoint relaxation lambda_x = g_x + sum_d win[d][x]
+// lambda_{nb_d(x)} over grid blockIdx.x, with the line order of the forward,
+// stopping after the first quiet cycle (unreached nodes keep lambda = 0). Rows
+// read win and g row-major, columns the transposed copies. LDS: lambda and the
+// reached flags live in LDS for the launch.
+template <typename R, int NT, int PER, bool LDS>
 __global__ __launch_bounds__(NT) void k_soft_adj_cycle(const SoftDesc *__restrict__ descs,
-                                                                const R *__restrict__ coefall,
-                                                                const R *__restrict__ gall,
-                                                                const R *__restrict__ Tall, R *lamall, R tol,
-                                                                SoftState<R> st)
+                                                      const R *__restrict__ winall, const R *__restrict__ wintall,
+                                                      const R *__restrict__ gall, const R *__restrict__ gtall,
+                                                      const R *__restrict__ Tall, R *lamall, R tol, int ncyc,
+                                                      SoftState<R> st)
 {
+    extern __shared__ __align__(16) unsigned char soft_lds[];
     const int gi = blockIdx.x;
     if (st.done[gi]) return;
     const SoftDesc g = descs[gi];
-    const int64_t n = (int64_t)g.nx * g.ny;
-    const R *coef = coefall + 8 * g.off, *gT = gall + g.off, *T = Tall + g.off;
-    R *lam = lamall + g.off;
+    const int n = g.nx * g.ny;
+    const R *win = winall + 8 * g.off, *wint = wintall + 8 * g.off, *gg = gall + g.off, *gt = gtall + g.off;
+    const R *Tg = Tall + g.off;
+    R *lamg = lamall + g.off;
+    const int tp = LDS ? soft_pitch(g.nx) : g.nx;
+    R *lam = LDS ? (R *)soft_lds : lamg;
+    uint8_t *reach = LDS ? soft_lds + (size_t)g.ny * tp * sizeof(R) : nullptr;
     __shared__ int s_changed;
     __shared__ R s_red[NT];
-    if (threadIdx.x == 0) s_changed = 0;
-    const R scale = st.scale[gi];
-    __syncthreads();
-    bool ch = false;
-    R vmax = R(0);
-    for (int dir = 0; dir < 4; ++dir) {
-        const int len = dir < 2 ? g.ny : g.nx, span = dir < 2 ? g.nx : g.ny;
-        for (int s = 0; s < len; ++s) {
-            const int line = (dir & 1) ? len - 1 - s : s;
-            R v[PER];
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int e = threadIdx.x + q * NT;
-                if (e >= span) continue;
-                int i, j;
-                line_node(g, dir, line, e, i, j);
-                const int64_t c = (int64_t)j * g.nx + i;
-                if (!(T[c] < inf_v<R>())) {
-                    v[q] = R(0);
-                    continue;
-                }
-                R acc = gT[c];
-#pragma unroll
-                for (int d = 0; d < 8; ++d) {
-                    const int a = i + nb_dx(d), b = j + nb_dy(d);
-                    if (a < 0 || a >= g.nx || b < 0 || b >= g.ny) continue;
-                    const int64_t nc = (int64_t)b * g.nx + a;
-                    acc += coef[((d + 4) & 7) * n + nc] * lam[nc]; // neighbour's dependence on this node
-                }
-                v[q] = acc;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int e = threadIdx.x + q * NT;
-                if (e >= span) continue;
-                int i, j;
-                line_node(g, dir, line, e, i, j);
-                const int64_t c = (int64_t)j * g.nx + i;
-                ch |= soft_change<R>(lam[c], v[q], tol, scale);
-                vmax = fmax(vmax, fabs(v[q]));
-                lam[c] = v[q];
-            }
-            __syncthreads();
+    if (LDS) {
+        for (int c = threadIdx.x; c < n; c += NT) {
+            const int at = (c / g.nx) * tp + c % g.nx;
+            lam[at] = lamg[c];
+            reach[at] = Tg[c] < inf_v<R>();
         }
     }
-    if (ch) atomicOr(&s_changed, 1);
-    vmax = block_max<R, NT>(vmax, s_red);
+    R scale = st.scale[gi];
+    int cyc = 0;
+    bool quiet = false;
+    while (cyc < ncyc && !quiet) {
+        if (threadIdx.x == 0) s_changed = 0;
+        __syncthreads();
+        bool ch = false;
+        R vmax = R(0);
+        for (int dir = 0; dir < 4; ++dir) {
+            const int len = dir < 2 ? g.ny : g.nx, span = dir < 2 ? g.nx : g.ny;
+            const R *W = dir < 2 ? win : wint;
+            const R *G = dir < 2 ? gg : gt;
+            // the weights and dL/dT of the next line load while a line is
+            // updated (c: the node in the layout W and G follow; lanes past
+            // the line read its last node)
+            auto fetch = [&](int s, R (*w)[9]) {
+                const int line = (dir & 1) ? len - 1 - s : s;
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = min(threadIdx.x + q * NT, span - 1);
+                    const int c = line * span + e;
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) w[q][d] = W[d * n + c];
+                    w[q][8] = G[c];
+                }
+            };
+            constexpr bool AHEAD = PER == 1; // as in the forward
+            R wc[PER][9], wn[AHEAD ? PER : 1][9];
+            if (AHEAD) fetch(0, wc);
+            for (int s = 0; s < len; ++s) {
+                const int line = (dir & 1) ? len - 1 - s : s;
+                if (!AHEAD) fetch(s, wc);
+                else if (s + 1 < len) fetch(s + 1, wn); // uniform over the workgroup
+                R v[PER];
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = threadIdx.x + q * NT;
+                    if (e >= span) continue;
+                    int i, j;
+                    line_node(dir, line, e, i, j);
+                    const bool reached = LDS ? reach[j * tp + i] != 0 : Tg[j * g.nx + i] < inf_v<R>();
+                    if (!reached) {
+                        v[q] = R(0);
+                        continue;
+                    }
+                    R acc = wc[q][8];
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        const int a = i + nb_dx(d), b = j + nb_dy(d);
+                        if (a < 0 || a >= g.nx || b < 0 || b >= g.ny) continue;
+                        acc += wc[q][d] * lam[b * tp + a];
+                    }
+                    v[q] = acc;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = threadIdx.x + q * NT;
+                    if (e >= span) continue;
+                    int i, j;
+                    line_node(dir, line, e, i, j);
+                    const int at = j * tp + i;
+                    ch |= soft_change<R>(lam[at], v[q], tol, scale);
+                    vmax = fmax(vmax, fabs(v[q]));
+                    lam[at] = v[q];
+                }
+                if (AHEAD) {
+#pragma unroll
+                    for (int d = 0; d < 9; ++d) wc[0][d] = wn[0][d];
+                }
+                __syncthreads();
+            }
+        }
+        quiet = !cycle_end<R, NT>(ch, vmax, &s_changed, s_red);
+        scale = vmax;
+        ++cyc;
+    }
+    if (LDS) {
+        for (int c = threadIdx.x; c < n; c += NT) lamg[c] = lam[(c / g.nx) * tp + c % g.nx];
+    }
     if (threadIdx.x == 0) {
-        if (!s_changed) st.done[gi] = 1;
-        st.scale[gi] = vmax;
-        st.cycles[gi] += 1;
+        if (quiet) st.done[gi] = 1;
+        st.scale[gi] = scale;
+        st.cycles[gi] += cyc;
     }
 }
 
@@ -454,55 +608,84 @@ static SoftState<R> soft_state(const SoftBatch &b)
     return SoftState<R>{(R *)b.scale, b.done, b.cycles};
 }
 
+// LDS bytes of the largest grid held in LDS by the cycle kernels (values and
+// one byte per node at the odd pitch); 0 when the batch's largest grid does
+// not fit the budget and the sweeps work on the global arrays.
 template <typename R>
-void launch_soft_init(const SoftBatch &b, const int32_t *src, const void *src_t, void *T, hipStream_t st)
+static size_t soft_lds_bytes(const SoftBatch &b)
+{
+    const size_t need = (size_t)b.max_rows * soft_pitch(b.max_cols) * (sizeof(R) + 1);
+    return need <= kSoftLdsBudget ? need : 0;
+}
+
+template <typename R>
+void launch_soft_init(const SoftBatch &b, const int32_t *src, const void *src_t, void *T, const void *M,
+                      const void *om, hipStream_t st)
 {
     hipLaunchKernelGGL(k_soft_init<R>, dim3((unsigned)std::min<int64_t>((b.n_nodes + 255) / 256, 4096)), dim3(256), 0,
                        st, b.n_nodes, (R *)T, b.mark, b.bad);
     hipLaunchKernelGGL(k_soft_sources<R>, dim3(b.n_grids), dim3(256), 0, st, (const SoftDesc *)b.descs, src,
                        (const R *)src_t, (R *)T, b.mark, b.bad, soft_state<R>(b));
+    if (M)
+        hipLaunchKernelGGL(k_soft_transpose<R>, soft_node_grid(b.n_grids, b.max_nodes), dim3(256), 0, st,
+                           (const SoftDesc *)b.descs, (const R *)M, (const R *)om, (R *)b.Pt);
 }
 
 template <typename R, int NT, int PER>
-static void soft_cycle_nt(const SoftBatch &b, const void *M, const void *om, void *T, double tau, double tol,
+static void soft_cycle_nt(const SoftBatch &b, const void *M, const void *om, void *T, double tau, double tol, int ncyc,
                           hipStream_t st)
 {
-    hipLaunchKernelGGL((k_soft_cycle<R, NT, PER>), dim3(b.n_grids), dim3(NT), 0, st, (const SoftDesc *)b.descs,
-                       (const R *)M, (const R *)om, (R *)T, b.mark, R(tau), R(tol), soft_state<R>(b));
+    const size_t lds = soft_lds_bytes<R>(b);
+    if (lds)
+        hipLaunchKernelGGL((k_soft_cycle<R, NT, PER, true>), dim3(b.n_grids), dim3(NT), lds, st,
+                           (const SoftDesc *)b.descs, (const R *)M, (const R *)om, (const R *)b.Pt, (R *)T, b.mark,
+                           R(tau), R(tol), ncyc, soft_state<R>(b));
+    else
+        hipLaunchKernelGGL((k_soft_cycle<R, NT, PER, false>), dim3(b.n_grids), dim3(NT), 0, st,
+                           (const SoftDesc *)b.descs, (const R *)M, (const R *)om, (const R *)b.Pt, (R *)T, b.mark,
+                           R(tau), R(tol), ncyc, soft_state<R>(b));
 }
 
 template <typename R>
-void launch_soft_cycle(const SoftBatch &b, const void *M, const void *om, void *T, double tau, double tol,
-                       hipStream_t st)
+void launch_soft_cycles(const SoftBatch &b, const void *M, const void *om, void *T, double tau, double tol, int ncyc,
+                        hipStream_t st)
 {
-    if (b.max_line <= 64) soft_cycle_nt<R, 64, 1>(b, M, om, T, tau, tol, st);
-    else if (b.max_line <= 128) soft_cycle_nt<R, 128, 1>(b, M, om, T, tau, tol, st);
-    else if (b.max_line <= 256) soft_cycle_nt<R, 256, 1>(b, M, om, T, tau, tol, st);
-    else soft_cycle_nt<R, kSoftWideThreads, kSoftWidePer>(b, M, om, T, tau, tol, st);
+    if (b.max_line <= 64) soft_cycle_nt<R, 64, 1>(b, M, om, T, tau, tol, ncyc, st);
+    else if (b.max_line <= 128) soft_cycle_nt<R, 128, 1>(b, M, om, T, tau, tol, ncyc, st);
+    else if (b.max_line <= 256) soft_cycle_nt<R, 256, 1>(b, M, om, T, tau, tol, ncyc, st);
+    else soft_cycle_nt<R, kSoftWideThreads, kSoftWidePer>(b, M, om, T, tau, tol, ncyc, st);
 }
 
 template <typename R>
-void launch_soft_coef(const SoftBatch &b, const void *M, const void *om, const void *T, double tau, hipStream_t st)
+void launch_soft_coef(const SoftBatch &b, const void *M, const void *om, const void *T, const void *gT, double tau,
+                      hipStream_t st)
 {
     hipLaunchKernelGGL(k_soft_coef<R>, soft_node_grid(b.n_grids, b.max_nodes), dim3(256), 0, st,
-                       (const SoftDesc *)b.descs, (const R *)M, (const R *)om, (const R *)T, b.mark, R(tau),
-                       (R *)b.coef, (R *)b.dth, (R *)b.lam, soft_state<R>(b));
+                       (const SoftDesc *)b.descs, (const R *)M, (const R *)om, (const R *)T, b.mark, (const R *)gT,
+                       R(tau), (R *)b.win, (R *)b.wint, (R *)b.dth, (R *)b.gt, (R *)b.lam, soft_state<R>(b));
 }
 
 template <typename R, int NT, int PER>
-static void soft_adj_cycle_nt(const SoftBatch &b, const void *gT, const void *T, double tol, hipStream_t st)
+static void soft_adj_cycle_nt(const SoftBatch &b, const void *gT, const void *T, double tol, int ncyc, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_soft_adj_cycle<R, NT, PER>), dim3(b.n_grids), dim3(NT), 0, st, (const SoftDesc *)b.descs,
-                       (const R *)b.coef, (const R *)gT, (const R *)T, (R *)b.lam, R(tol), soft_state<R>(b));
+    const size_t lds = soft_lds_bytes<R>(b);
+    if (lds)
+        hipLaunchKernelGGL((k_soft_adj_cycle<R, NT, PER, true>), dim3(b.n_grids), dim3(NT), lds, st,
+                           (const SoftDesc *)b.descs, (const R *)b.win, (const R *)b.wint, (const R *)gT,
+                           (const R *)b.gt, (const R *)T, (R *)b.lam, R(tol), ncyc, soft_state<R>(b));
+    else
+        hipLaunchKernelGGL((k_soft_adj_cycle<R, NT, PER, false>), dim3(b.n_grids), dim3(NT), 0, st,
+                           (const SoftDesc *)b.descs, (const R *)b.win, (const R *)b.wint, (const R *)gT,
+                           (const R *)b.gt, (const R *)T, (R *)b.lam, R(tol), ncyc, soft_state<R>(b));
 }
 
 template <typename R>
-void launch_soft_adj_cycle(const SoftBatch &b, const void *gT, const void *T, double tol, hipStream_t st)
+void launch_soft_adj_cycles(const SoftBatch &b, const void *gT, const void *T, double tol, int ncyc, hipStream_t st)
 {
-    if (b.max_line <= 64) soft_adj_cycle_nt<R, 64, 1>(b, gT, T, tol, st);
-    else if (b.max_line <= 128) soft_adj_cycle_nt<R, 128, 1>(b, gT, T, tol, st);
-    else if (b.max_line <= 256) soft_adj_cycle_nt<R, 256, 1>(b, gT, T, tol, st);
-    else soft_adj_cycle_nt<R, kSoftWideThreads, kSoftWidePer>(b, gT, T, tol, st);
+    if (b.max_line <= 64) soft_adj_cycle_nt<R, 64, 1>(b, gT, T, tol, ncyc, st);
+    else if (b.max_line <= 128) soft_adj_cycle_nt<R, 128, 1>(b, gT, T, tol, ncyc, st);
+    else if (b.max_line <= 256) soft_adj_cycle_nt<R, 256, 1>(b, gT, T, tol, ncyc, st);
+    else soft_adj_cycle_nt<R, kSoftWideThreads, kSoftWidePer>(b, gT, T, tol, ncyc, st);
 }
 
 template <typename R>
@@ -527,12 +710,14 @@ void write_soft_desc(int64_t off, double h, int32_t nx, int32_t ny, int32_t n_sr
 }
 
 #define EIK_SOFT_INST(R)                                                                                           \
-    template void launch_soft_init<R>(const SoftBatch &, const int32_t *, const void *, void *, hipStream_t);       \
-    template void launch_soft_cycle<R>(const SoftBatch &, const void *, const void *, void *, double, double,       \
-                                       hipStream_t);                                                               \
-    template void launch_soft_coef<R>(const SoftBatch &, const void *, const void *, const void *, double,          \
-                                      hipStream_t);                                                                \
-    template void launch_soft_adj_cycle<R>(const SoftBatch &, const void *, const void *, double, hipStream_t);    \
+    template void launch_soft_init<R>(const SoftBatch &, const int32_t *, const void *, void *, const void *,       \
+                                      const void *, hipStream_t);                                                  \
+    template void launch_soft_cycles<R>(const SoftBatch &, const void *, const void *, void *, double, double, int, \
+                                        hipStream_t);                                                              \
+    template void launch_soft_coef<R>(const SoftBatch &, const void *, const void *, const void *, const void *,    \
+                                      double, hipStream_t);                                                        \
+    template void launch_soft_adj_cycles<R>(const SoftBatch &, const void *, const void *, double, int,            \
+                                            hipStream_t);                                                          \
     template void launch_soft_params<R>(const SoftBatch &, const int32_t *, void *, void *, void *, hipStream_t);
 EIK_SOFT_INST(float)
 EIK_SOFT_INST(double)
