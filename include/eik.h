@@ -338,7 +338,7 @@ int eik_project_backward(int64_t n, int32_t dtype, const void *M_in, const void 
  * node (each H_k exceeds its smaller donor time by at least that much); it can
  * exist beyond.
  *
- * Workspace: eik_soft_workspace_bytes(grid, dtype) bytes (about 14 reals and
+ * Workspace: eik_soft_workspace_bytes(grid, dtype) bytes (about 28 reals and
  * one byte per node), caller-owned; 0 for an invalid grid or dtype. Grid sides
  * up to 4096 nodes (EIK_EINVAL beyond). The arrays, dtype and source
  * conventions are those of eik_forward / eik_backward. The batched calls take

@@ -138,7 +138,7 @@ def test_soft_mode_rejects_bad_arguments_on_host(case):
     nx, ny = (4097, 2) if case == "side" else (16, 16)
     g = L.EikGrid(nx, ny, 0.1, 1, 0x1000, None)
     need = lib.eik_soft_workspace_bytes(ctypes.byref(g), L.EIK_F64)
-    assert need >= nx * ny * (14 * 8 + 1)
+    assert need >= nx * ny * (28 * 8 + 1)
     tau = {"tau_zero": 0.0, "tau_inf": float("inf")}.get(case, 0.01)
     tol = -1.0 if case == "tol" else 1e-12
     cycles = 0 if case == "cycles" else 8
