@@ -234,3 +234,40 @@ def test_soft_batched_equals_single_grid_calls_and_oracle():
             dMo, domo, dso = oracle.soft_vjp(p, To, ta, gs[k])
             assert _rel_l2(dMs[k].cpu().numpy(), dMo) <= F64_VJP_RTOL
             assert _rel_l2(ds[s0:s1].cpu().numpy(), dso) <= F64_VJP_RTOL
+
+
+def test_soft_batch_at_the_bench_shape_sampled_against_oracle():
+    """The launch configuration the soft-min bench times: 1024 grids of 64^2
+    in FP64 with 1 % per-node noise on the anisotropic metric, tau = 0.3 h, in
+    one batched call each way; eight sampled grids (first, last and six
+    between) against the oracle's solve and sparse adjoint."""
+    from paper_2603_00035_amd import gradcheck as C
+    from paper_2603_00035_amd.batched import SoftBatch
+    from synthetic.fields import Problem
+    n, B = 64, 1024
+    h = 1.0 / (n - 1)
+    tau = 0.3 * h
+    M0, _ = C.config_fields("anisotropic", n, "cpu")
+    rng = np.random.default_rng(5)
+    Mnp = M0.numpy()[None] * (1.0 + 0.01 * rng.normal(size=(B, 3, n, n)))
+    omnp = np.zeros((B, 2, n, n))
+    cnp = rng.uniform(0.0, 1.0, (B, n, n))
+    centre = (n // 2) * n + n // 2
+    say("soft batch 1024 x 64^2")
+    SB = SoftBatch([(n, n, h, 1)] * B, dtype=torch.float64)
+    dev = torch.device("cuda:0")
+    M = torch.tensor(Mnp, device=dev).reshape(-1)
+    om = torch.tensor(omnp, device=dev).reshape(-1)
+    src = torch.full((B,), centre, dtype=torch.int32, device=dev)
+    T, cyc, conv = SB.forward(M, om, src, tau, tol=1e-13)
+    assert conv
+    dM, _, ds, _ = SB.backward(M, om, T, src, tau, torch.tensor(cnp, device=dev).reshape(-1), tol=1e-13)
+    Tn, dMn, dsn = T.reshape(B, n, n).cpu().numpy(), dM.reshape(B, 3, n, n).cpu().numpy(), ds.cpu().numpy()
+    for g in np.linspace(0, B - 1, 8).astype(int):
+        p = Problem(n, n, h, Mnp[g], omnp[g], np.array([centre], np.int32), np.zeros(1))
+        To, _, st = oracle.soft_forward(p, tau, tol=1e-13)
+        assert st == 0
+        assert _rel_max(Tn[g], To) <= F64_FWD_RTOL
+        dMo, _, dso = oracle.soft_vjp(p, To, tau, cnp[g])
+        assert _rel_l2(dMn[g], dMo) <= F64_VJP_RTOL
+        assert abs(dsn[g] - dso[0]) <= F64_VJP_RTOL * abs(dso[0])
