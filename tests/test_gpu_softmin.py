@@ -271,3 +271,33 @@ def test_soft_batch_at_the_bench_shape_sampled_against_oracle():
         dMo, _, dso = oracle.soft_vjp(p, To, tau, cnp[g])
         assert _rel_l2(dMn[g], dMo) <= F64_VJP_RTOL
         assert abs(dsn[g] - dso[0]) <= F64_VJP_RTOL * abs(dso[0])
+
+
+def test_soft_gradient_continuous_across_a_source_tie():
+    """At the node midway between two sources the hard solver's derivative in
+    one source time jumps from 1 to 0 as that time crosses the tie; the soft
+    mode's passes through 1/2 continuously (the oracle's values, FP64 bars)."""
+    from paper_2603_00035_amd import eikonal as E
+    from synthetic.fields import Problem
+    n, h = 17, 1 / 16
+    tau = 0.1 * h
+    p0 = constant_problem(n, n, h, 1.0, 0.0, 1.0, 0.0, 0.0, [(2, 8), (14, 8)])
+    g = np.zeros((n, n))
+    g[8, 8] = 1.0
+    say("soft tie 17x17")
+    vals = {}
+    for d in (-1e-5, 1e-5):
+        p = Problem(p0.nx, p0.ny, p0.h, p0.M, p0.omega, p0.src_idx, np.array([d, 0.0]))
+        M, om, src, t = to_dev(p, torch.float64)
+        Th, par, _, _ = E.solve(M, om, src, h, src_t=t, tol=0.0)
+        _, _, dsh = E.adjoint(M, om, Th, par, None, src, h, torch.tensor(g, device=M.device), src_t=t)
+        Ts, _, ok = E.soft_solve(M, om, src, h, tau, src_t=t)
+        assert ok
+        _, _, dss = E.soft_adjoint(M, om, Ts, src, h, tau, torch.tensor(g, device=M.device))
+        To, _, _ = oracle.soft_forward(p, tau)
+        dso = oracle.soft_vjp(p, To, tau, g)[2]
+        assert abs(float(dss[0]) - dso[0]) <= F64_VJP_RTOL
+        vals[d] = (float(dsh[0]), float(dss[0]))
+    assert vals[-1e-5][0] == 1.0 and vals[1e-5][0] == 0.0
+    assert 0.0 < vals[-1e-5][1] - vals[1e-5][1] < 1e-3
+    assert abs(vals[-1e-5][1] + vals[1e-5][1] - 1.0) < 1e-10

@@ -122,3 +122,35 @@ def test_vjp_matches_central_differences_at_every_sampled_entry():
             fd = (vals[0] - vals[1]) / (2 * eps)
             an = (dM if which < 3 else dom)[comp, j, i]
             assert abs(fd - an) <= 1e-5 * abs(an) + 1e-12, (cfg, which, j, i, fd, an)
+
+
+def _tie_gradients(dt, tau=None):
+    """dT_c/dt_A for the node c midway between two sources A and B of an
+    isotropic medium, with t_A = dt and t_B = 0: the hard update (oracle's
+    solve, stencils and VJP) or the soft one at tau."""
+    n, h = 17, 1 / 16
+    p0 = constant_problem(n, n, h, 1.0, 0.0, 1.0, 0.0, 0.0, [(2, 8), (14, 8)])
+    p = Problem(p0.nx, p0.ny, p0.h, p0.M, p0.omega, p0.src_idx, np.array([dt, 0.0]))
+    g = np.zeros((n, n))
+    g[8, 8] = 1.0
+    if tau is None:
+        T, _, _ = oracle.forward(p)
+        par, _ = oracle.parents_levels(p, T)
+        return oracle.vjp(p, T, par, g)[2][0]
+    T, _, st = oracle.soft_forward(p, tau)
+    assert st == 0
+    return oracle.soft_vjp(p, T, tau, g)[2][0]
+
+
+def test_soft_gradient_is_continuous_where_the_hard_one_jumps():
+    # at a tie between two sources the hard node takes one source's path: its
+    # derivative in t_A jumps from 1 to 0; the soft one passes through 1/2
+    # (the two paths are mirror images) and changes linearly in the gap
+    tau = 0.1 / 16
+    for d in (1e-5, 1e-7):
+        assert _tie_gradients(-d) == 1.0 and _tie_gradients(d) == 0.0
+    lo5, hi5 = _tie_gradients(-1e-5, tau), _tie_gradients(1e-5, tau)
+    lo7, hi7 = _tie_gradients(-1e-7, tau), _tie_gradients(1e-7, tau)
+    assert abs((lo5 + hi5) / 2 - 0.5) < 1e-12 and abs((lo7 + hi7) / 2 - 0.5) < 1e-12
+    assert 0.0 < lo7 - hi7 < lo5 - hi5 < 1e-2
+    assert abs((lo5 - hi5) / (lo7 - hi7) / 100 - 1) < 1e-3
