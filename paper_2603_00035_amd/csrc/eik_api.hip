@@ -265,11 +265,13 @@ struct LaunchTimer {
 // min(per_check, 8) rounds, so a phase that needs a few rounds more than the
 // estimate enqueues a few more launches, not another full batch (a host
 // check costs about as much as ten launches that find no flagged tile).
-// round_fn(act_in, act_out, count_next) enqueues one round.
+// round_fn(act_in, act_out, count_next) enqueues one round. With ctr_host,
+// every check also copies the counter block there.
 template <typename F>
 int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int budget, int per_check, bool sync,
                hipStream_t st, F round_fn, int *rounds_done, bool *converged, LaunchTimer *timer = nullptr,
-               int first_batch = 0, int32_t *last_count = nullptr)
+               int first_batch = 0, int32_t *last_count = nullptr, const unsigned long long *ctr_dev = nullptr,
+               unsigned long long *ctr_host = nullptr)
 {
     int r = first;
     const int end = std::min(first + budget, kMaxRounds);
@@ -285,6 +287,8 @@ int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int bud
         if (!sync) break;
         int32_t cnt = 0;
         HIP_OK(hipMemcpyAsync(&cnt, act_count + r, sizeof cnt, hipMemcpyDeviceToHost, st));
+        if (ctr_host) // the counter block rides along with the check
+            HIP_OK(hipMemcpyAsync(ctr_host, ctr_dev, kCtrCount * sizeof *ctr_host, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
         if (timer && timer->on) timer->collect();
         if (last_count) *last_count = cnt;
@@ -365,6 +369,12 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     if (rc) return rc;
     int r0 = 0, rounds = 0;
     bool conv = false;
+    // counters as of the last host check; when the last sweep phase ends
+    // converged at such a check and nothing after it counts (no level rounds),
+    // they are the final ones and the call returns without another
+    // synchronisation (the stencil pass that follows runs behind it)
+    unsigned long long hctr[kCtrCount];
+    bool hctr_final = false;
     // Warm start with a fallback: two full-update rounds from T_init probe it;
     // a field that leaves more than a quarter of the tiles changing is dropped
     // and the solve restarts from the cold start.
@@ -378,7 +388,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
                 launch_sweep_round<R>(a, kModeFull, M, om, w.Pt, T, parent, level, ain, aout, cnt, w.ctr, tol,
                                       tn.max_local_cycles, tn.full_waves == 4 ? kFullWavesCD : tn.node_lanes, st);
             },
-            &probe_rounds, &conv, &timer, 0, &left);
+            &probe_rounds, &conv, &timer, 0, &left, w.ctr, hctr);
         if (rc) return rc;
         probe_done = true;
         if (!conv && 4 * (int64_t)left > a.n_tiles) {
@@ -411,10 +421,12 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
                                       parent, sweep_level, ain, aout, cnt, w.ctr, fast_tol, tn.max_local_cycles, 1,
                                       st);
             },
-            &rounds, &conv, &timer);
+            &rounds, &conv, &timer, 0, nullptr, w.ctr, hctr);
         if (rc) return rc;
         r0 += rounds;
         launch_copy_u64(w.ctr + kCtrCellUpdates, w.ctr + kCtrFastUpdates, st);
+        hctr[kCtrFastUpdates] = hctr[kCtrCellUpdates]; // the copy just enqueued, as the host sees it
+        hctr_final = !certify && sync && conv;
         // certify with the full update: every tile runs once more
         if (certify) launch_all_active(a, w.act + (r0 & 1) * a.n_tiles, w.act_count + r0, st);
     }
@@ -427,6 +439,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         // the full update's fixed point from any start
     } else if (probe_done && !fell_back && conv) {
         launches = r0; // the warm start's two probe rounds reached the fixed point
+        hctr_final = true;
     } else if (tn.scheduler == EIK_SCHED_QUEUE) {
         // one persistent launch over a device queue of flagged tiles
         const int waves =
@@ -458,10 +471,11 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
                                       tol, tn.max_local_cycles, tn.full_waves == 4 ? kFullWavesCD : tn.node_lanes,
                                       st);
             },
-            &rounds, &conv, &timer, (fast || T_init) ? 2 : 0);
+            &rounds, &conv, &timer, (fast || T_init) ? 2 : 0, nullptr, w.ctr, hctr);
         if (rc) return rc;
         r0 += rounds;
         launches = r0;
+        hctr_final = sync && conv;
         launch_note_pending(w.act_count + r0, w.ctr + kCtrSweepPending, st);
         HIP_OK(hipGetLastError());
     }
@@ -492,8 +506,12 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     if (!sync) return EIK_OK;
 
     unsigned long long ctr[kCtrCount];
-    HIP_OK(hipMemcpyAsync(ctr, w.ctr, sizeof ctr, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    if (hctr_final && !level) {
+        memcpy(ctr, hctr, sizeof ctr);
+    } else {
+        HIP_OK(hipMemcpyAsync(ctr, w.ctr, sizeof ctr, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
     int status = conv ? EIK_OK : EIK_NOT_CONVERGED;
     if (ctr[kCtrBadSource]) status = fail(EIK_EINVAL, "%llu source indices out of range", ctr[kCtrBadSource]);
     else if (!conv) fail(EIK_NOT_CONVERGED, "tolerance not reached in %d rounds", r0);
