@@ -958,6 +958,9 @@ def main():
                                     "kernel_ms": round((ms32 - ms_fast) / args.steps, 3),
                                     "updates_per_cell": round((u32 - u_fast) / args.steps / prob.n, 2)}
     if head["s64"]:
+        # in the mixed path the FP64 phase's inputs are staged on a second
+        # stream during the first FP32 rounds, which share the GPU with it
+        roof["concurrent"] = "k_stage<double, 64> (256 workgroups) on a second stream beside the first rounds"
         u64 = sum(s.cell_updates for s in head["s64"])
         ms64 = sum(s.sweep_ms for s in head["s64"])
         roof["fp64_phase"] = {"kernel": "k_sweep_round_cd<double, 64, true>", "kernel_ms": round(ms64 / args.steps, 3),

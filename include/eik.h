@@ -36,9 +36,12 @@
  * sources of grid 0, then grid 1, ..., with indices local to their grid.
  *
  * Ownership: the caller owns every buffer, including the workspace (size from
- * eik_workspace_bytes / eik_batch_workspace_bytes). The library keeps no state
- * between calls and never allocates device memory. Work is enqueued on the
- * given HIP stream.
+ * eik_workspace_bytes / eik_batch_workspace_bytes). The library never
+ * allocates device memory and keeps no state between calls except one
+ * non-blocking stream of default priority per device, created on first use
+ * by eik_forward_mixed and kept until the process ends. Work is enqueued on
+ * the given HIP stream (eik_forward_mixed forks part of it onto that stream
+ * and joins it back with events before it returns).
  *
  * Errors: every call returns an int status and never throws. Negative values
  * are errors (nothing useful was written); EIK_NOT_CONVERGED is a warning
@@ -205,7 +208,9 @@ int eik_forward_noalloc(const eik_grid *grid, int32_t dtype, const void *M, cons
  * phase. EIK_CHECK_FEASIBLE tests the FP32 copies. tuning32 and tuning
  * (each optional) drive the two phases; stats is NULL or an array of two
  * (FP32 phase, FP64 phase). The workspace comes from
- * eik_mixed_workspace_bytes. The FP64 state it returns feeds eik_backward
+ * eik_mixed_workspace_bytes: the FP32 copies, the FP64 phase's workspace and
+ * one of its own for the FP32 phase, so that the FP64 phase's inputs are
+ * staged on the side stream while the FP32 sweeps run. The FP64 state it returns feeds eik_backward
  * with EIK_F64. Errors as eik_forward; the status is that of the FP64 phase
  * unless the FP32 phase failed. */
 size_t eik_mixed_workspace_bytes(const eik_grid *grid);

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -332,7 +333,8 @@ template <typename R>
 int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, const void *src_t, const void *M,
                  const void *om, const void *T_init, double tol, int max_rounds, int flags, void *T,
                  uint8_t *parent, int32_t *level, void *ws, size_t ws_bytes, const eik_tuning *tun,
-                 eik_stats *stats, bool single, hipStream_t st, bool certify = true)
+                 eik_stats *stats, bool single, hipStream_t st, bool certify = true, bool pre_staged = false,
+                 const std::function<int()> &after_init = nullptr)
 {
     const int dtype = sizeof(R) == 8 ? EIK_F64 : EIK_F32;
     // the sweeps keep the source marks in the parent array
@@ -359,10 +361,14 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         HIP_OK(hipStreamSynchronize(st));
         if (bad) return fail(EIK_EINFEASIBLE, "metric not SPD or |omega|_{M^-1} >= 1 somewhere");
     }
-    launch_stage<R>(a, M, om, w.Pt, st);
+    if (!pre_staged) launch_stage<R>(a, M, om, w.Pt, st); // else staged in this workspace already
     launch_init<R>(a, T_init, T, parent, level, src_idx, src_t, w.act, w.act_count, w.ctr, T_init != nullptr,
                    st);
     HIP_OK(hipGetLastError());
+    if (after_init) { // the caller's work to enqueue once the sweeps are next (the mixed path's side stream)
+        rc = after_init();
+        if (rc) return rc;
+    }
 
     LaunchTimer timer;
     rc = timer.init((flags & EIK_TIME_KERNELS) != 0 && sync);
@@ -536,11 +542,14 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
 // FP32 field and source times, then the workspace of the FP64 solve, which the
 // FP32 solve uses before it. The mixed adjoint keeps its FP32 weights, dL/dT
 // and lambda in the first three regions.
+// With split (the single-grid mixed forward), the FP32 phase gets a workspace
+// of its own after the FP64 one, so that the FP64 staging can run beside the
+// FP32 sweeps; the batched calls share one (their plan serves both phases).
 struct MixedLayout {
-    size_t M32, om32, T32, src32, base, total;
+    size_t M32, om32, T32, src32, base, ws32, total;
 };
 
-MixedLayout mixed_layout(const Extent &e)
+MixedLayout mixed_layout(const Extent &e, bool split = false)
 {
     const size_t n = (size_t)e.nodes;
     MixedLayout L;
@@ -549,10 +558,47 @@ MixedLayout mixed_layout(const Extent &e)
     L.om32 = o;  o += align256(2 * n * 4);
     L.T32 = o;   o += align256(n * 4);
     L.src32 = o; o += align256((size_t)e.n_src * 4);
-    L.base = o;
-    L.total = o + layout(e, EIK_F64).total;
+    L.base = o;  o += align256(layout(e, EIK_F64).total);
+    L.ws32 = split ? o : L.base;
+    if (split) o += layout(e, EIK_F32).total;
+    L.total = o;
     return L;
 }
+
+// Workgroups of the FP64 staging beside the FP32 sweeps, one per CU: on the
+// 2048^2 stress field one per tile (1024) holds the CUs until it ends and
+// delays the first rounds, 64 stretch it over the whole FP32 phase and slow
+// every round; 256 gave the shortest step (4.95 ms median against 5.07 and
+// 5.12; 5.26 without the overlap).
+constexpr int kSideStageBlocks = 256;
+
+// A non-blocking stream of default priority per device, created on first use
+// and kept for the life of the process: the mixed forward stages its FP64
+// inputs there while the FP32 sweeps run on the caller's stream.
+int side_stream(hipStream_t &out)
+{
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev]) HIP_OK(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+    out = streams[dev];
+    return EIK_OK;
+}
+
+// Events of one fork/join between the caller's stream and the side stream,
+// released when the call returns (a recorded event may be destroyed before it
+// completes).
+struct ForkEvents {
+    hipEvent_t fork = nullptr, join = nullptr;
+    ~ForkEvents()
+    {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+    }
+};
 
 // The adjoint relaxation (round or queue scheduler) on lambda of type RL.
 template <typename RL>
@@ -1004,7 +1050,7 @@ size_t eik_mixed_workspace_bytes(const eik_grid *grid)
     if (!grid || !grid->src_idx) return 0;
     Extent e;
     if (extent_of(1, grid, EIK_F64, e)) return 0;
-    return mixed_layout(e).total;
+    return mixed_layout(e, true).total;
 }
 
 int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega, double tol32, double tol,
@@ -1023,11 +1069,38 @@ int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega
     Extent e;
     rc = extent_of(1, grid, EIK_F64, e);
     if (rc) return rc;
-    const MixedLayout L = mixed_layout(e);
+    const MixedLayout L = mixed_layout(e, true);
     if (!ws || ws_bytes < L.total)
         return fail(EIK_EWORKSPACE, "workspace %zu bytes, %zu needed", ws_bytes, L.total);
     char *b = (char *)ws;
     float *M32 = (float *)(b + L.M32), *om32 = (float *)(b + L.om32), *T32 = (float *)(b + L.T32);
+    // The FP64 phase's staged inputs (parameters and metric roots) depend on
+    // M and omega only: they are staged on the side stream while the FP32
+    // sweeps run (forked once the FP32 phase's own passes over the grid are
+    // enqueued, which it would otherwise slow down), in the FP64 workspace,
+    // which the FP32 phase does not touch.
+    const eik_tuning tn64 = tuning_or_default(tuning);
+    hipStream_t side = nullptr;
+    rc = side_stream(side);
+    if (rc) return rc;
+    ForkEvents ev;
+    HIP_OK(hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&ev.join, hipEventDisableTiming));
+    bool forked = false;
+    auto fork_staging = [&]() -> int {
+        HIP_OK(hipEventRecord(ev.fork, stream));
+        HIP_OK(hipStreamWaitEvent(side, ev.fork, 0));
+        Extent e64;
+        Ws w64;
+        LaunchArgs a64;
+        int r = prepare(1, grid, EIK_F64, b + L.base, L.ws32 - L.base, tn64, true, side, e64, w64, a64);
+        if (r) return r;
+        launch_stage<double>(a64, M, omega, w64.Pt, side, kSideStageBlocks);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipEventRecord(ev.join, side));
+        forked = true;
+        return EIK_OK;
+    };
     launch_cast_f64_f32(3 * e.nodes, M, M32, stream);
     launch_cast_f64_f32(2 * e.nodes, omega, om32, stream);
     eik_grid g32 = *grid;
@@ -1038,16 +1111,18 @@ int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega
     HIP_OK(hipGetLastError());
     // FP32 sweeps from the cold start; not reaching tol32 is no error here
     rc = forward_impl<float>(1, &g32, g32.src_idx, g32.src_t, M32, om32, nullptr, tol32, max_rounds, flags, T32,
-                             parent, nullptr, b + L.base, ws_bytes - L.base, tuning32, stats, true, stream,
-                             /*certify=*/false);
+                             parent, nullptr, b + L.ws32, ws_bytes - L.ws32, tuning32, stats, true, stream,
+                             /*certify=*/false, /*pre_staged=*/false, fork_staging);
+    if (forked) HIP_OK(hipStreamWaitEvent(stream, ev.join, 0)); // joined before any return: the side work ends in order
     if (rc < 0) return rc;
+    if (!forked) return fail(EIK_EDEVICE, "the FP64 staging was not enqueued");
     // FP64 sweeps from that field, in place in T
     launch_cast_f32_f64(e.nodes, T32, T, stream);
     HIP_OK(hipGetLastError());
     return forward_impl<double>(1, grid, grid->src_idx, grid->src_t, M, omega, T, tol, max_rounds,
                                 flags & ~(EIK_CHECK_FEASIBLE | EIK_WARM_FALLBACK), T, parent, level, b + L.base,
-                                ws_bytes - L.base,
-                                tuning, stats ? stats + 1 : nullptr, true, stream);
+                                L.ws32 - L.base, tuning, stats ? stats + 1 : nullptr, true, stream,
+                                /*certify=*/true, /*pre_staged=*/true);
 }
 
 int eik_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,

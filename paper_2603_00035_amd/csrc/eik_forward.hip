@@ -90,12 +90,12 @@ __device__ __forceinline__ const R *staged_roots_rows(const LaunchArgs &a, const
 }
 
 template <typename R, int TH>
-__global__ __launch_bounds__(256) void k_stage(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
-                                               R *__restrict__ Pt)
+__device__ __forceinline__ void stage_tile(const LaunchArgs &a, int t, const R *__restrict__ M,
+                                           const R *__restrict__ om, R *__restrict__ Pt)
 {
     constexpr int kCols = Staged<R>::cols;
     __shared__ R buf[TH][TW + 1];
-    const TileGeo g = tile_geo<TH>(a, blockIdx.x);
+    const TileGeo g = tile_geo<TH>(a, t);
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
     const R *Mg = M + 3 * g.gd.off;
     R *Pc = Pt + kCols * a.n_nodes + kRoots * g.gd.off;
@@ -125,6 +125,16 @@ __global__ __launch_bounds__(256) void k_stage(LaunchArgs a, const R *__restrict
         }
         __syncthreads();
     }
+}
+
+// One workgroup per tile, or (a grid of fewer workgroups) each workgroup
+// taking tiles blockIdx.x, blockIdx.x + gridDim.x, ...: a narrow grid leaves
+// most CUs to work running beside it on another stream.
+template <typename R, int TH>
+__global__ __launch_bounds__(256) void k_stage(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
+                                               R *__restrict__ Pt)
+{
+    for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) stage_tile<R, TH>(a, t, M, om, Pt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1081,9 +1091,10 @@ void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_gr
 }
 
 template <typename R>
-void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, hipStream_t st)
+void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, hipStream_t st, int max_blocks)
 {
-    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_stage<R, TH>), dim3(a.n_tiles), dim3(256), 0, st, a, (const R *)M,
+    const int blocks = max_blocks > 0 ? std::min(max_blocks, a.n_tiles) : a.n_tiles;
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_stage<R, TH>), dim3(blocks), dim3(256), 0, st, a, (const R *)M,
                                              (const R *)om, (R *)Pt));
 }
 
@@ -1236,7 +1247,7 @@ void launch_check_feasible(int64_t n, const void *M, const void *om, unsigned lo
 }
 
 #define EIK_INST(R)                                                                                             \
-    template void launch_stage<R>(const LaunchArgs &, const void *, const void *, void *, hipStream_t);         \
+    template void launch_stage<R>(const LaunchArgs &, const void *, const void *, void *, hipStream_t, int);    \
     template void launch_init<R>(const LaunchArgs &, const void *, void *, uint8_t *, int32_t *,                 \
                                  const int32_t *, const void *, int32_t *, int32_t *, unsigned long long *,      \
                                  bool, hipStream_t);                                                             \

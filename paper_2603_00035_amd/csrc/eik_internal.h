@@ -67,7 +67,7 @@ void launch_note_queue(const WorkQueue &q, unsigned long long *slot, hipStream_t
 
 // forward
 template <typename R>
-void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, hipStream_t st);
+void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, hipStream_t st, int max_blocks = 0);
 template <typename R>
 void launch_init(const LaunchArgs &a, const void *T_init, void *T, uint8_t *code, int32_t *level,
                  const int32_t *src_idx, const void *src_t, int32_t *act, int32_t *act_count,
