@@ -575,12 +575,14 @@ constexpr int kSideStageBlocks = 256;
 // A non-blocking stream of default priority per device, created on first use
 // and kept for the life of the process: the mixed forward stages its FP64
 // inputs there while the FP32 sweeps run on the caller's stream.
-int side_stream(hipStream_t &out)
+int side_stream(hipStream_t caller, hipStream_t &out)
 {
     static std::mutex mu;
     static std::vector<hipStream_t> streams;
-    int dev = 0;
-    HIP_OK(hipGetDevice(&dev));
+    int dev = 0, cur = 0;
+    HIP_OK(hipStreamGetDevice(caller, &dev));
+    HIP_OK(hipGetDevice(&cur));
+    if (dev != cur) return fail(EIK_EINVAL, "the stream belongs to device %d while device %d is current", dev, cur);
     std::lock_guard<std::mutex> lock(mu);
     if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
     if (!streams[dev]) HIP_OK(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
@@ -1081,7 +1083,7 @@ int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega
     // which the FP32 phase does not touch.
     const eik_tuning tn64 = tuning_or_default(tuning);
     hipStream_t side = nullptr;
-    rc = side_stream(side);
+    rc = side_stream(stream, side);
     if (rc) return rc;
     ForkEvents ev;
     HIP_OK(hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming));
