@@ -257,6 +257,11 @@ struct LaunchTimer {
     }
 };
 
+// Slot of the counter block, beyond those the kernels use, that carries the
+// flagged-tile count of a host check.
+constexpr int kCtrCheck = kCtrCount - 1;
+static_assert(kCtrCheck > kCtrFastUpdates, "the check slot must be free");
+
 // Rounds until a round flags nothing (converged) or the budget runs out.
 // Without a host check (sync = false) exactly `budget` rounds are enqueued;
 // rounds after convergence find no flagged tile and exit at once. With host
@@ -267,11 +272,12 @@ struct LaunchTimer {
 // estimate enqueues a few more launches, not another full batch (a host
 // check costs about as much as ten launches that find no flagged tile).
 // round_fn(act_in, act_out, count_next) enqueues one round. With ctr_host,
-// every check also copies the counter block there.
+// every check also copies the counter block there (the count read through
+// slot kCtrCheck, so that one copy serves both).
 template <typename F>
 int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int budget, int per_check, bool sync,
                hipStream_t st, F round_fn, int *rounds_done, bool *converged, LaunchTimer *timer = nullptr,
-               int first_batch = 0, int32_t *last_count = nullptr, const unsigned long long *ctr_dev = nullptr,
+               int first_batch = 0, int32_t *last_count = nullptr, unsigned long long *ctr_dev = nullptr,
                unsigned long long *ctr_host = nullptr)
 {
     int r = first;
@@ -287,10 +293,17 @@ int run_rounds(int32_t *act, int32_t *act_count, int n_tiles, int first, int bud
         if (timer && timer->on) timer->after(st);
         if (!sync) break;
         int32_t cnt = 0;
-        HIP_OK(hipMemcpyAsync(&cnt, act_count + r, sizeof cnt, hipMemcpyDeviceToHost, st));
-        if (ctr_host) // the counter block rides along with the check
+        if (ctr_host) {
+            // one copy back for both: the flagged-tile count goes into a free
+            // slot of the counter block first
+            launch_note_pending(act_count + r, ctr_dev + kCtrCheck, st);
             HIP_OK(hipMemcpyAsync(ctr_host, ctr_dev, kCtrCount * sizeof *ctr_host, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
+            HIP_OK(hipStreamSynchronize(st));
+            cnt = (int32_t)ctr_host[kCtrCheck];
+        } else {
+            HIP_OK(hipMemcpyAsync(&cnt, act_count + r, sizeof cnt, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+        }
         if (timer && timer->on) timer->collect();
         if (last_count) *last_count = cnt;
         if (cnt == 0) {
@@ -334,7 +347,7 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
                  const void *om, const void *T_init, double tol, int max_rounds, int flags, void *T,
                  uint8_t *parent, int32_t *level, void *ws, size_t ws_bytes, const eik_tuning *tun,
                  eik_stats *stats, bool single, hipStream_t st, bool certify = true, bool pre_staged = false,
-                 const std::function<int()> &after_init = nullptr)
+                 const std::function<int()> &after_init = nullptr, int full_first_batch = -1)
 {
     const int dtype = sizeof(R) == 8 ? EIK_F64 : EIK_F32;
     // the sweeps keep the source marks in the parent array
@@ -477,7 +490,8 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
                                       tol, tn.max_local_cycles, tn.full_waves == 4 ? kFullWavesCD : tn.node_lanes,
                                       st);
             },
-            &rounds, &conv, &timer, (fast || T_init) ? 2 : 0, nullptr, w.ctr, hctr);
+            &rounds, &conv, &timer, full_first_batch >= 0 ? full_first_batch : ((fast || T_init) ? 2 : 0), nullptr,
+            w.ctr, hctr);
         if (rc) return rc;
         r0 += rounds;
         launches = r0;
@@ -1124,7 +1138,8 @@ int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega
     return forward_impl<double>(1, grid, grid->src_idx, grid->src_t, M, omega, T, tol, max_rounds,
                                 flags & ~(EIK_CHECK_FEASIBLE | EIK_WARM_FALLBACK), T, parent, level, b + L.base,
                                 L.ws32 - L.base, tuning, stats ? stats + 1 : nullptr, true, stream,
-                                /*certify=*/true, /*pre_staged=*/true);
+                                /*certify=*/true, /*pre_staged=*/true, nullptr,
+                                /*full_first_batch=*/0); // no early check: the FP32 field is not within tol
 }
 
 int eik_forward_batched(int32_t n_grids, const eik_grid *grids, int32_t dtype, const int32_t *src_idx,
