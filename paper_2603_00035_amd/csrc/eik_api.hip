@@ -363,11 +363,9 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
     const bool sync = single || stats != nullptr;
     max_rounds = std::max(1, std::min(max_rounds, kMaxRounds / 4));
 
-    launch_fill_u64(w.ctr, kCtrCount, st);
-    launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
-    launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
     HIP_OK(hipGetLastError());
     if (flags & EIK_CHECK_FEASIBLE) {
+        launch_fill_u64(w.ctr, kCtrCount, st);
         launch_check_feasible<R>(e.nodes, M, om, w.ctr, st);
         unsigned long long bad = 0;
         HIP_OK(hipMemcpyAsync(&bad, w.ctr + kCtrInfeasible, 8, hipMemcpyDeviceToHost, st));
@@ -375,8 +373,9 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         if (bad) return fail(EIK_EINFEASIBLE, "metric not SPD or |omega|_{M^-1} >= 1 somewhere");
     }
     if (!pre_staged) launch_stage<R>(a, M, om, w.Pt, st); // else staged in this workspace already
+    // initial field, and the round state cleared in the same launch
     launch_init<R>(a, T_init, T, parent, level, src_idx, src_t, w.act, w.act_count, w.ctr, T_init != nullptr,
-                   st);
+                   st, /*reset=*/true);
     HIP_OK(hipGetLastError());
     if (after_init) { // the caller's work to enqueue once the sweeps are next (the mixed path's side stream)
         rc = after_init();
@@ -443,9 +442,11 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
             &rounds, &conv, &timer, 0, nullptr, w.ctr, hctr);
         if (rc) return rc;
         r0 += rounds;
-        launch_copy_u64(w.ctr + kCtrCellUpdates, w.ctr + kCtrFastUpdates, st);
-        hctr[kCtrFastUpdates] = hctr[kCtrCellUpdates]; // the copy just enqueued, as the host sees it
         hctr_final = !certify && sync && conv;
+        // the cold start's update count, for the stats (read on the device
+        // only when the counters are read again at the end)
+        if (!hctr_final) launch_copy_u64(w.ctr + kCtrCellUpdates, w.ctr + kCtrFastUpdates, st);
+        hctr[kCtrFastUpdates] = hctr[kCtrCellUpdates];
         // certify with the full update: every tile runs once more
         if (certify) launch_all_active(a, w.act + (r0 & 1) * a.n_tiles, w.act_count + r0, st);
     }

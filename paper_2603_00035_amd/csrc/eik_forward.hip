@@ -140,13 +140,24 @@ __global__ __launch_bounds__(256) void k_stage(LaunchArgs a, const R *__restrict
 // ---------------------------------------------------------------------------
 // Initialisation: T, codes (source marks), levels, first active tiles.
 // ---------------------------------------------------------------------------
+// With act non-null it also resets the round state, one writer per element:
+// the tile flags of both buffers and the per-round counts (every tile flagged
+// for round 0 when warm), and the counter block.
 template <typename R>
-__global__ void k_init(int64_t n, const R *T_init, R *T, uint8_t *__restrict__ code, int32_t *__restrict__ level)
+__global__ void k_init(int64_t n, const R *T_init, R *T, uint8_t *__restrict__ code, int32_t *__restrict__ level,
+                       int32_t *__restrict__ act, int32_t *__restrict__ act_count, unsigned long long *__restrict__ ctr,
+                       int n_tiles, int warm)
 { // T_init may be T itself (in-place warm start): each element is read before it is written
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = tid; c < n; c += stride) {
         T[c] = T_init ? T_init[c] : inf_v<R>();
         code[c] = kUnreached;
         if (level) level[c] = -1;
+    }
+    if (act) {
+        for (int64_t i = tid; i < 2 * (int64_t)n_tiles; i += stride) act[i] = (warm && i < n_tiles) ? 1 : 0;
+        for (int64_t i = tid; i < kMaxRounds + 2; i += stride) act_count[i] = (warm && i == 0) ? n_tiles : 0;
+        for (int64_t i = tid; i < kCtrCount; i += stride) ctr[i] = 0;
     }
 }
 
@@ -1101,11 +1112,12 @@ void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, 
 template <typename R>
 void launch_init(const LaunchArgs &a, const void *T_init, void *T, uint8_t *code, int32_t *level,
                  const int32_t *src_idx, const void *src_t, int32_t *act, int32_t *act_count,
-                 unsigned long long *ctr, bool warm, hipStream_t st)
+                 unsigned long long *ctr, bool warm, hipStream_t st, bool reset)
 {
-    hipLaunchKernelGGL(k_init<R>, dim3(blocks_for(a.n_nodes, 256)), dim3(256), 0, st, a.n_nodes,
-                       (const R *)T_init, (R *)T, code, level);
-    if (warm) launch_all_active(a, act, act_count, st);
+    const int64_t work = std::max<int64_t>(a.n_nodes, reset ? kMaxRounds + 2 : 0);
+    hipLaunchKernelGGL(k_init<R>, dim3(blocks_for(work, 256)), dim3(256), 0, st, a.n_nodes, (const R *)T_init,
+                       (R *)T, code, level, reset ? act : nullptr, act_count, ctr, a.n_tiles, warm ? 1 : 0);
+    if (warm && !reset) launch_all_active(a, act, act_count, st);
     EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_sources<R, TH>), dim3(a.n_grids), dim3(64), 0, st, a, src_idx,
                                              (const R *)src_t, (R *)T, code, level, act, act_count, ctr));
 }
@@ -1250,7 +1262,7 @@ void launch_check_feasible(int64_t n, const void *M, const void *om, unsigned lo
     template void launch_stage<R>(const LaunchArgs &, const void *, const void *, void *, hipStream_t, int);    \
     template void launch_init<R>(const LaunchArgs &, const void *, void *, uint8_t *, int32_t *,                 \
                                  const int32_t *, const void *, int32_t *, int32_t *, unsigned long long *,      \
-                                 bool, hipStream_t);                                                             \
+                                 bool, hipStream_t, bool);                                                       \
     template void launch_sweep_round<R>(const LaunchArgs &, int, const void *, const void *, const void *,       \
                                         void *, uint8_t *, int32_t *, int32_t *, int32_t *, int32_t *,           \
                                         unsigned long long *, double, int, int, hipStream_t);                    \

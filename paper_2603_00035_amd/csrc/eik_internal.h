@@ -68,10 +68,12 @@ void launch_note_queue(const WorkQueue &q, unsigned long long *slot, hipStream_t
 // forward
 template <typename R>
 void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, hipStream_t st, int max_blocks = 0);
+// reset: the initialisation also clears the round state (act, act_count,
+// the counter block) and, when warm, flags every tile for round 0
 template <typename R>
 void launch_init(const LaunchArgs &a, const void *T_init, void *T, uint8_t *code, int32_t *level,
                  const int32_t *src_idx, const void *src_t, int32_t *act, int32_t *act_count,
-                 unsigned long long *ctr, bool warm, hipStream_t st);
+                 unsigned long long *ctr, bool warm, hipStream_t st, bool reset = false);
 template <typename R>
 void launch_sweep_round(const LaunchArgs &a, int mode, const void *M, const void *om, const void *Pt, void *T,
                         uint8_t *code, int32_t *level, int32_t *act_in, int32_t *act_out, int32_t *count_next,
