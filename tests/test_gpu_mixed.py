@@ -102,3 +102,28 @@ def test_mixed_adjoint_matches_oracle(cfg, seed, nx, ny):
     r = rel_l2([dM.cpu().numpy(), dom.cpu().numpy(), ds.cpu().numpy()], [dMo, domo, dso])
     say(f"  gradient rel L2 {r:.2e} (FP32 relaxation)")
     assert r <= 1e-5
+
+
+def test_mixed_forward_on_two_caller_streams():
+    """The mixed forward forks its FP64 staging onto one side stream per
+    device and joins it back with events: two solves issued on two caller
+    streams (default priority), each with its own workspace, share that side
+    stream (the second's staging can overlap the first's tail, which runs
+    behind its returning call); both reach the FP64 fixed point (tol 0) as a
+    solve on the current stream does."""
+    from paper_2603_00035_amd import eikonal as E
+    probs = [make_problem("c2", 21, nx=150, ny=120), make_problem("c3", 22, nx=130, ny=170)]
+    say("[mixed] two streams")
+    ins = [dev_inputs(p) for p in probs]
+    ref = [E.solve_mixed(M, om, src, p.h, tol=0.0, tol32=1e-5, levels=False)[0] for (M, om, src), p in zip(ins, probs)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    out = [None, None]
+    for k, ((M, om, src), p) in enumerate(zip(ins, probs)):
+        with torch.cuda.stream(streams[k]):
+            out[k] = E.solve_mixed(M, om, src, p.h, tol=0.0, tol32=1e-5, levels=False)[0]
+    torch.cuda.synchronize()
+    for k, p in enumerate(probs):
+        To, _, _ = oracle.forward(p)
+        assert rel_err_cells(out[k].cpu().numpy(), To, p.src_idx) <= 1e-12
+        assert rel_err_cells(ref[k].cpu().numpy(), To, p.src_idx) <= 1e-12
