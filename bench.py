@@ -987,6 +987,14 @@ def main():
         "fwd_ms": fh["fwd_ms"],
         "adj_ms": fh["adj_ms"],
         "sweeps_per_cell": fh["sweeps_per_cell"],
+        # the updates behind `value` by kind (per cell per step), and the
+        # throughput in grid cells solved and differentiated, which does not
+        # count repeated updates
+        "updates_per_cell": {"fp32_restricted": round(u_fast / args.steps / prob.n, 2),
+                             "fp32_full": round((sum(s.cell_updates for s in head["s32"]) - u_fast) / args.steps
+                                                / prob.n, 2),
+                             "fp64_full": round(sum(s.cell_updates for s in head["s64"]) / args.steps / prob.n, 2)},
+        "cells_per_s": prob.n * args.steps / head["wall"],
         "rounds": fh["rounds"],
         "step_ms_median": fh["step_ms_median"], "step_ms_min": fh["step_ms_min"], "step_ms_max": fh["step_ms_max"],
         "per_step": head["steps"],
