@@ -623,9 +623,7 @@ int relax(const LaunchArgs &a, Ws &w, const eik_tuning &tn, bool sync, const Adj
           hipStream_t st, int &rounds, bool &conv)
 {
     const int dtype = sizeof(RL) == 8 ? EIK_F64 : EIK_F32;
-    launch_fill_i32(w.act, 2 * (int64_t)a.n_tiles, 0, st);
-    launch_fill_i32(w.act_count, kMaxRounds + 2, 0, st);
-    launch_all_active(a, w.act, w.act_count, st);
+    launch_round_reset(a, w.act, w.act_count, st);
     HIP_OK(hipGetLastError());
     rounds = 0;
     conv = false;
@@ -693,14 +691,18 @@ int backward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, co
     if (by_levels && !level) return fail(EIK_EINVAL, "the level-scheduled adjoint needs the forward's levels");
     int32_t *lv_order = (int32_t *)w.Pt, *lv_bins = lv_order + e.nodes, *lv_gmax = lv_bins + e.nodes;
     launch_fill_u64(w.ctr + kCtrAdjPending, 1, st);
-    launch_adj_prep<R>(a, M, om, T, parent, w.w1, w.lam, st);
+    Prep32 p32; // the FP32 relaxation's inputs written by the preparation itself
+    if (r32) {
+        p32.w1 = r32->w1;
+        p32.g_src = dLdT;
+        p32.g = r32->g;
+        p32.lam = r32->lam;
+    }
+    launch_adj_prep<R>(a, M, om, T, parent, w.w1, w.lam, st, p32);
     int rounds = 0;
     bool conv = false;
     if (by_levels) launch_level_buckets(a, level, lv_gmax, lv_bins, lv_order, st);
     if (r32) { // weights from the state in R, lambda relaxed in FP32, then widened
-        launch_cast_f64_f32(e.nodes, (const double *)w.w1, r32->w1, st);
-        launch_cast_f64_f32(e.nodes, (const double *)dLdT, r32->g, st);
-        launch_fill_i32((int32_t *)r32->lam, e.nodes, 0, st); // +0.0f
         launch_adj_stage<float>(a, parent, r32->g, w.adjD, w.adjDT, w.adjGT, st);
         if (by_levels) {
             launch_level_gather<float>(a, lv_gmax, lv_bins, lv_order, w.adjD, r32->g, r32->w1, r32->lam, st);

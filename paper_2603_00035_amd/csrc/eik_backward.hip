@@ -52,7 +52,7 @@ __device__ __forceinline__ TileGeoB tile_geo_b(const LaunchArgs &a, int t)
 template <typename R, int TH>
 __global__ __launch_bounds__(256) void k_adj_prep(LaunchArgs a, const R *__restrict__ M, const R *__restrict__ om,
                                                   const R *__restrict__ Tall, const uint8_t *__restrict__ parall,
-                                                  R *__restrict__ w1all, R *__restrict__ lamall)
+                                                  R *__restrict__ w1all, R *__restrict__ lamall, Prep32 p32)
 {
     const TileGeoB g = tile_geo_b<TH>(a, blockIdx.x);
     const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
@@ -80,7 +80,27 @@ __global__ __launch_bounds__(256) void k_adj_prep(LaunchArgs a, const R *__restr
         }
         w1all[g.gd.off + c] = w;
         lamall[g.gd.off + c] = R(0);
+        if (p32.w1) { // the FP32 relaxation's inputs, rounded as a cast would
+            p32.w1[g.gd.off + c] = (float)w;
+            p32.g[g.gd.off + c] = (float)((const R *)p32.g_src)[g.gd.off + c];
+            p32.lam[g.gd.off + c] = 0.0f;
+        }
     }
+}
+
+// The round state of a relaxation: every tile flagged for round 0, the other
+// buffer and every later round's count cleared (one writer per element).
+__global__ void k_round_reset(int32_t *__restrict__ act, int n_tiles, int32_t *__restrict__ act_count)
+{
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < 2 * (int64_t)n_tiles; i += stride) act[i] = i < n_tiles ? 1 : 0;
+    for (int64_t i = tid; i < kMaxRounds + 2; i += stride) act_count[i] = i == 0 ? n_tiles : 0;
+}
+
+void launch_round_reset(const LaunchArgs &a, int32_t *act, int32_t *act_count, hipStream_t st)
+{
+    const int64_t work = std::max<int64_t>(2 * (int64_t)a.n_tiles, kMaxRounds + 2);
+    hipLaunchKernelGGL(k_round_reset, dim3(blocks_for(work, 256)), dim3(256), 0, st, act, a.n_tiles, act_count);
 }
 
 // One visit of a tile by directional sweeps: lambda_i = g_i + sum over the
@@ -424,10 +444,11 @@ __global__ void k_dsrc(LaunchArgs a, const int32_t *__restrict__ src_idx, const 
 
 template <typename R>
 void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const void *T, const uint8_t *parent,
-                     void *w1, void *lam, hipStream_t st)
+                     void *w1, void *lam, hipStream_t st, const Prep32 &p32)
 {
     EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_adj_prep<R, TH>), dim3(a.n_tiles), dim3(256), 0, st, a,
-                                             (const R *)M, (const R *)om, (const R *)T, parent, (R *)w1, (R *)lam));
+                                             (const R *)M, (const R *)om, (const R *)T, parent, (R *)w1, (R *)lam,
+                                             p32));
 }
 
 template <typename R>
@@ -493,7 +514,7 @@ void launch_dsrc(const LaunchArgs &a, const int32_t *src_idx, const void *lam, v
 
 #define EIK_INST(R)                                                                                              \
     template void launch_adj_prep<R>(const LaunchArgs &, const void *, const void *, const void *,              \
-                                     const uint8_t *, void *, void *, hipStream_t);                             \
+                                     const uint8_t *, void *, void *, hipStream_t, const Prep32 &);             \
     template void launch_adj_stage<R>(const LaunchArgs &, const uint8_t *, const void *, uint16_t *, uint16_t *, \
                                       void *, hipStream_t);                                                      \
     template void launch_adj_round<R>(const LaunchArgs &, const AdjNodes &, const void *, void *, int, int,     \

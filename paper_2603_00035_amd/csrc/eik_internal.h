@@ -139,9 +139,19 @@ void launch_cast_f32_f64(int64_t n, const float *src, double *dst, hipStream_t s
 void launch_write_single_desc(const GridDesc &d, GridDesc *dst, int32_t *tile_grid, int n_tiles, hipStream_t st);
 
 // backward
+// FP32 inputs of a mixed-precision relaxation, written by the adjoint
+// preparation when w1 is non-null: the donor weights and dL/dT (from g_src, in
+// the state's type) rounded to FP32, and lambda cleared
+struct Prep32 {
+    float *w1 = nullptr;
+    const void *g_src = nullptr;
+    float *g = nullptr, *lam = nullptr;
+};
 template <typename R>
 void launch_adj_prep(const LaunchArgs &a, const void *M, const void *om, const void *T, const uint8_t *parent,
-                     void *w1, void *lam, hipStream_t st);
+                     void *w1, void *lam, hipStream_t st, const Prep32 &p32 = Prep32());
+// every tile flagged for round 0, the other round state cleared, one launch
+void launch_round_reset(const LaunchArgs &a, int32_t *act, int32_t *act_count, hipStream_t st);
 // Per-node inputs of the adjoint relaxation sweeps, per grid at its node
 // offset: receiver descriptors and dL/dT, row-major (D, g) and transposed
 // (DT, gT, [nx][ny] per grid) for the column sweeps.
