@@ -127,3 +127,42 @@ def test_mixed_forward_on_two_caller_streams():
         To, _, _ = oracle.forward(p)
         assert rel_err_cells(out[k].cpu().numpy(), To, p.src_idx) <= 1e-12
         assert rel_err_cells(ref[k].cpu().numpy(), To, p.src_idx) <= 1e-12
+
+
+def test_mixed_stats_and_errors_without_a_closing_synchronisation():
+    """The forward phases take their counters from the last round check: the
+    stats still carry each phase's cell-updates (with the cold start forced,
+    its count equals the FP32 phase's; with this size's tuning the FP32 phase
+    runs full-update rounds and has none), the timings and the rounds, and a
+    source index outside the grid is still reported."""
+    from paper_2603_00035_amd import _lib as L
+    from paper_2603_00035_amd import eikonal as E
+    p = make_problem("c2", 31, nx=200, ny=150)
+    say("[mixed] stats")
+    M, om, src = dev_inputs(p)
+    for tune32 in (None, E.tuning(fast_cold_start=2)):  # the tuned FP32 phase, then the cold start forced
+        T, par, _, (s32, s64) = E.solve_mixed(M, om, src, p.h, tol=1e-7, tol32=1e-5, levels=False,
+                                              time_kernels=True, tune32=tune32)
+        torch.cuda.synchronize()
+        _check_mixed_stats(p, T, s32, s64)
+    bad = torch.tensor([p.n + 5], dtype=torch.int32, device=M.device)
+    with pytest.raises(L.EikError) as ei:
+        E.solve_mixed(M, om, bad, p.h, tol=1e-7, tol32=1e-5, levels=False)
+    assert ei.value.code == L.EIK_EINVAL
+
+
+def _check_mixed_stats(p, T, s32, s64):
+    torch.cuda.synchronize()
+    assert s32.converged and s64.converged
+    assert s32.rounds > 0 and s64.rounds > 0
+    assert s32.cell_updates > p.n
+    # the FP32 phase is the cold start alone when the tuning runs one (its
+    # counts are then the phase's), else full-update rounds (no cold-start counts)
+    if s32.fast_launches:
+        assert s32.fast_cell_updates == s32.cell_updates and s32.fast_ms > 0.0
+    else:
+        assert s32.fast_cell_updates == 0 and s32.fast_ms == 0.0
+    assert s64.cell_updates >= p.n  # every tile visited at least once
+    assert s32.sweep_ms > 0.0 and s32.sweep_ms >= s32.fast_ms and s64.sweep_ms > 0.0
+    To, _, _ = oracle.forward(p)
+    assert rel_err_cells(T.cpu().numpy(), To, p.src_idx) <= 1e-6
