@@ -347,8 +347,9 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
                  const void *om, const void *T_init, double tol, int max_rounds, int flags, void *T,
                  uint8_t *parent, int32_t *level, void *ws, size_t ws_bytes, const eik_tuning *tun,
                  eik_stats *stats, bool single, hipStream_t st, bool certify = true, bool pre_staged = false,
-                 const std::function<int()> &after_init = nullptr, int full_first_batch = -1)
-{
+                 const std::function<int()> &after_init = nullptr, int full_first_batch = -1,
+                 const double *M64 = nullptr, const double *om64 = nullptr)
+{ // M64, om64 (FP32 solves only): M and omega are FP32 copies to be made from them by the staging
     const int dtype = sizeof(R) == 8 ? EIK_F64 : EIK_F32;
     // the sweeps keep the source marks in the parent array
     if (!T || !parent) return fail(EIK_EINVAL, "T and parent arrays are required");
@@ -372,7 +373,12 @@ int forward_impl(int n_grids, const eik_grid *grids, const int32_t *src_idx, con
         HIP_OK(hipStreamSynchronize(st));
         if (bad) return fail(EIK_EINFEASIBLE, "metric not SPD or |omega|_{M^-1} >= 1 somewhere");
     }
-    if (!pre_staged) launch_stage<R>(a, M, om, w.Pt, st); // else staged in this workspace already
+    if constexpr (sizeof(R) == 4) {
+        if (M64) launch_stage_from64(a, M64, om64, (float *)M, (float *)om, w.Pt, st); // casts and staging at once
+        else if (!pre_staged) launch_stage<R>(a, M, om, w.Pt, st);
+    } else if (!pre_staged) {
+        launch_stage<R>(a, M, om, w.Pt, st); // else staged in this workspace already
+    }
     // initial field, and the round state cleared in the same launch
     launch_init<R>(a, T_init, T, parent, level, src_idx, src_t, w.act, w.act_count, w.ctr, T_init != nullptr,
                    st, /*reset=*/true);
@@ -1120,8 +1126,13 @@ int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega
         forked = true;
         return EIK_OK;
     };
-    launch_cast_f64_f32(3 * e.nodes, M, M32, stream);
-    launch_cast_f64_f32(2 * e.nodes, omega, om32, stream);
+    // the FP32 copies of M and omega: made by the FP32 staging itself, unless
+    // the feasibility check must read them before it
+    const bool fused = !(flags & EIK_CHECK_FEASIBLE);
+    if (!fused) {
+        launch_cast_f64_f32(3 * e.nodes, M, M32, stream);
+        launch_cast_f64_f32(2 * e.nodes, omega, om32, stream);
+    }
     eik_grid g32 = *grid;
     if (grid->src_t) {
         g32.src_t = b + L.src32;
@@ -1131,7 +1142,8 @@ int eik_forward_mixed(const eik_grid *grid, const double *M, const double *omega
     // FP32 sweeps from the cold start; not reaching tol32 is no error here
     rc = forward_impl<float>(1, &g32, g32.src_idx, g32.src_t, M32, om32, nullptr, tol32, max_rounds, flags, T32,
                              parent, nullptr, b + L.ws32, ws_bytes - L.ws32, tuning32, stats, true, stream,
-                             /*certify=*/false, /*pre_staged=*/false, fork_staging);
+                             /*certify=*/false, /*pre_staged=*/false, fork_staging, -1, fused ? M : nullptr,
+                             fused ? omega : nullptr);
     if (forked) HIP_OK(hipStreamWaitEvent(stream, ev.join, 0)); // joined before any return: the side work ends in order
     if (rc < 0) return rc;
     if (!forked) return fail(EIK_EDEVICE, "the FP64 staging was not enqueued");

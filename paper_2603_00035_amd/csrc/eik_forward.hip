@@ -127,6 +127,41 @@ __device__ __forceinline__ void stage_tile(const LaunchArgs &a, int t, const R *
     }
 }
 
+// The FP32 staging straight from FP64 parameters (the mixed path's FP32
+// phase): each plane of a tile is read once in FP64, rounded to FP32, written
+// row-major (the FP32 copies the row sweeps read, as a cast would make them)
+// and transposed (the column sweeps' copy).
+template <int TH>
+__global__ __launch_bounds__(256) void k_stage_from64(LaunchArgs a, const double *__restrict__ M,
+                                                      const double *__restrict__ om, float *__restrict__ M32,
+                                                      float *__restrict__ om32, float *__restrict__ Pt)
+{
+    constexpr int kCols = Staged<float>::cols;
+    __shared__ float buf[TH][TW + 1];
+    const TileGeo g = tile_geo<TH>(a, blockIdx.x);
+    const int64_t n = (int64_t)g.gd.nx * g.gd.ny;
+    for (int p = 0; p < kCols; ++p) {
+        const double *src = p < 3 ? M + 3 * g.gd.off + p * n : om + 2 * g.gd.off + (p - 3) * n;
+        float *row = p < 3 ? M32 + 3 * g.gd.off + p * n : om32 + 2 * g.gd.off + (p - 3) * n;
+        float *dst = Pt + kCols * g.gd.off + p * n;
+        for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+            const int r = idx / TW, c = idx - r * TW;
+            if (r < g.h && c < g.w) {
+                const size_t ad = (size_t)(g.j0 + r) * g.gd.nx + g.i0 + c;
+                const float v = (float)src[ad];
+                row[ad] = v;
+                buf[r][c] = v;
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < TH * TW; idx += blockDim.x) {
+            const int c = idx / TH, r = idx - c * TH;
+            if (r < g.h && c < g.w) dst[(size_t)(g.i0 + c) * g.gd.ny + g.j0 + r] = buf[r][c];
+        }
+        __syncthreads();
+    }
+}
+
 // One workgroup per tile, or (a grid of fewer workgroups) each workgroup
 // taking tiles blockIdx.x, blockIdx.x + gridDim.x, ...: a narrow grid leaves
 // most CUs to work running beside it on another stream.
@@ -1107,6 +1142,13 @@ void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, 
     const int blocks = max_blocks > 0 ? std::min(max_blocks, a.n_tiles) : a.n_tiles;
     EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_stage<R, TH>), dim3(blocks), dim3(256), 0, st, a, (const R *)M,
                                              (const R *)om, (R *)Pt));
+}
+
+void launch_stage_from64(const LaunchArgs &a, const double *M, const double *om, float *M32, float *om32, void *Pt,
+                         hipStream_t st)
+{
+    EIK_TH_DISPATCH(a.th, hipLaunchKernelGGL((k_stage_from64<TH>), dim3(a.n_tiles), dim3(256), 0, st, a, M, om, M32,
+                                             om32, (float *)Pt));
 }
 
 template <typename R>

@@ -68,6 +68,9 @@ void launch_note_queue(const WorkQueue &q, unsigned long long *slot, hipStream_t
 // forward
 template <typename R>
 void launch_stage(const LaunchArgs &a, const void *M, const void *om, void *Pt, hipStream_t st, int max_blocks = 0);
+// FP32 staging from FP64 parameters, writing the FP32 copies M32, om32 as well
+void launch_stage_from64(const LaunchArgs &a, const double *M, const double *om, float *M32, float *om32, void *Pt,
+                         hipStream_t st);
 // reset: the initialisation also clears the round state (act, act_count,
 // the counter block) and, when warm, flags every tile for round 0
 template <typename R>
