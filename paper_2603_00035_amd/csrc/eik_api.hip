@@ -1197,15 +1197,21 @@ int eik_forward_batched_mixed(int32_t n_grids, const eik_grid *grids, const int3
     char *b = (char *)ws;
     float *M32 = (float *)(b + L.M32), *om32 = (float *)(b + L.om32), *T32 = (float *)(b + L.T32);
     float *src32 = src_t ? (float *)(b + L.src32) : nullptr;
-    launch_cast_f64_f32(3 * e.nodes, M, M32, stream);
-    launch_cast_f64_f32(2 * e.nodes, omega, om32, stream);
+    // the FP32 copies of M and omega are made by the FP32 staging itself,
+    // unless the feasibility check must read them before it
+    const bool fused = !(flags & EIK_CHECK_FEASIBLE);
+    if (!fused) {
+        launch_cast_f64_f32(3 * e.nodes, M, M32, stream);
+        launch_cast_f64_f32(2 * e.nodes, omega, om32, stream);
+    }
     if (src_t) launch_cast_f64_f32(e.n_src, src_t, src32, stream);
     HIP_OK(hipGetLastError());
     // FP32 sweeps from the cold start (not reaching tol32 is no error here),
     // then FP64 sweeps from that field in place in T
     rc = forward_impl<float>(n_grids, grids, src_idx, src32, M32, om32, nullptr, tol32, max_rounds, flags, T32,
                              parent, nullptr, b + L.base, ws_bytes - L.base, tuning32, stats, false, stream,
-                             /*certify=*/false);
+                             /*certify=*/false, /*pre_staged=*/false, nullptr, -1, fused ? M : nullptr,
+                             fused ? omega : nullptr);
     if (rc < 0) return rc;
     launch_cast_f32_f64(e.nodes, T32, T, stream);
     HIP_OK(hipGetLastError());
