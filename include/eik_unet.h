@@ -9,8 +9,10 @@
  *
  * Tensors are NHWC with the batch folded into the pixel index: pixel
  * p = (b H + y) W + x, element (p, c) at p * cs + co + c, where cs is the
- * buffer's channel stride and co a channel offset (so a concatenation is two
- * producers writing disjoint channel ranges of one buffer). Activations and
+ * buffer's channel stride and co a channel offset. A concatenation of two
+ * producers' outputs is either two disjoint channel ranges of one buffer, or
+ * two buffers read by the _cat forms below (each producer then writes whole
+ * pixels, which interleaved channel ranges of one buffer do not). Activations and
  * weights are bfloat16 (raw uint16 bits); accumulation is FP32; weight and bias
  * gradients are FP32 and are accumulated (callers zero them first).
  * All pointers are device memory owned by the caller; calls enqueue on the
@@ -52,6 +54,23 @@ int eiku_conv_fwd(int32_t mode, int32_t B, int32_t H, int32_t W, const uint16_t 
 int eiku_conv_wgrad(int32_t mode, int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t x_cs, int32_t x_co,
                     int32_t Cin, const uint16_t *dy, int32_t dy_cs, int32_t dy_co, int32_t Cout, float *dw,
                     hipStream_t stream);
+
+/* EIKU_CONV3 of the concatenation [xa | xb]: input channels 0 .. Ca-1 are
+ * xa's (channel xa_co + c of a pixel), Ca .. Ca+Cb-1 are xb's (channel
+ * xb_co + c - Ca); w is [9][Cout][Ca+Cb] as for eiku_conv_fwd, and the result
+ * is that of eiku_conv_fwd on one buffer holding the concatenation. Ca and Cb
+ * are multiples of 16; both sources follow x's stride, offset and alignment
+ * rules. */
+int eiku_conv_fwd_cat(int32_t B, int32_t H, int32_t W, const uint16_t *xa, int32_t xa_cs, int32_t xa_co, int32_t Ca,
+                      const uint16_t *xb, int32_t xb_cs, int32_t xb_co, int32_t Cb, const uint16_t *w,
+                      const float *bias, int32_t relu, uint16_t *y, int32_t y_cs, int32_t y_co, int32_t Cout,
+                      hipStream_t stream);
+
+/* The EIKU_CONV3 weight gradient with x the concatenation [xa | xb], as in
+ * eiku_conv_fwd_cat; dw is [9][Cout][Ca+Cb], FP32, accumulated. */
+int eiku_conv_wgrad_cat(int32_t B, int32_t H, int32_t W, const uint16_t *xa, int32_t xa_cs, int32_t xa_co,
+                        int32_t Ca, const uint16_t *xb, int32_t xb_cs, int32_t xb_co, int32_t Cb, const uint16_t *dy,
+                        int32_t dy_cs, int32_t dy_co, int32_t Cout, float *dw, hipStream_t stream);
 
 /* db[c] += sum_p dy(p, c) over npix pixels. */
 int eiku_bias_grad(int64_t npix, const uint16_t *dy, int32_t cs, int32_t co, int32_t C, float *db,

@@ -37,6 +37,9 @@ __device__ __forceinline__ bf16 f2bf(float f)
     return (bf16)(u >> 16);
 }
 
+// Input channels c < csplit come from x (channel x_co + c), the rest from x2
+// (channel x2_co + c - csplit): a concatenation read from its two producers'
+// own buffers (the kernels' CAT forms; one source: x2 = x and csplit = Cin).
 struct ConvArgs {
     const bf16 *x;
     const bf16 *w;
@@ -44,7 +47,17 @@ struct ConvArgs {
     bf16 *y;
     int x_cs, x_co, y_cs, y_co;
     int B, H, W, Cin, Cout, relu;
+    const bf16 *x2;
+    int x2_cs, x2_co, csplit;
 };
+
+// Address of the 8 channels c .. c+7 of pixel pix of a two-source input
+// (csplit is a multiple of 16, so the 8 channels come from one source).
+__device__ __forceinline__ const bf16 *src8(const bf16 *x, int x_cs, int x_co, const bf16 *x2, int x2_cs, int x2_co,
+                                            int csplit, int64_t pix, int c)
+{
+    return c < csplit ? x + pix * x_cs + x_co + c : x2 + pix * x2_cs + x2_co + (c - csplit);
+}
 
 // ---------------------------------------------------------------------------
 // LDS-staged convolution (EIKU_CONV3, EIKU_UP2).
@@ -101,8 +114,10 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi) { return (uint32_t
 // The staging of one step: the patch's slice of KC input channels (skipped
 // when the slice is already resident) and the weights of the step's taps for
 // the workgroup's output channels, loaded into registers first so that every
-// load of the step is in flight at once, then written to LDS.
-template <int MODE, int KC, int NT> struct Staging {
+// load of the step is in flight at once, then written to LDS. CAT: the input
+// is a two-source concatenation split at a multiple of KC, so each slice
+// comes from one source, chosen once per slice.
+template <int MODE, int KC, int NT, bool CAT> struct Staging {
     using G = LdsConv<MODE, KC, NT>;
     static constexpr int NP = (G::NPATCH * G::U16 + 255) / 256;
     static constexpr int NW = (G::TAPS * G::COT * G::U16 + 255) / 256;
@@ -112,6 +127,9 @@ template <int MODE, int KC, int NT> struct Staging {
                                          bool patch)
     {
         if (patch) {
+            const bool hi = CAT && c0 >= a.csplit; // uniform over the workgroup
+            const bf16 *xs = hi ? a.x2 : a.x;
+            const int xcs = hi ? a.x2_cs : a.x_cs, xco = hi ? a.x2_co + (c0 - a.csplit) : a.x_co + c0;
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
                 const int u = t + 256 * i;
@@ -122,8 +140,8 @@ template <int MODE, int KC, int NT> struct Staging {
                     const int gy = G::SCALE * y0 + py - G::HALO, gx = G::SCALE * x0 + px - G::HALO;
                     const int hin = G::SCALE * a.H, win = G::SCALE * a.W;
                     if (gy >= 0 && gy < hin && gx >= 0 && gx < win)
-                        p[i] = *reinterpret_cast<const uint4 *>(a.x + (((int64_t)b * hin + gy) * win + gx) * a.x_cs +
-                                                                a.x_co + c0 + 8 * q);
+                        p[i] = *reinterpret_cast<const uint4 *>(xs + (((int64_t)b * hin + gy) * win + gx) * xcs + xco +
+                                                                8 * q);
                 }
             }
         }
@@ -166,7 +184,7 @@ template <int MODE, int KC, int NT> struct Staging {
 // slices of KC input channels; for EIKU_UP2 over (tap, slice) pairs, each tap's
 // outputs (one of the four interleaved sub-grids) stored after its last slice,
 // so the four sub-grids of a tile are written by one workgroup close in time.
-template <int MODE, int KC, int NT>
+template <int MODE, int KC, int NT, bool CAT>
 __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
 {
     using G = LdsConv<MODE, KC, NT>;
@@ -188,7 +206,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
     for (int f = 0; f < 4; ++f)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[f][nt] = f4{0.f, 0.f, 0.f, 0.f};
-    Staging<MODE, KC, NT> stg;
+    Staging<MODE, KC, NT, CAT> stg;
     stg.load(a, t, b, x0, y0, co0, 0, 0, true);
     for (int s = 0; s < nsteps; ++s) {
         const int ci = s % nch, utap = s / nch;
@@ -243,6 +261,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a)
     }
 }
 
+// x2 and csplit as in ConvArgs (read by the 3x3 weight gradient only).
 struct WgradArgs {
     const bf16 *x;
     const bf16 *dy;
@@ -250,6 +269,8 @@ struct WgradArgs {
     int x_cs, x_co, dy_cs, dy_co;
     int B, H, W, Cin, Cout;
     int64_t chunk;
+    const bf16 *x2;
+    int x2_cs, x2_co, csplit;
 };
 
 // Weight gradient of the transposed convolution, dW[tap][co][ci] = sum over
@@ -305,7 +326,7 @@ constexpr int kWdPitch = 264; // dy row per channel: 256 pixels + 8 (an odd numb
 constexpr int kWxCols = 40;   // x patch row: 34 columns + 6
 constexpr int kWxPlane = 408; // x patch per channel: 10 rows x 40 + 8 (an odd number of 16-byte bank groups)
 
-template <int CT, int IT>
+template <int CT, int IT, bool CAT>
 __global__ __launch_bounds__(256) void k_wgrad3_lds(WgradArgs a, int tiles_per_wg)
 {
     __shared__ __attribute__((aligned(16))) uint16_t s_dy[CT * 16 * kWdPitch];
@@ -358,9 +379,21 @@ __global__ __launch_bounds__(256) void k_wgrad3_lds(WgradArgs a, int tiles_per_w
             const int gy = y0 + py - 1, gx = x0 + pc - 1;
             uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
             if (gy >= 0 && gy < a.H) {
-                const bf16 *row = a.x + ((int64_t)b * a.H + gy) * a.W * a.x_cs + a.x_co + ci0 + 8 * q;
-                if (gx >= 0 && gx < a.W) v0 = *reinterpret_cast<const uint4 *>(row + (int64_t)gx * a.x_cs);
-                if (gx + 1 >= 0 && gx + 1 < a.W) v1 = *reinterpret_cast<const uint4 *>(row + (int64_t)(gx + 1) * a.x_cs);
+                if (CAT) { // a channel block may straddle the split: the source per 8 channels
+                    const int64_t pix = ((int64_t)b * a.H + gy) * a.W + gx;
+                    const int c = ci0 + 8 * q;
+                    if (gx >= 0 && gx < a.W)
+                        v0 = *reinterpret_cast<const uint4 *>(src8(a.x, a.x_cs, a.x_co, a.x2, a.x2_cs, a.x2_co,
+                                                                   a.csplit, pix, c));
+                    if (gx + 1 >= 0 && gx + 1 < a.W)
+                        v1 = *reinterpret_cast<const uint4 *>(src8(a.x, a.x_cs, a.x_co, a.x2, a.x2_cs, a.x2_co,
+                                                                   a.csplit, pix + 1, c));
+                } else {
+                    const bf16 *row = a.x + ((int64_t)b * a.H + gy) * a.W * a.x_cs + a.x_co + ci0 + 8 * q;
+                    if (gx >= 0 && gx < a.W) v0 = *reinterpret_cast<const uint4 *>(row + (int64_t)gx * a.x_cs);
+                    if (gx + 1 >= 0 && gx + 1 < a.W)
+                        v1 = *reinterpret_cast<const uint4 *>(row + (int64_t)(gx + 1) * a.x_cs);
+                }
             }
             const uint32_t e0[4] = {v0.x, v0.y, v0.z, v0.w}, e1[4] = {v1.x, v1.y, v1.z, v1.w};
             uint32_t *dst = reinterpret_cast<uint32_t *>(s_x + (8 * q) * kWxPlane + py * kWxCols + pc);
@@ -707,6 +740,72 @@ static inline int gblocks(int64_t n, int bs) { return (int)std::min<int64_t>((n 
 
 using namespace eiku;
 
+namespace {
+
+// Launch k_conv_lds for arguments already checked. cat: a two-source 3x3
+// convolution, its slices of KC channels kept on one side of the split.
+int conv_launch(int mode, const ConvArgs &a, hipStream_t st, bool cat = false)
+{
+    const int nt = a.Cout % 64 == 0 ? 4 : (a.Cout % 32 == 0 ? 2 : 1);
+    const int64_t tiles = (int64_t)a.B * ((a.H + kTileY - 1) / kTileY) * ((a.W + kTileX - 1) / kTileX);
+    if (tiles > 0x7fffffff) return -1;
+    const dim3 g((unsigned)tiles, (unsigned)(a.Cout / (16 * nt)));
+    const bool k32 = a.Cin % 32 == 0 && a.csplit % 32 == 0;
+#define EIKU_LDS(MODE, KC, CAT)                                                                               \
+    do {                                                                                                      \
+        if (nt == 4) hipLaunchKernelGGL((k_conv_lds<MODE, KC, 4, CAT>), g, dim3(256), 0, st, a);              \
+        else if (nt == 2) hipLaunchKernelGGL((k_conv_lds<MODE, KC, 2, CAT>), g, dim3(256), 0, st, a);         \
+        else hipLaunchKernelGGL((k_conv_lds<MODE, KC, 1, CAT>), g, dim3(256), 0, st, a);                      \
+    } while (0)
+    if (mode == EIKU_CONV3 && cat) {
+        if (k32) EIKU_LDS(EIKU_CONV3, 32, true);
+        else EIKU_LDS(EIKU_CONV3, 16, true);
+    } else if (mode == EIKU_CONV3) {
+        if (k32) EIKU_LDS(EIKU_CONV3, 32, false);
+        else EIKU_LDS(EIKU_CONV3, 16, false);
+    } else if (mode == EIKU_UP2) {
+        if (k32) EIKU_LDS(EIKU_UP2, 32, false);
+        else EIKU_LDS(EIKU_UP2, 16, false);
+    } else {
+        EIKU_LDS(EIKU_DOWN2, 16, false); // 16-channel slices keep the 2x patch at 48 KiB of LDS
+    }
+#undef EIKU_LDS
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Launch k_wgrad3_lds for arguments already checked.
+template <bool CAT>
+int wgrad3_launch(const WgradArgs &a, hipStream_t st)
+{
+    const int ct = a.Cout % 32 == 0 ? 2 : 1, it = a.Cin % 32 == 0 ? 2 : 1;
+    const int blocks = (a.Cout / (16 * ct)) * (a.Cin / (16 * it));
+    const int64_t ntiles = (int64_t)a.B * ((a.H + kTileY - 1) / kTileY) * ((a.W + kTileX - 1) / kTileX);
+    // about 2048 workgroups over the channel blocks and pixel runs
+    int64_t per = (ntiles * blocks + 2047) / 2048;
+    per = per < 1 ? 1 : per;
+    const int64_t runs = (ntiles + per - 1) / per;
+    if (runs > 0x7fffffff) return -1;
+    const dim3 g((unsigned)runs, (unsigned)blocks);
+    if (ct == 2 && it == 2) hipLaunchKernelGGL((k_wgrad3_lds<2, 2, CAT>), g, dim3(256), 0, st, a, (int)per);
+    else if (ct == 2) hipLaunchKernelGGL((k_wgrad3_lds<2, 1, CAT>), g, dim3(256), 0, st, a, (int)per);
+    else if (it == 2) hipLaunchKernelGGL((k_wgrad3_lds<1, 2, CAT>), g, dim3(256), 0, st, a, (int)per);
+    else hipLaunchKernelGGL((k_wgrad3_lds<1, 1, CAT>), g, dim3(256), 0, st, a, (int)per);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// The two sources of a concatenated input: channel strides and offsets in
+// multiples of 8, each slice inside its pixel, 16-byte aligned buffers, and
+// Ca, Cb multiples of 16.
+bool cat_ok(const uint16_t *xa, int xa_cs, int xa_co, int Ca, const uint16_t *xb, int xb_cs, int xb_co, int Cb)
+{
+    if (!xa || !xb || Ca < 16 || Cb < 16 || (Ca | Cb) % 16) return false;
+    if ((xa_cs | xa_co | xb_cs | xb_co) % 8 || xa_co < 0 || xb_co < 0 || xa_co + Ca > xa_cs || xb_co + Cb > xb_cs)
+        return false;
+    return ((uintptr_t)xa | (uintptr_t)xb) % 16 == 0;
+}
+
+} // namespace
+
 extern "C" {
 
 int eiku_conv_fwd(int32_t mode, int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t x_cs, int32_t x_co,
@@ -717,29 +816,20 @@ int eiku_conv_fwd(int32_t mode, int32_t B, int32_t H, int32_t W, const uint16_t 
     if ((x_cs | x_co) % 8 || (y_cs | y_co) % 4 || x_co + Cin > x_cs || y_co + Cout > y_cs) return -1;
     if (((uintptr_t)x | (uintptr_t)w) % 16 || (uintptr_t)y % 8) return -1;
     if (mode != EIKU_CONV3 && mode != EIKU_UP2 && mode != EIKU_DOWN2) return -1;
-    ConvArgs a{x, w, bias, y, x_cs, x_co, y_cs, y_co, B, H, W, Cin, Cout, relu};
-    const int nt = Cout % 64 == 0 ? 4 : (Cout % 32 == 0 ? 2 : 1);
-    const int64_t tiles = (int64_t)B * ((H + kTileY - 1) / kTileY) * ((W + kTileX - 1) / kTileX);
-    if (tiles > 0x7fffffff) return -1;
-    const dim3 g((unsigned)tiles, (unsigned)(Cout / (16 * nt)));
-    const bool k32 = Cin % 32 == 0;
-#define EIKU_LDS(MODE, KC)                                                                                    \
-    do {                                                                                                      \
-        if (nt == 4) hipLaunchKernelGGL((k_conv_lds<MODE, KC, 4>), g, dim3(256), 0, st, a);                   \
-        else if (nt == 2) hipLaunchKernelGGL((k_conv_lds<MODE, KC, 2>), g, dim3(256), 0, st, a);              \
-        else hipLaunchKernelGGL((k_conv_lds<MODE, KC, 1>), g, dim3(256), 0, st, a);                           \
-    } while (0)
-    if (mode == EIKU_CONV3) {
-        if (k32) EIKU_LDS(EIKU_CONV3, 32);
-        else EIKU_LDS(EIKU_CONV3, 16);
-    } else if (mode == EIKU_UP2) {
-        if (k32) EIKU_LDS(EIKU_UP2, 32);
-        else EIKU_LDS(EIKU_UP2, 16);
-    } else {
-        EIKU_LDS(EIKU_DOWN2, 16); // 16-channel slices keep the 2x patch at 48 KiB of LDS
-    }
-#undef EIKU_LDS
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    const ConvArgs a{x, w, bias, y, x_cs, x_co, y_cs, y_co, B, H, W, Cin, Cout, relu, x, x_cs, x_co, Cin};
+    return conv_launch(mode, a, st);
+}
+
+int eiku_conv_fwd_cat(int32_t B, int32_t H, int32_t W, const uint16_t *xa, int32_t xa_cs, int32_t xa_co, int32_t Ca,
+                      const uint16_t *xb, int32_t xb_cs, int32_t xb_co, int32_t Cb, const uint16_t *w,
+                      const float *bias, int32_t relu, uint16_t *y, int32_t y_cs, int32_t y_co, int32_t Cout,
+                      hipStream_t st)
+{
+    if (B < 1 || H < 1 || W < 1 || Cout < 16 || Cout % 16 || !w || !y) return -1;
+    if (!cat_ok(xa, xa_cs, xa_co, Ca, xb, xb_cs, xb_co, Cb)) return -1;
+    if ((y_cs | y_co) % 4 || y_co < 0 || y_co + Cout > y_cs || (uintptr_t)w % 16 || (uintptr_t)y % 8) return -1;
+    const ConvArgs a{xa, w, bias, y, xa_cs, xa_co, y_cs, y_co, B, H, W, Ca + Cb, Cout, relu, xb, xb_cs, xb_co, Ca};
+    return conv_launch(EIKU_CONV3, a, st, true);
 }
 
 int eiku_conv_wgrad(int32_t mode, int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t x_cs, int32_t x_co,
@@ -752,29 +842,27 @@ int eiku_conv_wgrad(int32_t mode, int32_t B, int32_t H, int32_t W, const uint16_
     const int64_t npix = (int64_t)B * H * W;
     if (mode == EIKU_CONV3) {
         if ((x_cs | x_co | dy_cs | dy_co) % 8 || ((uintptr_t)x | (uintptr_t)dy) % 16) return -1;
-        WgradArgs a{x, dy, dw, x_cs, x_co, dy_cs, dy_co, B, H, W, Cin, Cout, 0};
-        const int ct = Cout % 32 == 0 ? 2 : 1, it = Cin % 32 == 0 ? 2 : 1;
-        const int blocks = (Cout / (16 * ct)) * (Cin / (16 * it));
-        const int64_t ntiles = (int64_t)B * ((H + kTileY - 1) / kTileY) * ((W + kTileX - 1) / kTileX);
-        // about 2048 workgroups over the channel blocks and pixel runs
-        int64_t per = (ntiles * blocks + 2047) / 2048;
-        per = per < 1 ? 1 : per;
-        const int64_t runs = (ntiles + per - 1) / per;
-        if (runs > 0x7fffffff) return -1;
-        const dim3 g((unsigned)runs, (unsigned)blocks);
-        if (ct == 2 && it == 2) hipLaunchKernelGGL((k_wgrad3_lds<2, 2>), g, dim3(256), 0, st, a, (int)per);
-        else if (ct == 2) hipLaunchKernelGGL((k_wgrad3_lds<2, 1>), g, dim3(256), 0, st, a, (int)per);
-        else if (it == 2) hipLaunchKernelGGL((k_wgrad3_lds<1, 2>), g, dim3(256), 0, st, a, (int)per);
-        else hipLaunchKernelGGL((k_wgrad3_lds<1, 1>), g, dim3(256), 0, st, a, (int)per);
-        return hipGetLastError() == hipSuccess ? 0 : -1;
+        const WgradArgs a{x, dy, dw, x_cs, x_co, dy_cs, dy_co, B, H, W, Cin, Cout, 0, x, x_cs, x_co, Cin};
+        return wgrad3_launch<false>(a, st);
     }
     int64_t chunk = npix / 128;
     chunk = chunk < 256 ? 256 : (chunk > 8192 ? 8192 : chunk);
     chunk = (chunk + 15) / 16 * 16;
-    WgradArgs a{x, dy, dw, x_cs, x_co, dy_cs, dy_co, B, H, W, Cin, Cout, chunk};
+    WgradArgs a{x, dy, dw, x_cs, x_co, dy_cs, dy_co, B, H, W, Cin, Cout, chunk, x, x_cs, x_co, Cin};
     dim3 grid((unsigned)((npix + chunk - 1) / chunk), (unsigned)(4 * (Cout / 16) * (Cin / 16)));
     hipLaunchKernelGGL(k_wgrad_up2, grid, dim3(64), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int eiku_conv_wgrad_cat(int32_t B, int32_t H, int32_t W, const uint16_t *xa, int32_t xa_cs, int32_t xa_co,
+                        int32_t Ca, const uint16_t *xb, int32_t xb_cs, int32_t xb_co, int32_t Cb, const uint16_t *dy,
+                        int32_t dy_cs, int32_t dy_co, int32_t Cout, float *dw, hipStream_t st)
+{
+    if (B < 1 || H < 1 || W < 1 || Cout < 16 || Cout % 16 || !dy || !dw) return -1;
+    if (!cat_ok(xa, xa_cs, xa_co, Ca, xb, xb_cs, xb_co, Cb)) return -1;
+    if ((dy_cs | dy_co) % 8 || dy_co < 0 || dy_co + Cout > dy_cs || (uintptr_t)dy % 16) return -1;
+    const WgradArgs a{xa, dy, dw, xa_cs, xa_co, dy_cs, dy_co, B, H, W, Ca + Cb, Cout, 0, xb, xb_cs, xb_co, Ca};
+    return wgrad3_launch<true>(a, st);
 }
 
 int eiku_bias_grad(int64_t npix, const uint16_t *dy, int32_t cs, int32_t co, int32_t C, float *db, hipStream_t st)

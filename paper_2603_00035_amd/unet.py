@@ -39,6 +39,8 @@ def _bind():
     sig = {
         "eiku_conv_fwd": [i32, i32, i32, i32, vp, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, vp],
         "eiku_conv_wgrad": [i32, i32, i32, i32, vp, i32, i32, i32, vp, i32, i32, i32, vp, vp],
+        "eiku_conv_fwd_cat": [i32, i32, i32, vp, i32, i32, i32, vp, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, vp],
+        "eiku_conv_wgrad_cat": [i32, i32, i32, vp, i32, i32, i32, vp, i32, i32, i32, vp, i32, i32, i32, vp, vp],
         "eiku_bias_grad": [i64, vp, i32, i32, i32, vp, vp],
         "eiku_relu_mask": [i64, vp, i32, i32, vp, i32, i32, i32, vp],
         "eiku_add": [i64, vp, i32, i32, vp, i32, i32, i32, vp],
@@ -79,6 +81,27 @@ class Act:
     @property
     def npix(self):
         return self.B * self.H * self.W
+
+
+class Cat:
+    """The concatenation [a | b] of two views on the same grid, read from the
+    two producers' own buffers (each producer writes whole pixels)."""
+
+    def __init__(self, a, b):
+        assert (a.B, a.H, a.W) == (b.B, b.H, b.W)
+        self.a, self.b = a, b
+        self.B, self.H, self.W, self.C = a.B, a.H, a.W, a.C + b.C
+
+    @property
+    def npix(self):
+        return self.B * self.H * self.W
+
+
+# skip and upsampled halves of each level's concatenation; their gradients
+# share one buffer per level (the data gradient of the next convolution
+# writes both halves of every pixel at once)
+SPLIT = {"s0": ("g_cat0", 0), "up0": ("g_cat0", 1), "s1": ("g_cat1", 0), "up1": ("g_cat1", 1), "s2": ("g_cat2", 0),
+         "up2": ("g_cat2", 1)}
 
 
 class UNet:
@@ -139,13 +162,16 @@ class UNet:
         H1, W1, H2, W2, H3, W3 = H // 2, W // 2, H // 4, W // 4, H // 8, W // 8
         b = {"shape": (B, H, W)}
         b["x0"] = buf(H, W, 16)
-        for k, (h, w, c) in {"e0a": (H, W, 16), "cat0": (H, W, 32), "d0a": (H, W, 16), "d0b": (H, W, 16),
-                             "p0": (H1, W1, 16), "e1a": (H1, W1, 32), "cat1": (H1, W1, 64), "d1a": (H1, W1, 32),
-                             "d1b": (H1, W1, 32), "p1": (H2, W2, 32), "e2a": (H2, W2, 64), "cat2": (H2, W2, 128),
-                             "d2a": (H2, W2, 64), "d2b": (H2, W2, 64), "p2": (H3, W3, 64), "ba": (H3, W3, 128),
-                             "bb": (H3, W3, 128)}.items():
+        for k, (h, w, c) in {"e0a": (H, W, 16), "s0": (H, W, 16), "up0": (H, W, 16), "d0a": (H, W, 16),
+                             "d0b": (H, W, 16), "p0": (H1, W1, 16), "e1a": (H1, W1, 32), "s1": (H1, W1, 32),
+                             "up1": (H1, W1, 32), "d1a": (H1, W1, 32), "d1b": (H1, W1, 32), "p1": (H2, W2, 32),
+                             "e2a": (H2, W2, 64), "s2": (H2, W2, 64), "up2": (H2, W2, 64), "d2a": (H2, W2, 64),
+                             "d2b": (H2, W2, 64), "p2": (H3, W3, 64), "ba": (H3, W3, 128), "bb": (H3, W3, 128)}.items():
             b[k] = buf(h, w, c)
-            b["g_" + k] = buf(h, w, c)
+            if k not in SPLIT:
+                b["g_" + k] = buf(h, w, c)
+        for lv, (h, w, c) in enumerate([(H, W, 16), (H1, W1, 32), (H2, W2, 64)]):
+            b[f"g_cat{lv}"] = buf(h, w, 2 * c)
         b["g_pool"] = buf(H, W, 16)  # scratch for max-pool gradients (largest level)
         b["pred"] = torch.zeros(B * H * W, dtype=torch.float32, device=d)
         b["g_pred"] = torch.zeros(B * H * W, dtype=torch.float32, device=d)
@@ -162,21 +188,21 @@ class UNet:
 
         return {
             "e0a": (A("x0", H, W, 16, 0, 16), A("e0a", H, W, 16, 0, 16)),
-            "e0b": (A("e0a", H, W, 16, 0, 16), A("cat0", H, W, 32, 0, 16)),
+            "e0b": (A("e0a", H, W, 16, 0, 16), A("s0", H, W, 16, 0, 16)),
             "e1a": (A("p0", H1, W1, 16, 0, 16), A("e1a", H1, W1, 32, 0, 32)),
-            "e1b": (A("e1a", H1, W1, 32, 0, 32), A("cat1", H1, W1, 64, 0, 32)),
+            "e1b": (A("e1a", H1, W1, 32, 0, 32), A("s1", H1, W1, 32, 0, 32)),
             "e2a": (A("p1", H2, W2, 32, 0, 32), A("e2a", H2, W2, 64, 0, 64)),
-            "e2b": (A("e2a", H2, W2, 64, 0, 64), A("cat2", H2, W2, 128, 0, 64)),
+            "e2b": (A("e2a", H2, W2, 64, 0, 64), A("s2", H2, W2, 64, 0, 64)),
             "ba": (A("p2", H3, W3, 64, 0, 64), A("ba", H3, W3, 128, 0, 128)),
             "bb": (A("ba", H3, W3, 128, 0, 128), A("bb", H3, W3, 128, 0, 128)),
-            "u2": (A("bb", H3, W3, 128, 0, 128), A("cat2", H2, W2, 128, 64, 64)),
-            "d2a": (A("cat2", H2, W2, 128, 0, 128), A("d2a", H2, W2, 64, 0, 64)),
+            "u2": (A("bb", H3, W3, 128, 0, 128), A("up2", H2, W2, 64, 0, 64)),
+            "d2a": (Cat(A("s2", H2, W2, 64, 0, 64), A("up2", H2, W2, 64, 0, 64)), A("d2a", H2, W2, 64, 0, 64)),
             "d2b": (A("d2a", H2, W2, 64, 0, 64), A("d2b", H2, W2, 64, 0, 64)),
-            "u1": (A("d2b", H2, W2, 64, 0, 64), A("cat1", H1, W1, 64, 32, 32)),
-            "d1a": (A("cat1", H1, W1, 64, 0, 64), A("d1a", H1, W1, 32, 0, 32)),
+            "u1": (A("d2b", H2, W2, 64, 0, 64), A("up1", H1, W1, 32, 0, 32)),
+            "d1a": (Cat(A("s1", H1, W1, 32, 0, 32), A("up1", H1, W1, 32, 0, 32)), A("d1a", H1, W1, 32, 0, 32)),
             "d1b": (A("d1a", H1, W1, 32, 0, 32), A("d1b", H1, W1, 32, 0, 32)),
-            "u0": (A("d1b", H1, W1, 32, 0, 32), A("cat0", H, W, 32, 16, 16)),
-            "d0a": (A("cat0", H, W, 32, 0, 32), A("d0a", H, W, 16, 0, 16)),
+            "u0": (A("d1b", H1, W1, 32, 0, 32), A("up0", H, W, 16, 0, 16)),
+            "d0a": (Cat(A("s0", H, W, 16, 0, 16), A("up0", H, W, 16, 0, 16)), A("d0a", H, W, 16, 0, 16)),
             "d0b": (A("d0a", H, W, 16, 0, 16), A("d0b", H, W, 16, 0, 16)),
         }
 
@@ -194,6 +220,13 @@ class UNet:
     def _conv(self, name, mode, x, y, relu):
         st = L.stream_handle(self.dev)
         B, H, W = (x.B, x.H, x.W)
+        if isinstance(x, Cat):
+            assert mode == CONV3
+            xa, xb = x.a, x.b
+            _ok(name, self.lib.eiku_conv_fwd_cat(B, H, W, _p(xa.buf), xa.cs, xa.co, xa.C, _p(xb.buf), xb.cs, xb.co,
+                                                 xb.C, _p(self.wf[name]), _p(self.params[name + ".b"]), int(relu),
+                                                 _p(y.buf), y.cs, y.co, y.C, st))
+            return
         _ok(name, self.lib.eiku_conv_fwd(mode, B, H, W, _p(x.buf), x.cs, x.co, x.C, _p(self.wf[name]),
                                          _p(self.params[name + ".b"]), int(relu), _p(y.buf), y.cs, y.co, y.C, st))
 
@@ -207,11 +240,11 @@ class UNet:
             x, y = wire[name]
             self._conv(name, mode, x, y, relu)
             if name == "e0b":
-                _ok("pool0", self.lib.eiku_maxpool_fwd(B, H1, W1, _p(b["cat0"]), 32, 0, _p(b["p0"]), 16, 0, 16, st))
+                _ok("pool0", self.lib.eiku_maxpool_fwd(B, H1, W1, _p(b["s0"]), 16, 0, _p(b["p0"]), 16, 0, 16, st))
             elif name == "e1b":
-                _ok("pool1", self.lib.eiku_maxpool_fwd(B, H2, W2, _p(b["cat1"]), 64, 0, _p(b["p1"]), 32, 0, 32, st))
+                _ok("pool1", self.lib.eiku_maxpool_fwd(B, H2, W2, _p(b["s1"]), 32, 0, _p(b["p1"]), 32, 0, 32, st))
             elif name == "e2b":
-                _ok("pool2", self.lib.eiku_maxpool_fwd(B, H3, W3, _p(b["cat2"]), 128, 0, _p(b["p2"]), 64, 0, 64, st))
+                _ok("pool2", self.lib.eiku_maxpool_fwd(B, H3, W3, _p(b["s2"]), 64, 0, _p(b["p2"]), 64, 0, 64, st))
         _ok("head", self.lib.eiku_head_fwd(B * H * W, _p(b["d0b"]), 16, 0, 16, _p(self.params["head.w"]),
                                            _p(self.params["head.b"]), _p(b["pred"]), st))
         return b["pred"]
@@ -228,23 +261,31 @@ class UNet:
         _ok("head_bwd", lib.eiku_head_bwd(n0, _p(b["d0b"]), 16, 0, 16, _p(self.params["head.w"]), _p(b["g_pred"]),
                                           _p(b["g_d0b"]), 16, 0, _p(self.grads["head.w"]), _p(self.grads["head.b"]),
                                           st))
-        gbuf = {"e0a": "g_e0a", "cat0": "g_cat0", "d0a": "g_d0a", "d0b": "g_d0b", "e1a": "g_e1a", "cat1": "g_cat1",
-                "d1a": "g_d1a", "d1b": "g_d1b", "e2a": "g_e2a", "cat2": "g_cat2", "d2a": "g_d2a", "d2b": "g_d2b",
-                "ba": "g_ba", "bb": "g_bb", "p0": "g_p0", "p1": "g_p1", "p2": "g_p2", "x0": "g_x0"}
+        def key_of(a):
+            return [k for k, v in b.items() if v is a.buf][0]
 
         def gof(a):  # gradient view matching an activation view
-            key = [k for k, v in b.items() if v is a.buf][0]
-            return Act(b[gbuf[key]], a.B, a.H, a.W, a.cs, a.co, a.C)
+            if isinstance(a, Cat):  # both halves: the level's whole gradient buffer
+                return Act(b[SPLIT[key_of(a.a)][0]], a.B, a.H, a.W, a.C, 0, a.C)
+            key = key_of(a)
+            if key in SPLIT:
+                g, half = SPLIT[key]
+                return Act(b[g], a.B, a.H, a.W, 2 * a.C, half * a.C, a.C)
+            return Act(b["g_" + key], a.B, a.H, a.W, a.cs, a.co, a.C)
 
-        pools = {"e1a": ("cat0", 32, 0, 16, "p0", 16, H1, W1),
-                 "e2a": ("cat1", 64, 0, 32, "p1", 32, H2, W2),
-                 "ba": ("cat2", 128, 0, 64, "p2", 64, H3, W3)}
+        # layer whose input came from max pooling of a skip tensor: (skip, pooled, channels, pooled grid)
+        pools = {"e1a": ("s0", "p0", 16, H1, W1), "e2a": ("s1", "p1", 32, H2, W2), "ba": ("s2", "p2", 64, H3, W3)}
         for name, mode, cin, cout, relu in reversed(LAYERS):
             x, y = wire[name]
             gy, gx = gof(y), gof(x)
             if relu:
                 _ok("relu_mask", lib.eiku_relu_mask(y.npix, _p(y.buf), y.cs, y.co, _p(gy.buf), gy.cs, gy.co, y.C, st))
-            if mode == CONV3:
+            if isinstance(x, Cat):
+                xa, xb = x.a, x.b
+                _ok("wgrad", lib.eiku_conv_wgrad_cat(y.B, y.H, y.W, _p(xa.buf), xa.cs, xa.co, xa.C, _p(xb.buf), xb.cs,
+                                                     xb.co, xb.C, _p(gy.buf), gy.cs, gy.co, y.C,
+                                                     _p(self.grads[name + ".w"]), st))
+            elif mode == CONV3:
                 _ok("wgrad", lib.eiku_conv_wgrad(CONV3, y.B, y.H, y.W, _p(x.buf), x.cs, x.co, x.C, _p(gy.buf), gy.cs,
                                                  gy.co, y.C, _p(self.grads[name + ".w"]), st))
             else:
@@ -261,11 +302,11 @@ class UNet:
                 _ok("dgrad", lib.eiku_conv_fwd(DOWN2, x.B, x.H, x.W, _p(gy.buf), gy.cs, gy.co, y.C,
                                                _p(self.wb[name]), None, 0, _p(gx.buf), gx.cs, gx.co, x.C, st))
             if name in pools:  # the input came from max pooling of a skip tensor: route and add
-                src, scs, sco, C, pk, pcs, hp, wp = pools[name]
-                _ok("pool_bwd", lib.eiku_maxpool_bwd(B, hp, wp, _p(b[src]), scs, sco, _p(b["g_" + pk]), pcs, 0,
+                src, pk, C, hp, wp = pools[name]
+                gs = gof(Act(b[src], B, 2 * hp, 2 * wp, C, 0, C))
+                _ok("pool_bwd", lib.eiku_maxpool_bwd(B, hp, wp, _p(b[src]), C, 0, _p(b["g_" + pk]), C, 0,
                                                      _p(b["g_pool"]), C, 0, C, st))
-                _ok("add", lib.eiku_add(B * hp * 2 * wp * 2, _p(b["g_" + src]), scs, sco, _p(b["g_pool"]), C, 0, C,
-                                        st))
+                _ok("add", lib.eiku_add(B * hp * 2 * wp * 2, _p(gs.buf), gs.cs, gs.co, _p(b["g_pool"]), C, 0, C, st))
 
     # -- optimiser ----------------------------------------------------------
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -128,6 +128,26 @@ def test_network_kernels_reject_unaligned_layouts_on_host(case):
                              args["y_cs"], args["y_co"], 16, None) == -1
 
 
+@pytest.mark.parametrize("case", ["ca_4", "ca_8", "xb_offset", "xb_slice", "xa_pointer", "xb_pointer",
+                                  "wgrad_dy_offset", "wgrad_xb_slice"])
+def test_concatenated_input_forms_reject_bad_layouts_on_host(case):
+    """The two-source convolution and weight gradient check both sources'
+    channel counts, strides, offsets and alignment before any launch."""
+    from paper_2603_00035_amd import unet
+    lib = unet._bind()
+    Xa, Xb, Wt, Y = 0x10000, 0x20000, 0x30000, 0x40000
+    a = dict(xa=Xa, xa_cs=16, xa_co=0, Ca=16, xb=Xb, xb_cs=16, xb_co=0, Cb=16)
+    a.update({"ca_4": dict(Ca=4, xa_cs=16), "ca_8": dict(Ca=8, xa_cs=8),
+              "xb_offset": dict(xb_cs=24, xb_co=4), "xb_slice": dict(xb_cs=16, xb_co=8), "xa_pointer": dict(xa=Xa + 8),
+              "xb_pointer": dict(xb=Xb + 8), "wgrad_dy_offset": {}, "wgrad_xb_slice": dict(xb_cs=16, xb_co=8)}[case])
+    src = (a["xa"], a["xa_cs"], a["xa_co"], a["Ca"], a["xb"], a["xb_cs"], a["xb_co"], a["Cb"])
+    if case.startswith("wgrad"):
+        dy_co = 4 if case == "wgrad_dy_offset" else 0
+        assert lib.eiku_conv_wgrad_cat(1, 8, 8, *src, Y, 32, dy_co, 16, Wt, None) == -1
+        return
+    assert lib.eiku_conv_fwd_cat(1, 8, 8, *src, Wt, None, 0, Y, 16, 0, 16, None) == -1
+
+
 @pytest.mark.parametrize("case", ["tau_zero", "tau_inf", "side", "tol", "cycles", "workspace"])
 def test_soft_mode_rejects_bad_arguments_on_host(case):
     """The soft-min entry points check tau, the side limit of one line per

@@ -165,6 +165,54 @@ def test_conv3_weight_gradient(B, H, W, Cin, Cout, xs, dys):
           B * H * W, out_bf16=False)
 
 
+@pytest.mark.parametrize("B,H,W,Ca,Cb,Cout,pad", [(2, 16, 40, 16, 16, 16, 0), (1, 9, 33, 32, 32, 32, 8),
+                                                  (2, 8, 32, 64, 64, 64, 0), (1, 5, 7, 16, 48, 16, 16)])
+def test_conv3_two_sources_equal_one_concatenated_buffer(B, H, W, Ca, Cb, Cout, pad):
+    """The _cat forms read the concatenation [xa | xb] from two buffers (each a
+    channel slice of a wider one when pad > 0). The forward meets the oracle's
+    arithmetic bound, and equals the one-buffer convolution of the
+    concatenation bit for bit when both take the same K slices (32 channels
+    when both halves are multiples of 32 or neither form can, else the two
+    sources go in 16-channel slices and only the rounding order differs). The
+    weight gradient meets the oracle's bound."""
+    rng = np.random.default_rng(B + H + Ca + Cb)
+    Cin = Ca + Cb
+    xa = U.bf16_round(rng.standard_normal((B, H, W, Ca)))
+    xb = U.bf16_round(rng.standard_normal((B, H, W, Cb)))
+    x = np.concatenate([xa, xb], -1)
+    w = U.bf16_round(rng.standard_normal((9, Cout, Cin)) * 0.2)
+    bias = rng.standard_normal(Cout).astype(np.float32)
+    g = U.bf16_round(rng.standard_normal((B, H, W, Cout)))
+
+    def slab(v, C):  # v as channels pad .. pad+C-1 of a wider buffer
+        out = np.zeros(v.shape[:-1] + (C + 2 * pad,))
+        out[..., pad:pad + C] = v
+        return to_dev_bf16(out)
+
+    da, db = slab(xa, Ca), slab(xb, Cb)
+    say(f"[unet] conv3 of [{Ca} | {Cb}] channels, {B}x{H}x{W} -> {Cout}, slice offset {pad}")
+    bd = to_dev(bias)
+    y_cat = torch.zeros(B * H * W * Cout, dtype=torch.int16, device="cuda")
+    y_one = torch.zeros_like(y_cat)
+    wd = to_dev_bf16(w)
+    assert lib().eiku_conv_fwd_cat(B, H, W, P(da), Ca + 2 * pad, pad, Ca, P(db), Cb + 2 * pad, pad, Cb, P(wd), P(bd), 1,
+                                   P(y_cat), Cout, 0, Cout, st()) == 0
+    assert lib().eiku_conv_fwd(0, B, H, W, P(to_dev_bf16(x)), Cin, 0, Cin, P(wd), P(bd), 1, P(y_one), Cout, 0, Cout,
+                               st()) == 0
+    same_k = (Ca % 32 == 0 and Cb % 32 == 0) or Cin % 32 != 0
+    if same_k:
+        assert torch.equal(y_cat.cpu(), y_one.cpu())
+    ref = U.conv3(x, w, bias.astype(np.float64), True)
+    absterms = U.conv3(np.abs(x), np.abs(w)) + np.abs(bias)
+    check(from_dev_bf16(y_cat, (B, H, W, Cout)), ref, absterms, 9 * Cin + 1)
+    check(from_dev_bf16(y_one, (B, H, W, Cout)), ref, absterms, 9 * Cin + 1)
+    dw = torch.zeros(9 * Cout * Cin, dtype=torch.float32, device="cuda")
+    assert lib().eiku_conv_wgrad_cat(B, H, W, P(da), Ca + 2 * pad, pad, Ca, P(db), Cb + 2 * pad, pad, Cb,
+                                     P(to_dev_bf16(g)), Cout, 0, Cout, P(dw), st()) == 0
+    check(dw.cpu().numpy().reshape(9, Cout, Cin), U.conv3_wgrad(x, g), U.conv3_wgrad(np.abs(x), np.abs(g)),
+          B * H * W, out_bf16=False)
+
+
 def test_weight_prep_mirrors_taps_for_the_data_gradient():
     """conv3 with the prepared backward weights is the adjoint of conv3."""
     rng = np.random.default_rng(6)
