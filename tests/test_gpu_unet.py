@@ -213,6 +213,52 @@ def test_conv3_two_sources_equal_one_concatenated_buffer(B, H, W, Ca, Cb, Cout, 
           B * H * W, out_bf16=False)
 
 
+@pytest.mark.parametrize("mode,Cin,Cout,cat", [(0, 16, 16, False), (0, 32, 32, True), (1, 32, 16, False)])
+def test_multi_tile_workgroups_equal_single_image_launches(mode, Cin, Cout, cat):
+    """Launches of 32 768 pixel tiles or more give each workgroup two tiles (the
+    second tile's loads in flight while the first is computed). 111 grids of
+    260 x 264 make 32 967 tiles, ragged in both directions, the last workgroup
+    with one tile: the outputs of sampled grids equal those of launches over
+    that grid alone (one tile per workgroup) bit for bit, and the first grid's
+    meet the oracle's bound."""
+    B, H, W = 111, 260, 264
+    say(f"[unet] mode {mode} {Cin}->{Cout}{' from two buffers' if cat else ''}, {B}x{H}x{W}: two tiles per workgroup")
+    gen = torch.Generator(device="cuda").manual_seed(Cin + Cout + mode)
+    x = torch.randn(B, H, W, Cin, device="cuda", generator=gen).to(torch.bfloat16).view(torch.int16)
+    rng = np.random.default_rng(Cin * Cout)
+    taps = 9 if mode == 0 else 4
+    w = U.bf16_round(rng.standard_normal((taps, Cout, Cin)) * 0.2)
+    bias = rng.standard_normal(Cout).astype(np.float32)
+    wd, bd = to_dev_bf16(w), to_dev(bias)
+    Ho, Wo = (H, W) if mode == 0 else (2 * H, 2 * W)
+    h = Cin // 2
+    xa, xb = (x[..., :h].contiguous(), x[..., h:].contiguous()) if cat else (None, None)
+
+    def run(sel, n):
+        y = torch.zeros(n, Ho, Wo, Cout, dtype=torch.int16, device="cuda")
+        if cat:
+            rc = lib().eiku_conv_fwd_cat(n, H, W, P(xa[sel]), h, 0, h, P(xb[sel]), h, 0, h, P(wd), P(bd), 1, P(y),
+                                         Cout, 0, Cout, st())
+        else:
+            rc = lib().eiku_conv_fwd(mode, n, H, W, P(x[sel]), Cin, 0, Cin, P(wd), P(bd), int(mode == 0), P(y), Cout,
+                                     0, Cout, st())
+        assert rc == 0
+        return y
+
+    y_all = run(slice(0, B), B)
+    for g in (0, 55, B - 1):
+        y_one = run(slice(g, g + 1), 1)
+        assert torch.equal(y_all[g].cpu(), y_one[0].cpu()), f"grid {g}"
+    x0 = U.from_bits(x[0].cpu().numpy().view(np.uint16)).reshape(H, W, Cin)[None]
+    got = from_dev_bf16(y_all[0], (1, Ho, Wo, Cout))
+    if mode == 0:
+        ref = U.conv3(x0, w, bias.astype(np.float64), True)
+        check(got, ref, U.conv3(np.abs(x0), np.abs(w)) + np.abs(bias), 9 * Cin + 1)
+    else:
+        ref = U.up2(x0, w, bias.astype(np.float64))
+        check(got, ref, U.up2(np.abs(x0), np.abs(w)) + np.abs(bias), Cin + 1)
+
+
 def test_weight_prep_mirrors_taps_for_the_data_gradient():
     """conv3 with the prepared backward weights is the adjoint of conv3."""
     rng = np.random.default_rng(6)
