@@ -3,11 +3,13 @@
 // The convolutions are implicit GEMMs over output channels x pixels (NHWC,
 // batch folded in) with K over (tap, input channel), accumulated in FP32.
 // k_conv_lds (3x3 convolution, 2x2 transposed convolution and its data
-// gradient, the 2x2 stride-2 convolution): a workgroup owns an 8 x 32 tile of
-// output pixels (of input pixels for the transposed convolution) and 16 NT
-// output channels. Per slice of KC input channels it stages the tile's input
-// patch and the slice of the weights in LDS, loads of the next slice in flight
-// while the current one is used; each wave runs 2 rows x 32 pixels through
+// gradient, the 2x2 stride-2 convolution): a workgroup owns one or two 8 x 32
+// tiles of output pixels (of input pixels for the transposed convolution),
+// taken in turn, and 16 NT output channels. Per slice of KC input channels it
+// stages the tile's input patch and the slice of the weights in LDS, loads of
+// the next slice (or tile) in flight while the current one is used; the 3x3
+// convolution can read a concatenation from two buffers, one source per
+// slice. Each wave runs 2 rows x 32 pixels through
 // v_mfma_f32_16x16x32_bf16 (v_mfma_f32_16x16x16_bf16 for 16-channel slices),
 // weights as the A operand and pixels as B, so a lane ends up with 4
 // consecutive channels of one pixel and stores them as one 8-byte word.
