@@ -353,6 +353,50 @@ def test_features_are_the_rounded_inputs_and_the_source_distance():
         assert np.all(got[b, ..., 6:] == 0)
 
 
+def test_network_forward_matches_the_oracle_composition_of_its_layers():
+    """The whole forward (17 convolutions, 3 poolings, the head) against the
+    oracle's layers composed in float64, each stored activation rounded to
+    bfloat16 as the kernels store it, with the skip tensor first in every
+    concatenation. FP32 accumulation against float64 flips a bf16 rounding now
+    and then (one bf16 step, 2^-8 relative, of an element); the prediction's
+    relative L2 difference stays orders of magnitude below 1e-2, which a
+    mis-wired layer (swapped concatenation halves, a wrong pooling source)
+    exceeds by far."""
+    from paper_2603_00035_amd.unet import LAYERS, UNet
+    net = UNet(seed=11)
+    B, H, W = 2, 40, 48
+    rng = np.random.default_rng(12)
+    for name, *_ in LAYERS:
+        net.params[name + ".b"].copy_(torch.tensor(rng.standard_normal(net.params[name + ".b"].numel()) * 0.1))
+    b = net._layout(B, H, W)
+    x0 = np.zeros((B, H, W, 16))
+    x0[..., :6] = U.bf16_round(rng.uniform(-1, 1, (B, H, W, 6)))
+    b["x0"].copy_(torch.tensor(U.bf16_bits(x0).view(np.int16).reshape(-1), device="cuda"))
+    say(f"[unet] whole forward {B}x{H}x{W} against the oracle's layers")
+    pred = net.forward(B, H, W).cpu().numpy().astype(np.float64).reshape(B, H, W)
+
+    P_ = {k: v.cpu().numpy().astype(np.float64) for k, v in net.params.items()}
+    R = U.bf16_round
+
+    def conv(name, x, relu=True):
+        return R(U.conv3(x, R(P_[name + ".w"]), P_[name + ".b"], relu))
+
+    def up(name, x):
+        return R(U.up2(x, R(P_[name + ".w"]), P_[name + ".b"]))
+
+    s0 = conv("e0b", conv("e0a", x0))
+    s1 = conv("e1b", conv("e1a", U.maxpool(s0)))
+    s2 = conv("e2b", conv("e2a", U.maxpool(s1)))
+    bb = conv("bb", conv("ba", U.maxpool(s2)))
+    d2 = conv("d2b", conv("d2a", np.concatenate([s2, up("u2", bb)], -1)))
+    d1 = conv("d1b", conv("d1a", np.concatenate([s1, up("u1", d2)], -1)))
+    d0 = conv("d0b", conv("d0a", np.concatenate([s0, up("u0", d1)], -1)))
+    ref = U.head(d0, P_["head.w"], P_["head.b"][0])
+    r = np.linalg.norm(pred - ref) / np.linalg.norm(ref)
+    say(f"  prediction rel L2 {r:.2e}")
+    assert r <= 1e-2
+
+
 def test_network_gradient_matches_finite_differences_of_its_loss():
     """End to end: the backward pass of the whole network (all kernels) agrees
     with central differences of its own forward loss on a few parameters."""
